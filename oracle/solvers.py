@@ -1,0 +1,175 @@
+"""Textbook FP64 solvers of the oracle (test infrastructure only).
+
+Written from the paper (Babich et al., SC11): CG and CG on the normal
+equations (Section III-A), minimal residual for the Schwarz blocks and the
+additive Schwarz preconditioner (Section III-B, Section VIII-A), and the GCR-DD
+solver of Algorithm 1 (Section VIII-A), all in FP64 with numpy inner products
+<a,b> = sum conj(a) b. Every function takes the operator as a callable.
+"""
+import numpy as np
+
+
+def dot(a, b):
+    return np.vdot(a, b)
+
+
+def norm(a):
+    return float(np.sqrt(np.vdot(a, a).real))
+
+
+def cg(apply_A, b, tol=1e-10, maxiter=10000, x0=None):
+    """Hestenes-Stiefel CG for a Hermitian positive-definite operator.
+    Stops when ||b - A x|| (the recursively updated residual) <= tol ||b||.
+    Returns (x, iterations, residual-norm history)."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - apply_A(x) if x0 is not None else b.copy()
+    p = r.copy()
+    rr = dot(r, r).real
+    bn = norm(b)
+    hist = [np.sqrt(rr)]
+    it = 0
+    while np.sqrt(rr) > tol * bn and it < maxiter:
+        Ap = apply_A(p)
+        alpha = rr / dot(p, Ap).real
+        x += alpha * p
+        r -= alpha * Ap
+        rr_new = dot(r, r).real
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+        hist.append(np.sqrt(rr))
+    return x, it, hist
+
+
+def cgne(apply_A, apply_Adag, b, tol=1e-10, maxiter=10000, x0=None):
+    """CG on the normal equations A A^+ y = b, x = A^+ y (Craig's method).
+    r = b - A x is the true residual of A x = b in exact arithmetic.
+    Returns (x, iterations, residual-norm history)."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - apply_A(x) if x0 is not None else b.copy()
+    p = apply_Adag(r)
+    rr = dot(r, r).real
+    bn = norm(b)
+    hist = [np.sqrt(rr)]
+    it = 0
+    while np.sqrt(rr) > tol * bn and it < maxiter:
+        alpha = rr / dot(p, p).real
+        x += alpha * p
+        r -= alpha * apply_A(p)
+        rr_new = dot(r, r).real
+        p = apply_Adag(r) + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+        hist.append(np.sqrt(rr))
+    return x, it, hist
+
+
+def mr_blocks(apply_A, b, nsteps, labels=None, site_axes=4):
+    """Minimal-residual iteration started from x = 0, r = b, run independently on
+    every Dirichlet block: inner products are summed over one block only
+    (domain-restricted reductions, Section VIII-A). labels: integer block id per
+    site (natural grid) or None for one block. Each step:
+        q = A r ; alpha = <q,r>/<q,q> ; x += alpha r ; r -= alpha q.
+    """
+    x = np.zeros_like(b)
+    r = b.copy()
+    if labels is None:
+        for _ in range(nsteps):
+            q = apply_A(r)
+            qq = dot(q, q).real
+            if qq == 0.0:
+                break
+            alpha = dot(q, r) / qq
+            x += alpha * r
+            r -= alpha * q
+        return x
+    lab = labels.reshape(-1)
+    nb = int(lab.max()) + 1
+    inner = int(np.prod(b.shape[site_axes:]))
+    for _ in range(nsteps):
+        q = apply_A(r)
+        qf = q.reshape(-1, inner)
+        rf = r.reshape(-1, inner)
+        qr = np.bincount(lab, weights=np.sum(np.conj(qf) * rf, axis=1).real, minlength=nb) \
+            + 1j * np.bincount(lab, weights=np.sum(np.conj(qf) * rf, axis=1).imag, minlength=nb)
+        qq = np.bincount(lab, weights=np.sum(np.abs(qf) ** 2, axis=1), minlength=nb)
+        alpha = np.where(qq > 0, qr / np.where(qq > 0, qq, 1.0), 0.0)
+        a_site = alpha[labels].reshape(labels.shape + (1,) * (b.ndim - site_axes))
+        x += a_site * r
+        r -= a_site * q
+    return x
+
+
+def schwarz(op, r, block, nsteps):
+    """Non-overlapping additive Schwarz preconditioner (block Jacobi,
+    Section III-B): on every block B of size `block`, nsteps of MR on the
+    Dirichlet-cut even-odd operator Mhat_B with block-restricted inner products.
+    op is an oracle.WilsonClover; r lives on even sites."""
+    from . import block_labels
+    labels = block_labels(op.dims, block)
+    return mr_blocks(lambda v: op.schur(v, block=block), r, nsteps, labels)
+
+
+def gcr(apply_M, precond, b, tol=1e-10, kmax=16, delta=1e-3, maxiter=10000, x0=None, record=None):
+    """GCR with restarts, Algorithm 1, entirely in FP64.
+
+    Readings: the stopping tests are relative to ||b||; the normalisation
+    step divides the orthogonalised z_k by gamma_k; the restart residual is
+    r0 = b - M x. Orthogonalisation is modified Gram-Schmidt as printed.
+    precond(r) returns K r (None: K = 1).
+    record: optional dict that receives per-step diagnostics.
+    Returns (x, total Krylov steps, restarts, list of true residual norms at restarts).
+    """
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    bn = norm(b)
+    r0 = b - apply_M(x)
+    rhat = r0.copy()
+    r0n = norm(r0)
+    true_hist = [r0n]
+    p, z, alpha, gamma = [], [], [], []
+    beta = {}
+    k = 0
+    steps = 0
+    restarts = 0
+    while r0n > tol * bn and steps < maxiter:
+        pk = precond(rhat) if precond is not None else rhat.copy()
+        zk = apply_M(pk)
+        for i in range(k):
+            beta[(i, k)] = dot(z[i], zk)
+            zk = zk - beta[(i, k)] * z[i]
+        g = norm(zk)
+        zk = zk / g
+        a = dot(zk, rhat)
+        rhat = rhat - a * zk
+        p.append(pk)
+        z.append(zk)
+        gamma.append(g)
+        alpha.append(a)
+        k += 1
+        steps += 1
+        rn = norm(rhat)
+        if record is not None:
+            record.setdefault("rhat", []).append(rn)
+            record.setdefault("z", []).append(zk)
+            record.setdefault("rvec", []).append(rhat.copy())
+        if k == kmax or rn / r0n < delta or rn < tol * bn or steps >= maxiter:
+            chi = [0j] * k
+            for l in range(k - 1, -1, -1):
+                s = alpha[l]
+                for i in range(l + 1, k):
+                    s -= beta[(l, i)] * chi[i]
+                chi[l] = s / gamma[l]
+            xhat = np.zeros_like(b)
+            for i in range(k):
+                xhat += chi[i] * p[i]
+            if record is not None:
+                record.setdefault("restart_check", []).append((apply_M(xhat), r0 - rhat))
+            x += xhat
+            r0 = b - apply_M(x)
+            r0n = norm(r0)
+            true_hist.append(r0n)
+            rhat = r0.copy()
+            p, z, alpha, gamma, beta = [], [], [], [], {}
+            k = 0
+            restarts += 1
+    return x, steps, restarts, true_hist
