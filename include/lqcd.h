@@ -1,0 +1,274 @@
+/*
+ * lqcd.h - C ABI of the MI355X (gfx950) lattice-QCD linear-solver library.
+ *
+ * The library applies the even-odd preconditioned Wilson-clover operator of
+ * eq. (2) and the improved-staggered operator of eq. (3) of Babich et al.,
+ * "Scaling Lattice QCD beyond 100 GPUs" (SC11), and solves M x = b (eq. (1))
+ * with the mixed-precision, Schwarz-preconditioned GCR of Algorithm 1
+ * (Section VIII-A) or with CG (Section III-A), on one GPU.
+ *
+ * Conventions (fixed here because the paper leaves them open):
+ *   - lattice dims (Lx, Ly, Lz, Lt), all even; site parity (x+y+z+t) mod 2,
+ *     0 = even; every direction periodic, and a hop that crosses the t
+ *     boundary is multiplied by bc_t (+1 periodic, -1 antiperiodic);
+ *   - chiral gamma basis gamma_k = [[0,-i s_k],[i s_k,0]] (k = x,y,z),
+ *     gamma_t = [[0,1],[1,0]]; spin factors of eq. (2) read as (1 -/+ gamma_mu);
+ *   - Wilson-clover in kappa normalisation: M = A - kappa D, with
+ *     A = 1 + i kappa c_sw sum_{mu<nu} sigma_munu F_munu (clover leaves,
+ *     F = (Q_munu - Q_numu)/8); this is 2 kappa times the matrix of eq. (2);
+ *   - even-odd Schur complement on even sites (Section III-A):
+ *     Mhat = A_ee - kappa^2 D_eo A_oo^-1 D_oe;
+ *   - improved staggered: M = m - D/2 with Kogut-Susskind phases, backward
+ *     hops with a minus sign (D is anti-Hermitian), long link weight c_long;
+ *     the even normal operator N_e = m^2 - D_eo D_oe / 4.
+ *
+ * Memory. Every field pointer is DEVICE memory owned by the caller; the
+ * library neither frees nor retains caller pointers after a call returns.
+ * Packed fields use the library's layout; their sizes come from
+ * lqcd_field_bytes and must be 16-byte aligned. "Natural" fields are the
+ * exchange format: complex double (re, im interleaved), site index
+ * i = x + Lx*(y + Ly*(z + Lz*t)), gauge [i][mu][row][col], Wilson spinor
+ * [i][spin][colour], staggered spinor [i][colour].
+ * The context owns all scratch memory (allocated on first use, freed by
+ * lqcd_context_destroy).
+ *
+ * Streams. Work is enqueued on the given HIP stream (0 = null stream).
+ * Operator and import/export calls return once the work is enqueued.
+ * Solver calls block the host (they read reduction results).
+ *
+ * Errors. Every call returns lqcd_status. Arguments are validated before any
+ * launch and nothing is written when validation fails. LQCD_ERR_DEVICE wraps
+ * HIP failures; lqcd_last_error() returns the text of the most recent error
+ * of the context (or of the library, for calls without a context).
+ */
+#ifndef LQCD_H
+#define LQCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lqcd_context lqcd_context;
+typedef void *lqcd_stream; /* a hipStream_t */
+
+typedef enum {
+  LQCD_OK = 0,
+  LQCD_ERR_INVALID_ARG = 1,
+  LQCD_ERR_UNSUPPORTED = 2,
+  LQCD_ERR_OUT_OF_MEMORY = 3,
+  LQCD_ERR_DEVICE = 4,
+  LQCD_ERR_NOT_CONVERGED = 5,
+  LQCD_ERR_BREAKDOWN = 6
+} lqcd_status;
+
+typedef enum { LQCD_F64 = 0, LQCD_F32 = 1, LQCD_F16 = 2, LQCD_BF16 = 3 } lqcd_precision;
+
+typedef enum { LQCD_WILSON_CLOVER = 0, LQCD_STAGGERED = 1 } lqcd_action;
+
+typedef enum {
+  LQCD_FIELD_SPINOR = 0,      /* one parity of a colour-spinor field (Vh sites) */
+  LQCD_FIELD_SPINOR_FULL = 1, /* both parities: [parity 0 block][parity 1 block] */
+  LQCD_FIELD_GAUGE = 2,       /* Wilson links or staggered fat links, 4 directions x 2 parities */
+  LQCD_FIELD_LONG = 3,        /* staggered long links */
+  LQCD_FIELD_CLOVER = 4       /* clover A (or A^-1), both parities, 72 reals per site */
+} lqcd_field_kind;
+
+/*
+ * One operator instance: the action, geometry, precision and storage of its
+ * fields. The same physical operator is usually described by several
+ * instances of different precision (FP64 for restarts, FP32 Krylov, FP16/BF16
+ * preconditioner); each owns its own packed copies of the links and clover.
+ *
+ * tile: the site-ordering tile of every packed field of this operator. Sites
+ * of one parity are stored tile by tile (tiles in lexicographic order, sites
+ * lexicographic inside a tile), so a tile's sites are contiguous. Each entry
+ * must be even and divide dims. tile = dims gives plain lexicographic
+ * even-odd order. The Schwarz blocks of lqcd_schwarz_precond must equal the
+ * tile.
+ */
+typedef struct {
+  int32_t action;       /* lqcd_action */
+  int32_t dims[4];      /* Lx, Ly, Lz, Lt: all even, >= 2 */
+  int32_t tile[4];      /* layout tile (see above) */
+  int32_t bc_t;         /* +1 or -1 */
+  int32_t prec;         /* lqcd_precision of every packed field of this instance */
+  int32_t recon;        /* 18, 12 or 8 reals per stored SU(3) link (Wilson U, staggered long) */
+  double kappa, csw;    /* Wilson-clover */
+  double mass, c_long;  /* staggered */
+  const void *gauge;      /* packed LQCD_FIELD_GAUGE (staggered fat links are always 18 reals) */
+  const void *long_links; /* packed LQCD_FIELD_LONG (staggered only) */
+  const void *clover;     /* packed A, both parities (Wilson-clover only) */
+  const void *clover_inv; /* packed A^-1, both parities (Wilson-clover only) */
+} lqcd_operator;
+
+typedef struct {
+  int32_t iters;             /* Krylov steps (GCR) or CG iterations */
+  int32_t restarts;          /* high-precision restarts / reliable updates */
+  int32_t matvecs;           /* operator applications in the Krylov precision */
+  int32_t precond_applies;   /* applications of K */
+  double true_residual;      /* ||b - M x|| / ||b||, recomputed in FP64 at the end */
+  double seconds;            /* wall time of the call */
+} lqcd_solve_info;
+
+typedef enum { LQCD_PRECOND_NONE = 0, LQCD_PRECOND_SCHWARZ = 1, LQCD_PRECOND_LEARNED = 2 } lqcd_precond_kind;
+
+typedef struct {
+  int32_t block[4]; /* Dirichlet block; must equal the tile of op_precond */
+  int32_t mr_steps; /* MR steps per block (the paper uses 10) */
+} lqcd_schwarz_params;
+
+typedef struct {
+  double tol;        /* stop when ||b - M x|| <= tol ||b|| (FP64) */
+  int32_t k_max;     /* Krylov space size before a restart */
+  double delta;      /* early restart when ||rhat|| / ||r0|| < delta */
+  int32_t max_iter;  /* total Krylov steps */
+  int32_t precond;   /* lqcd_precond_kind */
+  lqcd_schwarz_params schwarz;
+  const void *learned; /* LQCD_PRECOND_LEARNED: device pointer to packed network weights */
+} lqcd_gcr_params;
+
+typedef enum { LQCD_CG_CGNE_SCHUR = 0, LQCD_CG_STAG_NORMAL = 1 } lqcd_cg_kind;
+
+typedef struct {
+  double tol;            /* stop when ||b - A x|| <= tol ||b|| (FP64) */
+  int32_t max_iter;
+  double delta_reliable; /* reliable update when ||r|| < delta * max ||r|| since the last one */
+  int32_t kind;          /* lqcd_cg_kind */
+} lqcd_cg_params;
+
+/* ---------------------------------------------------------------------- */
+/* context and sizes                                                       */
+
+/* Create a context on the current HIP device. */
+lqcd_status lqcd_context_create(lqcd_context **ctx);
+lqcd_status lqcd_context_destroy(lqcd_context *ctx);
+/* Text of the last error (never NULL; "" if none). ctx may be NULL. */
+const char *lqcd_last_error(const lqcd_context *ctx);
+
+/* Bytes of one packed field of `kind` for operator `op` (nrhs consecutive copies). */
+lqcd_status lqcd_field_bytes(const lqcd_operator *op, int32_t kind, int32_t nrhs, size_t *bytes);
+
+/* ---------------------------------------------------------------------- */
+/* setup: packing and derived fields                                       */
+
+/*
+ * Pack natural FP64 links (device, [V][4][3][3] complex) into op's layout,
+ * precision and compression. which = LQCD_FIELD_GAUGE packs Wilson links
+ * (recon op->recon) or staggered fat links (always 18 reals);
+ * which = LQCD_FIELD_LONG packs staggered long links already formed.
+ * Compression 12/8 assumes SU(3) links.
+ */
+lqcd_status lqcd_gauge_import(lqcd_context *ctx, const lqcd_operator *op, void *packed,
+                              const void *natural, int32_t which, lqcd_stream stream);
+
+/*
+ * Long links of eq. (3): L_mu(x) = U_mu(x) U_mu(x+mu) U_mu(x+2mu), formed in
+ * FP64 from natural thin links (device) and packed with op->recon.
+ */
+lqcd_status lqcd_long_link_build(lqcd_context *ctx, const lqcd_operator *op, void *packed_long,
+                                 const void *natural_thin, lqcd_stream stream);
+
+/*
+ * Clover field of eq. (2) (its footnote: 72 reals per site) in kappa
+ * normalisation, A = 1 + i kappa c_sw sum_{mu<nu} sigma_munu F_munu, built
+ * in FP64 from natural links (device) and inverted per site (two Hermitian
+ * 6x6 chiral blocks, Cholesky); both packed in op's layout and precision for
+ * both parities. Returns LQCD_ERR_BREAKDOWN if a block is not positive definite.
+ */
+lqcd_status lqcd_clover_build(lqcd_context *ctx, const lqcd_operator *op, void *clover,
+                              void *clover_inv, const void *natural_gauge, lqcd_stream stream);
+
+/*
+ * Pack / unpack a spinor between natural FP64 (device) and op's layout.
+ * parity 0 or 1: only that parity (packed = one LQCD_FIELD_SPINOR block);
+ * parity -1: both (packed = LQCD_FIELD_SPINOR_FULL). Export writes only the
+ * natural sites of the parities it covers.
+ */
+lqcd_status lqcd_spinor_import(lqcd_context *ctx, const lqcd_operator *op, void *packed,
+                               const void *natural, int32_t parity, lqcd_stream stream);
+lqcd_status lqcd_spinor_export(lqcd_context *ctx, const lqcd_operator *op, void *natural,
+                               const void *packed, int32_t parity, lqcd_stream stream);
+
+/* ---------------------------------------------------------------------- */
+/* operators                                                               */
+
+/*
+ * Hopping term between parities: out_p = D_{p,1-p} in_{1-p}.
+ * Wilson (eq. (2)): D = sum_mu (1-gamma_mu) U_mu(x) delta_{x+mu} + (1+gamma_mu) U^+_mu(x-mu) delta_{x-mu};
+ * dagger = 1 applies D^+ = gamma5 D gamma5.
+ * Staggered (eq. (3)): fat and long hops with Kogut-Susskind phases; dagger = 1 applies D^+ = -D.
+ * block: NULL, or the Dirichlet block size per axis (each divides dims):
+ * every hop whose two sites lie in different blocks is dropped (Section III-B,
+ * Section VIII-A); an axis with one block keeps its periodic hop.
+ * out and in are packed single-parity spinors; nrhs consecutive fields.
+ */
+lqcd_status lqcd_dslash(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in,
+                        int32_t out_parity, int32_t dagger, const int32_t *block, int32_t nrhs,
+                        lqcd_stream stream);
+
+/*
+ * Clover term of eq. (2): out_p = A_p in_p (inverse = 0) or A_p^-1 in_p
+ * (inverse = 1), single-parity packed spinors, nrhs consecutive fields.
+ */
+lqcd_status lqcd_clover_apply(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in,
+                              int32_t parity, int32_t inverse, int32_t nrhs, lqcd_stream stream);
+
+/*
+ * Even-odd operator on even sites (Section III-A):
+ * Wilson-clover: out = Mhat in = A_ee in - kappa^2 D_eo A_oo^-1 D_oe in (dagger: Mhat^+);
+ * staggered: out = N_e in = m^2 in - D_eo D_oe in / 4.
+ * block as in lqcd_dslash (Dirichlet-cut operator Mhat_B).
+ */
+lqcd_status lqcd_schur_apply(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in,
+                             int32_t dagger, const int32_t *block, int32_t nrhs, lqcd_stream stream);
+
+/*
+ * Additive Schwarz preconditioner (Section III-B; Section VIII-A): on every
+ * Dirichlet block B, mr_steps minimal-residual steps on the cut operator
+ * Mhat_B, started from zero, with inner products over B only; the blocks are
+ * independent (block Jacobi). out_even = K in_even, packed even spinors in
+ * op_precond's precision. K is positively homogeneous, K(c r) = c K(r).
+ */
+lqcd_status lqcd_schwarz_precond(lqcd_context *ctx, const lqcd_operator *op_precond,
+                                 const lqcd_schwarz_params *params, void *out_even,
+                                 const void *in_even, lqcd_stream stream);
+
+/* ---------------------------------------------------------------------- */
+/* solvers                                                                 */
+
+/*
+ * Mixed-precision GCR-DD, Algorithm 1: solves M x = b for the full
+ * Wilson-clover lattice through the even-odd system (source
+ * bhat = b_e + kappa D_eo A_oo^-1 b_o, solve Mhat x_e = bhat, then
+ * x_o = A_oo^-1 (b_o + kappa D_oe x_e)). The Krylov space (p, z) is built
+ * in op_krylov's precision, K in op_precond's, and every restart recomputes
+ * r = bhat - Mhat x with op_hi (FP64), where the solution accumulates.
+ * x_full (in: initial guess, out: solution) and b_full are packed
+ * LQCD_FIELD_SPINOR_FULL fields of op_hi. Returns LQCD_ERR_NOT_CONVERGED
+ * (best iterate in x_full, info filled) when max_iter is reached.
+ */
+lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op_hi,
+                           const lqcd_operator *op_krylov, const lqcd_operator *op_precond,
+                           const lqcd_gcr_params *params, void *x_full, const void *b_full,
+                           lqcd_solve_info *info, lqcd_stream stream);
+
+/*
+ * CG (Section III-A) with reliable updates when op_sloppy is less precise
+ * than op_hi (x and the true residual kept in op_hi's precision).
+ * kind = LQCD_CG_CGNE_SCHUR: solves M x = b for the full Wilson-clover
+ *   lattice through CG on the normal equations of Mhat (x, b packed FULL);
+ * kind = LQCD_CG_STAG_NORMAL: solves N_e x_e = b_e on even sites (eq. (4)
+ *   with one shift sigma = 0; x, b packed single-parity even).
+ * op_sloppy may be NULL (pure op_hi).
+ */
+lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_hi,
+                          const lqcd_operator *op_sloppy, const lqcd_cg_params *params, void *x,
+                          const void *b, lqcd_solve_info *info, lqcd_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LQCD_H */

@@ -1,0 +1,513 @@
+// C ABI entry points: validation, context and scratch management, packing
+// calls and the operator compositions (Schur complement, staggered normal
+// operator, additive Schwarz). Solvers live in solvers.cpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "lqcd_internal.h"
+#include "lqcd_ops.h"
+
+using namespace lqcd;
+
+static std::string g_last_error;  // errors of calls made without a context
+
+namespace lqcd {
+
+lqcd_status set_error(lqcd_context *ctx, lqcd_status st, const std::string &msg) {
+  if (ctx)
+    ctx->last_error = msg;
+  else
+    g_last_error = msg;
+  return st;
+}
+
+lqcd_status hip_check(lqcd_context *ctx, hipError_t e, const char *what) {
+  if (e == hipSuccess) return LQCD_OK;
+  return set_error(ctx, LQCD_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+Geom make_geom(const int32_t dims[4], const int32_t tile[4], int bc_t) {
+  Geom g;
+  memset(&g, 0, sizeof(g));
+  for (int m = 0; m < 4; ++m) {
+    g.L[m] = dims[m];
+    g.B[m] = tile[m];
+    g.NT[m] = dims[m] / tile[m];
+    g.cut[m] = dims[m];
+  }
+  const int64_t V = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
+  g.Vh = (int)(V / 2);
+  g.Vt2 = tile[0] * tile[1] * tile[2] * tile[3] / 2;
+  g.bc_t = bc_t;
+  g.has_cut = 0;
+  g.dVt2 = make_fastdiv(g.Vt2);
+  g.dBxh = make_fastdiv(tile[0] / 2);
+  g.dBy = make_fastdiv(tile[1]);
+  g.dBz = make_fastdiv(tile[2]);
+  g.dNTx = make_fastdiv(g.NT[0]);
+  g.dNTy = make_fastdiv(g.NT[1]);
+  g.dNTz = make_fastdiv(g.NT[2]);
+  for (int m = 0; m < 4; ++m) g.dcut[m] = make_fastdiv(dims[m]);
+  return g;
+}
+
+lqcd_status check_op(lqcd_context *ctx, const lqcd_operator *op, OpInfo *info) {
+  if (!op) return set_error(ctx, LQCD_ERR_INVALID_ARG, "operator is NULL");
+  if (op->action != LQCD_WILSON_CLOVER && op->action != LQCD_STAGGERED)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "unknown action");
+  int64_t V = 1;
+  for (int m = 0; m < 4; ++m) {
+    if (op->dims[m] < 2 || (op->dims[m] & 1))
+      return set_error(ctx, LQCD_ERR_INVALID_ARG, "lattice extents must be even and >= 2");
+    if (op->tile[m] < 2 || (op->tile[m] & 1) || op->dims[m] % op->tile[m])
+      return set_error(ctx, LQCD_ERR_INVALID_ARG, "tile extents must be even and divide the lattice");
+    V *= op->dims[m];
+  }
+  if (V / 2 >= (int64_t)1 << 30) return set_error(ctx, LQCD_ERR_UNSUPPORTED, "lattice too large");
+  if (op->bc_t != 1 && op->bc_t != -1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bc_t must be +1 or -1");
+  if (op->prec < LQCD_F64 || op->prec > LQCD_BF16) return set_error(ctx, LQCD_ERR_INVALID_ARG, "unknown precision");
+  if (op->recon != 18 && op->recon != 12 && op->recon != 8)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "recon must be 18, 12 or 8");
+  if (op->recon == 8 && (op->prec == LQCD_F16 || op->prec == LQCD_BF16))
+    return set_error(ctx, LQCD_ERR_UNSUPPORTED,
+                     "8-real link compression divides by |U01|^2+|U02|^2 and is not supported in 16-bit storage");
+  if (info) {
+    info->op = op;
+    info->g = make_geom(op->dims, op->tile, op->bc_t);
+    info->prec = op->prec;
+    info->recon = op->recon;
+    info->nsp = spinor_reals(op->action);
+    info->vh = (size_t)(V / 2);
+    info->spinor_bytes = info->vh * info->nsp * prec_bytes(op->prec);
+  }
+  return LQCD_OK;
+}
+
+lqcd_status apply_cut(lqcd_context *ctx, const OpInfo &info, const int32_t *block, Geom *g) {
+  *g = info.g;
+  if (!block) return LQCD_OK;
+  for (int m = 0; m < 4; ++m) {
+    if (block[m] < 2 || (block[m] & 1) || info.g.L[m] % block[m])
+      return set_error(ctx, LQCD_ERR_INVALID_ARG, "Dirichlet block extents must be even and divide the lattice");
+    g->cut[m] = block[m];
+    g->dcut[m] = make_fastdiv(block[m]);
+    if (block[m] < info.g.L[m]) g->has_cut = 1;
+  }
+  return LQCD_OK;
+}
+
+lqcd_status scratch(lqcd_context *ctx, int slot, size_t bytes, void **ptr) {
+  if (slot >= (int)ctx->scratch.size()) {
+    ctx->scratch.resize(slot + 1, nullptr);
+    ctx->scratch_bytes.resize(slot + 1, 0);
+  }
+  if (ctx->scratch_bytes[slot] < bytes) {
+    if (ctx->scratch[slot]) {
+      hipDeviceSynchronize();
+      hipFree(ctx->scratch[slot]);
+      ctx->scratch[slot] = nullptr;
+      ctx->scratch_bytes[slot] = 0;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return set_error(ctx, LQCD_ERR_OUT_OF_MEMORY, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    ctx->scratch[slot] = p;
+    ctx->scratch_bytes[slot] = bytes;
+  }
+  *ptr = ctx->scratch[slot];
+  return LQCD_OK;
+}
+
+RedScratch red_scratch(lqcd_context *ctx) {
+  RedScratch r;
+  r.partials = ctx->red_partials;
+  r.counter = ctx->red_counter;
+  r.result = ctx->red_result;
+  r.max_wg = 1024;
+  return r;
+}
+
+lqcd_status read_result(lqcd_context *ctx, hipStream_t st, int n, double *out) {
+  lqcd_status s = hip_check(ctx, hipMemcpyAsync(ctx->red_host, ctx->red_result, n * sizeof(double),
+                                                hipMemcpyDeviceToHost, st),
+                            "reduction result copy");
+  if (s) return s;
+  s = hip_check(ctx, hipStreamSynchronize(st), "stream synchronize");
+  if (s) return s;
+  for (int i = 0; i < n; ++i) out[i] = ctx->red_host[i];
+  return LQCD_OK;
+}
+
+const void *clover_block(const OpInfo &info, const void *clov, int parity) {
+  return (const char *)clov + (size_t)parity * info.vh * 72 * prec_bytes(info.prec);
+}
+
+// ---------------------------------------------------------------------------
+// operator compositions used by the entry points and the solvers
+
+lqcd_status wilson_hop(lqcd_context *ctx, const OpInfo &info, const Geom &g, int mode, void *out, const void *in,
+                       const void *xin, const void *clov, int parity, double coef, int dagger, double *partials,
+                       hipStream_t st) {
+  WilsonLaunch w;
+  w.g = g;
+  w.prec = info.prec;
+  w.recon = info.recon;
+  w.out = out;
+  w.in = in;
+  w.gauge = info.op->gauge;
+  w.clov = clov;
+  w.xin = xin;
+  w.parity = parity;
+  w.coef = coef;
+  w.dagger = dagger;
+  w.mode = mode;
+  w.partials = partials;
+  w.block_threads = 256;
+  return hip_check(ctx, launch_wilson(w, st, nullptr), "wilson dslash launch");
+}
+
+lqcd_status stag_hop(lqcd_context *ctx, const OpInfo &info, void *out, const void *in, const void *xin, int parity,
+                     double coef, double xcoef, hipStream_t st) {
+  StagLaunch l;
+  l.g = info.g;
+  l.prec = info.prec;
+  l.recon = info.recon;
+  l.out = out;
+  l.in = in;
+  l.fat = info.op->gauge;
+  l.lng = info.op->long_links;
+  l.xin = xin;
+  l.parity = parity;
+  l.coef = coef;
+  l.xcoef = xcoef;
+  l.c_long = info.op->c_long;
+  l.block_threads = 256;
+  return hip_check(ctx, launch_staggered(l, st), "staggered dslash launch");
+}
+
+// Wilson: Mhat in = A_ee in - kappa^2 D_eo A_oo^-1 D_oe in (optionally cut, daggered,
+// with per-workgroup partials <out,in>, <out,out>). Staggered: N_e in.
+// tmp: one single-parity spinor of this operator.
+lqcd_status schur_apply(lqcd_context *ctx, const OpInfo &info, const Geom &g, void *out, const void *in, void *tmp,
+                        int dagger, double *partials, hipStream_t st) {
+  const lqcd_operator *op = info.op;
+  if (op->action == LQCD_WILSON_CLOVER) {
+    lqcd_status s = wilson_hop(ctx, info, g, W_HOP_CLOV, tmp, in, nullptr, clover_block(info, op->clover_inv, 1), 1,
+                               1.0, dagger, nullptr, st);
+    if (s) return s;
+    return wilson_hop(ctx, info, g, W_XPAY_CLOV, out, tmp, in, clover_block(info, op->clover, 0), 0,
+                      -op->kappa * op->kappa, dagger, partials, st);
+  }
+  lqcd_status s = stag_hop(ctx, info, tmp, in, nullptr, 1, 1.0, 0.0, st);
+  if (s) return s;
+  return stag_hop(ctx, info, out, tmp, in, 0, -0.25, op->mass * op->mass, st);
+}
+
+// Additive Schwarz on the tile blocks: out = K in, both packed even spinors of
+// op_precond. Work vectors come from scratch slots [slot0, slot0+4).
+lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schwarz_params *prm, void *out,
+                          const void *in, int slot0, hipStream_t st) {
+  Geom g;
+  lqcd_status s = apply_cut(ctx, info, prm->block, &g);
+  if (s) return s;
+  const size_t sb = info.spinor_bytes;
+  void *r, *q, *t, *part;
+  if ((s = scratch(ctx, slot0, sb, &r)) || (s = scratch(ctx, slot0 + 1, sb, &q)) || (s = scratch(ctx, slot0 + 2, sb, &t)))
+    return s;
+  // one (<q,r>, <q,q>) triple per reduction segment of min(tile sites, 256) sites
+  const int seg = info.g.Vt2 < 256 ? info.g.Vt2 : 256;
+  const size_t nseg = (info.vh + seg - 1) / seg;
+  if ((s = scratch(ctx, slot0 + 3, nseg * 3 * sizeof(double), &part))) return s;
+  s = hip_check(ctx, hipMemcpyAsync(r, in, sb, hipMemcpyDeviceToDevice, st), "schwarz copy");
+  if (s) return s;
+  const int nps = info.g.Vt2 > 256 ? info.g.Vt2 / 256 : 1;  // reduction segments per block
+  for (int it = 0; it < prm->mr_steps; ++it) {
+    if ((s = schur_apply(ctx, info, g, q, r, t, 0, (double *)part, st))) return s;
+    if ((s = hip_check(ctx, launch_mr_update(info.g, info.prec, out, r, q, (const double *)part, nps, it == 0, st),
+                       "schwarz MR update")))
+      return s;
+  }
+  return LQCD_OK;
+}
+
+lqcd_status check_schwarz(lqcd_context *ctx, const OpInfo &info, const lqcd_schwarz_params *prm) {
+  if (!prm) return set_error(ctx, LQCD_ERR_INVALID_ARG, "schwarz params are NULL");
+  if (info.op->action != LQCD_WILSON_CLOVER)
+    return set_error(ctx, LQCD_ERR_UNSUPPORTED, "the Schwarz preconditioner is implemented for Wilson-clover");
+  lqcd_status s = check_fields_internal(ctx, info.op);
+  if (s) return s;
+  if (prm->mr_steps < 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "mr_steps must be >= 1");
+  for (int m = 0; m < 4; ++m)
+    if (prm->block[m] != info.op->tile[m])
+      return set_error(ctx, LQCD_ERR_INVALID_ARG, "Schwarz blocks must equal the operator's layout tile");
+  const int v = info.g.Vt2;
+  if (!((v <= 256 && 256 % v == 0) || (v > 256 && v % 256 == 0)))
+    return set_error(ctx, LQCD_ERR_UNSUPPORTED,
+                     "Schwarz block sites per parity must divide 256 or be a multiple of 256");
+  return LQCD_OK;
+}
+
+lqcd_status check_fields_internal(lqcd_context *ctx, const lqcd_operator *op) {
+  auto ok = [](const void *p) { return p && ((uintptr_t)p & 15) == 0; };
+  if (!ok(op->gauge)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "operator gauge field missing or misaligned");
+  if (op->action == LQCD_STAGGERED && !ok(op->long_links))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "staggered operator needs long links");
+  if (op->action == LQCD_WILSON_CLOVER && (!ok(op->clover) || !ok(op->clover_inv)))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "Wilson-clover operator needs clover and clover_inv");
+  return LQCD_OK;
+}
+
+}  // namespace lqcd
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+lqcd_status lqcd_context_create(lqcd_context **out) {
+  if (!out) return set_error(nullptr, LQCD_ERR_INVALID_ARG, "ctx pointer is NULL");
+  lqcd_context *ctx = new lqcd_context();
+  hipGetDevice(&ctx->device);
+  lqcd_status s = LQCD_OK;
+  if (hipMalloc(&ctx->red_partials, 1024 * kMaxRed * sizeof(double)) != hipSuccess ||
+      hipMalloc(&ctx->red_counter, 64) != hipSuccess ||
+      hipMalloc(&ctx->red_result, kMaxRed * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&ctx->red_host, kMaxRed * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    s = LQCD_ERR_OUT_OF_MEMORY;
+  if (!s && hipMemset(ctx->red_counter, 0, 64) != hipSuccess) s = LQCD_ERR_DEVICE;
+  if (s) {
+    (void)hipGetLastError();
+    lqcd_context_destroy(ctx);
+    return set_error(nullptr, s, "context allocation failed");
+  }
+  ctx->red_partials_count = 1024 * kMaxRed;
+  *out = ctx;
+  return LQCD_OK;
+}
+
+lqcd_status lqcd_context_destroy(lqcd_context *ctx) {
+  if (!ctx) return LQCD_OK;
+  hipDeviceSynchronize();
+  for (void *p : ctx->scratch)
+    if (p) hipFree(p);
+  if (ctx->red_partials) hipFree(ctx->red_partials);
+  if (ctx->red_counter) hipFree(ctx->red_counter);
+  if (ctx->red_result) hipFree(ctx->red_result);
+  if (ctx->red_host) hipHostFree(ctx->red_host);
+  delete ctx;
+  return LQCD_OK;
+}
+
+const char *lqcd_last_error(const lqcd_context *ctx) { return ctx ? ctx->last_error.c_str() : g_last_error.c_str(); }
+
+lqcd_status lqcd_field_bytes(const lqcd_operator *op, int32_t kind, int32_t nrhs, size_t *bytes) {
+  OpInfo info;
+  lqcd_status s = check_op(nullptr, op, &info);
+  if (s) return s;
+  if (!bytes || nrhs < 1) return set_error(nullptr, LQCD_ERR_INVALID_ARG, "bad bytes pointer or nrhs");
+  const size_t pb = prec_bytes(op->prec), vh = info.vh;
+  size_t n = 0;
+  switch (kind) {
+    case LQCD_FIELD_SPINOR: n = vh * info.nsp * pb; break;
+    case LQCD_FIELD_SPINOR_FULL: n = 2 * vh * info.nsp * pb; break;
+    case LQCD_FIELD_GAUGE: n = 8 * vh * (op->action == LQCD_STAGGERED ? 18 : op->recon) * pb; break;
+    case LQCD_FIELD_LONG:
+      if (op->action != LQCD_STAGGERED) return set_error(nullptr, LQCD_ERR_INVALID_ARG, "long links are staggered only");
+      n = 8 * vh * op->recon * pb;
+      break;
+    case LQCD_FIELD_CLOVER:
+      if (op->action != LQCD_WILSON_CLOVER) return set_error(nullptr, LQCD_ERR_INVALID_ARG, "clover is Wilson only");
+      n = 2 * vh * 72 * pb;
+      break;
+    default: return set_error(nullptr, LQCD_ERR_INVALID_ARG, "unknown field kind");
+  }
+  *bytes = n * (size_t)nrhs;
+  return LQCD_OK;
+}
+
+static bool aligned16(const void *p) { return p && ((uintptr_t)p & 15) == 0; }
+
+lqcd_status lqcd_gauge_import(lqcd_context *ctx, const lqcd_operator *op, void *packed, const void *natural,
+                              int32_t which, lqcd_stream stream) {
+  OpInfo info;
+  lqcd_status s = check_op(ctx, op, &info);
+  if (s) return s;
+  if (!aligned16(packed) || !aligned16(natural))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "field pointers must be non-NULL and 16-byte aligned");
+  int recon;
+  if (which == LQCD_FIELD_GAUGE)
+    recon = op->action == LQCD_STAGGERED ? 18 : op->recon;
+  else if (which == LQCD_FIELD_LONG && op->action == LQCD_STAGGERED)
+    recon = op->recon;
+  else
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "which must be LQCD_FIELD_GAUGE or (staggered) LQCD_FIELD_LONG");
+  return hip_check(ctx, launch_gauge_import(info.g, op->prec, recon, packed, (const double *)natural, 0,
+                                            (hipStream_t)stream),
+                   "gauge import");
+}
+
+lqcd_status lqcd_long_link_build(lqcd_context *ctx, const lqcd_operator *op, void *packed_long,
+                                 const void *natural_thin, lqcd_stream stream) {
+  OpInfo info;
+  lqcd_status s = check_op(ctx, op, &info);
+  if (s) return s;
+  if (op->action != LQCD_STAGGERED) return set_error(ctx, LQCD_ERR_INVALID_ARG, "long links need a staggered operator");
+  if (!aligned16(packed_long) || !aligned16(natural_thin))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "field pointers must be non-NULL and 16-byte aligned");
+  return hip_check(ctx, launch_gauge_import(info.g, op->prec, op->recon, packed_long, (const double *)natural_thin, 1,
+                                            (hipStream_t)stream),
+                   "long link build");
+}
+
+lqcd_status lqcd_clover_build(lqcd_context *ctx, const lqcd_operator *op, void *clover, void *clover_inv,
+                              const void *natural_gauge, lqcd_stream stream) {
+  OpInfo info;
+  lqcd_status s = check_op(ctx, op, &info);
+  if (s) return s;
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  if (op->action != LQCD_WILSON_CLOVER) return set_error(ctx, LQCD_ERR_INVALID_ARG, "clover needs a Wilson-clover operator");
+  if (!aligned16(clover) || !aligned16(clover_inv) || !aligned16(natural_gauge))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "field pointers must be non-NULL and 16-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  void *flag;
+  if ((s = scratch(ctx, kSlotFlag, 16, &flag))) return s;
+  if ((s = hip_check(ctx, hipMemsetAsync(flag, 0, 16, st), "flag clear"))) return s;
+  if ((s = hip_check(ctx, launch_clover_build(info.g, op->prec, op->kappa, op->csw, clover, clover_inv,
+                                              (const double *)natural_gauge, (int *)flag, st),
+                     "clover build")))
+    return s;
+  int h = 0;
+  if ((s = hip_check(ctx, hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st), "flag copy"))) return s;
+  if ((s = hip_check(ctx, hipStreamSynchronize(st), "stream synchronize"))) return s;
+  if (h) return set_error(ctx, LQCD_ERR_BREAKDOWN, "clover block not positive definite (Cholesky failed)");
+  return LQCD_OK;
+}
+
+static lqcd_status spinor_io(lqcd_context *ctx, const lqcd_operator *op, void *packed, const void *natural,
+                             int parity, lqcd_stream stream, bool imp) {
+  OpInfo info;
+  lqcd_status s = check_op(ctx, op, &info);
+  if (s) return s;
+  if (parity < -1 || parity > 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "parity must be 0, 1 or -1");
+  if (!aligned16(packed) || !aligned16(natural))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "field pointers must be non-NULL and 16-byte aligned");
+  for (int p = 0; p < 2; ++p) {
+    if (parity >= 0 && p != parity) continue;
+    char *blk = (char *)packed + (parity < 0 ? p * info.spinor_bytes : 0);
+    hipError_t e = imp ? launch_spinor_import(info.g, op->prec, info.nsp, blk, (const double *)natural, p,
+                                              (hipStream_t)stream)
+                       : launch_spinor_export(info.g, op->prec, info.nsp, (double *)natural, blk, p,
+                                              (hipStream_t)stream);
+    if ((s = hip_check(ctx, e, imp ? "spinor import" : "spinor export"))) return s;
+  }
+  return LQCD_OK;
+}
+
+lqcd_status lqcd_spinor_import(lqcd_context *ctx, const lqcd_operator *op, void *packed, const void *natural,
+                               int32_t parity, lqcd_stream stream) {
+  return spinor_io(ctx, op, packed, natural, parity, stream, true);
+}
+
+lqcd_status lqcd_spinor_export(lqcd_context *ctx, const lqcd_operator *op, void *natural, const void *packed,
+                               int32_t parity, lqcd_stream stream) {
+  return spinor_io(ctx, op, (void *)packed, natural, parity, stream, false);
+}
+
+static lqcd_status check_fields(lqcd_context *ctx, const lqcd_operator *op, bool need_clover) {
+  if (!aligned16(op->gauge)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "operator gauge field missing or misaligned");
+  if (op->action == LQCD_STAGGERED && !aligned16(op->long_links))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "staggered operator needs long links");
+  if (need_clover && op->action == LQCD_WILSON_CLOVER && (!aligned16(op->clover) || !aligned16(op->clover_inv)))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "Wilson-clover operator needs clover and clover_inv");
+  return LQCD_OK;
+}
+
+lqcd_status lqcd_dslash(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in, int32_t out_parity,
+                        int32_t dagger, const int32_t *block, int32_t nrhs, lqcd_stream stream) {
+  OpInfo info;
+  lqcd_status s = check_op(ctx, op, &info);
+  if (s) return s;
+  if ((s = check_fields(ctx, op, false))) return s;
+  if (out_parity != 0 && out_parity != 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "out_parity must be 0 or 1");
+  if (nrhs < 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "nrhs must be >= 1");
+  if (!aligned16(out) || !aligned16(in))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "field pointers must be non-NULL and 16-byte aligned");
+  Geom g;
+  if ((s = apply_cut(ctx, info, block, &g))) return s;
+  if (op->action == LQCD_STAGGERED && g.has_cut)
+    return set_error(ctx, LQCD_ERR_UNSUPPORTED, "Dirichlet cut is implemented for the Wilson operator");
+  for (int r = 0; r < nrhs; ++r) {
+    void *o = (char *)out + r * info.spinor_bytes;
+    const void *i = (const char *)in + r * info.spinor_bytes;
+    if (op->action == LQCD_WILSON_CLOVER)
+      s = wilson_hop(ctx, info, g, W_HOP, o, i, nullptr, nullptr, out_parity, 1.0, dagger, nullptr,
+                     (hipStream_t)stream);
+    else
+      s = stag_hop(ctx, info, o, i, nullptr, out_parity, dagger ? -1.0 : 1.0, 0.0, (hipStream_t)stream);
+    if (s) return s;
+  }
+  return LQCD_OK;
+}
+
+lqcd_status lqcd_clover_apply(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in, int32_t parity,
+                              int32_t inverse, int32_t nrhs, lqcd_stream stream) {
+  OpInfo info;
+  lqcd_status s = check_op(ctx, op, &info);
+  if (s) return s;
+  if (op->action != LQCD_WILSON_CLOVER) return set_error(ctx, LQCD_ERR_INVALID_ARG, "clover needs a Wilson-clover operator");
+  if (!aligned16(op->clover) || !aligned16(op->clover_inv))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "operator clover fields missing or misaligned");
+  if (parity != 0 && parity != 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "parity must be 0 or 1");
+  if (nrhs < 1 || !aligned16(out) || !aligned16(in)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad fields or nrhs");
+  const void *c = clover_block(info, inverse ? op->clover_inv : op->clover, parity);
+  for (int r = 0; r < nrhs; ++r) {
+    s = hip_check(ctx, launch_clover_apply(info.g, op->prec, (char *)out + r * info.spinor_bytes,
+                                           (const char *)in + r * info.spinor_bytes, c, (hipStream_t)stream),
+                  "clover apply");
+    if (s) return s;
+  }
+  return LQCD_OK;
+}
+
+lqcd_status lqcd_schur_apply(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in, int32_t dagger,
+                             const int32_t *block, int32_t nrhs, lqcd_stream stream) {
+  OpInfo info;
+  lqcd_status s = check_op(ctx, op, &info);
+  if (s) return s;
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  if ((s = check_fields(ctx, op, true))) return s;
+  if (nrhs < 1 || !aligned16(out) || !aligned16(in)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad fields or nrhs");
+  Geom g;
+  if ((s = apply_cut(ctx, info, block, &g))) return s;
+  if (op->action == LQCD_STAGGERED && g.has_cut)
+    return set_error(ctx, LQCD_ERR_UNSUPPORTED, "Dirichlet cut is implemented for the Wilson operator");
+  void *tmp;
+  if ((s = scratch(ctx, kSlotSchurTmp, info.spinor_bytes, &tmp))) return s;
+  for (int r = 0; r < nrhs; ++r) {
+    s = schur_apply(ctx, info, g, (char *)out + r * info.spinor_bytes, (const char *)in + r * info.spinor_bytes, tmp,
+                    dagger, nullptr, (hipStream_t)stream);
+    if (s) return s;
+  }
+  return LQCD_OK;
+}
+
+lqcd_status lqcd_schwarz_precond(lqcd_context *ctx, const lqcd_operator *op_precond, const lqcd_schwarz_params *params,
+                                 void *out_even, const void *in_even, lqcd_stream stream) {
+  OpInfo info;
+  lqcd_status s = check_op(ctx, op_precond, &info);
+  if (s) return s;
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  if ((s = check_schwarz(ctx, info, params))) return s;
+  if (!aligned16(out_even) || !aligned16(in_even)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
+  if (out_even == in_even) return set_error(ctx, LQCD_ERR_INVALID_ARG, "out and in must not alias");
+  return schwarz_apply(ctx, info, params, out_even, in_even, kSlotSchwarz, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,427 @@
+// Level-1 linear algebra and global reductions for the solvers.
+//
+// Vectors are flat arrays of n complex numbers (2n reals) in any storage
+// precision; the packed spinor layouts keep each (re, im) pair adjacent, so a
+// field of any layout is such a vector. Arithmetic is done in FP32 (FP64 for
+// FP64 vectors) and every reduction accumulates in FP64: per-thread sums, a
+// wave64 butterfly, the waves of a workgroup through LDS, then the last
+// workgroup to finish (ticket counter) sums the per-workgroup partials in a
+// fixed order. Results are therefore deterministic for a given n.
+#include <type_traits>
+
+#include "lqcd_internal.h"
+
+namespace lqcd {
+
+constexpr int kBT = 256;
+constexpr int kMaxVec = 32;
+
+// 4 consecutive reals (2 complex numbers) of storage type S.
+template <typename S> struct Quad;
+template <> struct Quad<double> {
+  __device__ static void load(const double *p, size_t i, double (&v)[4]) {
+    const Chunk<double, 2> *q = reinterpret_cast<const Chunk<double, 2> *>(p + 4 * i);
+    Chunk<double, 2> a = q[0], b = q[1];
+    v[0] = a.v[0]; v[1] = a.v[1]; v[2] = b.v[0]; v[3] = b.v[1];
+  }
+  __device__ static void store(double *p, size_t i, const double (&v)[4]) {
+    Chunk<double, 2> *q = reinterpret_cast<Chunk<double, 2> *>(p + 4 * i);
+    Chunk<double, 2> a, b;
+    a.v[0] = v[0]; a.v[1] = v[1]; b.v[0] = v[2]; b.v[1] = v[3];
+    q[0] = a;
+    q[1] = b;
+  }
+};
+template <typename S> struct Quad {
+  template <typename R> __device__ static void load(const S *p, size_t i, R (&v)[4]) {
+    Chunk<S, 4> a = reinterpret_cast<const Chunk<S, 4> *>(p)[i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = to_real<R>(a.v[k]);
+  }
+  template <typename R> __device__ static void store(S *p, size_t i, const R (&v)[4]) {
+    Chunk<S, 4> a;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.v[k] = Store<S>::from(v[k]);
+    reinterpret_cast<Chunk<S, 4> *>(p)[i] = a;
+  }
+};
+
+template <typename S> __device__ __forceinline__ void ld4(const S *p, size_t i, double (&v)[4]) {
+  if constexpr (sizeof(S) == 8) {
+    Quad<double>::load((const double *)p, i, v);
+  } else {
+    float f[4];
+    Quad<S>::load(p, i, f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = f[k];
+  }
+}
+template <typename S> __device__ __forceinline__ void st4(S *p, size_t i, const double (&v)[4]) {
+  if constexpr (sizeof(S) == 8) {
+    Quad<double>::store((double *)p, i, v);
+  } else {
+    float f[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) f[k] = (float)v[k];
+    Quad<S>::store(p, i, f);
+  }
+}
+
+__device__ __forceinline__ double atomic_load_relaxed(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int NR>
+__device__ void grid_reduce(double (&v)[NR], RedScratch r) {
+  __shared__ double lds[kBT / 64][NR];
+  __shared__ int last;
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) lds[wave][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NR; ++k) {
+      double t = 0;
+      for (int w = 0; w < kBT / 64; ++w) t += lds[w][k];
+      __hip_atomic_store(r.partials + (size_t)blockIdx.x * NR + k, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __threadfence();
+    const unsigned ticket = atomicAdd(r.counter, 1u);
+    last = (ticket == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0;
+  for (int w = threadIdx.x; w < (int)gridDim.x; w += kBT)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] += atomic_load_relaxed(r.partials + (size_t)w * NR + k);
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) lds[wave][k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NR; ++k) {
+      double t = 0;
+      for (int w = 0; w < kBT / 64; ++w) t += lds[w][k];
+      r.result[k] = t;
+    }
+    atomicExch(r.counter, 0u);
+  }
+}
+
+static int grid_for(size_t nquad, int max_wg) {
+  size_t g = (nquad + kBT - 1) / kBT;
+  if (g > (size_t)max_wg) g = max_wg;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+// ---------------------------------------------------------------------------
+
+template <typename SX, typename SY, bool RED>
+__global__ void __launch_bounds__(kBT) axpby_kernel(const SX *x, SY *y, size_t nq, double ar, double ai, double br,
+                                                   double bi, RedScratch r) {
+  double acc[1] = {0};
+  for (size_t i = (size_t)blockIdx.x * kBT + threadIdx.x; i < nq; i += (size_t)gridDim.x * kBT) {
+    double xv[4], yv[4], o[4];
+    ld4(x, i, xv);
+    ld4(y, i, yv);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      o[2 * c] = ar * xv[2 * c] - ai * xv[2 * c + 1] + br * yv[2 * c] - bi * yv[2 * c + 1];
+      o[2 * c + 1] = ar * xv[2 * c + 1] + ai * xv[2 * c] + br * yv[2 * c + 1] + bi * yv[2 * c];
+    }
+    st4(y, i, o);
+    if (RED) {
+      ld4(y, i, o);
+      acc[0] += o[0] * o[0] + o[1] * o[1] + o[2] * o[2] + o[3] * o[3];
+    }
+  }
+  if (RED) grid_reduce<1>(acc, r);
+}
+
+template <typename SX, typename SY>
+__global__ void __launch_bounds__(kBT) convert_kernel(const SX *x, SY *y, size_t nq, double s) {
+  for (size_t i = (size_t)blockIdx.x * kBT + threadIdx.x; i < nq; i += (size_t)gridDim.x * kBT) {
+    double v[4];
+    ld4(x, i, v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] *= s;
+    st4(y, i, v);
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kBT) norm2_kernel(const S *x, size_t nq, RedScratch r) {
+  double acc[1] = {0};
+  for (size_t i = (size_t)blockIdx.x * kBT + threadIdx.x; i < nq; i += (size_t)gridDim.x * kBT) {
+    double v[4];
+    ld4(x, i, v);
+    acc[0] += v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3];
+  }
+  grid_reduce<1>(acc, r);
+}
+
+struct VecPack {
+  const void *p[kMaxVec];
+  double c[2 * kMaxVec];
+  int k;
+};
+
+// <z_i, w> for i < k (k <= 8 per launch)
+template <typename S>
+__global__ void __launch_bounds__(kBT) multi_cdot_kernel(VecPack z, const S *w, size_t nq, RedScratch r) {
+  double acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0;
+  for (size_t i = (size_t)blockIdx.x * kBT + threadIdx.x; i < nq; i += (size_t)gridDim.x * kBT) {
+    double wv[4];
+    ld4(w, i, wv);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j < z.k) {
+        double zv[4];
+        ld4((const S *)z.p[j], i, zv);
+        acc[2 * j] += zv[0] * wv[0] + zv[1] * wv[1] + zv[2] * wv[2] + zv[3] * wv[3];
+        acc[2 * j + 1] += zv[0] * wv[1] - zv[1] * wv[0] + zv[2] * wv[3] - zv[3] * wv[2];
+      }
+    }
+  }
+  grid_reduce<16>(acc, r);
+}
+
+// w -= sum_i beta_i z_i ; reduce ||w||^2, <w, rr>
+template <typename S>
+__global__ void __launch_bounds__(kBT) multi_caxpy_dots_kernel(VecPack z, S *w, const S *rr, size_t nq, RedScratch r) {
+  double acc[3] = {0, 0, 0};
+  for (size_t i = (size_t)blockIdx.x * kBT + threadIdx.x; i < nq; i += (size_t)gridDim.x * kBT) {
+    double wv[4];
+    ld4(w, i, wv);
+    for (int j = 0; j < z.k; ++j) {
+      double zv[4];
+      ld4((const S *)z.p[j], i, zv);
+      const double br = z.c[2 * j], bi = z.c[2 * j + 1];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        wv[2 * c] -= br * zv[2 * c] - bi * zv[2 * c + 1];
+        wv[2 * c + 1] -= br * zv[2 * c + 1] + bi * zv[2 * c];
+      }
+    }
+    st4(w, i, wv);
+    ld4(w, i, wv);
+    double rv[4];
+    ld4(rr, i, rv);
+    acc[0] += wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2] + wv[3] * wv[3];
+    acc[1] += wv[0] * rv[0] + wv[1] * rv[1] + wv[2] * rv[2] + wv[3] * rv[3];
+    acc[2] += wv[0] * rv[1] - wv[1] * rv[0] + wv[2] * rv[3] - wv[3] * rv[2];
+  }
+  grid_reduce<3>(acc, r);
+}
+
+// z *= inv_gamma ; r -= alpha z ; reduce ||r||^2
+template <typename S>
+__global__ void __launch_bounds__(kBT) gcr_update_kernel(S *z, S *rv, size_t nq, double ig, double ar, double ai,
+                                                        RedScratch r) {
+  double acc[1] = {0};
+  for (size_t i = (size_t)blockIdx.x * kBT + threadIdx.x; i < nq; i += (size_t)gridDim.x * kBT) {
+    double zv[4], x[4];
+    ld4(z, i, zv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) zv[k] *= ig;
+    st4(z, i, zv);
+    ld4(z, i, zv);
+    ld4(rv, i, x);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      x[2 * c] -= ar * zv[2 * c] - ai * zv[2 * c + 1];
+      x[2 * c + 1] -= ar * zv[2 * c + 1] + ai * zv[2 * c];
+    }
+    st4(rv, i, x);
+    ld4(rv, i, x);
+    acc[0] += x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3];
+  }
+  grid_reduce<1>(acc, r);
+}
+
+// x += sum_i chi_i p_i
+template <typename SX, typename SP>
+__global__ void __launch_bounds__(kBT) multi_axpy_acc_kernel(SX *x, VecPack p, size_t nq) {
+  for (size_t i = (size_t)blockIdx.x * kBT + threadIdx.x; i < nq; i += (size_t)gridDim.x * kBT) {
+    double xv[4];
+    ld4(x, i, xv);
+    for (int j = 0; j < p.k; ++j) {
+      double pv[4];
+      ld4((const SP *)p.p[j], i, pv);
+      const double cr = p.c[2 * j], ci = p.c[2 * j + 1];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        xv[2 * c] += cr * pv[2 * c] - ci * pv[2 * c + 1];
+        xv[2 * c + 1] += cr * pv[2 * c + 1] + ci * pv[2 * c];
+      }
+    }
+    st4(x, i, xv);
+  }
+}
+
+// x += a p ; r -= a q ; reduce ||r||^2
+template <typename SX, typename SR>
+__global__ void __launch_bounds__(kBT) cg_update_kernel(SX *x, const SX *p, SR *rv, const SR *q, size_t nq, double a,
+                                                       RedScratch r) {
+  double acc[1] = {0};
+  for (size_t i = (size_t)blockIdx.x * kBT + threadIdx.x; i < nq; i += (size_t)gridDim.x * kBT) {
+    double xv[4], pv[4], rr[4], qv[4];
+    ld4(x, i, xv);
+    ld4(p, i, pv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xv[k] += a * pv[k];
+    st4(x, i, xv);
+    ld4(rv, i, rr);
+    ld4(q, i, qv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rr[k] -= a * qv[k];
+    st4(rv, i, rr);
+    ld4(rv, i, rr);
+    acc[0] += rr[0] * rr[0] + rr[1] * rr[1] + rr[2] * rr[2] + rr[3] * rr[3];
+  }
+  grid_reduce<1>(acc, r);
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+
+template <typename F> static hipError_t dispatch1(int p, F &&f) {
+  switch (p) {
+    case LQCD_F64: return f((double *)nullptr);
+    case LQCD_F32: return f((float *)nullptr);
+    case LQCD_F16: return f((_Float16 *)nullptr);
+    case LQCD_BF16: return f((bf16 *)nullptr);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename F> static hipError_t dispatch2(int p1, int p2, F &&f) {
+  return dispatch1(p1, [&](auto t1) { return dispatch1(p2, [&](auto t2) { return f(t1, t2); }); });
+}
+
+#define T1 std::remove_pointer_t<decltype(t1)>
+#define T2 std::remove_pointer_t<decltype(t2)>
+
+static const RedScratch kNoRed = {nullptr, nullptr, nullptr, 1024};
+
+hipError_t blas_axpby(int px, const void *x, int py, void *y, size_t n, double ar, double ai, double br, double bi,
+                      const RedScratch *red, hipStream_t st) {
+  const size_t nq = n / 2;
+  const int g = grid_for(nq, red ? red->max_wg : 1024);
+  const RedScratch r = red ? *red : kNoRed;
+  return dispatch2(px, py, [&](auto t1, auto t2) -> hipError_t {
+    if (red)
+      hipLaunchKernelGGL((axpby_kernel<T1, T2, true>), dim3(g), dim3(kBT), 0, st, (const T1 *)x, (T2 *)y, nq, ar, ai, br,
+                         bi, r);
+    else
+      hipLaunchKernelGGL((axpby_kernel<T1, T2, false>), dim3(g), dim3(kBT), 0, st, (const T1 *)x, (T2 *)y, nq, ar, ai,
+                         br, bi, r);
+    return hipGetLastError();});
+}
+
+hipError_t blas_convert(int px, const void *x, int py, void *y, size_t n, double s, hipStream_t st) {
+  const size_t nq = n / 2;
+  const int g = grid_for(nq, 4096);
+  return dispatch2(px, py, [&](auto t1, auto t2) -> hipError_t {
+    hipLaunchKernelGGL((convert_kernel<T1, T2>), dim3(g), dim3(kBT), 0, st, (const T1 *)x, (T2 *)y, nq, s);
+    return hipGetLastError();});
+}
+
+hipError_t blas_norm2(int px, const void *x, size_t n, const RedScratch &red, hipStream_t st) {
+  const size_t nq = n / 2;
+  const int g = grid_for(nq, red.max_wg);
+  return dispatch1(px, [&](auto t1) -> hipError_t {
+    hipLaunchKernelGGL((norm2_kernel<T1>), dim3(g), dim3(kBT), 0, st, (const T1 *)x, nq, red);
+    return hipGetLastError();});
+}
+
+hipError_t blas_cdot(int p, const void *x, const void *y, size_t n, const RedScratch &red, hipStream_t st) {
+  const void *z[1] = {x};
+  return blas_multi_cdot(p, z, 1, y, n, red, st);
+}
+
+hipError_t blas_multi_cdot(int p, const void *const *z, int k, const void *w, size_t n, const RedScratch &red,
+                           hipStream_t st) {
+  if (k < 1 || k > 8) return hipErrorInvalidValue;
+  VecPack pk;
+  pk.k = k;
+  for (int j = 0; j < k; ++j) pk.p[j] = z[j];
+  const size_t nq = n / 2;
+  const int g = grid_for(nq, red.max_wg);
+  return dispatch1(p, [&](auto t1) -> hipError_t {
+    hipLaunchKernelGGL((multi_cdot_kernel<T1>), dim3(g), dim3(kBT), 0, st, pk, (const T1 *)w, nq, red);
+    return hipGetLastError();});
+}
+
+hipError_t blas_multi_caxpy_dots(int p, const void *const *z, const double *beta, int k, void *w, const void *r,
+                                 size_t n, const RedScratch &red, hipStream_t st) {
+  if (k < 0 || k > kMaxVec) return hipErrorInvalidValue;
+  VecPack pk;
+  pk.k = k;
+  for (int j = 0; j < k; ++j) {
+    pk.p[j] = z[j];
+    pk.c[2 * j] = beta[2 * j];
+    pk.c[2 * j + 1] = beta[2 * j + 1];
+  }
+  const size_t nq = n / 2;
+  const int g = grid_for(nq, red.max_wg);
+  return dispatch1(p, [&](auto t1) -> hipError_t {
+    hipLaunchKernelGGL((multi_caxpy_dots_kernel<T1>), dim3(g), dim3(kBT), 0, st, pk, (T1 *)w, (const T1 *)r, nq, red);
+    return hipGetLastError();});
+}
+
+hipError_t blas_gcr_update(int p, void *z, void *r, size_t n, double inv_gamma, double ar, double ai,
+                           const RedScratch &red, hipStream_t st) {
+  const size_t nq = n / 2;
+  const int g = grid_for(nq, red.max_wg);
+  return dispatch1(p, [&](auto t1) -> hipError_t {
+    hipLaunchKernelGGL((gcr_update_kernel<T1>), dim3(g), dim3(kBT), 0, st, (T1 *)z, (T1 *)r, nq, inv_gamma, ar, ai,
+                       red);
+    return hipGetLastError();});
+}
+
+hipError_t blas_multi_axpy_acc(int px, void *x, int pp, const void *const *p, const double *chi, int k, size_t n,
+                               hipStream_t st) {
+  if (k < 1 || k > kMaxVec) return hipErrorInvalidValue;
+  VecPack pk;
+  pk.k = k;
+  for (int j = 0; j < k; ++j) {
+    pk.p[j] = p[j];
+    pk.c[2 * j] = chi[2 * j];
+    pk.c[2 * j + 1] = chi[2 * j + 1];
+  }
+  const size_t nq = n / 2;
+  const int g = grid_for(nq, 4096);
+  return dispatch2(px, pp, [&](auto t1, auto t2) -> hipError_t {
+    hipLaunchKernelGGL((multi_axpy_acc_kernel<T1, T2>), dim3(g), dim3(kBT), 0, st, (T1 *)x, pk, nq);
+    return hipGetLastError();});
+}
+
+hipError_t blas_cg_update(int px, void *x, const void *p, int pr, void *r, const void *q, size_t n, double a,
+                          const RedScratch &red, hipStream_t st) {
+  const size_t nq = n / 2;
+  const int g = grid_for(nq, red.max_wg);
+  return dispatch2(px, pr, [&](auto t1, auto t2) -> hipError_t {
+    hipLaunchKernelGGL((cg_update_kernel<T1, T2>), dim3(g), dim3(kBT), 0, st, (T1 *)x, (const T1 *)p, (T2 *)r,
+                       (const T2 *)q, nq, a, red);
+    return hipGetLastError();});
+}
+
+}  // namespace lqcd

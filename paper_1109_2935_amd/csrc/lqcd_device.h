@@ -1,0 +1,360 @@
+// Device-side building blocks shared by the gfx950 kernels: storage
+// precisions, chunked structure-of-arrays loads and stores, complex
+// arithmetic, magic-number division and the tiled even-odd site geometry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lqcd.h"
+
+namespace lqcd {
+
+// ---------------------------------------------------------------------------
+// storage types
+
+struct bf16 {
+  uint16_t bits;
+};
+
+template <int P> struct Prec;
+template <> struct Prec<LQCD_F64> { using S = double; using R = double; };
+template <> struct Prec<LQCD_F32> { using S = float; using R = float; };
+template <> struct Prec<LQCD_F16> { using S = _Float16; using R = float; };
+template <> struct Prec<LQCD_BF16> { using S = bf16; using R = float; };
+
+template <typename R> __device__ __forceinline__ R to_real(double v) { return (R)v; }
+template <typename R> __device__ __forceinline__ R to_real(float v) { return (R)v; }
+template <typename R> __device__ __forceinline__ R to_real(_Float16 v) { return (R)(float)v; }
+template <typename R> __device__ __forceinline__ R to_real(bf16 v) {
+  return (R)__uint_as_float(((uint32_t)v.bits) << 16);
+}
+
+template <typename S> struct Store;
+template <> struct Store<double> {
+  template <typename R> __device__ __forceinline__ static double from(R v) { return (double)v; }
+};
+template <> struct Store<float> {
+  template <typename R> __device__ __forceinline__ static float from(R v) { return (float)v; }
+};
+template <> struct Store<_Float16> {
+  template <typename R> __device__ __forceinline__ static _Float16 from(R v) { return (_Float16)(float)v; }
+};
+template <> struct Store<bf16> {
+  template <typename R> __device__ __forceinline__ static bf16 from(R v) {
+    // round to nearest even; NaN stays NaN
+    uint32_t u = __float_as_uint((float)v);
+    bf16 r;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+      r.bits = 0x7fc0;
+    } else {
+      u += 0x7fffu + ((u >> 16) & 1u);
+      r.bits = (uint16_t)(u >> 16);
+    }
+    return r;
+  }
+};
+
+// Reals per 16-byte chunk that also divide N: the unit of a coalesced load.
+template <typename S, int N> constexpr int chunk_reals() {
+  int c = 16 / (int)sizeof(S);
+  while (c > 1 && (N % c) != 0) c /= 2;
+  return c;
+}
+
+template <typename S, int CH> struct alignas(sizeof(S) * CH) Chunk {
+  S v[CH];
+};
+
+// A packed per-parity field of N reals per site is stored chunk-major: chunk
+// c (CH reals) of site s starts at real (c * stride + s) * CH, stride = sites
+// in the parity block, so consecutive threads (sites) touch consecutive
+// chunks. Each chunk is moved with accesses of at most 16 bytes.
+template <typename S, int N, int CH, typename R>
+__device__ __forceinline__ void load_chunks(const S *__restrict__ base, int64_t stride, int64_t s, R *out) {
+  constexpr int W = (CH * (int)sizeof(S) > 16) ? 16 / (int)sizeof(S) : CH;
+#pragma unroll
+  for (int c = 0; c < N / CH; ++c) {
+    const S *p = base + (c * stride + s) * CH;
+#pragma unroll
+    for (int w = 0; w < CH / W; ++w) {
+      Chunk<S, W> v = *reinterpret_cast<const Chunk<S, W> *>(p + w * W);
+#pragma unroll
+      for (int k = 0; k < W; ++k) out[c * CH + w * W + k] = to_real<R>(v.v[k]);
+    }
+  }
+}
+
+template <typename S, int N, int CH, typename R>
+__device__ __forceinline__ void store_chunks(S *__restrict__ base, int64_t stride, int64_t s, const R *in) {
+  constexpr int W = (CH * (int)sizeof(S) > 16) ? 16 / (int)sizeof(S) : CH;
+#pragma unroll
+  for (int c = 0; c < N / CH; ++c) {
+    S *p = base + (c * stride + s) * CH;
+#pragma unroll
+    for (int w = 0; w < CH / W; ++w) {
+      Chunk<S, W> v;
+#pragma unroll
+      for (int k = 0; k < W; ++k) v.v[k] = Store<S>::from(in[c * CH + w * W + k]);
+      *reinterpret_cast<Chunk<S, W> *>(p + w * W) = v;
+    }
+  }
+}
+
+// Links and clover: the chunk is the widest 16-byte-or-smaller unit that
+// divides N, so the layout of these fields depends on the precision.
+template <typename S, int N, typename R>
+__device__ __forceinline__ void load_site(const S *__restrict__ base, int64_t stride, int64_t s, R *out) {
+  load_chunks<S, N, chunk_reals<S, N>(), R>(base, stride, s, out);
+}
+template <typename S, int N, typename R>
+__device__ __forceinline__ void store_site(S *__restrict__ base, int64_t stride, int64_t s, const R *in) {
+  store_chunks<S, N, chunk_reals<S, N>(), R>(base, stride, s, in);
+}
+
+// Spinors: the chunk is 4 reals (Wilson, 24 reals per site) or 2 reals
+// (staggered, 6) in every precision, so the k-th real of a packed spinor is
+// the same spin-colour component at the same site whatever the precision and
+// the level-1 kernels can convert and combine fields of different precision
+// element by element.
+template <int N> constexpr int spinor_chunk() { return N % 4 == 0 ? 4 : 2; }
+template <typename S, int N, typename R>
+__device__ __forceinline__ void load_spinor_reals(const S *__restrict__ base, int64_t stride, int64_t s, R *out) {
+  load_chunks<S, N, spinor_chunk<N>(), R>(base, stride, s, out);
+}
+template <typename S, int N, typename R>
+__device__ __forceinline__ void store_spinor_reals(S *__restrict__ base, int64_t stride, int64_t s, const R *in) {
+  store_chunks<S, N, spinor_chunk<N>(), R>(base, stride, s, in);
+}
+
+// ---------------------------------------------------------------------------
+// complex arithmetic
+
+template <typename R> struct cpx {
+  R re, im;
+};
+template <typename R> __device__ __forceinline__ cpx<R> mk(R a, R b) { return cpx<R>{a, b}; }
+template <typename R> __device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> __device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> __device__ __forceinline__ cpx<R> operator*(cpx<R> a, cpx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ cpx<R> operator*(R s, cpx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R> __device__ __forceinline__ cpx<R> conj(cpx<R> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <typename R> __device__ __forceinline__ cpx<R> cmul_conj(cpx<R> a, cpx<R> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// i * a
+template <typename R> __device__ __forceinline__ cpx<R> times_i(cpx<R> a) { return {-a.im, a.re}; }
+// acc += a * b
+template <typename R> __device__ __forceinline__ void cmac(cpx<R> &acc, cpx<R> a, cpx<R> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+// acc += conj(a) * b
+template <typename R> __device__ __forceinline__ void cmac_conj(cpx<R> &acc, cpx<R> a, cpx<R> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+}
+
+// ---------------------------------------------------------------------------
+// SU(3) link storage: 18 reals (row-major complex), 12 (first two rows; the
+// third is conj(row0 x row1)) or 8 (U01, U02, U10, arg U00, arg U20; the rest
+// follows from unitarity and det = 1).
+
+template <typename R> struct Link {
+  cpx<R> m[3][3];
+};
+
+template <typename R> __device__ __forceinline__ void third_row(Link<R> &u) {
+  u.m[2][0] = conj(u.m[0][1] * u.m[1][2] - u.m[0][2] * u.m[1][1]);
+  u.m[2][1] = conj(u.m[0][2] * u.m[1][0] - u.m[0][0] * u.m[1][2]);
+  u.m[2][2] = conj(u.m[0][0] * u.m[1][1] - u.m[0][1] * u.m[1][0]);
+}
+
+__device__ __forceinline__ void sincos_r(double a, double *s, double *c) { sincos(a, s, c); }
+__device__ __forceinline__ void sincos_r(float a, float *s, float *c) { sincosf(a, s, c); }
+
+template <int RECON, typename R> __device__ __forceinline__ Link<R> unpack_link(const R *v) {
+  Link<R> u;
+  if constexpr (RECON == 18) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) u.m[i][j] = mk<R>(v[6 * i + 2 * j], v[6 * i + 2 * j + 1]);
+  } else if constexpr (RECON == 12) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) u.m[i][j] = mk<R>(v[6 * i + 2 * j], v[6 * i + 2 * j + 1]);
+    third_row(u);
+  } else {
+    const cpx<R> a2 = mk<R>(v[0], v[1]), a3 = mk<R>(v[2], v[3]), b1 = mk<R>(v[4], v[5]);
+    const R N = a2.re * a2.re + a2.im * a2.im + a3.re * a3.re + a3.im * a3.im;
+    const R b1n = b1.re * b1.re + b1.im * b1.im;
+    const R ra1 = sqrt(fmax(R(1) - N, R(0)));
+    const R rc1 = sqrt(fmax(N - b1n, R(0)));
+    R s0, c0, s2, c2;
+    sincos_r(v[6], &s0, &c0);
+    sincos_r(v[7], &s2, &c2);
+    const cpx<R> a1 = mk<R>(ra1 * c0, ra1 * s0), c1 = mk<R>(rc1 * c2, rc1 * s2);
+    const R inv = R(1) / N;
+    const cpx<R> ca1 = conj(a1), ca2 = conj(a2), ca3 = conj(a3), cb1 = conj(b1), cc1 = conj(c1);
+    u.m[0][0] = a1; u.m[0][1] = a2; u.m[0][2] = a3;
+    u.m[1][0] = b1;
+    u.m[2][0] = c1;
+    u.m[1][1] = (-inv) * (ca3 * cc1 + ca1 * a2 * b1);
+    u.m[1][2] = inv * (ca2 * cc1 - ca1 * a3 * b1);
+    u.m[2][1] = inv * (cb1 * ca3 - ca1 * a2 * c1);
+    u.m[2][2] = (-inv) * (ca2 * cb1 + ca1 * a3 * c1);
+  }
+  return u;
+}
+
+// out = U v  and  out = U^+ v
+template <typename R> __device__ __forceinline__ void su3_mv(const Link<R> &u, const cpx<R> *v, cpx<R> *out) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    cpx<R> a = u.m[i][0] * v[0];
+    cmac(a, u.m[i][1], v[1]);
+    cmac(a, u.m[i][2], v[2]);
+    out[i] = a;
+  }
+}
+template <typename R> __device__ __forceinline__ void su3_adj_mv(const Link<R> &u, const cpx<R> *v, cpx<R> *out) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    cpx<R> a = cmul_conj(u.m[0][i], v[0]);
+    cmac_conj(a, u.m[1][i], v[1]);
+    cmac_conj(a, u.m[2][i], v[2]);
+    out[i] = a;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// magic-number division for 0 <= n < 2^31
+
+struct FastDiv {
+  uint32_t d;
+  uint64_t m;
+  uint32_t shift;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  f.shift = 31 + s;
+  f.m = ((1ull << f.shift) + d - 1) / d;
+  return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f) {
+  return (uint32_t)(((uint64_t)n * f.m) >> f.shift);
+}
+
+// ---------------------------------------------------------------------------
+// tiled even-odd geometry
+//
+// Sites of parity p are numbered s = tile * Vt2 + k, where tiles are taken in
+// lexicographic order of their coordinates and k is the checkerboard index
+// inside the tile: k = (lx >> 1) + (Bx/2) * (ly + By * (lz + Bz * lt)). With
+// every tile extent even, a tile's origin is an even site, so the parity of a
+// local coordinate equals the global parity.
+
+struct Geom {
+  int L[4];     // lattice extents
+  int B[4];     // tile extents
+  int NT[4];    // tiles per axis
+  int Vh;       // sites per parity
+  int Vt2;      // sites per parity in one tile
+  int bc_t;     // +1 / -1
+  int cut[4];   // Dirichlet block extents (== L[mu]: no cut along mu)
+  int has_cut;  // any cut active
+  FastDiv dVt2, dBxh, dBy, dBz, dNTx, dNTy, dNTz;
+  FastDiv dcut[4];
+};
+
+struct Site {
+  int t[4];  // tile coordinate
+  int l[4];  // coordinate inside the tile
+  int p;     // parity
+};
+
+__device__ __forceinline__ Site decode_site(const Geom &g, int s, int parity) {
+  Site r;
+  r.p = parity;
+  uint32_t tile = fdiv((uint32_t)s, g.dVt2);
+  uint32_t k = (uint32_t)s - tile * (uint32_t)g.Vt2;
+  uint32_t q = fdiv(k, g.dBxh);
+  const int lxh = (int)(k - q * (uint32_t)(g.B[0] >> 1));
+  uint32_t q2 = fdiv(q, g.dBy);
+  r.l[1] = (int)(q - q2 * (uint32_t)g.B[1]);
+  uint32_t q3 = fdiv(q2, g.dBz);
+  r.l[2] = (int)(q2 - q3 * (uint32_t)g.B[2]);
+  r.l[3] = (int)q3;
+  r.l[0] = 2 * lxh + ((r.l[1] + r.l[2] + r.l[3] + parity) & 1);
+  uint32_t u = fdiv(tile, g.dNTx);
+  r.t[0] = (int)(tile - u * (uint32_t)g.NT[0]);
+  uint32_t u2 = fdiv(u, g.dNTy);
+  r.t[1] = (int)(u - u2 * (uint32_t)g.NT[1]);
+  uint32_t u3 = fdiv(u2, g.dNTz);
+  r.t[2] = (int)(u2 - u3 * (uint32_t)g.NT[2]);
+  r.t[3] = (int)u3;
+  return r;
+}
+
+__device__ __forceinline__ int encode_site(const Geom &g, const int t[4], const int l[4]) {
+  const int tile = t[0] + g.NT[0] * (t[1] + g.NT[1] * (t[2] + g.NT[2] * t[3]));
+  const int k = (l[0] >> 1) + (g.B[0] >> 1) * (l[1] + g.B[1] * (l[2] + g.B[2] * l[3]));
+  return tile * g.Vt2 + k;
+}
+
+__device__ __forceinline__ int global_coord(const Geom &g, const Site &x, int mu) { return x.t[mu] * g.B[mu] + x.l[mu]; }
+
+// Neighbour `step` hops along MU (|step| <= 3). Returns its site index;
+// *wraps = number of times the hop crossed the lattice boundary along MU.
+template <int MU>
+__device__ __forceinline__ int hop(const Geom &g, const Site &x, int step, int *wraps) {
+  int t[4] = {x.t[0], x.t[1], x.t[2], x.t[3]};
+  int l[4] = {x.l[0], x.l[1], x.l[2], x.l[3]};
+  int w = 0;
+  l[MU] += step;
+  while (l[MU] >= g.B[MU]) {
+    l[MU] -= g.B[MU];
+    if (++t[MU] == g.NT[MU]) { t[MU] = 0; ++w; }
+  }
+  while (l[MU] < 0) {
+    l[MU] += g.B[MU];
+    if (--t[MU] < 0) { t[MU] = g.NT[MU] - 1; ++w; }
+  }
+  *wraps = w;
+  return encode_site(g, t, l);
+}
+
+// Dirichlet cut: is the hop of `step` (+1 or -1) along MU inside one block?
+template <int MU>
+__device__ __forceinline__ bool hop_kept(const Geom &g, const Site &x, int step) {
+  if (!g.has_cut || g.cut[MU] >= g.L[MU]) return true;
+  const int c = global_coord(g, x, MU);
+  const uint32_t q = fdiv((uint32_t)c, g.dcut[MU]);
+  const int r = c - (int)q * g.cut[MU];
+  return step > 0 ? (r != g.cut[MU] - 1) : (r != 0);
+}
+
+// Map the hardware workgroup id to a logical one so that each XCD (the
+// dispatcher deals workgroups round-robin over 8 XCDs) owns a contiguous range
+// of sites and their neighbours stay in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int wg, int nwg) {
+  constexpr int NXCD = 8;
+  if (nwg % NXCD) return wg;
+  return (wg % NXCD) * (nwg / NXCD) + wg / NXCD;
+}
+
+}  // namespace lqcd

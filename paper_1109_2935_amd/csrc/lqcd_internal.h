@@ -1,0 +1,151 @@
+// Host-side internals shared by the library's translation units: the context,
+// validated operator descriptions and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "lqcd.h"
+#include "lqcd_device.h"
+
+struct lqcd_context {
+  int device = 0;
+  std::string last_error;
+  // reduction scratch: per-workgroup partials, a ticket counter and the result
+  double *red_partials = nullptr;
+  size_t red_partials_count = 0;
+  unsigned *red_counter = nullptr;
+  double *red_result = nullptr;
+  double *red_host = nullptr;  // pinned
+  // general scratch vectors, grown on demand and reused between calls
+  std::vector<void *> scratch;
+  std::vector<size_t> scratch_bytes;
+};
+
+namespace lqcd {
+
+constexpr int kMaxRed = 40;  // max values one reduction kernel returns
+
+// Spin-colour reals per site of the action's spinor.
+inline int spinor_reals(int action) { return action == LQCD_WILSON_CLOVER ? 24 : 6; }
+inline size_t prec_bytes(int prec) { return prec == LQCD_F64 ? 8 : (prec == LQCD_F32 ? 4 : 2); }
+
+struct OpInfo {
+  const lqcd_operator *op;
+  Geom g;             // no cut
+  int prec;
+  int recon;
+  int nsp;            // reals per site of the spinor
+  size_t vh;          // sites per parity
+  size_t spinor_bytes;  // one parity
+};
+
+// Validation helpers (return a status and set ctx->last_error).
+lqcd_status set_error(lqcd_context *ctx, lqcd_status st, const std::string &msg);
+lqcd_status check_op(lqcd_context *ctx, const lqcd_operator *op, OpInfo *info);
+lqcd_status apply_cut(lqcd_context *ctx, const OpInfo &info, const int32_t *block, Geom *g);
+lqcd_status hip_check(lqcd_context *ctx, hipError_t e, const char *what);
+Geom make_geom(const int32_t dims[4], const int32_t tile[4], int bc_t);
+
+// Scratch memory owned by the context (slot-indexed, grown on demand).
+lqcd_status scratch(lqcd_context *ctx, int slot, size_t bytes, void **ptr);
+
+// ---------------------------------------------------------------------------
+// Wilson-clover kernels (wilson.hip)
+
+enum WilsonMode {
+  W_HOP = 0,        // out = coef * D in
+  W_HOP_CLOV = 1,   // out = C (coef * D in)
+  W_XPAY_CLOV = 2,  // out = C xin + coef * D in
+  W_XPAY = 3        // out = xin + coef * D in
+};
+
+struct WilsonLaunch {
+  Geom g;
+  int prec, recon;
+  void *out;
+  const void *in;
+  const void *gauge;
+  const void *clov;  // clover block of the output parity (or nullptr)
+  const void *xin;   // second input (modes 2, 3)
+  int parity;        // output parity
+  double coef;
+  int dagger;
+  int mode;
+  double *partials;  // if non-null: per-workgroup <out,xin> (re, im) and <out,out>
+  int block_threads;
+};
+hipError_t launch_wilson(const WilsonLaunch &w, hipStream_t st, int *nwg_out);
+int wilson_nwg(const Geom &g, int block_threads);
+
+hipError_t launch_clover_apply(const Geom &g, int prec, void *out, const void *in, const void *clov,
+                               hipStream_t st);
+
+// setup kernels
+hipError_t launch_spinor_import(const Geom &g, int prec, int nsp, void *packed, const double *natural,
+                                int parity, hipStream_t st);
+hipError_t launch_spinor_export(const Geom &g, int prec, int nsp, double *natural, const void *packed,
+                                int parity, hipStream_t st);
+hipError_t launch_gauge_import(const Geom &g, int prec, int recon, void *packed, const double *natural,
+                               int form_long, hipStream_t st);
+hipError_t launch_clover_build(const Geom &g, int prec, double kappa, double csw, void *clov, void *clov_inv,
+                               const double *natural_gauge, int *d_fail, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// staggered kernels (staggered.hip)
+
+struct StagLaunch {
+  Geom g;
+  int prec, recon;
+  void *out;
+  const void *in;
+  const void *fat;
+  const void *lng;
+  const void *xin;  // xpay input or nullptr
+  int parity;
+  double coef;      // multiplies D in
+  double xcoef;     // multiplies xin
+  double c_long;
+  int block_threads;
+};
+hipError_t launch_staggered(const StagLaunch &s, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// BLAS and reductions (blas.hip). Vectors are flat arrays of n complex numbers
+// stored as 2n reals in precision `prec`.
+
+struct RedScratch {
+  double *partials;
+  unsigned *counter;
+  double *result;
+  int max_wg;
+};
+
+// y = a*x + b*y  (a, b complex; x, y may differ in precision). If red: ||y||^2.
+hipError_t blas_axpby(int px, const void *x, int py, void *y, size_t n, double ar, double ai, double br, double bi,
+                      const RedScratch *red, hipStream_t st);
+// y = s * x (conversion between precisions)
+hipError_t blas_convert(int px, const void *x, int py, void *y, size_t n, double s, hipStream_t st);
+// result[0] = ||x||^2
+hipError_t blas_norm2(int px, const void *x, size_t n, const RedScratch &red, hipStream_t st);
+// result[0..1] = <x, y>
+hipError_t blas_cdot(int p, const void *x, const void *y, size_t n, const RedScratch &red, hipStream_t st);
+// result[2i..2i+1] = <z_i, w>, i < k (all of precision p)
+hipError_t blas_multi_cdot(int p, const void *const *z, int k, const void *w, size_t n, const RedScratch &red,
+                           hipStream_t st);
+// w -= sum_i beta_i z_i; result: ||w||^2, <w, r> (re, im)
+hipError_t blas_multi_caxpy_dots(int p, const void *const *z, const double *beta, int k, void *w, const void *r,
+                                 size_t n, const RedScratch &red, hipStream_t st);
+// z *= 1/gamma; r -= alpha z (after scaling); result: ||r||^2
+hipError_t blas_gcr_update(int p, void *z, void *r, size_t n, double inv_gamma, double ar, double ai,
+                           const RedScratch &red, hipStream_t st);
+// x (precision px) += sum_i chi_i p_i (precision pp)
+hipError_t blas_multi_axpy_acc(int px, void *x, int pp, const void *const *p, const double *chi, int k, size_t n,
+                               hipStream_t st);
+// CG: x += a p; r -= a q; result ||r||^2 (x, p in px; r, q in pr)
+hipError_t blas_cg_update(int px, void *x, const void *p, int pr, void *r, const void *q, size_t n, double a,
+                          const RedScratch &red, hipStream_t st);
+
+}  // namespace lqcd

@@ -1,0 +1,37 @@
+// Host-side operator compositions shared by the entry points (api.cpp) and
+// the solvers (solvers.cpp).
+#pragma once
+
+#include "lqcd_internal.h"
+
+namespace lqcd {
+
+// Context scratch slots.
+enum ScratchSlot {
+  kSlotFlag = 0,
+  kSlotSchurTmp = 1,
+  kSlotSchwarz = 2,   // 4 slots: r, q, t, partials
+  kSlotSolver = 8,    // solver work vectors start here
+};
+
+RedScratch red_scratch(lqcd_context *ctx);
+lqcd_status read_result(lqcd_context *ctx, hipStream_t st, int n, double *out);
+const void *clover_block(const OpInfo &info, const void *clov, int parity);
+
+lqcd_status wilson_hop(lqcd_context *ctx, const OpInfo &info, const Geom &g, int mode, void *out, const void *in,
+                       const void *xin, const void *clov, int parity, double coef, int dagger, double *partials,
+                       hipStream_t st);
+lqcd_status stag_hop(lqcd_context *ctx, const OpInfo &info, void *out, const void *in, const void *xin, int parity,
+                     double coef, double xcoef, hipStream_t st);
+lqcd_status schur_apply(lqcd_context *ctx, const OpInfo &info, const Geom &g, void *out, const void *in, void *tmp,
+                        int dagger, double *partials, hipStream_t st);
+lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schwarz_params *prm, void *out,
+                          const void *in, int slot0, hipStream_t st);
+lqcd_status check_schwarz(lqcd_context *ctx, const OpInfo &info, const lqcd_schwarz_params *prm);
+// operator fields present and aligned (clover for Wilson, long links for staggered)
+lqcd_status check_fields_internal(lqcd_context *ctx, const lqcd_operator *op);
+
+hipError_t launch_mr_update(const Geom &g, int prec, void *x, void *r, const void *q, const double *partials, int nps,
+                            bool first, hipStream_t st);
+
+}  // namespace lqcd

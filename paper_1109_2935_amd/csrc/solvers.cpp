@@ -1,0 +1,461 @@
+// Solvers: mixed-precision GCR-DD (Algorithm 1, Section VIII-A) and CG with
+// reliable updates (Section III-A), as host loops over the device kernels.
+// Reductions come back to the host once per step; all scalars of the
+// recurrences are kept in FP64 on the host.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "lqcd_internal.h"
+#include "lqcd_ops.h"
+
+using namespace lqcd;
+using cd = std::complex<double>;
+
+#define TRY(expr)                    \
+  do {                               \
+    lqcd_status _s = (expr);         \
+    if (_s != LQCD_OK) return _s;    \
+  } while (0)
+
+namespace {
+
+bool same_system(const lqcd_operator *a, const lqcd_operator *b) {
+  if (a->action != b->action || a->bc_t != b->bc_t) return false;
+  for (int m = 0; m < 4; ++m)
+    if (a->dims[m] != b->dims[m] || a->tile[m] != b->tile[m]) return false;
+  if (a->action == LQCD_WILSON_CLOVER) return a->kappa == b->kappa && a->csw == b->csw;
+  return a->mass == b->mass && a->c_long == b->c_long;
+}
+
+struct Solver {
+  lqcd_context *ctx;
+  hipStream_t st;
+  int slot;  // next free scratch slot
+  lqcd_status vec(size_t bytes, void **p) { return scratch(ctx, slot++, bytes, p); }
+  lqcd_status result(int n, double *out) { return read_result(ctx, st, n, out); }
+  RedScratch red() { return red_scratch(ctx); }
+  lqcd_status hip(hipError_t e, const char *what) { return hip_check(ctx, e, what); }
+};
+
+// number of complex entries of one parity spinor
+size_t ncomplex(const OpInfo &i) { return i.vh * i.nsp / 2; }
+
+// y = b - y, returns ||y||^2 (same precision p)
+lqcd_status residual_from(Solver &S, int p, const void *b, void *y, size_t n, double *rr) {
+  RedScratch r = S.red();
+  TRY(S.hip(blas_axpby(p, b, p, y, n, 1.0, 0.0, -1.0, 0.0, &r, S.st), "axpby"));
+  return S.result(1, rr);
+}
+
+// Wilson even-odd source bhat = b_e + kappa D_eo A_oo^-1 b_o.
+lqcd_status wilson_schur_source(Solver &S, const OpInfo &hi, void *bhat, const void *b_full, void *tmp) {
+  const char *be = (const char *)b_full, *bo = be + hi.spinor_bytes;
+  TRY(S.hip(launch_clover_apply(hi.g, hi.prec, tmp, bo, clover_block(hi, hi.op->clover_inv, 1), S.st), "clover"));
+  return wilson_hop(S.ctx, hi, hi.g, W_XPAY, bhat, tmp, be, nullptr, 0, hi.op->kappa, 0, nullptr, S.st);
+}
+
+// x_o = A_oo^-1 (b_o + kappa D_oe x_e), then the true full residual ||b - M x|| / ||b||.
+lqcd_status wilson_finish(Solver &S, const OpInfo &hi, void *x_full, const void *b_full, void *tmp, void *y,
+                          double bnorm, double *true_res) {
+  char *xe = (char *)x_full, *xo = xe + hi.spinor_bytes;
+  const char *be = (const char *)b_full, *bo = be + hi.spinor_bytes;
+  const lqcd_operator *op = hi.op;
+  TRY(wilson_hop(S.ctx, hi, hi.g, W_XPAY, tmp, xe, bo, nullptr, 1, op->kappa, 0, nullptr, S.st));
+  TRY(S.hip(launch_clover_apply(hi.g, hi.prec, xo, tmp, clover_block(hi, op->clover_inv, 1), S.st), "clover"));
+  double tot = 0, rr;
+  // even: A_ee x_e - kappa D_eo x_o - b_e
+  TRY(wilson_hop(S.ctx, hi, hi.g, W_XPAY_CLOV, y, xo, xe, clover_block(hi, op->clover, 0), 0, -op->kappa, 0, nullptr,
+                 S.st));
+  TRY(residual_from(S, hi.prec, be, y, ncomplex(hi), &rr));
+  tot += rr;
+  TRY(wilson_hop(S.ctx, hi, hi.g, W_XPAY_CLOV, y, xe, xo, clover_block(hi, op->clover, 1), 1, -op->kappa, 0, nullptr,
+                 S.st));
+  TRY(residual_from(S, hi.prec, bo, y, ncomplex(hi), &rr));
+  tot += rr;
+  *true_res = bnorm > 0 ? std::sqrt(tot) / bnorm : 0.0;
+  return LQCD_OK;
+}
+
+// Per-iteration log on stderr when the environment variable LQCD_VERBOSE is set.
+bool verbose() {
+  static const bool v = std::getenv("LQCD_VERBOSE") != nullptr;
+  return v;
+}
+
+double elapsed(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Scale that brings a vector of norm `nrm` with `nreal` reals to unit RMS per
+// real (used before 16-bit storage; K and the Krylov recurrences are
+// positively homogeneous, so the scaling is exact).
+double unit_rms_scale(double nrm, size_t nreal) { return nrm > 0 ? std::sqrt((double)nreal) / nrm : 1.0; }
+
+}  // namespace
+
+extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op_hi, const lqcd_operator *op_krylov,
+                                      const lqcd_operator *op_precond, const lqcd_gcr_params *prm, void *x_full,
+                                      const void *b_full, lqcd_solve_info *info, lqcd_stream stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  OpInfo hi, kr, pc;
+  TRY(check_op(ctx, op_hi, &hi));
+  TRY(check_op(ctx, op_krylov, &kr));
+  if (op_hi->action != LQCD_WILSON_CLOVER) return set_error(ctx, LQCD_ERR_INVALID_ARG, "GCR solves Wilson-clover systems");
+  if (op_hi->prec != LQCD_F64) return set_error(ctx, LQCD_ERR_UNSUPPORTED, "op_hi must be FP64");
+  if (!same_system(op_hi, op_krylov)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "op_krylov describes another system");
+  TRY(check_fields_internal(ctx, op_hi));
+  TRY(check_fields_internal(ctx, op_krylov));
+  if (!prm) return set_error(ctx, LQCD_ERR_INVALID_ARG, "params are NULL");
+  if (!(prm->tol > 0) || prm->k_max < 1 || prm->k_max > 32 || !(prm->delta > 0) || prm->max_iter < 1)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "need tol > 0, 1 <= k_max <= 32, delta > 0, max_iter >= 1");
+  const int pk = prm->precond;
+  if (pk == LQCD_PRECOND_SCHWARZ) {
+    TRY(check_op(ctx, op_precond, &pc));
+    if (!same_system(op_hi, op_precond))
+      return set_error(ctx, LQCD_ERR_INVALID_ARG, "op_precond describes another system");
+    TRY(check_schwarz(ctx, pc, &prm->schwarz));
+  } else if (pk == LQCD_PRECOND_LEARNED) {
+    return set_error(ctx, LQCD_ERR_UNSUPPORTED, "learned preconditioner is not available in this build");
+  } else if (pk != LQCD_PRECOND_NONE) {
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "unknown preconditioner kind");
+  }
+  if (!x_full || !b_full || ((uintptr_t)x_full & 15) || ((uintptr_t)b_full & 15))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
+
+  Solver S{ctx, (hipStream_t)stream, kSlotSolver};
+  const size_t n = ncomplex(hi);
+  const int kmax = prm->k_max;
+  void *bhat, *r, *y, *tmp, *rhat, *ktmp, *pin = nullptr, *pout = nullptr;
+  TRY(S.vec(hi.spinor_bytes, &bhat));
+  TRY(S.vec(hi.spinor_bytes, &r));
+  TRY(S.vec(hi.spinor_bytes, &y));
+  TRY(S.vec(hi.spinor_bytes, &tmp));
+  TRY(S.vec(kr.spinor_bytes, &rhat));
+  TRY(S.vec(kr.spinor_bytes, &ktmp));
+  std::vector<void *> P(kmax), Z(kmax);
+  for (int i = 0; i < kmax; ++i) TRY(S.vec(kr.spinor_bytes, &P[i]));
+  for (int i = 0; i < kmax; ++i) TRY(S.vec(kr.spinor_bytes, &Z[i]));
+  if (pk == LQCD_PRECOND_SCHWARZ) {
+    TRY(S.vec(pc.spinor_bytes, &pin));
+    TRY(S.vec(pc.spinor_bytes, &pout));
+  }
+  RedScratch red = S.red();
+  void *xe = x_full;
+
+  double bn2;
+  TRY(S.hip(blas_norm2(hi.prec, b_full, 2 * n, red, S.st), "norm"));
+  TRY(S.result(1, &bn2));
+  if (!std::isfinite(bn2)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "source contains non-finite values");
+  lqcd_solve_info inf{};
+  if (bn2 == 0) {
+    TRY(S.hip(hipMemsetAsync(x_full, 0, 2 * hi.spinor_bytes, S.st), "memset"));
+    TRY(S.hip(hipStreamSynchronize(S.st), "sync"));
+    inf.seconds = elapsed(t0);
+    if (info) *info = inf;
+    return LQCD_OK;
+  }
+  const double bn = std::sqrt(bn2);
+  TRY(wilson_schur_source(S, hi, bhat, b_full, tmp));
+  // r = bhat - Mhat x_e
+  TRY(schur_apply(ctx, hi, hi.g, y, xe, tmp, 0, nullptr, S.st));
+  double rr;
+  TRY(S.hip(hipMemcpyAsync(r, bhat, hi.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
+  TRY(S.hip(blas_axpby(hi.prec, y, hi.prec, r, n, -1.0, 0.0, 1.0, 0.0, &red, S.st), "axpby"));
+  TRY(S.result(1, &rr));
+  double r0n = std::sqrt(rr);
+  TRY(S.hip(blas_convert(hi.prec, r, kr.prec, rhat, n, 1.0, S.st), "convert"));
+  double rhn = r0n;
+
+  std::vector<cd> alpha(kmax), beta((size_t)kmax * kmax), chi(kmax);
+  std::vector<double> gamma(kmax);
+  int k = 0, iters = 0, restarts = 0;
+  bool converged = r0n <= prm->tol * bn;
+  lqcd_status status = LQCD_OK;
+  while (!converged) {
+    // p_k = K rhat_k
+    if (pk == LQCD_PRECOND_SCHWARZ) {
+      const double sc = unit_rms_scale(rhn, 2 * n);
+      TRY(S.hip(blas_convert(kr.prec, rhat, pc.prec, pin, n, sc, S.st), "convert"));
+      TRY(schwarz_apply(ctx, pc, &prm->schwarz, pout, pin, kSlotSchwarz, S.st));
+      TRY(S.hip(blas_convert(pc.prec, pout, kr.prec, P[k], n, 1.0 / sc, S.st), "convert"));
+      inf.precond_applies++;
+    } else {
+      TRY(S.hip(hipMemcpyAsync(P[k], rhat, kr.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
+    }
+    // z_k = Mhat p_k
+    TRY(schur_apply(ctx, kr, kr.g, Z[k], P[k], ktmp, 0, nullptr, S.st));
+    inf.matvecs++;
+    // orthogonalise against z_0..z_{k-1} (classical Gram-Schmidt: all
+    // beta_{i,k} from one pass, then one multi-axpy)
+    for (int i0 = 0; i0 < k; i0 += 8) {
+      const int m = std::min(8, k - i0);
+      double d[16];
+      TRY(S.hip(blas_multi_cdot(kr.prec, (const void *const *)&Z[i0], m, Z[k], n, red, S.st), "multi dot"));
+      TRY(S.result(2 * m, d));
+      for (int j = 0; j < m; ++j) beta[(size_t)(i0 + j) * kmax + k] = cd(d[2 * j], d[2 * j + 1]);
+    }
+    std::vector<double> bc(2 * std::max(k, 1));
+    for (int i = 0; i < k; ++i) {
+      bc[2 * i] = beta[(size_t)i * kmax + k].real();
+      bc[2 * i + 1] = beta[(size_t)i * kmax + k].imag();
+    }
+    double zd[3];
+    TRY(S.hip(blas_multi_caxpy_dots(kr.prec, (const void *const *)Z.data(), bc.data(), k, Z[k], rhat, n, red, S.st),
+              "multi caxpy"));
+    TRY(S.result(3, zd));
+    const double g = std::sqrt(zd[0]);
+    if (!(g > 0) || !std::isfinite(g)) {
+      status = set_error(ctx, LQCD_ERR_BREAKDOWN, "GCR breakdown: orthogonalised direction has zero norm");
+      break;
+    }
+    gamma[k] = g;
+    alpha[k] = cd(zd[1], zd[2]) / g;
+    TRY(S.hip(blas_gcr_update(kr.prec, Z[k], rhat, n, 1.0 / g, alpha[k].real(), alpha[k].imag(), red, S.st),
+              "gcr update"));
+    TRY(S.result(1, &rr));
+    rhn = std::sqrt(rr);
+    if (verbose())
+      fprintf(stderr, "gcr it %d k %d |rhat|/|b| %.3e gamma %.3e |alpha| %.3e\n", iters, k, rhn / bn, g,
+              std::abs(alpha[k]));
+    ++k;
+    ++iters;
+    if (k == kmax || rhn / r0n < prm->delta || rhn < prm->tol * bn || iters >= prm->max_iter) {
+      // back substitution: gamma_l chi_l + sum_{i>l} beta_{l,i} chi_i = alpha_l
+      for (int l = k - 1; l >= 0; --l) {
+        cd sacc = alpha[l];
+        for (int i = l + 1; i < k; ++i) sacc -= beta[(size_t)l * kmax + i] * chi[i];
+        chi[l] = sacc / gamma[l];
+      }
+      std::vector<double> cc(2 * k);
+      for (int i = 0; i < k; ++i) {
+        cc[2 * i] = chi[i].real();
+        cc[2 * i + 1] = chi[i].imag();
+      }
+      TRY(S.hip(blas_multi_axpy_acc(hi.prec, xe, kr.prec, (const void *const *)P.data(), cc.data(), k, n, S.st),
+                "solution update"));
+      // high-precision restart: r = bhat - Mhat x
+      TRY(schur_apply(ctx, hi, hi.g, y, xe, tmp, 0, nullptr, S.st));
+      TRY(S.hip(hipMemcpyAsync(r, bhat, hi.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
+      TRY(S.hip(blas_axpby(hi.prec, y, hi.prec, r, n, -1.0, 0.0, 1.0, 0.0, &red, S.st), "axpby"));
+      TRY(S.result(1, &rr));
+      r0n = std::sqrt(rr);
+      rhn = r0n;
+      ++restarts;
+      if (verbose()) fprintf(stderr, "gcr restart %d true |r|/|b| %.3e\n", restarts, r0n / bn);
+      k = 0;
+      if (r0n <= prm->tol * bn) {
+        converged = true;
+        break;
+      }
+      if (iters >= prm->max_iter) break;
+      TRY(S.hip(blas_convert(hi.prec, r, kr.prec, rhat, n, 1.0, S.st), "convert"));
+    }
+  }
+  double tres = 0;
+  TRY(wilson_finish(S, hi, x_full, b_full, tmp, y, bn, &tres));
+  inf.iters = iters;
+  inf.restarts = restarts;
+  inf.true_residual = tres;
+  inf.seconds = elapsed(t0);
+  if (info) *info = inf;
+  if (status != LQCD_OK) return status;
+  if (!converged) return set_error(ctx, LQCD_ERR_NOT_CONVERGED, "GCR reached max_iter");
+  return LQCD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// CG with reliable updates
+
+namespace {
+
+struct CgOps {
+  Solver *S;
+  const OpInfo *hi, *lo;
+  int kind;
+  void *tmp_hi, *tmp_lo;
+  // A applied in the given precision. For CGNE: A = Mhat (dag = 0) or Mhat^+ (dag = 1).
+  lqcd_status apply(const OpInfo &o, void *out, const void *in, int dag, void *tmp) {
+    return schur_apply(S->ctx, o, o.g, out, in, tmp, dag, nullptr, S->st);
+  }
+};
+
+}  // namespace
+
+extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_hi, const lqcd_operator *op_sloppy,
+                                     const lqcd_cg_params *prm, void *x, const void *b, lqcd_solve_info *info,
+                                     lqcd_stream stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  if (!prm) return set_error(ctx, LQCD_ERR_INVALID_ARG, "params are NULL");
+  OpInfo hi, lo;
+  TRY(check_op(ctx, op_hi, &hi));
+  if (op_sloppy) {
+    TRY(check_op(ctx, op_sloppy, &lo));
+    if (!same_system(op_hi, op_sloppy)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "op_sloppy describes another system");
+    TRY(check_fields_internal(ctx, op_sloppy));
+  } else {
+    lo = hi;
+  }
+  TRY(check_fields_internal(ctx, op_hi));
+  const int kind = prm->kind;
+  if (kind == LQCD_CG_CGNE_SCHUR && op_hi->action != LQCD_WILSON_CLOVER)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "CGNE_SCHUR needs a Wilson-clover operator");
+  if (kind == LQCD_CG_STAG_NORMAL && op_hi->action != LQCD_STAGGERED)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "STAG_NORMAL needs a staggered operator");
+  if (kind != LQCD_CG_CGNE_SCHUR && kind != LQCD_CG_STAG_NORMAL)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "unknown CG kind");
+  if (!(prm->tol > 0) || prm->max_iter < 1 || prm->delta_reliable < 0 || prm->delta_reliable >= 1)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "need tol > 0, max_iter >= 1, 0 <= delta_reliable < 1");
+  if (!x || !b || ((uintptr_t)x & 15) || ((uintptr_t)b & 15))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
+  if (hi.prec != LQCD_F64) return set_error(ctx, LQCD_ERR_UNSUPPORTED, "op_hi must be FP64");
+
+  Solver S{ctx, (hipStream_t)stream, kSlotSolver};
+  const bool cgne = kind == LQCD_CG_CGNE_SCHUR;
+  const size_t n = ncomplex(hi);
+  const bool mixed = lo.prec != hi.prec;
+  const bool half = lo.prec == LQCD_F16 || lo.prec == LQCD_BF16;
+  const double delta = prm->delta_reliable;
+  void *bhat, *r, *y, *tmp_hi, *rs, *xs, *p, *q, *t, *tmp_lo;
+  TRY(S.vec(hi.spinor_bytes, &bhat));
+  TRY(S.vec(hi.spinor_bytes, &r));
+  TRY(S.vec(hi.spinor_bytes, &y));
+  TRY(S.vec(hi.spinor_bytes, &tmp_hi));
+  TRY(S.vec(lo.spinor_bytes, &rs));
+  TRY(S.vec(lo.spinor_bytes, &xs));
+  TRY(S.vec(lo.spinor_bytes, &p));
+  TRY(S.vec(lo.spinor_bytes, &q));
+  TRY(S.vec(lo.spinor_bytes, &t));
+  TRY(S.vec(lo.spinor_bytes, &tmp_lo));
+  RedScratch red = S.red();
+  CgOps A{&S, &hi, &lo, kind, tmp_hi, tmp_lo};
+  lqcd_solve_info inf{};
+
+  // source norm (full lattice for CGNE, even sites for the staggered system)
+  double bn2;
+  TRY(S.hip(blas_norm2(hi.prec, b, cgne ? 2 * n : n, red, S.st), "norm"));
+  TRY(S.result(1, &bn2));
+  if (!std::isfinite(bn2)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "source contains non-finite values");
+  if (bn2 == 0) {
+    TRY(S.hip(hipMemsetAsync(x, 0, (cgne ? 2 : 1) * hi.spinor_bytes, S.st), "memset"));
+    TRY(S.hip(hipStreamSynchronize(S.st), "sync"));
+    inf.seconds = elapsed(t0);
+    if (info) *info = inf;
+    return LQCD_OK;
+  }
+  const double bn = std::sqrt(bn2);
+  if (cgne)
+    TRY(wilson_schur_source(S, hi, bhat, b, tmp_hi));
+  else
+    TRY(S.hip(hipMemcpyAsync(bhat, b, hi.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
+  void *xe = x;
+
+  // true residual r = bhat - A x (A = Mhat or N_e), returns ||r||^2
+  auto true_residual = [&](double *rr) -> lqcd_status {
+    TRY(A.apply(hi, y, xe, 0, tmp_hi));
+    TRY(S.hip(hipMemcpyAsync(r, bhat, hi.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
+    TRY(S.hip(blas_axpby(hi.prec, y, hi.prec, r, n, -1.0, 0.0, 1.0, 0.0, &red, S.st), "axpby"));
+    return S.result(1, rr);
+  };
+
+  double rr_true;
+  TRY(true_residual(&rr_true));
+  double sc = half ? unit_rms_scale(std::sqrt(rr_true), 2 * n) : 1.0;
+  TRY(S.hip(blas_convert(hi.prec, r, lo.prec, rs, n, sc, S.st), "convert"));
+  TRY(S.hip(hipMemsetAsync(xs, 0, lo.spinor_bytes, S.st), "memset"));
+  double rr = rr_true * sc * sc;  // in scaled units
+  double pp = 0;
+  if (cgne) {
+    TRY(A.apply(lo, p, rs, 1, tmp_lo));
+    TRY(S.hip(blas_norm2(lo.prec, p, n, red, S.st), "norm"));
+    TRY(S.result(1, &pp));
+    inf.matvecs++;
+  } else {
+    TRY(S.hip(hipMemcpyAsync(p, rs, lo.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
+  }
+  double maxrr = rr_true;
+  const double stop = prm->tol * prm->tol * bn2;
+  bool converged = rr_true <= stop;
+  lqcd_status status = LQCD_OK;
+  int it = 0;
+  while (!converged && it < prm->max_iter) {
+    double a;
+    TRY(A.apply(lo, q, p, 0, tmp_lo));
+    inf.matvecs++;
+    if (cgne) {
+      if (!(pp > 0)) { status = set_error(ctx, LQCD_ERR_BREAKDOWN, "CGNE breakdown: |p| = 0"); break; }
+      a = rr / pp;
+    } else {
+      double d[2];
+      TRY(S.hip(blas_cdot(lo.prec, p, q, n, red, S.st), "dot"));
+      TRY(S.result(2, d));
+      if (!(d[0] > 0)) { status = set_error(ctx, LQCD_ERR_BREAKDOWN, "CG breakdown: <p, A p> <= 0"); break; }
+      a = rr / d[0];
+    }
+    double rr_new;
+    TRY(S.hip(blas_cg_update(lo.prec, xs, p, lo.prec, rs, q, n, a, red, S.st), "cg update"));
+    TRY(S.result(1, &rr_new));
+    ++it;
+    double rr_new_true = rr_new / (sc * sc);
+    if (verbose()) fprintf(stderr, "cg it %d |r|/|b| %.3e alpha %.3e\n", it, std::sqrt(rr_new_true) / bn, a);
+    // reliable update when the iterated residual dropped by delta since the
+    // last one (mixed precision), and always before declaring convergence
+    const bool trigger = rr_new_true <= stop || (mixed && rr_new_true < delta * delta * maxrr);
+    if (trigger) {
+      // x += xs / sc ; r = bhat - A x ; restart the sloppy residual from it
+      TRY(S.hip(blas_axpby(lo.prec, xs, hi.prec, xe, n, 1.0 / sc, 0.0, 1.0, 0.0, nullptr, S.st), "x update"));
+      TRY(true_residual(&rr_new_true));
+      inf.restarts++;
+      if (verbose()) fprintf(stderr, "cg reliable update %d true |r|/|b| %.3e\n", inf.restarts, std::sqrt(rr_new_true) / bn);
+      const double sc_new = half ? unit_rms_scale(std::sqrt(rr_new_true), 2 * n) : 1.0;
+      TRY(S.hip(blas_convert(hi.prec, r, lo.prec, rs, n, sc_new, S.st), "convert"));
+      TRY(S.hip(hipMemsetAsync(xs, 0, lo.spinor_bytes, S.st), "memset"));
+      if (sc_new != sc) TRY(S.hip(blas_convert(lo.prec, p, lo.prec, p, n, sc_new / sc, S.st), "rescale"));
+      rr *= (sc_new / sc) * (sc_new / sc);
+      sc = sc_new;
+      rr_new = rr_new_true * sc * sc;
+      maxrr = rr_new_true;
+      if (rr_new_true <= stop) {
+        converged = true;
+        break;
+      }
+    }
+    const double bta = rr_new / rr;
+    if (cgne) {
+      TRY(A.apply(lo, t, rs, 1, tmp_lo));
+      inf.matvecs++;
+      TRY(S.hip(blas_axpby(lo.prec, t, lo.prec, p, n, 1.0, 0.0, bta, 0.0, &red, S.st), "xpay"));
+      TRY(S.result(1, &pp));
+    } else {
+      TRY(S.hip(blas_axpby(lo.prec, rs, lo.prec, p, n, 1.0, 0.0, bta, 0.0, nullptr, S.st), "xpay"));
+    }
+    rr = rr_new;
+    maxrr = std::max(maxrr, rr_new / (sc * sc));
+  }
+  if (!converged) {
+    // fold in the last sloppy correction
+    TRY(S.hip(blas_axpby(lo.prec, xs, hi.prec, xe, n, 1.0 / sc, 0.0, 1.0, 0.0, nullptr, S.st), "x update"));
+  }
+  double tres;
+  if (cgne) {
+    TRY(wilson_finish(S, hi, x, b, tmp_hi, y, bn, &tres));
+  } else {
+    double rrt;
+    TRY(true_residual(&rrt));
+    tres = std::sqrt(rrt) / bn;
+  }
+  inf.iters = it;
+  inf.true_residual = tres;
+  inf.seconds = elapsed(t0);
+  if (info) *info = inf;
+  if (status != LQCD_OK) return status;
+  if (!converged) return set_error(ctx, LQCD_ERR_NOT_CONVERGED, "CG reached max_iter");
+  return LQCD_OK;
+}

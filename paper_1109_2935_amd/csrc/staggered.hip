@@ -1,0 +1,165 @@
+// Improved-staggered hopping term for gfx950 (eq. (3) of the paper):
+//   (D chi)(x) = sum_mu eta_mu(x) [ F_mu(x) chi(x+mu) - F_mu(x-mu)^+ chi(x-mu)
+//                                  + c_long ( L_mu(x) chi(x+3mu) - L_mu(x-3mu)^+ chi(x-3mu) ) ]
+// with Kogut-Susskind phases eta_x = 1, eta_y = (-1)^x, eta_z = (-1)^(x+y),
+// eta_t = (-1)^(x+y+z), fat links F (general complex, 18 reals) and long links
+// L (SU(3), 18/12/8 reals). One thread per output site; the kernel can fuse
+// out = coef * D in + xcoef * xin.
+#include "lqcd_internal.h"
+
+namespace lqcd {
+
+template <typename S> struct SArgs {
+  Geom g;
+  S *out;
+  const S *in;
+  const S *fat;
+  const S *lng;
+  const S *xin;
+  int parity;
+  double coef, xcoef, c_long;
+};
+
+template <typename S, typename R>
+__device__ __forceinline__ void load_cvec(const S *__restrict__ f, int64_t vh, int s, cpx<R> (&v)[3]) {
+  R r[6];
+  load_spinor_reals<S, 6, R>(f, vh, s, r);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] = mk<R>(r[2 * c], r[2 * c + 1]);
+}
+
+template <int MU, typename S, typename R, int RECON>
+__device__ __forceinline__ void stag_dir(const SArgs<S> &a, const Site &x, int s, R eta, R cl, cpx<R> (&acc)[3]) {
+  const int64_t vh = a.g.Vh;
+  const int neg = a.g.bc_t < 0;
+  // one hop: fat; three hops: long
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = h == 0 ? 1 : 3;
+    const R wgt = h == 0 ? eta : eta * cl;
+    {
+      int w;
+      const int n = hop<MU>(a.g, x, +k, &w);
+      cpx<R> v[3], u[3];
+      load_cvec<S, R>(a.in, vh, n, v);
+      Link<R> U;
+      if (h == 0) {
+        R r[18];
+        load_site<S, 18, R>(a.fat + (int64_t)(2 * MU + x.p) * vh * 18, vh, s, r);
+        U = unpack_link<18, R>(r);
+      } else {
+        R r[RECON];
+        load_site<S, RECON, R>(a.lng + (int64_t)(2 * MU + x.p) * vh * RECON, vh, s, r);
+        U = unpack_link<RECON, R>(r);
+      }
+      su3_mv(U, v, u);
+      const R f = (MU == 3 && (w & 1) && neg) ? -wgt : wgt;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] = acc[c] + f * u[c];
+    }
+    {
+      int w;
+      const int n = hop<MU>(a.g, x, -k, &w);
+      cpx<R> v[3], u[3];
+      load_cvec<S, R>(a.in, vh, n, v);
+      Link<R> U;
+      if (h == 0) {
+        R r[18];
+        load_site<S, 18, R>(a.fat + (int64_t)(2 * MU + 1 - x.p) * vh * 18, vh, n, r);
+        U = unpack_link<18, R>(r);
+      } else {
+        R r[RECON];
+        load_site<S, RECON, R>(a.lng + (int64_t)(2 * MU + 1 - x.p) * vh * RECON, vh, n, r);
+        U = unpack_link<RECON, R>(r);
+      }
+      su3_adj_mv(U, v, u);
+      const R f = (MU == 3 && (w & 1) && neg) ? wgt : -wgt;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] = acc[c] + f * u[c];
+    }
+  }
+}
+
+template <typename S, typename R, int RECON, bool XPAY>
+__global__ void __launch_bounds__(256) stag_kernel(SArgs<S> a) {
+  const int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (s >= a.g.Vh) return;
+  const Site x = decode_site(a.g, s, a.parity);
+  const int X0 = x.t[0] * a.g.B[0] + x.l[0], X1 = x.t[1] * a.g.B[1] + x.l[1], X2 = x.t[2] * a.g.B[2] + x.l[2];
+  const R e1 = (X0 & 1) ? R(-1) : R(1);
+  const R e2 = ((X0 + X1) & 1) ? R(-1) : R(1);
+  const R e3 = ((X0 + X1 + X2) & 1) ? R(-1) : R(1);
+  const R cl = (R)a.c_long;
+  cpx<R> acc[3] = {mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0)};
+  stag_dir<0, S, R, RECON>(a, x, s, R(1), cl, acc);
+  stag_dir<1, S, R, RECON>(a, x, s, e1, cl, acc);
+  stag_dir<2, S, R, RECON>(a, x, s, e2, cl, acc);
+  stag_dir<3, S, R, RECON>(a, x, s, e3, cl, acc);
+  const R coef = (R)a.coef;
+  R out[6];
+  if constexpr (XPAY) {
+    cpx<R> xv[3];
+    load_cvec<S, R>(a.xin, a.g.Vh, s, xv);
+    const R xc = (R)a.xcoef;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      out[2 * c] = fma(coef, acc[c].re, xc * xv[c].re);
+      out[2 * c + 1] = fma(coef, acc[c].im, xc * xv[c].im);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      out[2 * c] = coef * acc[c].re;
+      out[2 * c + 1] = coef * acc[c].im;
+    }
+  }
+  store_spinor_reals<S, 6, R>(a.out, a.g.Vh, s, out);
+}
+
+template <int P, int RECON>
+static hipError_t launch_s2(const StagLaunch &l, hipStream_t st) {
+  using S = typename Prec<P>::S;
+  using R = typename Prec<P>::R;
+  SArgs<S> a;
+  a.g = l.g;
+  a.out = (S *)l.out;
+  a.in = (const S *)l.in;
+  a.fat = (const S *)l.fat;
+  a.lng = (const S *)l.lng;
+  a.xin = (const S *)l.xin;
+  a.parity = l.parity;
+  a.coef = l.coef;
+  a.xcoef = l.xcoef;
+  a.c_long = l.c_long;
+  const int bt = l.block_threads, nwg = (l.g.Vh + bt - 1) / bt;
+  if (l.xin)
+    hipLaunchKernelGGL((stag_kernel<S, R, RECON, true>), dim3(nwg), dim3(bt), 0, st, a);
+  else
+    hipLaunchKernelGGL((stag_kernel<S, R, RECON, false>), dim3(nwg), dim3(bt), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_s1(const StagLaunch &l, hipStream_t st) {
+  switch (l.recon) {
+    case 18: return launch_s2<P, 18>(l, st);
+    case 12: return launch_s2<P, 12>(l, st);
+    case 8:
+      if constexpr (P == LQCD_F64 || P == LQCD_F32) return launch_s2<P, 8>(l, st);
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_staggered(const StagLaunch &l, hipStream_t st) {
+  if (l.g.Vh == 0) return hipSuccess;
+  switch (l.prec) {
+    case LQCD_F64: return launch_s1<LQCD_F64>(l, st);
+    case LQCD_F32: return launch_s1<LQCD_F32>(l, st);
+    case LQCD_F16: return launch_s1<LQCD_F16>(l, st);
+    case LQCD_BF16: return launch_s1<LQCD_BF16>(l, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lqcd

@@ -1,0 +1,424 @@
+// Wilson-clover operator kernels for gfx950 (eq. (2) of the paper, kappa
+// normalisation M = A - kappa D).
+//
+// One thread per output site of one parity. For each of the 8 hops the
+// neighbour spinor is spin-projected to a half spinor (2 colour vectors) with
+// (1 -/+ gamma_mu) before the SU(3) multiply, and the product is expanded back
+// to 4 spins; the boundary phase and the Dirichlet cut are applied in-kernel.
+// Epilogues fuse the clover term (A or A^-1), an xpay and, for the Schwarz
+// block solver, per-workgroup partial inner products.
+#include "lqcd_internal.h"
+
+namespace lqcd {
+
+// ---------------------------------------------------------------------------
+// spin projection in the chiral basis.
+// For P = 1 + g gamma_mu (g = +-1) the result has rows 2,3 proportional to
+// rows 0,1, so only h0 = row 0 and h1 = row 1 are formed:
+//   x: h0 = s0 - g i s3, h1 = s1 - g i s2;  rows 2,3 = ( g i h1,  g i h0)
+//   y: h0 = s0 - g s3,   h1 = s1 + g s2;    rows 2,3 = ( g h1,   -g h0)
+//   z: h0 = s0 - g i s2, h1 = s1 + g i s3;  rows 2,3 = ( g i h0, -g i h1)
+//   t: h0 = s0 + g s2,   h1 = s1 + g s3;    rows 2,3 = ( g h0,    g h1)
+
+template <int MU, typename R>
+__device__ __forceinline__ void project(const cpx<R> (&s)[4][3], R g, cpx<R> (&h)[2][3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if constexpr (MU == 0) {
+      h[0][c] = s[0][c] - g * times_i(s[3][c]);
+      h[1][c] = s[1][c] - g * times_i(s[2][c]);
+    } else if constexpr (MU == 1) {
+      h[0][c] = s[0][c] - g * s[3][c];
+      h[1][c] = s[1][c] + g * s[2][c];
+    } else if constexpr (MU == 2) {
+      h[0][c] = s[0][c] - g * times_i(s[2][c]);
+      h[1][c] = s[1][c] + g * times_i(s[3][c]);
+    } else {
+      h[0][c] = s[0][c] + g * s[2][c];
+      h[1][c] = s[1][c] + g * s[3][c];
+    }
+  }
+}
+
+template <int MU, typename R>
+__device__ __forceinline__ void expand_acc(cpx<R> (&acc)[4][3], const cpx<R> (&u)[2][3], R g) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    acc[0][c] = acc[0][c] + u[0][c];
+    acc[1][c] = acc[1][c] + u[1][c];
+    if constexpr (MU == 0) {
+      acc[2][c] = acc[2][c] + g * times_i(u[1][c]);
+      acc[3][c] = acc[3][c] + g * times_i(u[0][c]);
+    } else if constexpr (MU == 1) {
+      acc[2][c] = acc[2][c] + g * u[1][c];
+      acc[3][c] = acc[3][c] - g * u[0][c];
+    } else if constexpr (MU == 2) {
+      acc[2][c] = acc[2][c] + g * times_i(u[0][c]);
+      acc[3][c] = acc[3][c] - g * times_i(u[1][c]);
+    } else {
+      acc[2][c] = acc[2][c] + g * u[0][c];
+      acc[3][c] = acc[3][c] + g * u[1][c];
+    }
+  }
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ void load_spinor(const S *__restrict__ f, int64_t vh, int s, cpx<R> (&v)[4][3]) {
+  R r[24];
+  load_spinor_reals<S, 24, R>(f, vh, s, r);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[sp][c] = mk<R>(r[6 * sp + 2 * c], r[6 * sp + 2 * c + 1]);
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ void store_spinor(S *__restrict__ f, int64_t vh, int s, const cpx<R> (&v)[4][3]) {
+  R r[24];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r[6 * sp + 2 * c] = v[sp][c].re;
+      r[6 * sp + 2 * c + 1] = v[sp][c].im;
+    }
+  store_spinor_reals<S, 24, R>(f, vh, s, r);
+}
+
+template <typename S, typename R, int RECON>
+__device__ __forceinline__ Link<R> load_link(const S *__restrict__ gauge, int64_t vh, int mu, int parity, int s) {
+  R v[RECON];
+  load_site<S, RECON, R>(gauge + (int64_t)(2 * mu + parity) * vh * RECON, vh, s, v);
+  return unpack_link<RECON, R>(v);
+}
+
+// Clover: per site and chirality block a Hermitian 6x6 (index = spin-in-block*3
+// + colour): 6 real diagonal entries, then the strictly lower triangle in row
+// order as (re, im); block 0 = spins 0,1, block 1 = spins 2,3 (72 reals).
+template <typename S, typename R>
+__device__ __forceinline__ void clover_mul(const S *__restrict__ clov, int64_t vh, int s, const cpx<R> (&in)[4][3],
+                                           cpx<R> (&out)[4][3]) {
+  R a[72];
+  load_site<S, 72, R>(clov, vh, s, a);
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const R *A = a + 36 * b;
+    cpx<R> x[6], y[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) x[i] = in[2 * b + i / 3][i % 3];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) y[i] = A[i] * x[i];
+    int off = 6;
+#pragma unroll
+    for (int i = 1; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < i; ++j) {
+        const cpx<R> aij = mk<R>(A[off], A[off + 1]);
+        off += 2;
+        cmac(y[i], aij, x[j]);
+        cmac_conj(y[j], aij, x[i]);
+      }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) out[2 * b + i / 3][i % 3] = y[i];
+  }
+}
+
+template <typename S> struct WArgs {
+  Geom g;
+  S *out;
+  const S *in;
+  const S *gauge;
+  const S *clov;
+  const S *xin;
+  double *partials;
+  double coef;
+  int parity;
+  int dagger;
+};
+
+template <int MU, typename S, typename R, int RECON>
+__device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int s, R sgn, cpx<R> (&acc)[4][3]) {
+  const int64_t vh = a.g.Vh;
+  // forward: (1 - sgn gamma_mu) U_mu(x) psi(x+mu)
+  if (hop_kept<MU>(a.g, x, +1)) {
+    int w;
+    const int n = hop<MU>(a.g, x, +1, &w);
+    cpx<R> psi[4][3], h[2][3], u[2][3];
+    load_spinor<S, R>(a.in, vh, n, psi);
+    project<MU, R>(psi, -sgn, h);
+    const Link<R> U = load_link<S, R, RECON>(a.gauge, vh, MU, x.p, s);
+    su3_mv(U, h[0], u[0]);
+    su3_mv(U, h[1], u[1]);
+    if (MU == 3 && (w & 1) && a.g.bc_t < 0) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) u[k][c] = R(-1) * u[k][c];
+    }
+    expand_acc<MU, R>(acc, u, -sgn);
+  }
+  // backward: (1 + sgn gamma_mu) U_mu(x-mu)^+ psi(x-mu)
+  if (hop_kept<MU>(a.g, x, -1)) {
+    int w;
+    const int n = hop<MU>(a.g, x, -1, &w);
+    cpx<R> psi[4][3], h[2][3], u[2][3];
+    load_spinor<S, R>(a.in, vh, n, psi);
+    project<MU, R>(psi, sgn, h);
+    const Link<R> U = load_link<S, R, RECON>(a.gauge, vh, MU, 1 - x.p, n);
+    su3_adj_mv(U, h[0], u[0]);
+    su3_adj_mv(U, h[1], u[1]);
+    if (MU == 3 && (w & 1) && a.g.bc_t < 0) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) u[k][c] = R(-1) * u[k][c];
+    }
+    expand_acc<MU, R>(acc, u, sgn);
+  }
+}
+
+// Per-segment sums of 3 values for the Schwarz block solver. A segment is
+// min(sites per tile and parity, blockDim) consecutive sites (a power of two
+// that divides 256, or 256 when a tile spans several workgroups); segment j
+// covers sites [j*seg, (j+1)*seg) and its sums go to dst[3*j .. 3*j+2].
+__device__ __forceinline__ void segment_reduce_store(double (&v)[3], int seg, int site, int vh, double *dst) {
+  __shared__ double lds[4][3];
+  const int width = seg < 64 ? seg : 64;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    for (int off = width >> 1; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  if (seg <= 64) {
+    if ((site % seg) == 0 && site < vh)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dst[3 * (site / seg) + k] = v[k];
+    return;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lds[wave][k] = v[k];
+  __syncthreads();
+  const int wps = seg >> 6;  // waves per segment
+  if (lane == 0 && (wave % wps) == 0 && site < vh) {
+    for (int k = 0; k < 3; ++k) {
+      double t = 0;
+      for (int w = 0; w < wps; ++w) t += lds[wave + w][k];
+      dst[3 * (site / seg) + k] = t;
+    }
+  }
+}
+
+template <typename S, typename R, int RECON, int MODE, bool REDUCE>
+__global__ void __launch_bounds__(256) wilson_kernel(WArgs<S> a) {
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = wg * blockDim.x + threadIdx.x;
+  double red[3] = {0, 0, 0};
+  if (s < a.g.Vh) {
+    const Site x = decode_site(a.g, s, a.parity);
+    const R sgn = a.dagger ? R(-1) : R(1);
+    cpx<R> acc[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[i][c] = mk<R>(0, 0);
+    wilson_dir<0, S, R, RECON>(a, x, s, sgn, acc);
+    wilson_dir<1, S, R, RECON>(a, x, s, sgn, acc);
+    wilson_dir<2, S, R, RECON>(a, x, s, sgn, acc);
+    wilson_dir<3, S, R, RECON>(a, x, s, sgn, acc);
+    const R coef = (R)a.coef;
+    const int64_t vh = a.g.Vh;
+    cpx<R> res[4][3];
+    if constexpr (MODE == W_HOP) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) res[i][c] = coef * acc[i][c];
+    } else if constexpr (MODE == W_HOP_CLOV) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[i][c] = coef * acc[i][c];
+      clover_mul<S, R>(a.clov, vh, s, acc, res);
+    } else {
+      cpx<R> xv[4][3];
+      load_spinor<S, R>(a.xin, vh, s, xv);
+      if constexpr (MODE == W_XPAY_CLOV) {
+        clover_mul<S, R>(a.clov, vh, s, xv, res);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) res[i][c] = res[i][c] + coef * acc[i][c];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) res[i][c] = xv[i][c] + coef * acc[i][c];
+      }
+      if constexpr (REDUCE) {
+        // store precision first, so the inner products see the stored values
+        store_spinor<S, R>(a.out, vh, s, res);
+        load_spinor<S, R>(a.out, vh, s, res);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double qr = res[i][c].re, qi = res[i][c].im, rr = xv[i][c].re, ri = xv[i][c].im;
+            red[0] += qr * rr + qi * ri;
+            red[1] += qr * ri - qi * rr;
+            red[2] += qr * qr + qi * qi;
+          }
+      }
+    }
+    if constexpr (!REDUCE) store_spinor<S, R>(a.out, vh, s, res);
+  }
+  if constexpr (REDUCE) {
+    const int seg = a.g.Vt2 < (int)blockDim.x ? a.g.Vt2 : (int)blockDim.x;
+    segment_reduce_store(red, seg, s, a.g.Vh, a.partials);
+  }
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(256) clover_apply_kernel(Geom g, S *out, const S *in, const S *clov) {
+  const int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (s >= g.Vh) return;
+  cpx<R> x[4][3], y[4][3];
+  load_spinor<S, R>(in, g.Vh, s, x);
+  clover_mul<S, R>(clov, g.Vh, s, x, y);
+  store_spinor<S, R>(out, g.Vh, s, y);
+}
+
+// Schwarz MR step on every block at once, after q = Mhat_B r and the
+// per-segment partials of <q,r> and <q,q>: alpha_B = <q,r>_B / <q,q>_B,
+// x += alpha_B r (x = alpha_B r on the first step), r -= alpha_B q.
+template <typename S, typename R>
+__global__ void __launch_bounds__(256) mr_update_kernel(Geom g, S *x, S *r, const S *q, const double *part, int nps,
+                                                        int first) {
+  const int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (s >= g.Vh) return;
+  const int b = (int)fdiv((uint32_t)s, g.dVt2);
+  double qr = 0, qi = 0, qq = 0;
+  for (int j = 0; j < nps; ++j) {
+    const double *p = part + 3 * (b * nps + j);
+    qr += p[0];
+    qi += p[1];
+    qq += p[2];
+  }
+  const R ar = qq > 0 ? (R)(qr / qq) : R(0), ai = qq > 0 ? (R)(qi / qq) : R(0);
+  R rv[24], qv[24], xv[24];
+  load_spinor_reals<S, 24, R>(r, g.Vh, s, rv);
+  load_spinor_reals<S, 24, R>(q, g.Vh, s, qv);
+  if (first) {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) xv[k] = R(0);
+  } else {
+    load_spinor_reals<S, 24, R>(x, g.Vh, s, xv);
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const R re = rv[2 * k], im = rv[2 * k + 1];
+    xv[2 * k] += ar * re - ai * im;
+    xv[2 * k + 1] += ar * im + ai * re;
+    rv[2 * k] = re - (ar * qv[2 * k] - ai * qv[2 * k + 1]);
+    rv[2 * k + 1] = im - (ar * qv[2 * k + 1] + ai * qv[2 * k]);
+  }
+  store_spinor_reals<S, 24, R>(x, g.Vh, s, xv);
+  store_spinor_reals<S, 24, R>(r, g.Vh, s, rv);
+}
+
+hipError_t launch_mr_update(const Geom &g, int prec, void *x, void *r, const void *q, const double *partials, int nps,
+                            bool first, hipStream_t st) {
+  const int bt = 256, nwg = (g.Vh + bt - 1) / bt;
+  if (g.Vh == 0) return hipSuccess;
+  switch (prec) {
+#define CASE(P)                                                                                              \
+  case P:                                                                                                    \
+    hipLaunchKernelGGL((mr_update_kernel<Prec<P>::S, Prec<P>::R>), dim3(nwg), dim3(bt), 0, st, g,            \
+                       (Prec<P>::S *)x, (Prec<P>::S *)r, (const Prec<P>::S *)q, partials, nps, (int)first);  \
+    return hipGetLastError();
+    CASE(LQCD_F64)
+    CASE(LQCD_F32)
+    CASE(LQCD_F16)
+    CASE(LQCD_BF16)
+#undef CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+int wilson_nwg(const Geom &g, int bt) { return (g.Vh + bt - 1) / bt; }
+
+template <int P, int RECON, int MODE, bool RED>
+static hipError_t launch_w3(const WilsonLaunch &w, hipStream_t st) {
+  using S = typename Prec<P>::S;
+  using R = typename Prec<P>::R;
+  WArgs<S> a;
+  a.g = w.g;
+  a.out = (S *)w.out;
+  a.in = (const S *)w.in;
+  a.gauge = (const S *)w.gauge;
+  a.clov = (const S *)w.clov;
+  a.xin = (const S *)w.xin;
+  a.partials = w.partials;
+  a.coef = w.coef;
+  a.parity = w.parity;
+  a.dagger = w.dagger;
+  const int nwg = wilson_nwg(w.g, w.block_threads);
+  hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED>), dim3(nwg), dim3(w.block_threads), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int P, int RECON>
+static hipError_t launch_w2(const WilsonLaunch &w, hipStream_t st) {
+  switch (w.mode) {
+    case W_HOP: return launch_w3<P, RECON, W_HOP, false>(w, st);
+    case W_HOP_CLOV: return launch_w3<P, RECON, W_HOP_CLOV, false>(w, st);
+    case W_XPAY_CLOV:
+      return w.partials ? launch_w3<P, RECON, W_XPAY_CLOV, true>(w, st) : launch_w3<P, RECON, W_XPAY_CLOV, false>(w, st);
+    case W_XPAY:
+      return w.partials ? launch_w3<P, RECON, W_XPAY, true>(w, st) : launch_w3<P, RECON, W_XPAY, false>(w, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P>
+static hipError_t launch_w1(const WilsonLaunch &w, hipStream_t st) {
+  switch (w.recon) {
+    case 18: return launch_w2<P, 18>(w, st);
+    case 12: return launch_w2<P, 12>(w, st);
+    case 8:
+      if constexpr (P == LQCD_F64 || P == LQCD_F32) return launch_w2<P, 8>(w, st);
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wilson(const WilsonLaunch &w, hipStream_t st, int *nwg_out) {
+  if (nwg_out) *nwg_out = wilson_nwg(w.g, w.block_threads);
+  if (w.g.Vh == 0) return hipSuccess;
+  switch (w.prec) {
+    case LQCD_F64: return launch_w1<LQCD_F64>(w, st);
+    case LQCD_F32: return launch_w1<LQCD_F32>(w, st);
+    case LQCD_F16: return launch_w1<LQCD_F16>(w, st);
+    case LQCD_BF16: return launch_w1<LQCD_BF16>(w, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_clover_apply(const Geom &g, int prec, void *out, const void *in, const void *clov, hipStream_t st) {
+  const int bt = 256, nwg = (g.Vh + bt - 1) / bt;
+  if (g.Vh == 0) return hipSuccess;
+  switch (prec) {
+#define CASE(P)                                                                                           \
+  case P:                                                                                                 \
+    hipLaunchKernelGGL((clover_apply_kernel<Prec<P>::S, Prec<P>::R>), dim3(nwg), dim3(bt), 0, st, g,      \
+                       (Prec<P>::S *)out, (const Prec<P>::S *)in, (const Prec<P>::S *)clov);              \
+    return hipGetLastError();
+    CASE(LQCD_F64)
+    CASE(LQCD_F32)
+    CASE(LQCD_F16)
+    CASE(LQCD_BF16)
+#undef CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lqcd

@@ -1,0 +1,130 @@
+"""Operator instances on the GPU: packed links, clover and spinor buffers.
+
+Convenience layer over the C ABI for Python callers: it allocates the packed
+fields as torch uint8 device tensors, imports natural FP64 links (device or
+host arrays) and builds the derived fields (clover and its inverse, long
+links) with the library's own kernels. All arithmetic stays in liblqcd.so.
+"""
+import numpy as np
+import torch
+
+from . import lqcd as L
+
+
+def _device_complex(a, device="cuda"):
+    """Natural complex128 field as a contiguous device tensor."""
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.complex128).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(device)
+
+
+class Operator:
+    """One operator instance (action, geometry, precision, compression)."""
+
+    def __init__(self, ctx, action, dims, prec, recon=18, tile=None, bc_t=-1, kappa=0.0, csw=0.0, mass=0.0,
+                 c_long=1.0, device="cuda"):
+        self.ctx = ctx
+        self.device = device
+        self.dims = tuple(int(d) for d in dims)
+        tile = self.dims if tile is None else tuple(int(t) for t in tile)
+        op = L.lqcd_operator()
+        op.action = action
+        op.dims[:] = self.dims
+        op.tile[:] = tile
+        op.bc_t = bc_t
+        op.prec = prec
+        op.recon = recon
+        op.kappa, op.csw, op.mass, op.c_long = kappa, csw, mass, c_long
+        self.op = op
+        self._keep = {}
+
+    # -- allocation ---------------------------------------------------------
+    def bytes(self, kind, nrhs=1):
+        return L.lqcd_field_bytes(self.op, kind, nrhs)
+
+    def empty(self, kind, nrhs=1):
+        return torch.empty(self.bytes(kind, nrhs), dtype=torch.uint8, device=self.device)
+
+    def spinor(self, full=False, nrhs=1, zero=True):
+        kind = L.LQCD_FIELD_SPINOR_FULL if full else L.LQCD_FIELD_SPINOR
+        t = self.empty(kind, nrhs)
+        if zero:
+            t.zero_()
+        return t
+
+    @property
+    def spinor_bytes(self):
+        return self.bytes(L.LQCD_FIELD_SPINOR)
+
+    # -- spinor exchange ----------------------------------------------------
+    def import_spinor(self, natural, parity, out=None):
+        nat = _device_complex(natural, self.device)
+        if out is None:
+            out = self.spinor(full=(parity < 0), zero=False)
+        L.lqcd_spinor_import(self.ctx, self.op, out, nat, parity)
+        return out
+
+    def export_spinor(self, packed, parity, natural=None):
+        """Unpack to a natural complex128 device tensor (zeros on sites not covered)."""
+        lx, ly, lz, lt = self.dims
+        inner = (4, 3) if self.op.action == L.LQCD_WILSON_CLOVER else (3,)
+        if natural is None:
+            natural = torch.zeros((lt, lz, ly, lx) + inner, dtype=torch.complex128, device=self.device)
+        L.lqcd_spinor_export(self.ctx, self.op, natural, packed, parity)
+        return natural
+
+
+def wilson_clover(ctx, U, dims, kappa, csw, prec, recon=18, tile=None, bc_t=-1, device="cuda", U_device=None):
+    """Wilson-clover instance: packs U and builds A, A^-1 from it on the GPU."""
+    o = Operator(ctx, L.LQCD_WILSON_CLOVER, dims, prec, recon, tile, bc_t, kappa=kappa, csw=csw, device=device)
+    Ud = U_device if U_device is not None else _device_complex(U, device)
+    g = o.empty(L.LQCD_FIELD_GAUGE)
+    L.lqcd_gauge_import(ctx, o.op, g, Ud, L.LQCD_FIELD_GAUGE)
+    c = o.empty(L.LQCD_FIELD_CLOVER)
+    ci = o.empty(L.LQCD_FIELD_CLOVER)
+    o.op.gauge = g.data_ptr()
+    o.op.clover = c.data_ptr()
+    o.op.clover_inv = ci.data_ptr()
+    L.lqcd_clover_build(ctx, o.op, c, ci, Ud)
+    o._keep.update(gauge=g, clover=c, clover_inv=ci)
+    return o
+
+
+def staggered(ctx, fat, U, dims, mass, prec, recon=18, tile=None, bc_t=-1, c_long=1.0, device="cuda",
+              fat_device=None, U_device=None):
+    """Improved-staggered instance: packs the fat links and forms the long
+    links U_mu(x) U_mu(x+mu) U_mu(x+2mu) from the thin links on the GPU."""
+    o = Operator(ctx, L.LQCD_STAGGERED, dims, prec, recon, tile, bc_t, mass=mass, c_long=c_long, device=device)
+    Fd = fat_device if fat_device is not None else _device_complex(fat, device)
+    Ud = U_device if U_device is not None else _device_complex(U, device)
+    g = o.empty(L.LQCD_FIELD_GAUGE)
+    L.lqcd_gauge_import(ctx, o.op, g, Fd, L.LQCD_FIELD_GAUGE)
+    lg = o.empty(L.LQCD_FIELD_LONG)
+    L.lqcd_long_link_build(ctx, o.op, lg, Ud)
+    o.op.gauge = g.data_ptr()
+    o.op.long_links = lg.data_ptr()
+    o._keep.update(gauge=g, long=lg)
+    return o
+
+
+def gcr_params(tol=1e-10, k_max=16, delta=1e-3, max_iter=10000, precond=L.LQCD_PRECOND_NONE, block=(8, 8, 8, 8),
+               mr_steps=8):
+    p = L.lqcd_gcr_params()
+    p.tol, p.k_max, p.delta, p.max_iter, p.precond = tol, k_max, delta, max_iter, precond
+    p.schwarz.block[:] = [int(b) for b in block]
+    p.schwarz.mr_steps = mr_steps
+    p.learned = None
+    return p
+
+
+def cg_params(tol=1e-10, max_iter=10000, delta_reliable=0.1, kind=L.LQCD_CG_CGNE_SCHUR):
+    p = L.lqcd_cg_params()
+    p.tol, p.max_iter, p.delta_reliable, p.kind = tol, max_iter, delta_reliable, kind
+    return p
+
+
+def schwarz_params(block, mr_steps=8):
+    p = L.lqcd_schwarz_params()
+    p.block[:] = [int(b) for b in block]
+    p.mr_steps = mr_steps
+    return p

@@ -1,0 +1,200 @@
+"""GPU parity of the Wilson-clover kernels against the FP64 CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import TOL, ctx, np_of, on_parity, rel  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_1109_2935_amd.lqcd")
+from paper_1109_2935_amd import ops  # noqa: E402
+
+# (dims, tile): plain lexicographic layouts (tile = dims) with a non-power-of-two
+# extent, and tiled layouts that span several tiles with a ragged tile count.
+LAYOUTS = [((4, 4, 6, 8), None), ((8, 8, 8, 8), (4, 4, 4, 4)), ((4, 8, 4, 12), (2, 4, 2, 4))]
+PREC_RECON = [(0, 18), (0, 12), (0, 8), (1, 18), (1, 12), (1, 8), (2, 18), (2, 12), (3, 18), (3, 12)]
+
+
+class Fields:
+    cache = {}
+
+    @classmethod
+    def get(cls, dims, seed=11):
+        key = (dims, seed)
+        if key not in cls.cache:
+            U = synth.gauge_field(dims, 0.25, seed)
+            psi = synth.gaussian_spinor(dims, seed + 1)
+            cls.cache[key] = (U, psi, torch.from_numpy(U).cuda())
+        return cls.cache[key]
+
+
+def make_op(ctx, dims, prec, recon, tile=None, kappa=0.124, csw=1.0, bc_t=-1):
+    U, psi, Ud = Fields.get(dims)
+    return ops.wilson_clover(ctx, U, dims, kappa, csw, prec, recon, tile=tile, bc_t=bc_t, U_device=Ud)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS, ids=lambda l: "x".join(map(str, l[0])))
+@pytest.mark.parametrize("prec,recon", PREC_RECON, ids=lambda v: str(v))
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_dslash_parity(ctx, layout, prec, recon, dagger):
+    dims, tile = layout
+    U, psi, _ = Fields.get(dims)
+    o = make_op(ctx, dims, prec, recon, tile)
+    for p in (0, 1):
+        mask_in = oracle.parity_mask(dims, 1 - p)
+        src = on_parity(psi, mask_in)
+        inp = o.import_spinor(src, 1 - p)
+        out = o.spinor()
+        L.lqcd_dslash(ctx, o.op, out, inp, p, dagger)
+        got = np_of(o.export_spinor(out, p))
+        ref = oracle.wilson_dslash(dims, U, src, bc_t=-1, out_parity=p, dagger=bool(dagger))
+        e = rel(got, ref)
+        assert e < TOL[prec], (p, e)
+
+
+@pytest.mark.parametrize("prec,recon", [(0, 18), (1, 12), (2, 12)])
+@pytest.mark.parametrize("block", [(4, 4, 4, 4), (2, 4, 4, 2), (8, 8, 2, 8)])
+def test_dslash_dirichlet_cut(ctx, prec, recon, block):
+    dims = (8, 8, 8, 8)
+    U, psi, _ = Fields.get(dims)
+    o = make_op(ctx, dims, prec, recon, tile=(4, 4, 4, 4))
+    for dagger in (0, 1):
+        for p in (0, 1):
+            src = on_parity(psi, oracle.parity_mask(dims, 1 - p))
+            inp = o.import_spinor(src, 1 - p)
+            out = o.spinor()
+            L.lqcd_dslash(ctx, o.op, out, inp, p, dagger, block=block)
+            got = np_of(o.export_spinor(out, p))
+            ref = oracle.wilson_dslash(dims, U, src, out_parity=p, dagger=bool(dagger), block=block)
+            assert rel(got, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("bc_t", [1, -1])
+def test_dslash_periodic_and_antiperiodic(ctx, bc_t):
+    dims = (4, 4, 6, 8)
+    U, psi, _ = Fields.get(dims)
+    o = make_op(ctx, dims, 0, 18, bc_t=bc_t)
+    src = on_parity(psi, oracle.parity_mask(dims, 1))
+    out = o.spinor()
+    L.lqcd_dslash(ctx, o.op, out, o.import_spinor(src, 1), 0, 0)
+    ref = oracle.wilson_dslash(dims, U, src, bc_t=bc_t, out_parity=0)
+    assert rel(np_of(o.export_spinor(out, 0)), ref) < 1e-12
+
+
+@pytest.mark.parametrize("layout", LAYOUTS[:2], ids=lambda l: "x".join(map(str, l[0])))
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_clover_build_and_apply(ctx, layout, prec):
+    dims, tile = layout
+    U, psi, _ = Fields.get(dims)
+    o = make_op(ctx, dims, prec, 18, tile)
+    A = oracle.clover_build(dims, U, 0.124, 1.0)
+    Ainv = oracle.clover_invert(dims, A)
+    for p in (0, 1):
+        src = on_parity(psi, oracle.parity_mask(dims, p))
+        inp = o.import_spinor(src, p)
+        for inverse, M in ((0, A), (1, Ainv)):
+            out = o.spinor()
+            L.lqcd_clover_apply(ctx, o.op, out, inp, p, inverse)
+            ref = oracle.clover_apply(dims, M, src, parity=p)
+            assert rel(np_of(o.export_spinor(out, p)), ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS, ids=lambda l: "x".join(map(str, l[0])))
+@pytest.mark.parametrize("prec,recon", [(0, 18), (0, 12), (1, 12), (1, 8), (2, 12), (3, 12)])
+def test_schur_parity(ctx, layout, prec, recon):
+    dims, tile = layout
+    U, psi, _ = Fields.get(dims)
+    o = make_op(ctx, dims, prec, recon, tile)
+    ref_op = oracle.WilsonClover(dims, U, 0.124, 1.0, bc_t=-1)
+    src = on_parity(psi, ref_op.even)
+    inp = o.import_spinor(src, 0)
+    for dagger in (0, 1):
+        out = o.spinor()
+        L.lqcd_schur_apply(ctx, o.op, out, inp, dagger)
+        ref = ref_op.schur(src, dagger=bool(dagger))
+        assert rel(np_of(o.export_spinor(out, 0)), ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("block", [(4, 4, 4, 4), (2, 2, 2, 2)])
+def test_schur_cut_parity(ctx, block):
+    dims = (8, 8, 8, 8)
+    U, psi, _ = Fields.get(dims)
+    o = make_op(ctx, dims, 0, 18, tile=(4, 4, 4, 4))
+    ref_op = oracle.WilsonClover(dims, U, 0.124, 1.0, bc_t=-1)
+    src = on_parity(psi, ref_op.even)
+    out = o.spinor()
+    L.lqcd_schur_apply(ctx, o.op, out, o.import_spinor(src, 0), 0, block=block)
+    assert rel(np_of(o.export_spinor(out, 0)), ref_op.schur(src, block=block)) < 1e-12
+
+
+@pytest.mark.parametrize("dims,block", [((8, 8, 8, 8), (4, 4, 4, 4)), ((4, 4, 8, 8), (2, 2, 2, 2)),
+                                        ((16, 8, 8, 8), (8, 8, 8, 8))])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_schwarz_parity(ctx, dims, block, prec):
+    """K r = block-Jacobi of 8 MR steps on each Dirichlet block (FP64: 1e-12)."""
+    U, psi, _ = Fields.get(dims)
+    o = make_op(ctx, dims, prec, 18 if prec in (0, 1) else 12, tile=block)
+    ref_op = oracle.WilsonClover(dims, U, 0.124, 1.0, bc_t=-1)
+    from oracle import solvers
+    src = on_parity(psi, ref_op.even)
+    ref = solvers.schwarz(ref_op, src, block, 8)
+    inp = o.import_spinor(src, 0)
+    out = o.spinor()
+    L.lqcd_schwarz_precond(ctx, o.op, ops.schwarz_params(block, 8), out, inp)
+    e = rel(np_of(o.export_spinor(out, 0)), ref)
+    # 16-bit storage of the MR iterates: the MR recursion amplifies the storage
+    # rounding by the number of steps
+    tol = {0: 1e-12, 1: 1e-5, 2: 2e-2, 3: 1e-1}[prec]
+    assert e < tol, e
+
+
+def test_dslash_deterministic(ctx):
+    dims = (8, 8, 8, 8)
+    U, psi, _ = Fields.get(dims)
+    o = make_op(ctx, dims, 1, 12, tile=(4, 4, 4, 4))
+    inp = o.import_spinor(on_parity(psi, oracle.parity_mask(dims, 1)), 1)
+    a, b = o.spinor(), o.spinor()
+    L.lqcd_dslash(ctx, o.op, a, inp, 0)
+    L.lqcd_dslash(ctx, o.op, b, inp, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_multi_rhs_equals_single(ctx):
+    dims = (4, 4, 6, 8)
+    U, psi, _ = Fields.get(dims)
+    o = make_op(ctx, dims, 1, 12)
+    srcs = [on_parity(synth.gaussian_spinor(dims, 100 + r), oracle.parity_mask(dims, 1)) for r in range(3)]
+    sb = o.spinor_bytes
+    inp = o.spinor(nrhs=3)
+    for r, s in enumerate(srcs):
+        o.import_spinor(s, 1, out=inp[r * sb:(r + 1) * sb])
+    out = o.spinor(nrhs=3)
+    L.lqcd_dslash(ctx, o.op, out, inp, 0, nrhs=3)
+    for r in range(3):
+        single = o.spinor()
+        L.lqcd_dslash(ctx, o.op, single, inp[r * sb:(r + 1) * sb], 0)
+        torch.cuda.synchronize()
+        assert torch.equal(single, out[r * sb:(r + 1) * sb])
+
+
+def test_invalid_arguments_write_nothing(ctx):
+    dims = (4, 4, 6, 8)
+    o = make_op(ctx, dims, 1, 12)
+    out = o.spinor()
+    out.fill_(7)
+    inp = o.spinor()
+    for kwargs, code in [(dict(out_parity=2), L.LQCD_ERR_INVALID_ARG),
+                         (dict(out_parity=0, nrhs=0), L.LQCD_ERR_INVALID_ARG),
+                         (dict(out_parity=0, block=(3, 4, 6, 8)), L.LQCD_ERR_INVALID_ARG)]:
+        with pytest.raises(L.LqcdError) as ei:
+            L.lqcd_dslash(ctx, o.op, out, inp, **kwargs)
+        assert ei.value.status == code
+    with pytest.raises(L.LqcdError) as ei:
+        L.lqcd_dslash(ctx, o.op, int(out.data_ptr()) + 4, inp, 0)
+    assert ei.value.status == L.LQCD_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert bool((out == 7).all())
