@@ -65,6 +65,17 @@ def time_kernel(torch, fn, launches):
     return s.elapsed_time(e) / 1e3 / launches
 
 
+def device_copy(torch, nbytes=2 << 30, launches=20):
+    """Bandwidth of a plain device-to-device copy kernel (read + write bytes /
+    time), the practical ceiling next to the 8 TB/s specification. The same
+    kernel, with known bytes, calibrates the HBM traffic counters."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    c = torch.empty_like(a)
+    dt = time_kernel(torch, lambda: c.copy_(a), launches)
+    del a, c
+    return {"bytes_per_launch": 2 * nbytes, "us": round(dt * 1e6, 1), "GB/s": round(2 * nbytes / dt / 1e9, 1)}
+
+
 def cpu_baseline(dims, U, b, kappa, csw):
     """The oracle's FP64 Wilson dslash (one parity) on the same fields, timed
     on the host cores; reported in the same unit (algorithmic GB/s, FP64
@@ -139,8 +150,10 @@ def main():
             "frac": round(sb / dts / 1e9 / HBM_PEAK_GBS, 4), "bytes": sb}
         log("%-18s %8.1f us %7.1f GB/s | schur %8.1f us %7.1f GB/s" % (
             "%s r%d" % (PREC_NAME[prec], recon), dt * 1e6, byts / dt / 1e9, dts * 1e6, sb / dts / 1e9))
+    copy = device_copy(torch)
+    log("device copy %.1f GB/s" % copy["GB/s"])
     if args.kernels_only:
-        print(json.dumps({"kernels": kernels}))
+        print(json.dumps({"kernels": kernels, "device_copy": copy}))
         return
 
     o64, o32, o16 = inst[(0, 18)], inst[(1, 12)], inst[(2, 12)]
@@ -204,6 +217,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
         "time_to_solution": tts,
+        "device_copy": copy,
         "kernels": kernels,
     }
     if not args.no_cpu_baseline:

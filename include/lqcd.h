@@ -148,7 +148,7 @@ lqcd_status lqcd_context_destroy(lqcd_context *ctx);
 /* Text of the last error (never NULL; "" if none). ctx may be NULL. */
 const char *lqcd_last_error(const lqcd_context *ctx);
 
-/* Bytes of one packed field of `kind` for operator `op` (nrhs consecutive copies). */
+/* Bytes of one packed field of `kind` for operator `op` with nrhs right-hand sides. */
 lqcd_status lqcd_field_bytes(const lqcd_operator *op, int32_t kind, int32_t nrhs, size_t *bytes);
 
 /* ---------------------------------------------------------------------- */
@@ -186,11 +186,15 @@ lqcd_status lqcd_clover_build(lqcd_context *ctx, const lqcd_operator *op, void *
  * parity 0 or 1: only that parity (packed = one LQCD_FIELD_SPINOR block);
  * parity -1: both (packed = LQCD_FIELD_SPINOR_FULL). Export writes only the
  * natural sites of the parities it covers.
+ * nrhs > 1: `natural` holds nrhs consecutive natural fields, and the packed
+ * field stores the right-hand sides interleaved per site (packed site index
+ * site * nrhs + rhs), the layout every nrhs > 1 call below expects; its size
+ * is lqcd_field_bytes(op, kind, nrhs).
  */
 lqcd_status lqcd_spinor_import(lqcd_context *ctx, const lqcd_operator *op, void *packed,
-                               const void *natural, int32_t parity, lqcd_stream stream);
+                               const void *natural, int32_t parity, int32_t nrhs, lqcd_stream stream);
 lqcd_status lqcd_spinor_export(lqcd_context *ctx, const lqcd_operator *op, void *natural,
-                               const void *packed, int32_t parity, lqcd_stream stream);
+                               const void *packed, int32_t parity, int32_t nrhs, lqcd_stream stream);
 
 /* ---------------------------------------------------------------------- */
 /* operators                                                               */
@@ -203,7 +207,9 @@ lqcd_status lqcd_spinor_export(lqcd_context *ctx, const lqcd_operator *op, void 
  * block: NULL, or the Dirichlet block size per axis (each divides dims):
  * every hop whose two sites lie in different blocks is dropped (Section III-B,
  * Section VIII-A); an axis with one block keeps its periodic hop.
- * out and in are packed single-parity spinors; nrhs consecutive fields.
+ * out and in are packed single-parity spinors with nrhs right-hand sides
+ * interleaved per site (one launch; the link of a site is shared by its
+ * right-hand sides). out must not alias in.
  */
 lqcd_status lqcd_dslash(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in,
                         int32_t out_parity, int32_t dagger, const int32_t *block, int32_t nrhs,
@@ -211,7 +217,7 @@ lqcd_status lqcd_dslash(lqcd_context *ctx, const lqcd_operator *op, void *out, c
 
 /*
  * Clover term of eq. (2): out_p = A_p in_p (inverse = 0) or A_p^-1 in_p
- * (inverse = 1), single-parity packed spinors, nrhs consecutive fields.
+ * (inverse = 1), single-parity packed spinors, nrhs interleaved right-hand sides.
  */
 lqcd_status lqcd_clover_apply(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in,
                               int32_t parity, int32_t inverse, int32_t nrhs, lqcd_stream stream);
@@ -224,6 +230,26 @@ lqcd_status lqcd_clover_apply(lqcd_context *ctx, const lqcd_operator *op, void *
  */
 lqcd_status lqcd_schur_apply(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in,
                              int32_t dagger, const int32_t *block, int32_t nrhs, lqcd_stream stream);
+
+/*
+ * Batched Wilson hopping term over several operators in one persistent
+ * launch (the lattices may differ in size): for every job,
+ * out = D_{p,1-p} in (dagger: D^+) with nrhs interleaved right-hand sides.
+ * All jobs share precision and link compression; at most 8 jobs. Workgroups
+ * take work items from a queue until every job is done; the work-item size,
+ * workgroup size and grid come from the autotuner (timed on first use of a
+ * batch shape, see LQCD_TUNE / LQCD_TUNE_CACHE). The paper is silent on
+ * batching; each job computes exactly lqcd_dslash.
+ */
+typedef struct {
+  const lqcd_operator *op;
+  void *out;
+  const void *in;
+  int32_t out_parity;
+  int32_t nrhs;
+} lqcd_dslash_job;
+lqcd_status lqcd_dslash_batch(lqcd_context *ctx, const lqcd_dslash_job *jobs, int32_t njobs, int32_t dagger,
+                              lqcd_stream stream);
 
 /*
  * Additive Schwarz preconditioner (Section III-B; Section VIII-A): on every

@@ -100,6 +100,13 @@ lqcd_status apply_cut(lqcd_context *ctx, const OpInfo &info, const int32_t *bloc
   return LQCD_OK;
 }
 
+lqcd_status check_nrhs(lqcd_context *ctx, const OpInfo &info, int nrhs) {
+  if (nrhs < 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "nrhs must be >= 1");
+  if ((int64_t)info.vh * nrhs >= ((int64_t)1 << 31))
+    return set_error(ctx, LQCD_ERR_UNSUPPORTED, "sites x right-hand sides must stay below 2^31");
+  return LQCD_OK;
+}
+
 lqcd_status scratch(lqcd_context *ctx, int slot, size_t bytes, void **ptr) {
   if (slot >= (int)ctx->scratch.size()) {
     ctx->scratch.resize(slot + 1, nullptr);
@@ -154,7 +161,7 @@ const void *clover_block(const OpInfo &info, const void *clov, int parity) {
 
 lqcd_status wilson_hop(lqcd_context *ctx, const OpInfo &info, const Geom &g, int mode, void *out, const void *in,
                        const void *xin, const void *clov, int parity, double coef, int dagger, double *partials,
-                       hipStream_t st) {
+                       hipStream_t st, int nrhs) {
   WilsonLaunch w;
   w.g = g;
   w.prec = info.prec;
@@ -169,12 +176,24 @@ lqcd_status wilson_hop(lqcd_context *ctx, const OpInfo &info, const Geom &g, int
   w.dagger = dagger;
   w.mode = mode;
   w.partials = partials;
+  w.nrhs = nrhs;
   w.block_threads = 256;
-  return hip_check(ctx, launch_wilson(w, st, nullptr), "wilson dslash launch");
+  // Workgroup size picked by the autotuner per (kernel, precision, links,
+  // geometry, rhs). Calls that overwrite one of their inputs are not re-run
+  // for timing; they use the tuned value if there is one, else 128.
+  const bool rerunnable = out != in && out != xin;
+  const std::string key = "wilson m" + std::to_string(mode) + (partials ? "r" : "") + " p" + std::to_string(info.prec) +
+                          " r" + std::to_string(info.recon) + " " + geom_key(g) + " n" + std::to_string(nrhs);
+  w.block_threads = tune_pick(ctx, key, {64, 128, 256}, 128, rerunnable, st, [&](int bt) {
+    WilsonLaunch v = w;
+    v.block_threads = bt;
+    return launch_wilson(v, st);
+  });
+  return hip_check(ctx, launch_wilson(w, st), "wilson dslash launch");
 }
 
 lqcd_status stag_hop(lqcd_context *ctx, const OpInfo &info, void *out, const void *in, const void *xin, int parity,
-                     double coef, double xcoef, hipStream_t st) {
+                     double coef, double xcoef, hipStream_t st, int nrhs) {
   StagLaunch l;
   l.g = info.g;
   l.prec = info.prec;
@@ -188,7 +207,16 @@ lqcd_status stag_hop(lqcd_context *ctx, const OpInfo &info, void *out, const voi
   l.coef = coef;
   l.xcoef = xcoef;
   l.c_long = info.op->c_long;
+  l.nrhs = nrhs;
   l.block_threads = 256;
+  const bool rerunnable = out != in && out != xin;
+  const std::string key = "stag x" + std::to_string(xin != nullptr) + " p" + std::to_string(info.prec) + " r" +
+                          std::to_string(info.recon) + " " + geom_key(info.g) + " n" + std::to_string(nrhs);
+  l.block_threads = tune_pick(ctx, key, {64, 128, 256}, 128, rerunnable, st, [&](int bt) {
+    StagLaunch v = l;
+    v.block_threads = bt;
+    return launch_staggered(v, st);
+  });
   return hip_check(ctx, launch_staggered(l, st), "staggered dslash launch");
 }
 
@@ -196,18 +224,18 @@ lqcd_status stag_hop(lqcd_context *ctx, const OpInfo &info, void *out, const voi
 // with per-workgroup partials <out,in>, <out,out>). Staggered: N_e in.
 // tmp: one single-parity spinor of this operator.
 lqcd_status schur_apply(lqcd_context *ctx, const OpInfo &info, const Geom &g, void *out, const void *in, void *tmp,
-                        int dagger, double *partials, hipStream_t st) {
+                        int dagger, double *partials, hipStream_t st, int nrhs) {
   const lqcd_operator *op = info.op;
   if (op->action == LQCD_WILSON_CLOVER) {
     lqcd_status s = wilson_hop(ctx, info, g, W_HOP_CLOV, tmp, in, nullptr, clover_block(info, op->clover_inv, 1), 1,
-                               1.0, dagger, nullptr, st);
+                               1.0, dagger, nullptr, st, nrhs);
     if (s) return s;
     return wilson_hop(ctx, info, g, W_XPAY_CLOV, out, tmp, in, clover_block(info, op->clover, 0), 0,
-                      -op->kappa * op->kappa, dagger, partials, st);
+                      -op->kappa * op->kappa, dagger, partials, st, nrhs);
   }
-  lqcd_status s = stag_hop(ctx, info, tmp, in, nullptr, 1, 1.0, 0.0, st);
+  lqcd_status s = stag_hop(ctx, info, tmp, in, nullptr, 1, 1.0, 0.0, st, nrhs);
   if (s) return s;
-  return stag_hop(ctx, info, out, tmp, in, 0, -0.25, op->mass * op->mass, st);
+  return stag_hop(ctx, info, out, tmp, in, 0, -0.25, op->mass * op->mass, st, nrhs);
 }
 
 // Additive Schwarz on the tile blocks: out = K in, both packed even spinors of
@@ -221,13 +249,13 @@ lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schw
   void *r, *q, *t, *part;
   if ((s = scratch(ctx, slot0, sb, &r)) || (s = scratch(ctx, slot0 + 1, sb, &q)) || (s = scratch(ctx, slot0 + 2, sb, &t)))
     return s;
-  // one (<q,r>, <q,q>) triple per reduction segment of min(tile sites, 256) sites
-  const int seg = info.g.Vt2 < 256 ? info.g.Vt2 : 256;
+  // one (<q,r>, <q,q>) triple per reduction segment of min(tile sites, 64) sites
+  const int seg = info.g.Vt2 < 64 ? info.g.Vt2 : 64;
   const size_t nseg = (info.vh + seg - 1) / seg;
   if ((s = scratch(ctx, slot0 + 3, nseg * 3 * sizeof(double), &part))) return s;
   s = hip_check(ctx, hipMemcpyAsync(r, in, sb, hipMemcpyDeviceToDevice, st), "schwarz copy");
   if (s) return s;
-  const int nps = info.g.Vt2 > 256 ? info.g.Vt2 / 256 : 1;  // reduction segments per block
+  const int nps = info.g.Vt2 > 64 ? info.g.Vt2 / 64 : 1;  // reduction segments per block
   for (int it = 0; it < prm->mr_steps; ++it) {
     if ((s = schur_apply(ctx, info, g, q, r, t, 0, (double *)part, st))) return s;
     if ((s = hip_check(ctx, launch_mr_update(info.g, info.prec, out, r, q, (const double *)part, nps, it == 0, st),
@@ -248,9 +276,9 @@ lqcd_status check_schwarz(lqcd_context *ctx, const OpInfo &info, const lqcd_schw
     if (prm->block[m] != info.op->tile[m])
       return set_error(ctx, LQCD_ERR_INVALID_ARG, "Schwarz blocks must equal the operator's layout tile");
   const int v = info.g.Vt2;
-  if (!((v <= 256 && 256 % v == 0) || (v > 256 && v % 256 == 0)))
+  if (!((v <= 64 && 64 % v == 0) || (v > 64 && v % 64 == 0)))
     return set_error(ctx, LQCD_ERR_UNSUPPORTED,
-                     "Schwarz block sites per parity must divide 256 or be a multiple of 256");
+                     "Schwarz block sites per parity must divide 64 or be a multiple of 64");
   return LQCD_OK;
 }
 
@@ -391,19 +419,20 @@ lqcd_status lqcd_clover_build(lqcd_context *ctx, const lqcd_operator *op, void *
 }
 
 static lqcd_status spinor_io(lqcd_context *ctx, const lqcd_operator *op, void *packed, const void *natural,
-                             int parity, lqcd_stream stream, bool imp) {
+                             int parity, int nrhs, lqcd_stream stream, bool imp) {
   OpInfo info;
   lqcd_status s = check_op(ctx, op, &info);
   if (s) return s;
   if (parity < -1 || parity > 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "parity must be 0, 1 or -1");
+  if ((s = check_nrhs(ctx, info, nrhs))) return s;
   if (!aligned16(packed) || !aligned16(natural))
     return set_error(ctx, LQCD_ERR_INVALID_ARG, "field pointers must be non-NULL and 16-byte aligned");
   for (int p = 0; p < 2; ++p) {
     if (parity >= 0 && p != parity) continue;
-    char *blk = (char *)packed + (parity < 0 ? p * info.spinor_bytes : 0);
-    hipError_t e = imp ? launch_spinor_import(info.g, op->prec, info.nsp, blk, (const double *)natural, p,
+    char *blk = (char *)packed + (parity < 0 ? p * info.spinor_bytes * nrhs : 0);
+    hipError_t e = imp ? launch_spinor_import(info.g, op->prec, info.nsp, blk, (const double *)natural, p, nrhs,
                                               (hipStream_t)stream)
-                       : launch_spinor_export(info.g, op->prec, info.nsp, (double *)natural, blk, p,
+                       : launch_spinor_export(info.g, op->prec, info.nsp, (double *)natural, blk, p, nrhs,
                                               (hipStream_t)stream);
     if ((s = hip_check(ctx, e, imp ? "spinor import" : "spinor export"))) return s;
   }
@@ -411,13 +440,13 @@ static lqcd_status spinor_io(lqcd_context *ctx, const lqcd_operator *op, void *p
 }
 
 lqcd_status lqcd_spinor_import(lqcd_context *ctx, const lqcd_operator *op, void *packed, const void *natural,
-                               int32_t parity, lqcd_stream stream) {
-  return spinor_io(ctx, op, packed, natural, parity, stream, true);
+                               int32_t parity, int32_t nrhs, lqcd_stream stream) {
+  return spinor_io(ctx, op, packed, natural, parity, nrhs, stream, true);
 }
 
 lqcd_status lqcd_spinor_export(lqcd_context *ctx, const lqcd_operator *op, void *natural, const void *packed,
-                               int32_t parity, lqcd_stream stream) {
-  return spinor_io(ctx, op, (void *)packed, natural, parity, stream, false);
+                               int32_t parity, int32_t nrhs, lqcd_stream stream) {
+  return spinor_io(ctx, op, (void *)packed, natural, parity, nrhs, stream, false);
 }
 
 static lqcd_status check_fields(lqcd_context *ctx, const lqcd_operator *op, bool need_clover) {
@@ -436,24 +465,18 @@ lqcd_status lqcd_dslash(lqcd_context *ctx, const lqcd_operator *op, void *out, c
   if (s) return s;
   if ((s = check_fields(ctx, op, false))) return s;
   if (out_parity != 0 && out_parity != 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "out_parity must be 0 or 1");
-  if (nrhs < 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "nrhs must be >= 1");
+  if ((s = check_nrhs(ctx, info, nrhs))) return s;
   if (!aligned16(out) || !aligned16(in))
     return set_error(ctx, LQCD_ERR_INVALID_ARG, "field pointers must be non-NULL and 16-byte aligned");
+  if (out == in) return set_error(ctx, LQCD_ERR_INVALID_ARG, "out and in must not alias");
   Geom g;
   if ((s = apply_cut(ctx, info, block, &g))) return s;
   if (op->action == LQCD_STAGGERED && g.has_cut)
     return set_error(ctx, LQCD_ERR_UNSUPPORTED, "Dirichlet cut is implemented for the Wilson operator");
-  for (int r = 0; r < nrhs; ++r) {
-    void *o = (char *)out + r * info.spinor_bytes;
-    const void *i = (const char *)in + r * info.spinor_bytes;
-    if (op->action == LQCD_WILSON_CLOVER)
-      s = wilson_hop(ctx, info, g, W_HOP, o, i, nullptr, nullptr, out_parity, 1.0, dagger, nullptr,
-                     (hipStream_t)stream);
-    else
-      s = stag_hop(ctx, info, o, i, nullptr, out_parity, dagger ? -1.0 : 1.0, 0.0, (hipStream_t)stream);
-    if (s) return s;
-  }
-  return LQCD_OK;
+  if (op->action == LQCD_WILSON_CLOVER)
+    return wilson_hop(ctx, info, g, W_HOP, out, in, nullptr, nullptr, out_parity, 1.0, dagger, nullptr,
+                      (hipStream_t)stream, nrhs);
+  return stag_hop(ctx, info, out, in, nullptr, out_parity, dagger ? -1.0 : 1.0, 0.0, (hipStream_t)stream, nrhs);
 }
 
 lqcd_status lqcd_clover_apply(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in, int32_t parity,
@@ -465,15 +488,10 @@ lqcd_status lqcd_clover_apply(lqcd_context *ctx, const lqcd_operator *op, void *
   if (!aligned16(op->clover) || !aligned16(op->clover_inv))
     return set_error(ctx, LQCD_ERR_INVALID_ARG, "operator clover fields missing or misaligned");
   if (parity != 0 && parity != 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "parity must be 0 or 1");
-  if (nrhs < 1 || !aligned16(out) || !aligned16(in)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad fields or nrhs");
+  if ((s = check_nrhs(ctx, info, nrhs))) return s;
+  if (!aligned16(out) || !aligned16(in)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
   const void *c = clover_block(info, inverse ? op->clover_inv : op->clover, parity);
-  for (int r = 0; r < nrhs; ++r) {
-    s = hip_check(ctx, launch_clover_apply(info.g, op->prec, (char *)out + r * info.spinor_bytes,
-                                           (const char *)in + r * info.spinor_bytes, c, (hipStream_t)stream),
-                  "clover apply");
-    if (s) return s;
-  }
-  return LQCD_OK;
+  return hip_check(ctx, launch_clover_apply(info.g, op->prec, out, in, c, nrhs, (hipStream_t)stream), "clover apply");
 }
 
 lqcd_status lqcd_schur_apply(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in, int32_t dagger,
@@ -483,19 +501,71 @@ lqcd_status lqcd_schur_apply(lqcd_context *ctx, const lqcd_operator *op, void *o
   if (s) return s;
   if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
   if ((s = check_fields(ctx, op, true))) return s;
-  if (nrhs < 1 || !aligned16(out) || !aligned16(in)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad fields or nrhs");
+  if ((s = check_nrhs(ctx, info, nrhs))) return s;
+  if (!aligned16(out) || !aligned16(in)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
+  if (out == in) return set_error(ctx, LQCD_ERR_INVALID_ARG, "out and in must not alias");
   Geom g;
   if ((s = apply_cut(ctx, info, block, &g))) return s;
   if (op->action == LQCD_STAGGERED && g.has_cut)
     return set_error(ctx, LQCD_ERR_UNSUPPORTED, "Dirichlet cut is implemented for the Wilson operator");
   void *tmp;
-  if ((s = scratch(ctx, kSlotSchurTmp, info.spinor_bytes, &tmp))) return s;
-  for (int r = 0; r < nrhs; ++r) {
-    s = schur_apply(ctx, info, g, (char *)out + r * info.spinor_bytes, (const char *)in + r * info.spinor_bytes, tmp,
-                    dagger, nullptr, (hipStream_t)stream);
+  if ((s = scratch(ctx, kSlotSchurTmp, info.spinor_bytes * nrhs, &tmp))) return s;
+  return schur_apply(ctx, info, g, out, in, tmp, dagger, nullptr, (hipStream_t)stream, nrhs);
+}
+
+lqcd_status lqcd_dslash_batch(lqcd_context *ctx, const lqcd_dslash_job *jobs, int32_t njobs, int32_t dagger,
+                              lqcd_stream stream) {
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  if (!jobs || njobs < 1 || njobs > 8) return set_error(ctx, LQCD_ERR_INVALID_ARG, "need 1 to 8 jobs");
+  BatchJob bj[8];
+  int prec = -1, recon = -1;
+  std::string key = "batch d" + std::to_string(dagger != 0);
+  for (int j = 0; j < njobs; ++j) {
+    OpInfo info;
+    lqcd_status s = check_op(ctx, jobs[j].op, &info);
     if (s) return s;
+    if (jobs[j].op->action != LQCD_WILSON_CLOVER)
+      return set_error(ctx, LQCD_ERR_UNSUPPORTED, "batched dslash is implemented for Wilson-clover operators");
+    if ((s = check_nrhs(ctx, info, jobs[j].nrhs))) return s;
+    if (!aligned16(jobs[j].op->gauge)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "job gauge field missing");
+    if (!aligned16(jobs[j].out) || !aligned16(jobs[j].in) || jobs[j].out == jobs[j].in)
+      return set_error(ctx, LQCD_ERR_INVALID_ARG, "job fields must be aligned, non-NULL and distinct");
+    if (jobs[j].out_parity != 0 && jobs[j].out_parity != 1)
+      return set_error(ctx, LQCD_ERR_INVALID_ARG, "out_parity must be 0 or 1");
+    if (j == 0) {
+      prec = info.prec;
+      recon = info.recon;
+    } else if (info.prec != prec || info.recon != recon) {
+      return set_error(ctx, LQCD_ERR_INVALID_ARG, "all jobs of a batch share precision and link format");
+    }
+    bj[j].g = info.g;
+    bj[j].out = jobs[j].out;
+    bj[j].in = jobs[j].in;
+    bj[j].gauge = jobs[j].op->gauge;
+    bj[j].parity = jobs[j].out_parity;
+    bj[j].nrhs = jobs[j].nrhs;
+    key += " " + geom_key(info.g) + "n" + std::to_string(jobs[j].nrhs);
   }
-  return LQCD_OK;
+  key += " p" + std::to_string(prec) + " r" + std::to_string(recon);
+  void *counter;
+  lqcd_status s = scratch(ctx, kSlotBatchCounter, 256, &counter);
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  // candidates: workgroup size x (site, rhs) pairs per work item x persistent grid
+  static const BatchTune cands[] = {{128, 1024, 2048}, {128, 2048, 2048}, {256, 2048, 1024}, {256, 4096, 1024},
+                                    {256, 1024, 2048}, {128, 512, 4096},   {256, 8192, 1024}, {64, 512, 4096}};
+  const int ncand = sizeof(cands) / sizeof(cands[0]);
+  std::vector<int> idx(ncand);
+  for (int i = 0; i < ncand; ++i) idx[i] = i;
+  bool distinct = true;
+  for (int a = 0; a < njobs; ++a)
+    for (int b = 0; b < njobs; ++b)
+      if (bj[a].out == bj[b].in || (a != b && bj[a].out == bj[b].out)) distinct = false;
+  const int pick = tune_pick(ctx, key, idx, 2, distinct, st, [&](int i) {
+    return launch_wilson_batch(prec, recon, bj, njobs, dagger, cands[i], (unsigned *)counter, st);
+  });
+  return hip_check(ctx, launch_wilson_batch(prec, recon, bj, njobs, dagger, cands[pick], (unsigned *)counter, st),
+                   "batched dslash launch");
 }
 
 lqcd_status lqcd_schwarz_precond(lqcd_context *ctx, const lqcd_operator *op_precond, const lqcd_schwarz_params *params,

@@ -70,7 +70,26 @@ template <typename S, int CH> struct alignas(sizeof(S) * CH) Chunk {
 // c (CH reals) of site s starts at real (c * stride + s) * CH, stride = sites
 // in the parity block, so consecutive threads (sites) touch consecutive
 // chunks. Each chunk is moved with accesses of at most 16 bytes.
-template <typename S, int N, int CH, typename R>
+// Raw integer vectors of 2..16 bytes, for non-temporal accesses of any chunk type.
+template <int BYTES> struct RawVec;
+template <> struct RawVec<16> { typedef unsigned T __attribute__((ext_vector_type(4))); };
+template <> struct RawVec<8> { typedef unsigned T __attribute__((ext_vector_type(2))); };
+template <> struct RawVec<4> { typedef unsigned T; };
+template <> struct RawVec<2> { typedef unsigned short T; };
+
+// Streaming (non-temporal) load / store: data touched once per kernel (links,
+// outputs) is marked so that it does not displace reusable lines (neighbour
+// spinors) from the L2.
+template <typename C> __device__ __forceinline__ C nt_load(const C *p) {
+  using R = typename RawVec<sizeof(C)>::T;
+  return __builtin_bit_cast(C, __builtin_nontemporal_load(reinterpret_cast<const R *>(p)));
+}
+template <typename C> __device__ __forceinline__ void nt_store(C *p, const C &v) {
+  using R = typename RawVec<sizeof(C)>::T;
+  __builtin_nontemporal_store(__builtin_bit_cast(R, v), reinterpret_cast<R *>(p));
+}
+
+template <typename S, int N, int CH, typename R, bool NT = false>
 __device__ __forceinline__ void load_chunks(const S *__restrict__ base, int64_t stride, int64_t s, R *out) {
   constexpr int W = (CH * (int)sizeof(S) > 16) ? 16 / (int)sizeof(S) : CH;
 #pragma unroll
@@ -78,14 +97,15 @@ __device__ __forceinline__ void load_chunks(const S *__restrict__ base, int64_t 
     const S *p = base + (c * stride + s) * CH;
 #pragma unroll
     for (int w = 0; w < CH / W; ++w) {
-      Chunk<S, W> v = *reinterpret_cast<const Chunk<S, W> *>(p + w * W);
+      const Chunk<S, W> *q = reinterpret_cast<const Chunk<S, W> *>(p + w * W);
+      Chunk<S, W> v = NT ? nt_load(q) : *q;
 #pragma unroll
       for (int k = 0; k < W; ++k) out[c * CH + w * W + k] = to_real<R>(v.v[k]);
     }
   }
 }
 
-template <typename S, int N, int CH, typename R>
+template <typename S, int N, int CH, typename R, bool NT = false>
 __device__ __forceinline__ void store_chunks(S *__restrict__ base, int64_t stride, int64_t s, const R *in) {
   constexpr int W = (CH * (int)sizeof(S) > 16) ? 16 / (int)sizeof(S) : CH;
 #pragma unroll
@@ -96,16 +116,20 @@ __device__ __forceinline__ void store_chunks(S *__restrict__ base, int64_t strid
       Chunk<S, W> v;
 #pragma unroll
       for (int k = 0; k < W; ++k) v.v[k] = Store<S>::from(in[c * CH + w * W + k]);
-      *reinterpret_cast<Chunk<S, W> *>(p + w * W) = v;
+      Chunk<S, W> *q = reinterpret_cast<Chunk<S, W> *>(p + w * W);
+      if (NT)
+        nt_store(q, v);
+      else
+        *q = v;
     }
   }
 }
 
 // Links and clover: the chunk is the widest 16-byte-or-smaller unit that
 // divides N, so the layout of these fields depends on the precision.
-template <typename S, int N, typename R>
+template <typename S, int N, typename R, bool NT = false>
 __device__ __forceinline__ void load_site(const S *__restrict__ base, int64_t stride, int64_t s, R *out) {
-  load_chunks<S, N, chunk_reals<S, N>(), R>(base, stride, s, out);
+  load_chunks<S, N, chunk_reals<S, N>(), R, NT>(base, stride, s, out);
 }
 template <typename S, int N, typename R>
 __device__ __forceinline__ void store_site(S *__restrict__ base, int64_t stride, int64_t s, const R *in) {
@@ -122,9 +146,9 @@ template <typename S, int N, typename R>
 __device__ __forceinline__ void load_spinor_reals(const S *__restrict__ base, int64_t stride, int64_t s, R *out) {
   load_chunks<S, N, spinor_chunk<N>(), R>(base, stride, s, out);
 }
-template <typename S, int N, typename R>
+template <typename S, int N, typename R, bool NT = false>
 __device__ __forceinline__ void store_spinor_reals(S *__restrict__ base, int64_t stride, int64_t s, const R *in) {
-  store_chunks<S, N, spinor_chunk<N>(), R>(base, stride, s, in);
+  store_chunks<S, N, spinor_chunk<N>(), R, NT>(base, stride, s, in);
 }
 
 // ---------------------------------------------------------------------------

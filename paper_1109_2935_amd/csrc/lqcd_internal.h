@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,10 @@ struct lqcd_context {
   // general scratch vectors, grown on demand and reused between calls
   std::vector<void *> scratch;
   std::vector<size_t> scratch_bytes;
+  // autotuner results: launch parameter per kernel/shape key
+  std::map<std::string, int> tuned;
+  std::string tune_file;
+  bool tune_enabled = true;
 };
 
 namespace lqcd {
@@ -74,20 +79,37 @@ struct WilsonLaunch {
   double coef;
   int dagger;
   int mode;
-  double *partials;  // if non-null: per-workgroup <out,xin> (re, im) and <out,out>
+  double *partials;  // if non-null: per-segment <out,xin> (re, im) and <out,out> (nrhs = 1)
   int block_threads;
+  int nrhs;          // right-hand sides interleaved per site
 };
-hipError_t launch_wilson(const WilsonLaunch &w, hipStream_t st, int *nwg_out);
-int wilson_nwg(const Geom &g, int block_threads);
+hipError_t launch_wilson(const WilsonLaunch &w, hipStream_t st);
 
-hipError_t launch_clover_apply(const Geom &g, int prec, void *out, const void *in, const void *clov,
+// Persistent multi-operator hopping term (mode W_HOP, coef 1).
+struct BatchJob {
+  Geom g;
+  void *out;
+  const void *in;
+  const void *gauge;
+  int parity;
+  int nrhs;
+};
+struct BatchTune {
+  int block_threads;  // 64..256
+  int chunk;          // (site, rhs) pairs per work item
+  int grid;           // workgroups of the persistent launch
+};
+hipError_t launch_wilson_batch(int prec, int recon, const BatchJob *jobs, int njobs, int dagger, const BatchTune &t,
+                               unsigned *counter, hipStream_t st);
+
+hipError_t launch_clover_apply(const Geom &g, int prec, void *out, const void *in, const void *clov, int nrhs,
                                hipStream_t st);
 
 // setup kernels
 hipError_t launch_spinor_import(const Geom &g, int prec, int nsp, void *packed, const double *natural,
-                                int parity, hipStream_t st);
+                                int parity, int nrhs, hipStream_t st);
 hipError_t launch_spinor_export(const Geom &g, int prec, int nsp, double *natural, const void *packed,
-                                int parity, hipStream_t st);
+                                int parity, int nrhs, hipStream_t st);
 hipError_t launch_gauge_import(const Geom &g, int prec, int recon, void *packed, const double *natural,
                                int form_long, hipStream_t st);
 hipError_t launch_clover_build(const Geom &g, int prec, double kappa, double csw, void *clov, void *clov_inv,
@@ -109,6 +131,7 @@ struct StagLaunch {
   double xcoef;     // multiplies xin
   double c_long;
   int block_threads;
+  int nrhs;
 };
 hipError_t launch_staggered(const StagLaunch &s, hipStream_t st);
 

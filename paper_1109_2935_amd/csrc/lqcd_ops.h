@@ -2,6 +2,10 @@
 // the solvers (solvers.cpp).
 #pragma once
 
+#include <functional>
+#include <string>
+#include <vector>
+
 #include "lqcd_internal.h"
 
 namespace lqcd {
@@ -11,6 +15,7 @@ enum ScratchSlot {
   kSlotFlag = 0,
   kSlotSchurTmp = 1,
   kSlotSchwarz = 2,   // 4 slots: r, q, t, partials
+  kSlotBatchCounter = 6,
   kSlotSolver = 8,    // solver work vectors start here
 };
 
@@ -20,11 +25,20 @@ const void *clover_block(const OpInfo &info, const void *clov, int parity);
 
 lqcd_status wilson_hop(lqcd_context *ctx, const OpInfo &info, const Geom &g, int mode, void *out, const void *in,
                        const void *xin, const void *clov, int parity, double coef, int dagger, double *partials,
-                       hipStream_t st);
+                       hipStream_t st, int nrhs = 1);
 lqcd_status stag_hop(lqcd_context *ctx, const OpInfo &info, void *out, const void *in, const void *xin, int parity,
-                     double coef, double xcoef, hipStream_t st);
+                     double coef, double xcoef, hipStream_t st, int nrhs = 1);
 lqcd_status schur_apply(lqcd_context *ctx, const OpInfo &info, const Geom &g, void *out, const void *in, void *tmp,
-                        int dagger, double *partials, hipStream_t st);
+                        int dagger, double *partials, hipStream_t st, int nrhs = 1);
+lqcd_status check_nrhs(lqcd_context *ctx, const OpInfo &info, int nrhs);
+
+// Autotuner (tune.cpp): the best of `cands` for `key`, timing `launch(c)` on
+// the stream the first time the key is seen (if `may_time`); `fallback`
+// otherwise. Results persist in the context (and in the file named by
+// LQCD_TUNE_CACHE, if set). LQCD_TUNE=0 disables timing.
+int tune_pick(lqcd_context *ctx, const std::string &key, const std::vector<int> &cands, int fallback, bool may_time,
+              hipStream_t st, const std::function<hipError_t(int)> &launch);
+std::string geom_key(const Geom &g);
 lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schwarz_params *prm, void *out,
                           const void *in, int slot0, hipStream_t st);
 lqcd_status check_schwarz(lqcd_context *ctx, const OpInfo &info, const lqcd_schwarz_params *prm);

@@ -17,47 +17,55 @@ __device__ __forceinline__ void site_global(const Geom &g, const Site &x, int X[
 // ---------------------------------------------------------------------------
 // spinors
 
+// nrhs natural fields (consecutive, V sites each) <-> one packed field with the
+// right-hand sides interleaved per site (packed index site * nrhs + rhs).
 template <typename S, int NSP>
-__global__ void __launch_bounds__(256) spinor_import_kernel(Geom g, S *packed, const double *nat, int parity) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.Vh) return;
+__global__ void __launch_bounds__(256) spinor_import_kernel(Geom g, S *packed, const double *nat, int parity,
+                                                            int nrhs) {
+  const int pidx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pidx >= g.Vh * nrhs) return;
+  const int s = pidx / nrhs, r = pidx - s * nrhs;
   const Site x = decode_site(g, s, parity);
   int X[4];
   site_global(g, x, X);
-  const double *src = nat + NSP * natural_index(g, X);
+  const int64_t V = 2 * (int64_t)g.Vh;
+  const double *src = nat + NSP * (r * V + natural_index(g, X));
   double v[NSP];
 #pragma unroll
   for (int k = 0; k < NSP; ++k) v[k] = src[k];
-  store_spinor_reals<S, NSP, double>(packed, g.Vh, s, v);
+  store_spinor_reals<S, NSP, double>(packed, (int64_t)g.Vh * nrhs, pidx, v);
 }
 
 template <typename S, int NSP>
-__global__ void __launch_bounds__(256) spinor_export_kernel(Geom g, double *nat, const S *packed, int parity) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.Vh) return;
+__global__ void __launch_bounds__(256) spinor_export_kernel(Geom g, double *nat, const S *packed, int parity,
+                                                            int nrhs) {
+  const int pidx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pidx >= g.Vh * nrhs) return;
+  const int s = pidx / nrhs, r = pidx - s * nrhs;
   const Site x = decode_site(g, s, parity);
   int X[4];
   site_global(g, x, X);
   double v[NSP];
-  load_spinor_reals<S, NSP, double>(packed, g.Vh, s, v);
-  double *dst = nat + NSP * natural_index(g, X);
+  load_spinor_reals<S, NSP, double>(packed, (int64_t)g.Vh * nrhs, pidx, v);
+  const int64_t V = 2 * (int64_t)g.Vh;
+  double *dst = nat + NSP * (r * V + natural_index(g, X));
 #pragma unroll
   for (int k = 0; k < NSP; ++k) dst[k] = v[k];
 }
 
 template <int NSP>
-static hipError_t spinor_io(const Geom &g, int prec, void *packed, double *natural, int parity, bool imp,
+static hipError_t spinor_io(const Geom &g, int prec, void *packed, double *natural, int parity, int nrhs, bool imp,
                             hipStream_t st) {
-  const int bt = 256, nwg = (g.Vh + bt - 1) / bt;
+  const int bt = 256, nwg = (int)(((int64_t)g.Vh * nrhs + bt - 1) / bt);
   switch (prec) {
 #define CASE(P)                                                                                               \
   case P:                                                                                                     \
     if (imp)                                                                                                  \
       hipLaunchKernelGGL((spinor_import_kernel<Prec<P>::S, NSP>), dim3(nwg), dim3(bt), 0, st, g,              \
-                         (Prec<P>::S *)packed, (const double *)natural, parity);                               \
+                         (Prec<P>::S *)packed, (const double *)natural, parity, nrhs);                         \
     else                                                                                                      \
       hipLaunchKernelGGL((spinor_export_kernel<Prec<P>::S, NSP>), dim3(nwg), dim3(bt), 0, st, g, natural,     \
-                         (const Prec<P>::S *)packed, parity);                                                 \
+                         (const Prec<P>::S *)packed, parity, nrhs);                                           \
     return hipGetLastError();
     CASE(LQCD_F64)
     CASE(LQCD_F32)
@@ -69,17 +77,17 @@ static hipError_t spinor_io(const Geom &g, int prec, void *packed, double *natur
 }
 
 hipError_t launch_spinor_import(const Geom &g, int prec, int nsp, void *packed, const double *natural, int parity,
-                                hipStream_t st) {
+                                int nrhs, hipStream_t st) {
   if (g.Vh == 0) return hipSuccess;
-  return nsp == 24 ? spinor_io<24>(g, prec, packed, (double *)natural, parity, true, st)
-                   : spinor_io<6>(g, prec, packed, (double *)natural, parity, true, st);
+  return nsp == 24 ? spinor_io<24>(g, prec, packed, (double *)natural, parity, nrhs, true, st)
+                   : spinor_io<6>(g, prec, packed, (double *)natural, parity, nrhs, true, st);
 }
 
 hipError_t launch_spinor_export(const Geom &g, int prec, int nsp, double *natural, const void *packed, int parity,
-                                hipStream_t st) {
+                                int nrhs, hipStream_t st) {
   if (g.Vh == 0) return hipSuccess;
-  return nsp == 24 ? spinor_io<24>(g, prec, (void *)packed, natural, parity, false, st)
-                   : spinor_io<6>(g, prec, (void *)packed, natural, parity, false, st);
+  return nsp == 24 ? spinor_io<24>(g, prec, (void *)packed, natural, parity, nrhs, false, st)
+                   : spinor_io<6>(g, prec, (void *)packed, natural, parity, nrhs, false, st);
 }
 
 // ---------------------------------------------------------------------------

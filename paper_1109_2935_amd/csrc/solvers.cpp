@@ -56,7 +56,7 @@ lqcd_status residual_from(Solver &S, int p, const void *b, void *y, size_t n, do
 // Wilson even-odd source bhat = b_e + kappa D_eo A_oo^-1 b_o.
 lqcd_status wilson_schur_source(Solver &S, const OpInfo &hi, void *bhat, const void *b_full, void *tmp) {
   const char *be = (const char *)b_full, *bo = be + hi.spinor_bytes;
-  TRY(S.hip(launch_clover_apply(hi.g, hi.prec, tmp, bo, clover_block(hi, hi.op->clover_inv, 1), S.st), "clover"));
+  TRY(S.hip(launch_clover_apply(hi.g, hi.prec, tmp, bo, clover_block(hi, hi.op->clover_inv, 1), 1, S.st), "clover"));
   return wilson_hop(S.ctx, hi, hi.g, W_XPAY, bhat, tmp, be, nullptr, 0, hi.op->kappa, 0, nullptr, S.st);
 }
 
@@ -67,7 +67,7 @@ lqcd_status wilson_finish(Solver &S, const OpInfo &hi, void *x_full, const void 
   const char *be = (const char *)b_full, *bo = be + hi.spinor_bytes;
   const lqcd_operator *op = hi.op;
   TRY(wilson_hop(S.ctx, hi, hi.g, W_XPAY, tmp, xe, bo, nullptr, 1, op->kappa, 0, nullptr, S.st));
-  TRY(S.hip(launch_clover_apply(hi.g, hi.prec, xo, tmp, clover_block(hi, op->clover_inv, 1), S.st), "clover"));
+  TRY(S.hip(launch_clover_apply(hi.g, hi.prec, xo, tmp, clover_block(hi, op->clover_inv, 1), 1, S.st), "clover"));
   double tot = 0, rr;
   // even: A_ee x_e - kappa D_eo x_o - b_e
   TRY(wilson_hop(S.ctx, hi, hi.g, W_XPAY_CLOV, y, xo, xe, clover_block(hi, op->clover, 0), 0, -op->kappa, 0, nullptr,

@@ -18,6 +18,8 @@ template <typename S> struct SArgs {
   const S *xin;
   int parity;
   double coef, xcoef, c_long;
+  int nrhs;
+  FastDiv dN;
 };
 
 template <typename S, typename R>
@@ -29,8 +31,9 @@ __device__ __forceinline__ void load_cvec(const S *__restrict__ f, int64_t vh, i
 }
 
 template <int MU, typename S, typename R, int RECON>
-__device__ __forceinline__ void stag_dir(const SArgs<S> &a, const Site &x, int s, R eta, R cl, cpx<R> (&acc)[3]) {
-  const int64_t vh = a.g.Vh;
+__device__ __forceinline__ void stag_dir(const SArgs<S> &a, const Site &x, int s, int rhs, R eta, R cl,
+                                         cpx<R> (&acc)[3]) {
+  const int64_t vh = a.g.Vh, vs = vh * a.nrhs;
   const int neg = a.g.bc_t < 0;
   // one hop: fat; three hops: long
 #pragma unroll
@@ -41,15 +44,15 @@ __device__ __forceinline__ void stag_dir(const SArgs<S> &a, const Site &x, int s
       int w;
       const int n = hop<MU>(a.g, x, +k, &w);
       cpx<R> v[3], u[3];
-      load_cvec<S, R>(a.in, vh, n, v);
+      load_cvec<S, R>(a.in, vs, (int64_t)n * a.nrhs + rhs, v);
       Link<R> U;
       if (h == 0) {
         R r[18];
-        load_site<S, 18, R>(a.fat + (int64_t)(2 * MU + x.p) * vh * 18, vh, s, r);
+        load_site<S, 18, R, true>(a.fat + (int64_t)(2 * MU + x.p) * vh * 18, vh, s, r);
         U = unpack_link<18, R>(r);
       } else {
         R r[RECON];
-        load_site<S, RECON, R>(a.lng + (int64_t)(2 * MU + x.p) * vh * RECON, vh, s, r);
+        load_site<S, RECON, R, true>(a.lng + (int64_t)(2 * MU + x.p) * vh * RECON, vh, s, r);
         U = unpack_link<RECON, R>(r);
       }
       su3_mv(U, v, u);
@@ -61,15 +64,15 @@ __device__ __forceinline__ void stag_dir(const SArgs<S> &a, const Site &x, int s
       int w;
       const int n = hop<MU>(a.g, x, -k, &w);
       cpx<R> v[3], u[3];
-      load_cvec<S, R>(a.in, vh, n, v);
+      load_cvec<S, R>(a.in, vs, (int64_t)n * a.nrhs + rhs, v);
       Link<R> U;
       if (h == 0) {
         R r[18];
-        load_site<S, 18, R>(a.fat + (int64_t)(2 * MU + 1 - x.p) * vh * 18, vh, n, r);
+        load_site<S, 18, R, true>(a.fat + (int64_t)(2 * MU + 1 - x.p) * vh * 18, vh, n, r);
         U = unpack_link<18, R>(r);
       } else {
         R r[RECON];
-        load_site<S, RECON, R>(a.lng + (int64_t)(2 * MU + 1 - x.p) * vh * RECON, vh, n, r);
+        load_site<S, RECON, R, true>(a.lng + (int64_t)(2 * MU + 1 - x.p) * vh * RECON, vh, n, r);
         U = unpack_link<RECON, R>(r);
       }
       su3_adj_mv(U, v, u);
@@ -81,9 +84,11 @@ __device__ __forceinline__ void stag_dir(const SArgs<S> &a, const Site &x, int s
 }
 
 template <typename S, typename R, int RECON, bool XPAY>
-__global__ void __launch_bounds__(256) stag_kernel(SArgs<S> a) {
-  const int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (s >= a.g.Vh) return;
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) stag_kernel(SArgs<S> a) {
+  const int pidx = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (pidx >= a.g.Vh * a.nrhs) return;
+  const int s = (int)fdiv((uint32_t)pidx, a.dN), rhs = pidx - s * a.nrhs;
+  const int64_t vs = (int64_t)a.g.Vh * a.nrhs;
   const Site x = decode_site(a.g, s, a.parity);
   const int X0 = x.t[0] * a.g.B[0] + x.l[0], X1 = x.t[1] * a.g.B[1] + x.l[1], X2 = x.t[2] * a.g.B[2] + x.l[2];
   const R e1 = (X0 & 1) ? R(-1) : R(1);
@@ -91,15 +96,15 @@ __global__ void __launch_bounds__(256) stag_kernel(SArgs<S> a) {
   const R e3 = ((X0 + X1 + X2) & 1) ? R(-1) : R(1);
   const R cl = (R)a.c_long;
   cpx<R> acc[3] = {mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0)};
-  stag_dir<0, S, R, RECON>(a, x, s, R(1), cl, acc);
-  stag_dir<1, S, R, RECON>(a, x, s, e1, cl, acc);
-  stag_dir<2, S, R, RECON>(a, x, s, e2, cl, acc);
-  stag_dir<3, S, R, RECON>(a, x, s, e3, cl, acc);
+  stag_dir<0, S, R, RECON>(a, x, s, rhs, R(1), cl, acc);
+  stag_dir<1, S, R, RECON>(a, x, s, rhs, e1, cl, acc);
+  stag_dir<2, S, R, RECON>(a, x, s, rhs, e2, cl, acc);
+  stag_dir<3, S, R, RECON>(a, x, s, rhs, e3, cl, acc);
   const R coef = (R)a.coef;
   R out[6];
   if constexpr (XPAY) {
     cpx<R> xv[3];
-    load_cvec<S, R>(a.xin, a.g.Vh, s, xv);
+    load_cvec<S, R>(a.xin, vs, pidx, xv);
     const R xc = (R)a.xcoef;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -113,7 +118,7 @@ __global__ void __launch_bounds__(256) stag_kernel(SArgs<S> a) {
       out[2 * c + 1] = coef * acc[c].im;
     }
   }
-  store_spinor_reals<S, 6, R>(a.out, a.g.Vh, s, out);
+  store_spinor_reals<S, 6, R, true>(a.out, vs, pidx, out);
 }
 
 template <int P, int RECON>
@@ -131,7 +136,9 @@ static hipError_t launch_s2(const StagLaunch &l, hipStream_t st) {
   a.coef = l.coef;
   a.xcoef = l.xcoef;
   a.c_long = l.c_long;
-  const int bt = l.block_threads, nwg = (l.g.Vh + bt - 1) / bt;
+  a.nrhs = l.nrhs;
+  a.dN = make_fastdiv(l.nrhs);
+  const int bt = l.block_threads, nwg = (int)(((int64_t)l.g.Vh * l.nrhs + bt - 1) / bt);
   if (l.xin)
     hipLaunchKernelGGL((stag_kernel<S, R, RECON, true>), dim3(nwg), dim3(bt), 0, st, a);
   else

@@ -72,7 +72,7 @@ __device__ __forceinline__ void load_spinor(const S *__restrict__ f, int64_t vh,
     for (int c = 0; c < 3; ++c) v[sp][c] = mk<R>(r[6 * sp + 2 * c], r[6 * sp + 2 * c + 1]);
 }
 
-template <typename S, typename R>
+template <typename S, typename R, bool NT = false>
 __device__ __forceinline__ void store_spinor(S *__restrict__ f, int64_t vh, int s, const cpx<R> (&v)[4][3]) {
   R r[24];
 #pragma unroll
@@ -82,13 +82,16 @@ __device__ __forceinline__ void store_spinor(S *__restrict__ f, int64_t vh, int 
       r[6 * sp + 2 * c] = v[sp][c].re;
       r[6 * sp + 2 * c + 1] = v[sp][c].im;
     }
-  store_spinor_reals<S, 24, R>(f, vh, s, r);
+  store_spinor_reals<S, 24, R, NT>(f, vh, s, r);
 }
+
+// Round to the storage precision and back (what a store followed by a load returns).
+template <typename S, typename R> __device__ __forceinline__ R quantize(R v) { return to_real<R>(Store<S>::from(v)); }
 
 template <typename S, typename R, int RECON>
 __device__ __forceinline__ Link<R> load_link(const S *__restrict__ gauge, int64_t vh, int mu, int parity, int s) {
   R v[RECON];
-  load_site<S, RECON, R>(gauge + (int64_t)(2 * mu + parity) * vh * RECON, vh, s, v);
+  load_site<S, RECON, R, true>(gauge + (int64_t)(2 * mu + parity) * vh * RECON, vh, s, v);
   return unpack_link<RECON, R>(v);
 }
 
@@ -99,7 +102,7 @@ template <typename S, typename R>
 __device__ __forceinline__ void clover_mul(const S *__restrict__ clov, int64_t vh, int s, const cpx<R> (&in)[4][3],
                                            cpx<R> (&out)[4][3]) {
   R a[72];
-  load_site<S, 72, R>(clov, vh, s, a);
+  load_site<S, 72, R, true>(clov, vh, s, a);
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const R *A = a + 36 * b;
@@ -134,17 +137,20 @@ template <typename S> struct WArgs {
   double coef;
   int parity;
   int dagger;
+  int nrhs;    // right-hand sides interleaved per site (spinor index site * nrhs + rhs)
+  FastDiv dN;  // division by nrhs
 };
 
 template <int MU, typename S, typename R, int RECON>
-__device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int s, R sgn, cpx<R> (&acc)[4][3]) {
-  const int64_t vh = a.g.Vh;
+__device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int s, int rhs, R sgn,
+                                           cpx<R> (&acc)[4][3]) {
+  const int64_t vh = a.g.Vh, vs = vh * a.nrhs;
   // forward: (1 - sgn gamma_mu) U_mu(x) psi(x+mu)
   if (hop_kept<MU>(a.g, x, +1)) {
     int w;
     const int n = hop<MU>(a.g, x, +1, &w);
     cpx<R> psi[4][3], h[2][3], u[2][3];
-    load_spinor<S, R>(a.in, vh, n, psi);
+    load_spinor<S, R>(a.in, vs, (int64_t)n * a.nrhs + rhs, psi);
     project<MU, R>(psi, -sgn, h);
     const Link<R> U = load_link<S, R, RECON>(a.gauge, vh, MU, x.p, s);
     su3_mv(U, h[0], u[0]);
@@ -162,7 +168,7 @@ __device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int
     int w;
     const int n = hop<MU>(a.g, x, -1, &w);
     cpx<R> psi[4][3], h[2][3], u[2][3];
-    load_spinor<S, R>(a.in, vh, n, psi);
+    load_spinor<S, R>(a.in, vs, (int64_t)n * a.nrhs + rhs, psi);
     project<MU, R>(psi, sgn, h);
     const Link<R> U = load_link<S, R, RECON>(a.gauge, vh, MU, 1 - x.p, n);
     su3_adj_mv(U, h[0], u[0]);
@@ -178,113 +184,147 @@ __device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int
 }
 
 // Per-segment sums of 3 values for the Schwarz block solver. A segment is
-// min(sites per tile and parity, blockDim) consecutive sites (a power of two
-// that divides 256, or 256 when a tile spans several workgroups); segment j
-// covers sites [j*seg, (j+1)*seg) and its sums go to dst[3*j .. 3*j+2].
+// seg = min(sites per tile and parity, 64) consecutive sites (a power of two:
+// the tile's site count divides 64 or is a multiple of it), so a segment never
+// spans two waves and the layout of the partials does not depend on the
+// workgroup size. Segment j covers sites [j*seg, (j+1)*seg); its sums go to
+// dst[3*j .. 3*j+2].
 __device__ __forceinline__ void segment_reduce_store(double (&v)[3], int seg, int site, int vh, double *dst) {
-  __shared__ double lds[4][3];
-  const int width = seg < 64 ? seg : 64;
 #pragma unroll
   for (int k = 0; k < 3; ++k)
-    for (int off = width >> 1; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-  if (seg <= 64) {
-    if ((site % seg) == 0 && site < vh)
+    for (int off = seg >> 1; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  if ((site & (seg - 1)) == 0 && site < vh)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) dst[3 * (site / seg) + k] = v[k];
-    return;
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) lds[wave][k] = v[k];
-  __syncthreads();
-  const int wps = seg >> 6;  // waves per segment
-  if (lane == 0 && (wave % wps) == 0 && site < vh) {
-    for (int k = 0; k < 3; ++k) {
-      double t = 0;
-      for (int w = 0; w < wps; ++w) t += lds[wave + w][k];
-      dst[3 * (site / seg) + k] = t;
-    }
-  }
+    for (int k = 0; k < 3; ++k) dst[3 * (site / seg) + k] = v[k];
 }
 
+// One output (site s, right-hand side rhs) of the hopping term and its epilogue.
 template <typename S, typename R, int RECON, int MODE, bool REDUCE>
-__global__ void __launch_bounds__(256) wilson_kernel(WArgs<S> a) {
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int s = wg * blockDim.x + threadIdx.x;
-  double red[3] = {0, 0, 0};
-  if (s < a.g.Vh) {
-    const Site x = decode_site(a.g, s, a.parity);
-    const R sgn = a.dagger ? R(-1) : R(1);
-    cpx<R> acc[4][3];
+__device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, double (&red)[3]) {
+  const Site x = decode_site(a.g, s, a.parity);
+  const R sgn = a.dagger ? R(-1) : R(1);
+  cpx<R> acc[4][3];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[i][c] = mk<R>(0, 0);
+  wilson_dir<0, S, R, RECON>(a, x, s, rhs, sgn, acc);
+  wilson_dir<1, S, R, RECON>(a, x, s, rhs, sgn, acc);
+  wilson_dir<2, S, R, RECON>(a, x, s, rhs, sgn, acc);
+  wilson_dir<3, S, R, RECON>(a, x, s, rhs, sgn, acc);
+  const R coef = (R)a.coef;
+  const int64_t vh = a.g.Vh, vs = vh * a.nrhs, v = (int64_t)s * a.nrhs + rhs;
+  cpx<R> res[4][3];
+  if constexpr (MODE == W_HOP) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc[i][c] = mk<R>(0, 0);
-    wilson_dir<0, S, R, RECON>(a, x, s, sgn, acc);
-    wilson_dir<1, S, R, RECON>(a, x, s, sgn, acc);
-    wilson_dir<2, S, R, RECON>(a, x, s, sgn, acc);
-    wilson_dir<3, S, R, RECON>(a, x, s, sgn, acc);
-    const R coef = (R)a.coef;
-    const int64_t vh = a.g.Vh;
-    cpx<R> res[4][3];
-    if constexpr (MODE == W_HOP) {
+      for (int c = 0; c < 3; ++c) res[i][c] = coef * acc[i][c];
+  } else if constexpr (MODE == W_HOP_CLOV) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[i][c] = coef * acc[i][c];
+    clover_mul<S, R>(a.clov, vh, s, acc, res);
+  } else {
+    cpx<R> xv[4][3];
+    load_spinor<S, R>(a.xin, vs, v, xv);
+    if constexpr (MODE == W_XPAY_CLOV) {
+      clover_mul<S, R>(a.clov, vh, s, xv, res);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) res[i][c] = coef * acc[i][c];
-    } else if constexpr (MODE == W_HOP_CLOV) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc[i][c] = coef * acc[i][c];
-      clover_mul<S, R>(a.clov, vh, s, acc, res);
+        for (int c = 0; c < 3; ++c) res[i][c] = res[i][c] + coef * acc[i][c];
     } else {
-      cpx<R> xv[4][3];
-      load_spinor<S, R>(a.xin, vh, s, xv);
-      if constexpr (MODE == W_XPAY_CLOV) {
-        clover_mul<S, R>(a.clov, vh, s, xv, res);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) res[i][c] = res[i][c] + coef * acc[i][c];
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) res[i][c] = xv[i][c] + coef * acc[i][c];
-      }
-      if constexpr (REDUCE) {
-        // store precision first, so the inner products see the stored values
-        store_spinor<S, R>(a.out, vh, s, res);
-        load_spinor<S, R>(a.out, vh, s, res);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const double qr = res[i][c].re, qi = res[i][c].im, rr = xv[i][c].re, ri = xv[i][c].im;
-            red[0] += qr * rr + qi * ri;
-            red[1] += qr * ri - qi * rr;
-            red[2] += qr * qr + qi * qi;
-          }
-      }
+        for (int c = 0; c < 3; ++c) res[i][c] = xv[i][c] + coef * acc[i][c];
     }
-    if constexpr (!REDUCE) store_spinor<S, R>(a.out, vh, s, res);
+    if constexpr (REDUCE) {
+      // inner products of the values as stored
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double qr = quantize<S, R>(res[i][c].re), qi = quantize<S, R>(res[i][c].im);
+          const double rr = xv[i][c].re, ri = xv[i][c].im;
+          red[0] += qr * rr + qi * ri;
+          red[1] += qr * ri - qi * rr;
+          red[2] += qr * qr + qi * qi;
+        }
+    }
   }
-  if constexpr (REDUCE) {
-    const int seg = a.g.Vt2 < (int)blockDim.x ? a.g.Vt2 : (int)blockDim.x;
-    segment_reduce_store(red, seg, s, a.g.Vh, a.partials);
+  store_spinor<S, R, true>(a.out, vs, v, res);
+}
+
+// One thread per (site, rhs) pair, rhs fastest, so the lanes of one site share
+// its link and clover loads. Workgroup ids are remapped per XCD.
+template <typename S, typename R, int RECON, int MODE, bool REDUCE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) wilson_kernel(WArgs<S> a) {
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int pidx = wg * blockDim.x + threadIdx.x;
+  double red[3] = {0, 0, 0};
+  if (pidx < a.g.Vh * a.nrhs) {
+    const int s = (int)fdiv((uint32_t)pidx, a.dN);
+    wilson_point<S, R, RECON, MODE, REDUCE>(a, s, pidx - s * a.nrhs, red);
+  }
+  if constexpr (REDUCE) {  // single right-hand side only
+    segment_reduce_store(red, a.g.Vt2 < 64 ? a.g.Vt2 : 64, pidx, a.g.Vh, a.partials);
   }
 }
 
+// Persistent launch over several operators (uneven lattices, several
+// right-hand sides each): workgroups take work items of `chunk` (site, rhs)
+// pairs from a global counter until every item of every job is done.
+constexpr int kMaxBatchJobs = 8;
+template <typename S> struct BatchArgs {
+  WArgs<S> job[kMaxBatchJobs];
+  int begin[kMaxBatchJobs + 1];  // first work item of each job (prefix sums)
+  int njobs;
+  int chunk;
+  unsigned *counter;  // zero at launch
+};
+
+template <typename S, typename R, int RECON>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) wilson_batch_kernel(BatchArgs<S> b) {
+  __shared__ int item;
+  const int total = b.begin[b.njobs];
+  for (;;) {
+    if (threadIdx.x == 0) item = (int)atomicAdd(b.counter, 1u);
+    __syncthreads();
+    const int it = item;
+    __syncthreads();
+    if (it >= total) break;
+    int j = 0;
+    while (j + 1 < b.njobs && it >= b.begin[j + 1]) ++j;
+    const WArgs<S> &a = b.job[j];
+    const int first = (it - b.begin[j]) * b.chunk;
+    const int npairs = a.g.Vh * a.nrhs;
+    for (int q = threadIdx.x; q < b.chunk; q += blockDim.x) {
+      const int pidx = first + q;
+      if (pidx < npairs) {
+        double red[3];
+        const int s = (int)fdiv((uint32_t)pidx, a.dN);
+        wilson_point<S, R, RECON, W_HOP, false>(a, s, pidx - s * a.nrhs, red);
+      }
+    }
+  }
+}
+
+__global__ void zero_counter_kernel(unsigned *c) { c[threadIdx.x] = 0u; }
+
 template <typename S, typename R>
-__global__ void __launch_bounds__(256) clover_apply_kernel(Geom g, S *out, const S *in, const S *clov) {
-  const int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (s >= g.Vh) return;
+__global__ void __launch_bounds__(256) clover_apply_kernel(Geom g, S *out, const S *in, const S *clov, int nrhs,
+                                                           FastDiv dN) {
+  const int pidx = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (pidx >= g.Vh * nrhs) return;
+  const int s = (int)fdiv((uint32_t)pidx, dN);
+  const int64_t vs = (int64_t)g.Vh * nrhs;
   cpx<R> x[4][3], y[4][3];
-  load_spinor<S, R>(in, g.Vh, s, x);
+  load_spinor<S, R>(in, vs, pidx, x);
   clover_mul<S, R>(clov, g.Vh, s, x, y);
-  store_spinor<S, R>(out, g.Vh, s, y);
+  store_spinor<S, R, true>(out, vs, pidx, y);
 }
 
 // Schwarz MR step on every block at once, after q = Mhat_B r and the
@@ -344,7 +384,6 @@ hipError_t launch_mr_update(const Geom &g, int prec, void *x, void *r, const voi
   return hipErrorInvalidValue;
 }
 
-int wilson_nwg(const Geom &g, int bt) { return (g.Vh + bt - 1) / bt; }
 
 template <int P, int RECON, int MODE, bool RED>
 static hipError_t launch_w3(const WilsonLaunch &w, hipStream_t st) {
@@ -361,7 +400,9 @@ static hipError_t launch_w3(const WilsonLaunch &w, hipStream_t st) {
   a.coef = w.coef;
   a.parity = w.parity;
   a.dagger = w.dagger;
-  const int nwg = wilson_nwg(w.g, w.block_threads);
+  a.nrhs = w.nrhs;
+  a.dN = make_fastdiv(w.nrhs);
+  const int nwg = (int)(((int64_t)w.g.Vh * w.nrhs + w.block_threads - 1) / w.block_threads);
   hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED>), dim3(nwg), dim3(w.block_threads), 0, st, a);
   return hipGetLastError();
 }
@@ -391,8 +432,7 @@ static hipError_t launch_w1(const WilsonLaunch &w, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_wilson(const WilsonLaunch &w, hipStream_t st, int *nwg_out) {
-  if (nwg_out) *nwg_out = wilson_nwg(w.g, w.block_threads);
+hipError_t launch_wilson(const WilsonLaunch &w, hipStream_t st) {
   if (w.g.Vh == 0) return hipSuccess;
   switch (w.prec) {
     case LQCD_F64: return launch_w1<LQCD_F64>(w, st);
@@ -403,20 +443,79 @@ hipError_t launch_wilson(const WilsonLaunch &w, hipStream_t st, int *nwg_out) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_clover_apply(const Geom &g, int prec, void *out, const void *in, const void *clov, hipStream_t st) {
-  const int bt = 256, nwg = (g.Vh + bt - 1) / bt;
+hipError_t launch_clover_apply(const Geom &g, int prec, void *out, const void *in, const void *clov, int nrhs,
+                               hipStream_t st) {
+  const int bt = 256, nwg = (int)(((int64_t)g.Vh * nrhs + bt - 1) / bt);
   if (g.Vh == 0) return hipSuccess;
+  const FastDiv dN = make_fastdiv(nrhs);
   switch (prec) {
 #define CASE(P)                                                                                           \
   case P:                                                                                                 \
     hipLaunchKernelGGL((clover_apply_kernel<Prec<P>::S, Prec<P>::R>), dim3(nwg), dim3(bt), 0, st, g,      \
-                       (Prec<P>::S *)out, (const Prec<P>::S *)in, (const Prec<P>::S *)clov);              \
+                       (Prec<P>::S *)out, (const Prec<P>::S *)in, (const Prec<P>::S *)clov, nrhs, dN);    \
     return hipGetLastError();
     CASE(LQCD_F64)
     CASE(LQCD_F32)
     CASE(LQCD_F16)
     CASE(LQCD_BF16)
 #undef CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P, int RECON>
+static hipError_t launch_b2(const BatchJob *jobs, int njobs, int dagger, const BatchTune &t, unsigned *counter,
+                            hipStream_t st) {
+  using S = typename Prec<P>::S;
+  using R = typename Prec<P>::R;
+  BatchArgs<S> b;
+  b.njobs = njobs;
+  b.chunk = t.chunk;
+  b.counter = counter;
+  b.begin[0] = 0;
+  for (int j = 0; j < njobs; ++j) {
+    WArgs<S> &a = b.job[j];
+    a.g = jobs[j].g;
+    a.out = (S *)jobs[j].out;
+    a.in = (const S *)jobs[j].in;
+    a.gauge = (const S *)jobs[j].gauge;
+    a.clov = nullptr;
+    a.xin = nullptr;
+    a.partials = nullptr;
+    a.coef = 1.0;
+    a.parity = jobs[j].parity;
+    a.dagger = dagger;
+    a.nrhs = jobs[j].nrhs;
+    a.dN = make_fastdiv(jobs[j].nrhs);
+    const int64_t pairs = (int64_t)jobs[j].g.Vh * jobs[j].nrhs;
+    b.begin[j + 1] = b.begin[j] + (int)((pairs + t.chunk - 1) / t.chunk);
+  }
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+  hipLaunchKernelGGL((wilson_batch_kernel<S, R, RECON>), dim3(t.grid), dim3(t.block_threads), 0, st, b);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_b1(int recon, const BatchJob *jobs, int njobs, int dagger, const BatchTune &t, unsigned *c,
+                            hipStream_t st) {
+  switch (recon) {
+    case 18: return launch_b2<P, 18>(jobs, njobs, dagger, t, c, st);
+    case 12: return launch_b2<P, 12>(jobs, njobs, dagger, t, c, st);
+    case 8:
+      if constexpr (P == LQCD_F64 || P == LQCD_F32) return launch_b2<P, 8>(jobs, njobs, dagger, t, c, st);
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wilson_batch(int prec, int recon, const BatchJob *jobs, int njobs, int dagger, const BatchTune &t,
+                               unsigned *counter, hipStream_t st) {
+  if (njobs < 1 || njobs > kMaxBatchJobs) return hipErrorInvalidValue;
+  switch (prec) {
+    case LQCD_F64: return launch_b1<LQCD_F64>(recon, jobs, njobs, dagger, t, counter, st);
+    case LQCD_F32: return launch_b1<LQCD_F32>(recon, jobs, njobs, dagger, t, counter, st);
+    case LQCD_F16: return launch_b1<LQCD_F16>(recon, jobs, njobs, dagger, t, counter, st);
+    case LQCD_BF16: return launch_b1<LQCD_BF16>(recon, jobs, njobs, dagger, t, counter, st);
   }
   return hipErrorInvalidValue;
 }

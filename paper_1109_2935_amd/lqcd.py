@@ -65,6 +65,11 @@ class lqcd_gcr_params(ctypes.Structure):
                 ("schwarz", lqcd_schwarz_params), ("learned", ctypes.c_void_p)]
 
 
+class lqcd_dslash_job(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_void_p), ("out", ctypes.c_void_p), ("in_", ctypes.c_void_p),
+                ("out_parity", ctypes.c_int32), ("nrhs", ctypes.c_int32)]
+
+
 class lqcd_cg_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("delta_reliable", ctypes.c_double),
                 ("kind", ctypes.c_int32)]
@@ -83,8 +88,9 @@ _SIGNATURES = {
     "lqcd_gauge_import": [_P, _OPP, _P, _P, _I, _P],
     "lqcd_long_link_build": [_P, _OPP, _P, _P, _P],
     "lqcd_clover_build": [_P, _OPP, _P, _P, _P, _P],
-    "lqcd_spinor_import": [_P, _OPP, _P, _P, _I, _P],
-    "lqcd_spinor_export": [_P, _OPP, _P, _P, _I, _P],
+    "lqcd_spinor_import": [_P, _OPP, _P, _P, _I, _I, _P],
+    "lqcd_spinor_export": [_P, _OPP, _P, _P, _I, _I, _P],
+    "lqcd_dslash_batch": [_P, ctypes.POINTER(lqcd_dslash_job), _I, _I, _P],
     "lqcd_dslash": [_P, _OPP, _P, _P, _I, _I, ctypes.POINTER(ctypes.c_int32), _I, _P],
     "lqcd_clover_apply": [_P, _OPP, _P, _P, _I, _I, _I, _P],
     "lqcd_schur_apply": [_P, _OPP, _P, _P, _I, ctypes.POINTER(ctypes.c_int32), _I, _P],
@@ -173,12 +179,28 @@ def lqcd_clover_build(ctx, op, clover, clover_inv, natural_gauge, stream=None):
                                    _stream(stream)), ctx)
 
 
-def lqcd_spinor_import(ctx, op, packed, natural, parity, stream=None):
-    _check(lib().lqcd_spinor_import(ctx, ctypes.byref(op), _ptr(packed), _ptr(natural), parity, _stream(stream)), ctx)
+def lqcd_spinor_import(ctx, op, packed, natural, parity, nrhs=1, stream=None):
+    _check(lib().lqcd_spinor_import(ctx, ctypes.byref(op), _ptr(packed), _ptr(natural), parity, nrhs,
+                                    _stream(stream)), ctx)
 
 
-def lqcd_spinor_export(ctx, op, natural, packed, parity, stream=None):
-    _check(lib().lqcd_spinor_export(ctx, ctypes.byref(op), _ptr(natural), _ptr(packed), parity, _stream(stream)), ctx)
+def lqcd_spinor_export(ctx, op, natural, packed, parity, nrhs=1, stream=None):
+    _check(lib().lqcd_spinor_export(ctx, ctypes.byref(op), _ptr(natural), _ptr(packed), parity, nrhs,
+                                    _stream(stream)), ctx)
+
+
+def lqcd_dslash_batch(ctx, jobs, dagger=0, stream=None):
+    """jobs: sequence of (op, out, in, out_parity, nrhs)."""
+    arr = (lqcd_dslash_job * len(jobs))()
+    keep = []
+    for j, (op, out, inp, parity, nrhs) in enumerate(jobs):
+        keep.append(op)
+        arr[j].op = ctypes.addressof(op)
+        arr[j].out = _ptr(out).value
+        arr[j].in_ = _ptr(inp).value
+        arr[j].out_parity = parity
+        arr[j].nrhs = nrhs
+    _check(lib().lqcd_dslash_batch(ctx, arr, len(jobs), int(dagger), _stream(stream)), ctx)
 
 
 def lqcd_dslash(ctx, op, out, inp, out_parity, dagger=0, block=None, nrhs=1, stream=None):

@@ -57,20 +57,23 @@ class Operator:
         return self.bytes(L.LQCD_FIELD_SPINOR)
 
     # -- spinor exchange ----------------------------------------------------
-    def import_spinor(self, natural, parity, out=None):
+    def import_spinor(self, natural, parity, out=None, nrhs=1):
+        """Pack natural field(s); nrhs > 1: natural is [nrhs, t, z, y, x, ...] and the
+        right-hand sides are interleaved per site in the packed field."""
         nat = _device_complex(natural, self.device)
         if out is None:
-            out = self.spinor(full=(parity < 0), zero=False)
-        L.lqcd_spinor_import(self.ctx, self.op, out, nat, parity)
+            out = self.spinor(full=(parity < 0), zero=False, nrhs=nrhs)
+        L.lqcd_spinor_import(self.ctx, self.op, out, nat, parity, nrhs)
         return out
 
-    def export_spinor(self, packed, parity, natural=None):
+    def export_spinor(self, packed, parity, natural=None, nrhs=1):
         """Unpack to a natural complex128 device tensor (zeros on sites not covered)."""
         lx, ly, lz, lt = self.dims
         inner = (4, 3) if self.op.action == L.LQCD_WILSON_CLOVER else (3,)
+        lead = (nrhs,) if nrhs > 1 else ()
         if natural is None:
-            natural = torch.zeros((lt, lz, ly, lx) + inner, dtype=torch.complex128, device=self.device)
-        L.lqcd_spinor_export(self.ctx, self.op, natural, packed, parity)
+            natural = torch.zeros(lead + (lt, lz, ly, lx) + inner, dtype=torch.complex128, device=self.device)
+        L.lqcd_spinor_export(self.ctx, self.op, natural, packed, parity, nrhs)
         return natural
 
 

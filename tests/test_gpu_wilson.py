@@ -163,22 +163,69 @@ def test_dslash_deterministic(ctx):
     assert torch.equal(a, b)
 
 
-def test_multi_rhs_equals_single(ctx):
+@pytest.mark.parametrize("prec,recon", [(0, 18), (1, 12), (2, 12)])
+def test_multi_rhs_equals_single(ctx, prec, recon):
+    """nrhs right-hand sides interleaved per site: each equals its single-field
+    result bit for bit (same arithmetic per site), for dslash, clover and Schur."""
     dims = (4, 4, 6, 8)
     U, psi, _ = Fields.get(dims)
-    o = make_op(ctx, dims, 1, 12)
-    srcs = [on_parity(synth.gaussian_spinor(dims, 100 + r), oracle.parity_mask(dims, 1)) for r in range(3)]
-    sb = o.spinor_bytes
-    inp = o.spinor(nrhs=3)
-    for r, s in enumerate(srcs):
-        o.import_spinor(s, 1, out=inp[r * sb:(r + 1) * sb])
-    out = o.spinor(nrhs=3)
-    L.lqcd_dslash(ctx, o.op, out, inp, 0, nrhs=3)
-    for r in range(3):
+    o = make_op(ctx, dims, prec, recon)
+    nr = 3
+    srcs = np.stack([on_parity(synth.gaussian_spinor(dims, 100 + r), oracle.parity_mask(dims, 1)) for r in range(nr)])
+    inp = o.import_spinor(srcs, 1, nrhs=nr)
+    out = o.spinor(nrhs=nr)
+    L.lqcd_dslash(ctx, o.op, out, inp, 0, nrhs=nr)
+    multi = np_of(o.export_spinor(out, 0, nrhs=nr))
+    esrc = np.stack([on_parity(synth.gaussian_spinor(dims, 200 + r), oracle.parity_mask(dims, 0)) for r in range(nr)])
+    ein = o.import_spinor(esrc, 0, nrhs=nr)
+    eout, cout = o.spinor(nrhs=nr), o.spinor(nrhs=nr)
+    L.lqcd_schur_apply(ctx, o.op, eout, ein, nrhs=nr)
+    L.lqcd_clover_apply(ctx, o.op, cout, ein, 0, 1, nrhs=nr)
+    emulti = np_of(o.export_spinor(eout, 0, nrhs=nr))
+    cmulti = np_of(o.export_spinor(cout, 0, nrhs=nr))
+    for r in range(nr):
         single = o.spinor()
-        L.lqcd_dslash(ctx, o.op, single, inp[r * sb:(r + 1) * sb], 0)
-        torch.cuda.synchronize()
-        assert torch.equal(single, out[r * sb:(r + 1) * sb])
+        L.lqcd_dslash(ctx, o.op, single, o.import_spinor(srcs[r], 1), 0)
+        assert np.array_equal(np_of(o.export_spinor(single, 0)), multi[r])
+        ref = oracle.wilson_dslash(dims, U, srcs[r], out_parity=0)
+        assert rel(multi[r], ref) < TOL[prec]
+        es = o.spinor()
+        e1 = o.import_spinor(esrc[r], 0)
+        L.lqcd_schur_apply(ctx, o.op, es, e1)
+        assert np.array_equal(np_of(o.export_spinor(es, 0)), emulti[r])
+        L.lqcd_clover_apply(ctx, o.op, es, e1, 0, 1)
+        assert np.array_equal(np_of(o.export_spinor(es, 0)), cmulti[r])
+
+
+@pytest.mark.parametrize("prec,recon", [(0, 18), (1, 12), (2, 12), (3, 12)])
+def test_batched_persistent_uneven_lattices(ctx, prec, recon):
+    """One persistent launch over lattices of different size and rhs count
+    equals the per-operator dslash (bitwise) and the oracle (per-precision bound)."""
+    shapes = [((4, 4, 4, 8), 4), ((6, 6, 6, 12), 4), ((8, 8, 8, 8), 12), ((4, 6, 4, 6), 1)]
+    jobs, ref_single, refs = [], [], []
+    keep = []
+    for k, (dims, nr) in enumerate(shapes):
+        U = synth.gauge_field(dims, 0.25, 4001 + 10 * k)
+        o = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon)
+        srcs = np.stack([on_parity(synth.gaussian_spinor(dims, 4002 + 10 * k + r), oracle.parity_mask(dims, 1))
+                         for r in range(nr)])
+        inp = o.import_spinor(srcs, 1, nrhs=nr)
+        out = o.spinor(nrhs=nr)
+        single = o.spinor(nrhs=nr)
+        L.lqcd_dslash(ctx, o.op, single, inp, 0, nrhs=nr)
+        jobs.append((o.op, out, inp, 0, nr))
+        keep.append((o, out, inp, single, srcs, U, dims, nr))
+    L.lqcd_dslash_batch(ctx, jobs)
+    L.lqcd_dslash_batch(ctx, jobs)  # second call: tuned parameters
+    torch.cuda.synchronize()
+    for o, out, inp, single, srcs, U, dims, nr in keep:
+        assert torch.equal(out, single)
+        got = np_of(o.export_spinor(out, 0, nrhs=nr))
+        if nr == 1:
+            got = got[None]
+        for r in range(nr):
+            ref = oracle.wilson_dslash(dims, U, srcs[r], out_parity=0)
+            assert rel(got[r], ref) < TOL[prec]
 
 
 def test_invalid_arguments_write_nothing(ctx):
