@@ -115,6 +115,26 @@ typedef struct {
 
 typedef enum { LQCD_PRECOND_NONE = 0, LQCD_PRECOND_SCHWARZ = 1, LQCD_PRECOND_LEARNED = 2 } lqcd_precond_kind;
 
+/*
+ * Parallel-transport convolution network (the learned preconditioner; the
+ * paper has none: it only requires the outer solver to be flexible,
+ * Section III-B). Layer l maps channels[l] -> channels[l+1] colour-spinor
+ * fields: psi'_o(x) = sum_i sum_p W[o,i,p] (T_p psi_i)(x) over 9 paths
+ * (identity and the 8 one-hop parallel transports), W[o,i,p] a complex 4x4
+ * spin matrix; the network is linear, channels[0] = channels[nlayers] = 1.
+ * Master weights: FP32 complex (re, im), [layer][o][i][p][s][s'];
+ * lqcd_ptc_pack converts them to the BF16 matrix-core layout.
+ */
+typedef struct {
+  int32_t nlayers;      /* 1..8 */
+  int32_t channels[9];  /* 1..4 or multiples of 4 up to 16 */
+} lqcd_ptc_shape;
+
+typedef struct {
+  lqcd_ptc_shape shape;
+  const void *packed;   /* device, lqcd_ptc_sizes(...)->packed_bytes */
+} lqcd_ptc_net;
+
 typedef struct {
   int32_t block[4]; /* Dirichlet block; must equal the tile of op_precond */
   int32_t mr_steps; /* MR steps per block (the paper uses 10) */
@@ -126,8 +146,8 @@ typedef struct {
   double delta;      /* early restart when ||rhat|| / ||r0|| < delta */
   int32_t max_iter;  /* total Krylov steps */
   int32_t precond;   /* lqcd_precond_kind */
-  lqcd_schwarz_params schwarz;
-  const void *learned; /* LQCD_PRECOND_LEARNED: device pointer to packed network weights */
+  lqcd_schwarz_params schwarz; /* SCHWARZ; with LEARNED, the fallback (mr_steps 0: none) */
+  const lqcd_ptc_net *learned; /* LEARNED: the network (op_precond: FP32 instance for its transports) */
 } lqcd_gcr_params;
 
 typedef enum { LQCD_CG_CGNE_SCHUR = 0, LQCD_CG_STAG_NORMAL = 1 } lqcd_cg_kind;
@@ -137,6 +157,18 @@ typedef struct {
   int32_t max_iter;
   double delta_reliable; /* reliable update when ||r|| < delta * max ||r|| since the last one */
   int32_t kind;          /* lqcd_cg_kind */
+  /* Optional iterate recording (kind CGNE_SCHUR, op_sloppy NULL): after every
+   * record_every-th iteration, while fewer than record_max are stored, the
+   * even-site residual r_k = bhat - Mhat x_k goes to record_r[j] and the error
+   * e_k = record_xstar - x_k to record_e[j] (packed even spinors of op_hi, j
+   * consecutive fields); *record_count (host) receives the number stored.
+   * These are the residual -> error pairs the learned preconditioner trains on. */
+  void *record_r;
+  void *record_e;
+  const void *record_xstar;
+  int32_t record_every;
+  int32_t record_max;
+  int32_t *record_count;
 } lqcd_cg_params;
 
 /* ---------------------------------------------------------------------- */
@@ -195,6 +227,16 @@ lqcd_status lqcd_spinor_import(lqcd_context *ctx, const lqcd_operator *op, void 
                                const void *natural, int32_t parity, int32_t nrhs, lqcd_stream stream);
 lqcd_status lqcd_spinor_export(lqcd_context *ctx, const lqcd_operator *op, void *natural,
                                const void *packed, int32_t parity, int32_t nrhs, lqcd_stream stream);
+
+/*
+ * out = scale * in between two instances of the same action, geometry and
+ * tile (any precisions): parity 0 or 1 (single-parity fields) or -1 (full
+ * fields), nrhs interleaved right-hand sides. out and in may be the same
+ * buffer only if the precisions are equal.
+ */
+lqcd_status lqcd_spinor_convert(lqcd_context *ctx, const lqcd_operator *op_out, void *out,
+                                const lqcd_operator *op_in, const void *in, int32_t parity, int32_t nrhs,
+                                double scale, lqcd_stream stream);
 
 /* ---------------------------------------------------------------------- */
 /* operators                                                               */
@@ -293,6 +335,36 @@ lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op_hi,
 lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_hi,
                           const lqcd_operator *op_sloppy, const lqcd_cg_params *params, void *x,
                           const void *b, lqcd_solve_info *info, lqcd_stream stream);
+
+/* ---------------------------------------------------------------------- */
+/* learned preconditioner                                                  */
+
+/* Number of complex master weights and bytes of the packed weights. */
+lqcd_status lqcd_ptc_sizes(const lqcd_ptc_shape *shape, size_t *n_weights, size_t *packed_bytes);
+
+/* Convert FP32 master weights (device) to the packed BF16 layout (device). */
+lqcd_status lqcd_ptc_pack(lqcd_context *ctx, const lqcd_ptc_shape *shape, const void *weights, void *packed,
+                          lqcd_stream stream);
+
+/*
+ * out_even = N(in_even): the network applied to a residual on even sites
+ * (zero on odd sites), output read on even sites. op: FP32 Wilson-clover
+ * instance (links for the transports, its layout for the fields).
+ */
+lqcd_status lqcd_ptc_apply(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc_net *net, void *out_even,
+                           const void *in_even, lqcd_stream stream);
+
+/*
+ * Loss L = |N(r) - e|^2 / |e|^2 over even sites and its gradient
+ * grad = dL/d conj(W) (FP32 complex, master layout; dL = 2 Re <grad, dW>).
+ * r_even, e_even: FP32 packed even spinors of op. *loss (host) is set.
+ */
+lqcd_status lqcd_ptc_gradient(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc_net *net,
+                              const void *r_even, const void *e_even, void *grad, double *loss, lqcd_stream stream);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the FP32 master weights. */
+lqcd_status lqcd_ptc_adam(lqcd_context *ctx, const lqcd_ptc_shape *shape, void *weights, void *m, void *v,
+                          const void *grad, int32_t step, double lr, lqcd_stream stream);
 
 #ifdef __cplusplus
 }

@@ -449,6 +449,26 @@ lqcd_status lqcd_spinor_export(lqcd_context *ctx, const lqcd_operator *op, void 
   return spinor_io(ctx, op, (void *)packed, natural, parity, nrhs, stream, false);
 }
 
+lqcd_status lqcd_spinor_convert(lqcd_context *ctx, const lqcd_operator *op_out, void *out, const lqcd_operator *op_in,
+                                const void *in, int32_t parity, int32_t nrhs, double scale, lqcd_stream stream) {
+  OpInfo io, ii;
+  lqcd_status s = check_op(ctx, op_out, &io);
+  if (s) return s;
+  if ((s = check_op(ctx, op_in, &ii))) return s;
+  if (op_out->action != op_in->action) return set_error(ctx, LQCD_ERR_INVALID_ARG, "actions differ");
+  for (int m = 0; m < 4; ++m)
+    if (op_out->dims[m] != op_in->dims[m] || op_out->tile[m] != op_in->tile[m])
+      return set_error(ctx, LQCD_ERR_INVALID_ARG, "geometry or tile differs");
+  if (parity < -1 || parity > 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "parity must be 0, 1 or -1");
+  if ((s = check_nrhs(ctx, io, nrhs))) return s;
+  if (!aligned16(out) || !aligned16(in)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
+  if (out == in && op_out->prec != op_in->prec)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "in-place conversion needs equal precisions");
+  // the packed spinor layout does not depend on the precision: element-wise
+  const size_t n = io.vh * io.nsp / 2 * (parity < 0 ? 2 : 1) * (size_t)nrhs;
+  return hip_check(ctx, blas_convert(op_in->prec, in, op_out->prec, out, n, scale, (hipStream_t)stream), "convert");
+}
+
 static lqcd_status check_fields(lqcd_context *ctx, const lqcd_operator *op, bool need_clover) {
   if (!aligned16(op->gauge)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "operator gauge field missing or misaligned");
   if (op->action == LQCD_STAGGERED && !aligned16(op->long_links))

@@ -16,7 +16,8 @@ enum ScratchSlot {
   kSlotSchurTmp = 1,
   kSlotSchwarz = 2,   // 4 slots: r, q, t, partials
   kSlotBatchCounter = 6,
-  kSlotSolver = 8,    // solver work vectors start here
+  kSlotSolver = 8,    // solver work vectors start here (up to 80 slots)
+  kSlotPtc = 100,     // network activations and gradients
 };
 
 RedScratch red_scratch(lqcd_context *ctx);
@@ -39,6 +40,10 @@ lqcd_status check_nrhs(lqcd_context *ctx, const OpInfo &info, int nrhs);
 int tune_pick(lqcd_context *ctx, const std::string &key, const std::vector<int> &cands, int fallback, bool may_time,
               hipStream_t st, const std::function<hipError_t(int)> &launch);
 std::string geom_key(const Geom &g);
+
+// the learned preconditioner applied to an even residual (ptc_api.cpp)
+lqcd_status ptc_apply(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc_net *net, void *out_even,
+                      const void *in_even, hipStream_t st);
 lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schwarz_params *prm, void *out,
                           const void *in, int slot0, hipStream_t st);
 lqcd_status check_schwarz(lqcd_context *ctx, const OpInfo &info, const lqcd_schwarz_params *prm);

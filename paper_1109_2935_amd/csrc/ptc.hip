@@ -1,0 +1,574 @@
+// Gauge-equivariant parallel-transport convolution (PTC) network kernels.
+//
+// One layer maps Cin channels of colour-spinor fields to Cout channels:
+//   psi'_o(x) = sum_i sum_p W[o,i,p] (T_p psi_i)(x),
+// p = 0 identity, 1+2mu forward hop (U_mu(x) psi(x+mu)), 2+2mu backward hop
+// (U_mu(x-mu)^+ psi(x-mu)), W[o,i,p] a complex 4x4 spin matrix. The paper has
+// no such network; it is used as a learned preconditioner of flexible GCR
+// (Section III-B: the outer solver must be flexible).
+//
+// Activations are FP32, channel-interleaved per site (packed spinor index
+// site * C + channel). The channel mixing is a complex GEMM
+//   O[(o,s)][(c,x)] = sum_{(i,p,s')} W[(o,s)][(i,p,s')] Y[(i,p,s')][(c,x)],
+// Y = T_p psi_i, run on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation) in real form with interleaved real/imaginary rows:
+//   A[2m+r][2k+r'] = [[Wr, -Wi],[Wi, Wr]][r][r'],  B[2k+r'][n] = (Yr, Yi)[r'].
+// A workgroup owns a tile of 16 sites of one parity: it builds Y for a chunk of
+// input channels in LDS (parallel transport, converted to BF16), then each of
+// its 4 waves runs the MFMA tiles it owns; weights come pre-packed in the
+// per-lane A-operand order, so each A fragment is one coalesced 16-byte load.
+#include "lqcd_internal.h"
+#include "lqcd_ptc.h"
+
+namespace lqcd {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 16;      // sites per workgroup tile
+constexpr int kPtcThreads = 256;
+constexpr int kLdsPad = 8;     // bf16 padding per LDS row (bank spread)
+
+__device__ __forceinline__ f32x4_t mfma_bf16(const bf16x8_t &a, const bf16x8_t &b, const f32x4_t &c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// (T_p psi)(x) for one channel of a channel-interleaved FP32 field.
+// x: site index of parity `par`; the identity path reads parity par, the hops
+// read parity 1 - par. Boundary phases as in the Dirac operator.
+template <int RECON>
+__device__ __forceinline__ void transport_one(const PtcGeo &q, const float *__restrict__ act, int C, int ch, int p,
+                                              const Site &x, int s, cpx<float> (&out)[4][3]) {
+  const int par = x.p;
+  const int64_t vh = q.g.Vh, vs = vh * C;
+  const float *blk_same = act + (int64_t)par * vs * 24;
+  const float *blk_other = act + (int64_t)(1 - par) * vs * 24;
+  float r[24];
+  if (p == 0) {
+    load_spinor_reals<float, 24, float>(blk_same, vs, (int64_t)s * C + ch, r);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) out[sp][c] = mk<float>(r[6 * sp + 2 * c], r[6 * sp + 2 * c + 1]);
+    return;
+  }
+  const int mu = (p - 1) >> 1;
+  const bool fwd = ((p - 1) & 1) == 0;
+  int w = 0, n = 0;
+  switch (mu) {
+    case 0: n = hop<0>(q.g, x, fwd ? 1 : -1, &w); break;
+    case 1: n = hop<1>(q.g, x, fwd ? 1 : -1, &w); break;
+    case 2: n = hop<2>(q.g, x, fwd ? 1 : -1, &w); break;
+    default: n = hop<3>(q.g, x, fwd ? 1 : -1, &w); break;
+  }
+  load_spinor_reals<float, 24, float>(blk_other, vs, (int64_t)n * C + ch, r);
+  float lv[RECON];
+  if (fwd)
+    load_site<float, RECON, float>(q.gauge + (int64_t)(2 * mu + par) * vh * RECON, vh, s, lv);
+  else
+    load_site<float, RECON, float>(q.gauge + (int64_t)(2 * mu + 1 - par) * vh * RECON, vh, n, lv);
+  const Link<float> U = unpack_link<RECON, float>(lv);
+  const float ph = (mu == 3 && (w & 1) && q.g.bc_t < 0) ? -1.f : 1.f;
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp) {
+    cpx<float> v[3], u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = mk<float>(r[6 * sp + 2 * c], r[6 * sp + 2 * c + 1]);
+    if (fwd)
+      su3_mv(U, v, u);
+    else
+      su3_adj_mv(U, v, u);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[sp][c] = ph * u[c];
+  }
+}
+
+template <int RECON>
+__device__ __forceinline__ void transport_dispatch(const PtcGeo &q, const float *act, int C, int ch, int p,
+                                                   const Site &x, int s, cpx<float> (&out)[4][3]) {
+  transport_one<RECON>(q, act, C, ch, p, x, s, out);
+}
+
+__device__ __forceinline__ void transport_any(const PtcGeo &q, const float *act, int C, int ch, int p, const Site &x,
+                                              int s, cpx<float> (&out)[4][3]) {
+  if (q.recon == 12)
+    transport_dispatch<12>(q, act, C, ch, p, x, s, out);
+  else
+    transport_dispatch<18>(q, act, C, ch, p, x, s, out);
+}
+
+__device__ __forceinline__ bf16x8_t lds_frag(const __bf16 *row) {
+  return *reinterpret_cast<const bf16x8_t *>(row);
+}
+
+// ---------------------------------------------------------------------------
+// forward: out (Cout channels, parity par) = sum W (T psi_in)
+
+__global__ void __launch_bounds__(kPtcThreads) ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const float *in,
+                                                                   float *out, int par) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int krow = L.kchunk + kLdsPad;                  // bf16 per LDS row
+  __bf16 *Bt = reinterpret_cast<__bf16 *>(smem);        // [48][krow]
+  float *Ot = reinterpret_cast<float *>(smem + 48 * krow * 2);  // [16][Cout][24]
+  const int tile = blockIdx.x;
+  const int s0 = tile * kTile;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ntile_total = L.mtiles * 3;
+  f32x4_t acc[6];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) acc[t] = f32x4_t{0, 0, 0, 0};
+  for (int e = threadIdx.x; e < 48 * krow; e += kPtcThreads) Bt[e] = (__bf16)0.f;
+  for (int ck = 0; ck < L.nchunk; ++ck) {
+    __syncthreads();
+    const int nitem = kTile * L.chunk_ch * 9;
+    for (int it = threadIdx.x; it < nitem; it += kPtcThreads) {
+      const int sl = it % kTile, rem = it / kTile, p = rem % 9, il = rem / 9;
+      const int i = ck * L.chunk_ch + il;
+      const int s = s0 + sl;
+      cpx<float> y[4][3];
+      if (s < q.g.Vh && i < L.cin) {
+        const Site x = decode_site(q.g, s, par);
+        transport_any(q, in, L.cin, i, p, x, s, y);
+      } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) y[a][c] = mk<float>(0, 0);
+      }
+      const int k0 = 2 * ((il * 9 + p) * 4);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        bf16x8_t v;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+          v[2 * sp] = (__bf16)y[sp][c].re;
+          v[2 * sp + 1] = (__bf16)y[sp][c].im;
+        }
+        *reinterpret_cast<bf16x8_t *>(Bt + (c * kTile + sl) * krow + k0) = v;
+      }
+    }
+    __syncthreads();
+    const bf16x8_t *A = (const bf16x8_t *)L.A + (size_t)ck * L.mtiles * (L.kchunk / 32) * 64;
+    for (int ks = 0; ks < L.kchunk / 32; ++ks) {
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int tid = wave + 4 * t;
+        if (tid < ntile_total) {
+          const int mt = tid / 3, nt = tid % 3;
+          const bf16x8_t a = A[((size_t)mt * (L.kchunk / 32) + ks) * 64 + lane];
+          const bf16x8_t b = lds_frag(Bt + (nt * kTile + (lane & 15)) * krow + ks * 32 + 8 * (lane >> 4));
+          acc[t] = mfma_bf16(a, b, acc[t]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // accumulators -> LDS [site][o][spin*6 + colour*2 + re/im]
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    const int tid = wave + 4 * t;
+    if (tid < ntile_total) {
+      const int mt = tid / 3, nt = tid % 3;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = mt * 16 + 4 * (lane >> 4) + j;
+        const int mp = m >> 1, ri = m & 1;
+        const int o = mp >> 2, sp = mp & 3;
+        if (o < L.cout) Ot[((lane & 15) * L.cout + o) * 24 + sp * 6 + nt * 2 + ri] = acc[t][j];
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t vs = (int64_t)q.g.Vh * L.cout;
+  float *blk = out + (int64_t)par * vs * 24;
+  for (int it = threadIdx.x; it < kTile * L.cout; it += kPtcThreads) {
+    const int sl = it / L.cout, o = it % L.cout;
+    const int s = s0 + sl;
+    if (s < q.g.Vh) store_spinor_reals<float, 24, float>(blk, vs, (int64_t)s * L.cout + o, Ot + it * 24);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward, data: gY[(i,p)](x) = sum_o W[o,i,p]^+ delta_o(x), on parity par.
+// Output channel-interleaved with Cin*9 channels.
+
+__global__ void __launch_bounds__(kPtcThreads) ptc_bwd_data_kernel(PtcGeo q, PtcLayerDev L, const float *delta,
+                                                                    float *gy, int par) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int krow = L.kadj + kLdsPad;
+  __bf16 *Bt = reinterpret_cast<__bf16 *>(smem);  // [48][krow]: delta, k = 2*(o*4+s) + r
+  const int s0 = blockIdx.x * kTile;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < 48 * krow; e += kPtcThreads) Bt[e] = (__bf16)0.f;
+  __syncthreads();
+  const int64_t vsd = (int64_t)q.g.Vh * L.cout;
+  const float *dblk = delta + (int64_t)par * vsd * 24;
+  for (int it = threadIdx.x; it < kTile * L.cout; it += kPtcThreads) {
+    const int sl = it / L.cout, o = it % L.cout;
+    const int s = s0 + sl;
+    float r[24];
+    if (s < q.g.Vh)
+      load_spinor_reals<float, 24, float>(dblk, vsd, (int64_t)s * L.cout + o, r);
+    else
+      for (int k = 0; k < 24; ++k) r[k] = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bf16x8_t v;
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) {
+        v[2 * sp] = (__bf16)r[6 * sp + 2 * c];
+        v[2 * sp + 1] = (__bf16)r[6 * sp + 2 * c + 1];
+      }
+      *reinterpret_cast<bf16x8_t *>(Bt + (c * kTile + sl) * krow + 8 * o) = v;
+    }
+  }
+  __syncthreads();
+  const int C9 = L.cin * 9;
+  const int64_t vsg = (int64_t)q.g.Vh * C9;
+  float *gblk = gy + (int64_t)par * vsg * 24;
+  const int ks_n = L.kadj / 32;
+  const int ntile_total = L.madj_tiles * 3;
+  for (int tid = wave; tid < ntile_total; tid += 4) {
+    const int mt = tid / 3, nt = tid % 3;
+    f32x4_t acc = {0, 0, 0, 0};
+    for (int ks = 0; ks < ks_n; ++ks) {
+      const bf16x8_t a = ((const bf16x8_t *)L.Aadj)[((size_t)mt * ks_n + ks) * 64 + lane];
+      const bf16x8_t b = lds_frag(Bt + (nt * kTile + (lane & 15)) * krow + ks * 32 + 8 * (lane >> 4));
+      acc = mfma_bf16(a, b, acc);
+    }
+    const int sl = lane & 15, s = s0 + sl;
+    if (s >= q.g.Vh) continue;
+    // rows 4*(lane>>4)+j: two complex entries (k', k'+1) of the same (i,p) group
+#pragma unroll
+    for (int j = 0; j < 4; j += 2) {
+      const int m = mt * 16 + 4 * (lane >> 4) + j;
+      const int kp = m >> 1;  // (i*9 + p)*4 + s'
+      const int ip = kp >> 2, sp = kp & 3;
+      if (ip < C9) {
+        float *dst = gblk + ((int64_t)(sp * 6 + nt * 2) / 4 * vsg + (int64_t)s * C9 + ip) * 4 + ((sp * 6 + nt * 2) & 3);
+        dst[0] = acc[j];
+        dst[1] = acc[j + 1];
+      }
+    }
+  }
+}
+
+// gpsi_i(x) = sum_p (T_p^+ gY[i,p])(x); T_{+mu}^+ = T_{-mu}. One thread per
+// (site, channel) of parity par.
+__global__ void __launch_bounds__(256) ptc_adjoint_gather_kernel(PtcGeo q, int cin, const float *gy, float *gpsi,
+                                                                  int par) {
+  const int pidx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pidx >= q.g.Vh * cin) return;
+  const int s = pidx / cin, i = pidx - s * cin;
+  const Site x = decode_site(q.g, s, par);
+  const int C9 = cin * 9;
+  const int64_t vh = q.g.Vh, vsg = vh * C9;
+  const float *same = gy + (int64_t)par * vsg * 24;
+  const float *other = gy + (int64_t)(1 - par) * vsg * 24;
+  float acc[24], r[24];
+  load_spinor_reals<float, 24, float>(same, vsg, (int64_t)s * C9 + i * 9 + 0, acc);
+  for (int mu = 0; mu < 4; ++mu) {
+    for (int f = 0; f < 2; ++f) {
+      // f = 0: term T_{-mu} gY[i,+mu] = U_mu(x-mu)^+ g(x-mu); f = 1: T_{+mu} gY[i,-mu] = U_mu(x) g(x+mu)
+      const int p = f == 0 ? 1 + 2 * mu : 2 + 2 * mu;
+      int w = 0, n = 0;
+      const int step = f == 0 ? -1 : 1;
+      switch (mu) {
+        case 0: n = hop<0>(q.g, x, step, &w); break;
+        case 1: n = hop<1>(q.g, x, step, &w); break;
+        case 2: n = hop<2>(q.g, x, step, &w); break;
+        default: n = hop<3>(q.g, x, step, &w); break;
+      }
+      load_spinor_reals<float, 24, float>(other, vsg, (int64_t)n * C9 + i * 9 + p, r);
+      float lv[18];
+      Link<float> U;
+      if (q.recon == 12) {
+        if (f == 0)
+          load_site<float, 12, float>(q.gauge + (int64_t)(2 * mu + 1 - par) * vh * 12, vh, n, lv);
+        else
+          load_site<float, 12, float>(q.gauge + (int64_t)(2 * mu + par) * vh * 12, vh, s, lv);
+        U = unpack_link<12, float>(lv);
+      } else {
+        if (f == 0)
+          load_site<float, 18, float>(q.gauge + (int64_t)(2 * mu + 1 - par) * vh * 18, vh, n, lv);
+        else
+          load_site<float, 18, float>(q.gauge + (int64_t)(2 * mu + par) * vh * 18, vh, s, lv);
+        U = unpack_link<18, float>(lv);
+      }
+      const float ph = (mu == 3 && (w & 1) && q.g.bc_t < 0) ? -1.f : 1.f;
+      for (int sp = 0; sp < 4; ++sp) {
+        cpx<float> v[3], u[3];
+        for (int c = 0; c < 3; ++c) v[c] = mk<float>(r[6 * sp + 2 * c], r[6 * sp + 2 * c + 1]);
+        if (f == 0)
+          su3_adj_mv(U, v, u);
+        else
+          su3_mv(U, v, u);
+        for (int c = 0; c < 3; ++c) {
+          acc[6 * sp + 2 * c] += ph * u[c].re;
+          acc[6 * sp + 2 * c + 1] += ph * u[c].im;
+        }
+      }
+    }
+  }
+  store_spinor_reals<float, 24, float>(gpsi + (int64_t)par * vh * cin * 24, vh * cin, pidx, acc);
+}
+
+// ---------------------------------------------------------------------------
+// backward, weights: partial sums over site tiles of
+//   G[(m', r)][k'] = sum_{(n, r')} D[(m', r)][(n, r')] Y'[(n, r')][k'],
+//   D = [[dr, di],[di, -dr]],  Y' = (Yr, Yi),
+// i.e. G = (Re, Im) of sum_x delta (T psi)^+. A workgroup owns one input
+// channel chunk and a strided set of site tiles of parity par.
+
+__global__ void __launch_bounds__(kPtcThreads) ptc_bwd_weight_kernel(PtcGeo q, PtcLayerDev L, const float *in,
+                                                                      const float *delta, float *partial, int par,
+                                                                      int groups) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int KROW = 2 * 48 + kLdsPad;  // k = 2*n + r', n = colour*16 + site
+  __bf16 *At = reinterpret_cast<__bf16 *>(smem);             // [Mpad][KROW]  (delta embedding)
+  const int mrows = L.mw_tiles * 16;
+  __bf16 *Bt = At + mrows * KROW;                             // [chunk_ch*36][KROW]  (Y' transposed)
+  const int ck = blockIdx.y;
+  const int grp = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ncol = L.chunk_ch * 36;        // k' in this chunk
+  const int ntiles_n = (ncol + 15) / 16;
+  const int ntile_total = L.mw_tiles * ntiles_n;
+  f32x4_t acc[24];
+#pragma unroll
+  for (int t = 0; t < 24; ++t) acc[t] = f32x4_t{0, 0, 0, 0};
+  const int ntile_sites = (q.g.Vh + kTile - 1) / kTile;
+  const int64_t vsd = (int64_t)q.g.Vh * L.cout;
+  const float *dblk = delta + (int64_t)par * vsd * 24;
+  for (int tile = grp; tile < ntile_sites; tile += groups) {
+    const int s0 = tile * kTile;
+    __syncthreads();
+    for (int e = threadIdx.x; e < (mrows + ntiles_n * 16) * KROW; e += kPtcThreads) At[e] = (__bf16)0.f;
+    __syncthreads();
+    // delta -> A: row 2*(o*4+s)+r, col 2*(c*16+sl)+r'
+    for (int it = threadIdx.x; it < kTile * L.cout; it += kPtcThreads) {
+      const int sl = it / L.cout, o = it % L.cout;
+      const int s = s0 + sl;
+      if (s >= q.g.Vh) continue;
+      float r[24];
+      load_spinor_reals<float, 24, float>(dblk, vsd, (int64_t)s * L.cout + o, r);
+      for (int sp = 0; sp < 4; ++sp)
+        for (int c = 0; c < 3; ++c) {
+          const float dr = r[6 * sp + 2 * c], di = r[6 * sp + 2 * c + 1];
+          const int row = 2 * (o * 4 + sp), col = 2 * (c * kTile + sl);
+          At[row * KROW + col] = (__bf16)dr;
+          At[row * KROW + col + 1] = (__bf16)di;
+          At[(row + 1) * KROW + col] = (__bf16)di;
+          At[(row + 1) * KROW + col + 1] = (__bf16)(-dr);
+        }
+    }
+    // Y' -> B (stored [k'][k]): transported inputs of this channel chunk
+    const int nitem = kTile * L.chunk_ch * 9;
+    for (int it = threadIdx.x; it < nitem; it += kPtcThreads) {
+      const int sl = it % kTile, rem = it / kTile, p = rem % 9, il = rem / 9;
+      const int i = ck * L.chunk_ch + il;
+      const int s = s0 + sl;
+      if (s >= q.g.Vh || i >= L.cin) continue;
+      const Site x = decode_site(q.g, s, par);
+      cpx<float> y[4][3];
+      transport_any(q, in, L.cin, i, p, x, s, y);
+      for (int sp = 0; sp < 4; ++sp) {
+        const int kp = (il * 9 + p) * 4 + sp;
+        for (int c = 0; c < 3; ++c) {
+          const int col = 2 * (c * kTile + sl);
+          Bt[kp * KROW + col] = (__bf16)y[sp][c].re;
+          Bt[kp * KROW + col + 1] = (__bf16)y[sp][c].im;
+        }
+      }
+    }
+    __syncthreads();
+    for (int ks = 0; ks < 3; ++ks) {
+#pragma unroll
+      for (int t = 0; t < 24; ++t) {
+        const int tid = wave + 4 * t;
+        if (tid < ntile_total) {
+          const int mt = tid / ntiles_n, nt = tid % ntiles_n;
+          const bf16x8_t a = lds_frag(At + (mt * 16 + (lane & 15)) * KROW + ks * 32 + 8 * (lane >> 4));
+          const bf16x8_t b = lds_frag(Bt + (nt * 16 + (lane & 15)) * KROW + ks * 32 + 8 * (lane >> 4));
+          acc[t] = mfma_bf16(a, b, acc[t]);
+        }
+      }
+    }
+  }
+  // partial[ck][grp][row][col]
+  float *dst = partial + ((size_t)ck * groups + grp) * (size_t)mrows * (ntiles_n * 16);
+#pragma unroll
+  for (int t = 0; t < 24; ++t) {
+    const int tid = wave + 4 * t;
+    if (tid < ntile_total) {
+      const int mt = tid / ntiles_n, nt = tid % ntiles_n;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = mt * 16 + 4 * (lane >> 4) + j, col = nt * 16 + (lane & 15);
+        dst[(size_t)row * (ntiles_n * 16) + col] = acc[t][j];
+      }
+    }
+  }
+}
+
+// gW[o][i][p][s][s'] (complex, FP32) += sum over groups of the partials, in a
+// fixed order (deterministic).
+__global__ void ptc_weight_reduce_kernel(PtcLayerDev L, const float *partial, int groups, float *gw, int accumulate) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // complex entry index
+  const int total = L.cout * L.cin * 9 * 16;
+  if (idx >= total) return;
+  const int sp2 = idx % 4, sp = (idx / 4) % 4, p = (idx / 16) % 9, i = (idx / 144) % L.cin, o = idx / (144 * L.cin);
+  const int ck = i / L.chunk_ch, il = i - ck * L.chunk_ch;
+  const int ncol = L.chunk_ch * 36, ldc = ((ncol + 15) / 16) * 16;
+  const int mrows = L.mw_tiles * 16;
+  const int col = (il * 9 + p) * 4 + sp2;
+  const int row = 2 * (o * 4 + sp);
+  double re = 0, im = 0;
+  for (int g = 0; g < groups; ++g) {
+    const float *base = partial + ((size_t)ck * groups + g) * (size_t)mrows * ldc;
+    re += base[(size_t)row * ldc + col];
+    im += base[(size_t)(row + 1) * ldc + col];
+  }
+  if (accumulate) {
+    gw[2 * idx] += (float)re;
+    gw[2 * idx + 1] += (float)im;
+  } else {
+    gw[2 * idx] = (float)re;
+    gw[2 * idx + 1] = (float)im;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// weight packing: master FP32 complex W[o][i][p][s][s'] -> MFMA A fragments.
+
+__device__ __forceinline__ float wval(const float *W, int cin, int o, int i, int p, int s, int s2, int im) {
+  return W[2 * ((((o * cin + i) * 9 + p) * 4 + s) * 4 + s2) + im];
+}
+
+// forward A: row m = 2*(o*4+s) + r, col k (within chunk) = 2*((il*9+p)*4+s') + r'
+__global__ void ptc_pack_forward_kernel(PtcLayerDev L, const float *W, bf16x8_t *A) {
+  const int ks_n = L.kchunk / 32;
+  const int total = L.nchunk * L.mtiles * ks_n * 64;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int lane = idx % 64, ks = (idx / 64) % ks_n, mt = (idx / (64 * ks_n)) % L.mtiles;
+  const int ck = idx / (64 * ks_n * L.mtiles);
+  const int m = mt * 16 + (lane & 15);
+  const int mp = m >> 1, r = m & 1, o = mp >> 2, s = mp & 3;
+  bf16x8_t v;
+  for (int j = 0; j < 8; ++j) {
+    const int k = ks * 32 + 8 * (lane >> 4) + j;
+    const int kp = k >> 1, r2 = k & 1;
+    const int il = kp / 36, p = (kp / 4) % 9, s2 = kp & 3;
+    const int i = ck * L.chunk_ch + il;
+    float val = 0.f;
+    if (o < L.cout && il < L.chunk_ch && i < L.cin && kp < L.chunk_ch * 36) {
+      const float wr = wval(W, L.cin, o, i, p, s, s2, 0), wi = wval(W, L.cin, o, i, p, s, s2, 1);
+      val = (r == 0) ? (r2 == 0 ? wr : -wi) : (r2 == 0 ? wi : wr);
+    }
+    v[j] = (__bf16)val;
+  }
+  A[idx] = v;
+}
+
+// adjoint A: row m = 2*((i*9+p)*4+s') + r, col k = 2*(o*4+s) + r'; conj(W)^T embedded.
+__global__ void ptc_pack_adjoint_kernel(PtcLayerDev L, const float *W, bf16x8_t *A) {
+  const int ks_n = L.kadj / 32;
+  const int total = L.madj_tiles * ks_n * 64;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int lane = idx % 64, ks = (idx / 64) % ks_n, mt = idx / (64 * ks_n);
+  const int m = mt * 16 + (lane & 15);
+  const int kp = m >> 1, r = m & 1;
+  const int i = kp / 36, p = (kp / 4) % 9, s2 = kp & 3;
+  bf16x8_t v;
+  for (int j = 0; j < 8; ++j) {
+    const int k = ks * 32 + 8 * (lane >> 4) + j;
+    const int mp = k >> 1, r2 = k & 1, o = mp >> 2, s = mp & 3;
+    float val = 0.f;
+    if (i < L.cin && o < L.cout) {
+      const float wr = wval(W, L.cin, o, i, p, s, s2, 0), wi = wval(W, L.cin, o, i, p, s, s2, 1);
+      // conj(W)^T: [[Wr, Wi], [-Wi, Wr]]
+      val = (r == 0) ? (r2 == 0 ? wr : wi) : (r2 == 0 ? -wi : wr);
+    }
+    v[j] = (__bf16)val;
+  }
+  A[idx] = v;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+
+size_t ptc_forward_lds(const PtcLayerDev &L) { return 48 * (L.kchunk + kLdsPad) * 2 + kTile * L.cout * 24 * 4; }
+size_t ptc_bwd_data_lds(const PtcLayerDev &L) { return 48 * (L.kadj + kLdsPad) * 2; }
+size_t ptc_bwd_weight_lds(const PtcLayerDev &L) {
+  const int ncol = L.chunk_ch * 36, ntn = (ncol + 15) / 16;
+  return (size_t)(L.mw_tiles * 16 + ntn * 16) * (2 * 48 + kLdsPad) * 2;
+}
+
+hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const float *in, float *out, int par,
+                              hipStream_t st) {
+  const int nt = (q.g.Vh + kTile - 1) / kTile;
+  hipLaunchKernelGGL(ptc_forward_kernel, dim3(nt), dim3(kPtcThreads), ptc_forward_lds(L), st, q, L, in, out, par);
+  return hipGetLastError();
+}
+
+hipError_t launch_ptc_bwd_data(const PtcGeo &q, const PtcLayerDev &L, const float *delta, float *gy, int par,
+                               hipStream_t st) {
+  const int nt = (q.g.Vh + kTile - 1) / kTile;
+  hipLaunchKernelGGL(ptc_bwd_data_kernel, dim3(nt), dim3(kPtcThreads), ptc_bwd_data_lds(L), st, q, L, delta, gy, par);
+  return hipGetLastError();
+}
+
+hipError_t launch_ptc_adjoint_gather(const PtcGeo &q, int cin, const float *gy, float *gpsi, int par,
+                                     hipStream_t st) {
+  const int n = q.g.Vh * cin, bt = 256;
+  hipLaunchKernelGGL(ptc_adjoint_gather_kernel, dim3((n + bt - 1) / bt), dim3(bt), 0, st, q, cin, gy, gpsi, par);
+  return hipGetLastError();
+}
+
+hipError_t launch_ptc_bwd_weight(const PtcGeo &q, const PtcLayerDev &L, const float *in, const float *delta,
+                                 float *partial, int par, int groups, hipStream_t st) {
+  hipLaunchKernelGGL(ptc_bwd_weight_kernel, dim3(groups, L.nchunk), dim3(kPtcThreads), ptc_bwd_weight_lds(L), st, q,
+                     L, in, delta, partial, par, groups);
+  return hipGetLastError();
+}
+
+hipError_t launch_ptc_weight_reduce(const PtcLayerDev &L, const float *partial, int groups, float *gw, int accumulate,
+                                    hipStream_t st) {
+  const int total = L.cout * L.cin * 9 * 16, bt = 256;
+  hipLaunchKernelGGL(ptc_weight_reduce_kernel, dim3((total + bt - 1) / bt), dim3(bt), 0, st, L, partial, groups, gw,
+                     accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_ptc_pack(const PtcLayerDev &L, const float *W, hipStream_t st) {
+  const int bt = 256;
+  const int nf = L.nchunk * L.mtiles * (L.kchunk / 32) * 64;
+  hipLaunchKernelGGL(ptc_pack_forward_kernel, dim3((nf + bt - 1) / bt), dim3(bt), 0, st, L, W, (bf16x8_t *)L.A);
+  const int na = L.madj_tiles * (L.kadj / 32) * 64;
+  hipLaunchKernelGGL(ptc_pack_adjoint_kernel, dim3((na + bt - 1) / bt), dim3(bt), 0, st, L, W, (bf16x8_t *)L.Aadj);
+  return hipGetLastError();
+}
+
+__global__ void adam_kernel(float *w, float *m, float *v, const float *g, size_t n, float lr, float b1, float b2,
+                            float eps, float bc1, float bc2, float gscale) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = gscale * g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+hipError_t launch_adam(float *w, float *m, float *v, const float *g, size_t n, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2, float gscale, hipStream_t st) {
+  const int bt = 256;
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + bt - 1) / bt)), dim3(bt), 0, st, w, m, v, g, n, lr, b1, b2, eps,
+                     bc1, bc2, gscale);
+  return hipGetLastError();
+}
+
+}  // namespace lqcd

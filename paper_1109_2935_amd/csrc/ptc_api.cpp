@@ -1,0 +1,238 @@
+// C ABI of the learned preconditioner: weight packing, inference, gradients
+// and the Adam update, as host sequences of the kernels in ptc.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "lqcd_internal.h"
+#include "lqcd_ops.h"
+#include "lqcd_ptc.h"
+
+using namespace lqcd;
+
+#define TRY(expr)                 \
+  do {                            \
+    lqcd_status _s = (expr);      \
+    if (_s != LQCD_OK) return _s; \
+  } while (0)
+
+namespace lqcd {
+
+struct PtcPlan {
+  int nl;
+  std::vector<PtcLayerDev> layers;
+  std::vector<size_t> woff;   // complex-weight offset of each layer in the master array
+  std::vector<size_t> poff;   // byte offset of each layer's packed fragments
+  size_t nweights = 0, packed_bytes = 0;
+};
+
+lqcd_status ptc_plan(lqcd_context *ctx, const lqcd_ptc_shape *sh, PtcPlan *plan) {
+  if (!sh) return set_error(ctx, LQCD_ERR_INVALID_ARG, "network shape is NULL");
+  if (sh->nlayers < 1 || sh->nlayers > kPtcMaxLayers)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "network needs 1 to 8 layers");
+  if (sh->channels[0] != 1 || sh->channels[sh->nlayers] != 1)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "network input and output have one channel");
+  plan->nl = sh->nlayers;
+  plan->layers.clear();
+  plan->woff.clear();
+  plan->poff.clear();
+  size_t w = 0, p = 0;
+  for (int l = 0; l < sh->nlayers; ++l) {
+    const int cin = sh->channels[l], cout = sh->channels[l + 1];
+    if (cin < 1 || cout < 1 || cin > 16 || cout > 16 || (cin > 4 && cin % 4))
+      return set_error(ctx, LQCD_ERR_UNSUPPORTED, "channels must be 1..4 or a multiple of 4 up to 16");
+    PtcLayerDev L = ptc_layer_desc(cin, cout);
+    plan->woff.push_back(w);
+    plan->poff.push_back(p);
+    w += (size_t)cout * cin * 9 * 16;
+    p += ptc_fwd_frag_bytes(L) + ptc_adj_frag_bytes(L);
+    plan->layers.push_back(L);
+  }
+  plan->nweights = w;
+  plan->packed_bytes = p;
+  return LQCD_OK;
+}
+
+static void bind_packed(PtcPlan &plan, const void *packed) {
+  for (int l = 0; l < plan.nl; ++l) {
+    PtcLayerDev &L = plan.layers[l];
+    L.A = (const char *)packed + plan.poff[l];
+    L.Aadj = (const char *)packed + plan.poff[l] + ptc_fwd_frag_bytes(L);
+  }
+}
+
+static lqcd_status ptc_geo(lqcd_context *ctx, const lqcd_operator *op, OpInfo *info, PtcGeo *q) {
+  TRY(check_op(ctx, op, info));
+  if (op->action != LQCD_WILSON_CLOVER || op->prec != LQCD_F32 || (op->recon != 18 && op->recon != 12))
+    return set_error(ctx, LQCD_ERR_UNSUPPORTED, "the network transports with an FP32 Wilson instance (recon 18/12)");
+  if (!op->gauge || ((uintptr_t)op->gauge & 15)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "operator gauge missing");
+  q->g = info->g;
+  q->gauge = (const float *)op->gauge;
+  q->recon = op->recon;
+  return LQCD_OK;
+}
+
+// Forward pass; activation k (input of layer k) is kept in acts[k] (full
+// lattice, channel-interleaved FP32); the output y (even sites) in acts[nl].
+static lqcd_status ptc_forward_all(lqcd_context *ctx, const PtcPlan &plan, const PtcGeo &q, const OpInfo &info,
+                                   const void *in_even, std::vector<float *> &acts, hipStream_t st) {
+  const size_t vh = info.vh;
+  // layer-0 input: r on even sites, zero on odd sites
+  TRY(hip_check(ctx, hipMemcpyAsync(acts[0], in_even, vh * 24 * sizeof(float), hipMemcpyDeviceToDevice, st), "copy"));
+  TRY(hip_check(ctx, hipMemsetAsync(acts[0] + vh * 24, 0, vh * 24 * sizeof(float), st), "memset"));
+  for (int l = 0; l < plan.nl; ++l) {
+    const bool last = l == plan.nl - 1;
+    for (int par = 0; par < (last ? 1 : 2); ++par)
+      TRY(hip_check(ctx, launch_ptc_forward(q, plan.layers[l], acts[l], acts[l + 1], par, st), "ptc forward"));
+  }
+  return LQCD_OK;
+}
+
+// Scratch: activation buffers start at slot `slot0`.
+static lqcd_status ptc_buffers(lqcd_context *ctx, const PtcPlan &plan, const OpInfo &info, int slot0,
+                               std::vector<float *> &acts) {
+  acts.assign(plan.nl + 1, nullptr);
+  for (int l = 0; l <= plan.nl; ++l) {
+    const int c = l == 0 ? 1 : plan.layers[l - 1].cout;
+    void *p;
+    TRY(scratch(ctx, slot0 + l, 2 * info.vh * 24 * c * sizeof(float), &p));
+    acts[l] = (float *)p;
+  }
+  return LQCD_OK;
+}
+
+lqcd_status ptc_apply(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc_net *net, void *out_even,
+                      const void *in_even, hipStream_t st) {
+  if (!net) return set_error(ctx, LQCD_ERR_INVALID_ARG, "network is NULL");
+  PtcPlan plan;
+  TRY(ptc_plan(ctx, &net->shape, &plan));
+  if (!net->packed || ((uintptr_t)net->packed & 15)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "packed weights");
+  bind_packed(plan, net->packed);
+  OpInfo info;
+  PtcGeo q;
+  TRY(ptc_geo(ctx, op, &info, &q));
+  std::vector<float *> acts;
+  TRY(ptc_buffers(ctx, plan, info, kSlotPtc, acts));
+  TRY(ptc_forward_all(ctx, plan, q, info, in_even, acts, st));
+  return hip_check(ctx, hipMemcpyAsync(out_even, acts[plan.nl], info.vh * 24 * sizeof(float), hipMemcpyDeviceToDevice, st),
+                   "copy");
+}
+
+}  // namespace lqcd
+
+extern "C" {
+
+lqcd_status lqcd_ptc_sizes(const lqcd_ptc_shape *shape, size_t *n_weights, size_t *packed_bytes) {
+  PtcPlan plan;
+  lqcd_status s = ptc_plan(nullptr, shape, &plan);
+  if (s) return s;
+  if (n_weights) *n_weights = plan.nweights;
+  if (packed_bytes) *packed_bytes = plan.packed_bytes;
+  return LQCD_OK;
+}
+
+lqcd_status lqcd_ptc_pack(lqcd_context *ctx, const lqcd_ptc_shape *shape, const void *weights, void *packed,
+                          lqcd_stream stream) {
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  PtcPlan plan;
+  TRY(ptc_plan(ctx, shape, &plan));
+  if (!weights || !packed || ((uintptr_t)packed & 15)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad pointers");
+  bind_packed(plan, packed);
+  for (int l = 0; l < plan.nl; ++l)
+    TRY(hip_check(ctx, launch_ptc_pack(plan.layers[l], (const float *)weights + 2 * plan.woff[l], (hipStream_t)stream),
+                  "ptc pack"));
+  return LQCD_OK;
+}
+
+lqcd_status lqcd_ptc_apply(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc_net *net, void *out_even,
+                           const void *in_even, lqcd_stream stream) {
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  if (!out_even || !in_even || ((uintptr_t)out_even & 15) || ((uintptr_t)in_even & 15))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
+  return ptc_apply(ctx, op, net, out_even, in_even, (hipStream_t)stream);
+}
+
+lqcd_status lqcd_ptc_gradient(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc_net *net,
+                              const void *r_even, const void *e_even, void *grad, double *loss, lqcd_stream stream) {
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  if (!net || !r_even || !e_even || !grad) return set_error(ctx, LQCD_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  PtcPlan plan;
+  TRY(ptc_plan(ctx, &net->shape, &plan));
+  bind_packed(plan, net->packed);
+  OpInfo info;
+  PtcGeo q;
+  TRY(ptc_geo(ctx, op, &info, &q));
+  const size_t vh = info.vh;
+  std::vector<float *> acts;
+  TRY(ptc_buffers(ctx, plan, info, kSlotPtc, acts));
+  TRY(ptc_forward_all(ctx, plan, q, info, r_even, acts, st));
+  // loss = |y - e|^2 / |e|^2 on even sites; delta = (y - e) / |e|^2
+  int maxc = 1, maxc9 = 9;
+  for (auto &L : plan.layers) {
+    maxc = std::max(maxc, std::max(L.cin, L.cout));
+    maxc9 = std::max(maxc9, 9 * L.cin);
+  }
+  void *d0, *d1, *gy, *part;
+  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 1, 2 * vh * 24 * maxc * sizeof(float), &d0));
+  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 2, 2 * vh * 24 * maxc * sizeof(float), &d1));
+  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 3, 2 * vh * 24 * (size_t)maxc9 * sizeof(float), &gy));
+  const int groups = 128;
+  size_t pbytes = 0;
+  for (auto &L : plan.layers) {
+    const size_t ldc = (size_t)((L.chunk_ch * 36 + 15) / 16) * 16;
+    pbytes = std::max(pbytes, (size_t)L.nchunk * groups * L.mw_tiles * 16 * ldc * sizeof(float));
+  }
+  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 4, pbytes, &part));
+  RedScratch red = red_scratch(ctx);
+  const size_t n = vh * 12;  // complex entries of one even field
+  double en2 = 0, dn2 = 0;
+  TRY(hip_check(ctx, blas_norm2(LQCD_F32, e_even, n, red, st), "norm"));
+  TRY(read_result(ctx, st, 1, &en2));
+  if (!(en2 > 0)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "target has zero norm");
+  float *delta = (float *)d0;
+  TRY(hip_check(ctx, hipMemsetAsync(delta, 0, 2 * vh * 24 * sizeof(float), st), "memset"));
+  TRY(hip_check(ctx, hipMemcpyAsync(delta, acts[plan.nl], vh * 24 * sizeof(float), hipMemcpyDeviceToDevice, st), "copy"));
+  TRY(hip_check(ctx, blas_axpby(LQCD_F32, e_even, LQCD_F32, delta, n, -1.0, 0.0, 1.0, 0.0, &red, st), "axpby"));
+  TRY(read_result(ctx, st, 1, &dn2));
+  TRY(hip_check(ctx, blas_convert(LQCD_F32, delta, LQCD_F32, delta, n, 1.0 / en2, st), "scale"));
+  if (loss) *loss = dn2 / en2;
+  // backward through the layers
+  float *dcur = (float *)d0, *dnext = (float *)d1;
+  for (int l = plan.nl - 1; l >= 0; --l) {
+    const PtcLayerDev &L = plan.layers[l];
+    const bool last = l == plan.nl - 1;
+    float *gw = (float *)grad + 2 * plan.woff[l];
+    for (int par = 0; par < (last ? 1 : 2); ++par) {
+      TRY(hip_check(ctx, launch_ptc_bwd_weight(q, L, acts[l], dcur, (float *)part, par, groups, st), "ptc dW"));
+      TRY(hip_check(ctx, launch_ptc_weight_reduce(L, (const float *)part, groups, gw, par, st), "ptc dW reduce"));
+    }
+    if (l == 0) break;
+    TRY(hip_check(ctx, hipMemsetAsync(gy, 0, 2 * vh * 24 * (size_t)(9 * L.cin) * sizeof(float), st), "memset"));
+    for (int par = 0; par < (last ? 1 : 2); ++par)
+      TRY(hip_check(ctx, launch_ptc_bwd_data(q, L, dcur, (float *)gy, par, st), "ptc dY"));
+    for (int par = 0; par < 2; ++par)
+      TRY(hip_check(ctx, launch_ptc_adjoint_gather(q, L.cin, (const float *)gy, dnext, par, st), "ptc adjoint"));
+    std::swap(dcur, dnext);
+  }
+  return LQCD_OK;
+}
+
+lqcd_status lqcd_ptc_adam(lqcd_context *ctx, const lqcd_ptc_shape *shape, void *weights, void *m, void *v,
+                          const void *grad, int32_t step, double lr, lqcd_stream stream) {
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  PtcPlan plan;
+  TRY(ptc_plan(ctx, shape, &plan));
+  if (!weights || !m || !v || !grad || step < 1 || !(lr > 0))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "need weights, moments, gradient, step >= 1, lr > 0");
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float bc1 = 1.f - std::pow(b1, (float)step), bc2 = 1.f - std::pow(b2, (float)step);
+  // dL/d(Re W, Im W) = 2 (Re G, Im G) for G = dL/d conj(W)
+  return hip_check(ctx, launch_adam((float *)weights, (float *)m, (float *)v, (const float *)grad, 2 * plan.nweights,
+                                    (float)lr, b1, b2, 1e-8f, bc1, bc2, 2.f, (hipStream_t)stream),
+                   "adam");
+}
+
+}  // extern "C"

@@ -122,7 +122,14 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
       return set_error(ctx, LQCD_ERR_INVALID_ARG, "op_precond describes another system");
     TRY(check_schwarz(ctx, pc, &prm->schwarz));
   } else if (pk == LQCD_PRECOND_LEARNED) {
-    return set_error(ctx, LQCD_ERR_UNSUPPORTED, "learned preconditioner is not available in this build");
+    TRY(check_op(ctx, op_precond, &pc));
+    if (!same_system(op_hi, op_precond))
+      return set_error(ctx, LQCD_ERR_INVALID_ARG, "op_precond describes another system");
+    if (op_precond->prec != LQCD_F32 || op_krylov->prec != LQCD_F32)
+      return set_error(ctx, LQCD_ERR_UNSUPPORTED, "the learned preconditioner runs with FP32 op_krylov and op_precond");
+    if (!prm->learned) return set_error(ctx, LQCD_ERR_INVALID_ARG, "learned network is NULL");
+    TRY(check_fields_internal(ctx, op_precond));
+    if (prm->schwarz.mr_steps > 0) TRY(check_schwarz(ctx, pc, &prm->schwarz));
   } else if (pk != LQCD_PRECOND_NONE) {
     return set_error(ctx, LQCD_ERR_INVALID_ARG, "unknown preconditioner kind");
   }
@@ -142,10 +149,14 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
   std::vector<void *> P(kmax), Z(kmax);
   for (int i = 0; i < kmax; ++i) TRY(S.vec(kr.spinor_bytes, &P[i]));
   for (int i = 0; i < kmax; ++i) TRY(S.vec(kr.spinor_bytes, &Z[i]));
-  if (pk == LQCD_PRECOND_SCHWARZ) {
+  if (pk == LQCD_PRECOND_SCHWARZ || (pk == LQCD_PRECOND_LEARNED && prm->schwarz.mr_steps > 0)) {
     TRY(S.vec(pc.spinor_bytes, &pin));
     TRY(S.vec(pc.spinor_bytes, &pout));
   }
+  // LEARNED: a step whose residual reduction stalls (or whose network output
+  // is not finite) makes the next step use the Schwarz preconditioner.
+  bool use_fallback = false;
+  double rhn_prev = 0;
   RedScratch red = S.red();
   void *xe = x_full;
 
@@ -180,11 +191,16 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
   lqcd_status status = LQCD_OK;
   while (!converged) {
     // p_k = K rhat_k
-    if (pk == LQCD_PRECOND_SCHWARZ) {
+    const bool schwarz_now = pk == LQCD_PRECOND_SCHWARZ || (pk == LQCD_PRECOND_LEARNED && use_fallback);
+    if (schwarz_now) {
       const double sc = unit_rms_scale(rhn, 2 * n);
       TRY(S.hip(blas_convert(kr.prec, rhat, pc.prec, pin, n, sc, S.st), "convert"));
       TRY(schwarz_apply(ctx, pc, &prm->schwarz, pout, pin, kSlotSchwarz, S.st));
       TRY(S.hip(blas_convert(pc.prec, pout, kr.prec, P[k], n, 1.0 / sc, S.st), "convert"));
+      inf.precond_applies++;
+      use_fallback = false;
+    } else if (pk == LQCD_PRECOND_LEARNED) {
+      TRY(ptc_apply(ctx, op_precond, prm->learned, P[k], rhat, S.st));
       inf.precond_applies++;
     } else {
       TRY(S.hip(hipMemcpyAsync(P[k], rhat, kr.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
@@ -220,7 +236,11 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
     TRY(S.hip(blas_gcr_update(kr.prec, Z[k], rhat, n, 1.0 / g, alpha[k].real(), alpha[k].imag(), red, S.st),
               "gcr update"));
     TRY(S.result(1, &rr));
+    rhn_prev = rhn;
     rhn = std::sqrt(rr);
+    if (pk == LQCD_PRECOND_LEARNED && prm->schwarz.mr_steps > 0 && !schwarz_now &&
+        (!(rhn < 0.95 * rhn_prev) || !std::isfinite(rhn)))
+      use_fallback = true;
     if (verbose())
       fprintf(stderr, "gcr it %d k %d |rhat|/|b| %.3e gamma %.3e |alpha| %.3e\n", iters, k, rhn / bn, g,
               std::abs(alpha[k]));
@@ -321,6 +341,14 @@ extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
   const bool cgne = kind == LQCD_CG_CGNE_SCHUR;
   const size_t n = ncomplex(hi);
   const bool mixed = lo.prec != hi.prec;
+  const bool recording = prm->record_max > 0;
+  if (recording) {
+    if (!cgne || op_sloppy || prm->record_every < 1 || !prm->record_r || !prm->record_e || !prm->record_xstar ||
+        !prm->record_count)
+      return set_error(ctx, LQCD_ERR_INVALID_ARG,
+                       "recording needs CGNE_SCHUR in pure op_hi precision, record_every >= 1 and all record buffers");
+    *prm->record_count = 0;
+  }
   const bool half = lo.prec == LQCD_F16 || lo.prec == LQCD_BF16;
   const double delta = prm->delta_reliable;
   void *bhat, *r, *y, *tmp_hi, *rs, *xs, *p, *q, *t, *tmp_lo;
@@ -405,6 +433,17 @@ extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
     ++it;
     double rr_new_true = rr_new / (sc * sc);
     if (verbose()) fprintf(stderr, "cg it %d |r|/|b| %.3e alpha %.3e\n", it, std::sqrt(rr_new_true) / bn, a);
+    if (recording && it % prm->record_every == 0 && *prm->record_count < prm->record_max) {
+      // pure precision: x_k = x_e + xs, r_k = rs; e_k = x* - x_k
+      const int j = *prm->record_count;
+      char *rdst = (char *)prm->record_r + (size_t)j * hi.spinor_bytes;
+      char *edst = (char *)prm->record_e + (size_t)j * hi.spinor_bytes;
+      TRY(S.hip(hipMemcpyAsync(rdst, rs, hi.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "record"));
+      TRY(S.hip(hipMemcpyAsync(edst, prm->record_xstar, hi.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "record"));
+      TRY(S.hip(blas_axpby(hi.prec, xe, hi.prec, edst, n, -1.0, 0.0, 1.0, 0.0, nullptr, S.st), "record"));
+      TRY(S.hip(blas_axpby(lo.prec, xs, hi.prec, edst, n, -1.0, 0.0, 1.0, 0.0, nullptr, S.st), "record"));
+      *prm->record_count = j + 1;
+    }
     // reliable update when the iterated residual dropped by delta since the
     // last one (mixed precision), and always before declaring convergence
     const bool trigger = rr_new_true <= stop || (mixed && rr_new_true < delta * delta * maxrr);

@@ -59,10 +59,18 @@ class lqcd_schwarz_params(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32 * 4), ("mr_steps", ctypes.c_int32)]
 
 
+class lqcd_ptc_shape(ctypes.Structure):
+    _fields_ = [("nlayers", ctypes.c_int32), ("channels", ctypes.c_int32 * 9)]
+
+
+class lqcd_ptc_net(ctypes.Structure):
+    _fields_ = [("shape", lqcd_ptc_shape), ("packed", ctypes.c_void_p)]
+
+
 class lqcd_gcr_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("k_max", ctypes.c_int32), ("delta", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("schwarz", lqcd_schwarz_params), ("learned", ctypes.c_void_p)]
+                ("schwarz", lqcd_schwarz_params), ("learned", ctypes.POINTER(lqcd_ptc_net))]
 
 
 class lqcd_dslash_job(ctypes.Structure):
@@ -72,7 +80,9 @@ class lqcd_dslash_job(ctypes.Structure):
 
 class lqcd_cg_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("delta_reliable", ctypes.c_double),
-                ("kind", ctypes.c_int32)]
+                ("kind", ctypes.c_int32), ("record_r", ctypes.c_void_p), ("record_e", ctypes.c_void_p),
+                ("record_xstar", ctypes.c_void_p), ("record_every", ctypes.c_int32), ("record_max", ctypes.c_int32),
+                ("record_count", ctypes.POINTER(ctypes.c_int32))]
 
 
 _lib = None
@@ -91,6 +101,7 @@ _SIGNATURES = {
     "lqcd_spinor_import": [_P, _OPP, _P, _P, _I, _I, _P],
     "lqcd_spinor_export": [_P, _OPP, _P, _P, _I, _I, _P],
     "lqcd_dslash_batch": [_P, ctypes.POINTER(lqcd_dslash_job), _I, _I, _P],
+    "lqcd_spinor_convert": [_P, _OPP, _P, _OPP, _P, _I, _I, ctypes.c_double, _P],
     "lqcd_dslash": [_P, _OPP, _P, _P, _I, _I, ctypes.POINTER(ctypes.c_int32), _I, _P],
     "lqcd_clover_apply": [_P, _OPP, _P, _P, _I, _I, _I, _P],
     "lqcd_schur_apply": [_P, _OPP, _P, _P, _I, ctypes.POINTER(ctypes.c_int32), _I, _P],
@@ -98,6 +109,11 @@ _SIGNATURES = {
     "lqcd_gcr_solve": [_P, _OPP, _OPP, _OPP, ctypes.POINTER(lqcd_gcr_params), _P, _P,
                        ctypes.POINTER(lqcd_solve_info), _P],
     "lqcd_cg_solve": [_P, _OPP, _OPP, ctypes.POINTER(lqcd_cg_params), _P, _P, ctypes.POINTER(lqcd_solve_info), _P],
+    "lqcd_ptc_sizes": [ctypes.POINTER(lqcd_ptc_shape), ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+    "lqcd_ptc_pack": [_P, ctypes.POINTER(lqcd_ptc_shape), _P, _P, _P],
+    "lqcd_ptc_apply": [_P, _OPP, ctypes.POINTER(lqcd_ptc_net), _P, _P, _P],
+    "lqcd_ptc_gradient": [_P, _OPP, ctypes.POINTER(lqcd_ptc_net), _P, _P, _P, ctypes.POINTER(ctypes.c_double), _P],
+    "lqcd_ptc_adam": [_P, ctypes.POINTER(lqcd_ptc_shape), _P, _P, _P, _P, _I, ctypes.c_double, _P],
 }
 EXPORTED = tuple(_SIGNATURES)
 
@@ -189,6 +205,11 @@ def lqcd_spinor_export(ctx, op, natural, packed, parity, nrhs=1, stream=None):
                                     _stream(stream)), ctx)
 
 
+def lqcd_spinor_convert(ctx, op_out, out, op_in, inp, parity, nrhs=1, scale=1.0, stream=None):
+    _check(lib().lqcd_spinor_convert(ctx, ctypes.byref(op_out), _ptr(out), ctypes.byref(op_in), _ptr(inp), parity,
+                                     nrhs, float(scale), _stream(stream)), ctx)
+
+
 def lqcd_dslash_batch(ctx, jobs, dagger=0, stream=None):
     """jobs: sequence of (op, out, in, out_parity, nrhs)."""
     arr = (lqcd_dslash_job * len(jobs))()
@@ -240,3 +261,31 @@ def lqcd_cg_solve(ctx, op_hi, op_sloppy, params, x, b, stream=None):
     if st not in (LQCD_OK, LQCD_ERR_NOT_CONVERGED):
         _check(st, ctx)
     return st, info
+
+
+def lqcd_ptc_sizes(shape):
+    nw, nb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().lqcd_ptc_sizes(ctypes.byref(shape), ctypes.byref(nw), ctypes.byref(nb)), None)
+    return nw.value, nb.value
+
+
+def lqcd_ptc_pack(ctx, shape, weights, packed, stream=None):
+    _check(lib().lqcd_ptc_pack(ctx, ctypes.byref(shape), _ptr(weights), _ptr(packed), _stream(stream)), ctx)
+
+
+def lqcd_ptc_apply(ctx, op, net, out_even, in_even, stream=None):
+    _check(lib().lqcd_ptc_apply(ctx, ctypes.byref(op), ctypes.byref(net), _ptr(out_even), _ptr(in_even),
+                                _stream(stream)), ctx)
+
+
+def lqcd_ptc_gradient(ctx, op, net, r_even, e_even, grad, stream=None):
+    loss = ctypes.c_double()
+    _check(lib().lqcd_ptc_gradient(ctx, ctypes.byref(op), ctypes.byref(net), _ptr(r_even), _ptr(e_even), _ptr(grad),
+                                   ctypes.byref(loss), _stream(stream)), ctx)
+    return loss.value
+
+
+def lqcd_ptc_adam(ctx, shape, weights, m, v, grad, step, lr, stream=None):
+    _check(lib().lqcd_ptc_adam(ctx, ctypes.byref(shape), _ptr(weights), _ptr(m), _ptr(v), _ptr(grad), int(step),
+                               float(lr), _stream(stream)), ctx)
+

@@ -28,6 +28,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.lqcd_operator) == 48 + 32 + 32
     assert ctypes.sizeof(L.lqcd_solve_info) == 32
     assert ctypes.sizeof(L.lqcd_gcr_params) == 8 + 4 + 4 + 8 + 4 + 4 + 20 + 4 + 8
+    assert ctypes.sizeof(L.lqcd_ptc_net) == 40 + 8
+    assert ctypes.sizeof(L.lqcd_cg_params) == 8 + 4 + 4 + 8 + 4 + 4 + 3 * 8 + 4 + 4 + 8
 
 
 def test_validation_without_gpu():
