@@ -29,6 +29,21 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "dslash GB/s & % of HBM roofline; time-to-solution at 1e-10 residual vs FP64 CG"
 
 WILSON_REALS = {18: 192, 12: 144, 8: 112}  # in 24 + out 24 + 8 links per output site
+
+# HBM traffic of the headline kernel per launch, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE scaled by the same counters on a 2 GiB device copy (summary under
+# profiles/). Valid only for the kernel sources it was measured on: their hash
+# is checked at run time and the traffic is reported as null when they differ.
+PROFILED_TRAFFIC = {"sources_sha1": "344b8e009d5040faa9aa053fea86bb3af6b3acf9", "bytes_per_launch": 852.3e6}
+
+
+def kernel_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("wilson.hip", "lqcd_device.h"):
+        with open(os.path.join(ROOT, "paper_1109_2935_amd", "csrc", f), "rb") as fh:
+            h.update((hashlib.sha1(fh.read()).hexdigest() + "  " + os.path.join("paper_1109_2935_amd", "csrc", f) + "\n").encode())
+    return h.hexdigest()
 SCHUR_REALS = {18: 552, 12: 456, 8: 392}   # two fused kernels, per even site
 PREC_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 PREC_NAME = {0: "f64", 1: "f32", 2: "f16", 3: "bf16"}
@@ -44,6 +59,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--kernels-only", action="store_true", help="time kernels only (for profiling runs)")
+    ap.add_argument("--learned", default=os.path.join(ROOT, "paper_1109_2935_amd", "data", "ptc_16x4.npz"),
+                    help="trained network weights; FGCR with it is timed when the file exists")
+    ap.add_argument("--staggered", action="store_true", help="also measure the 48^3x96 staggered workload")
+    ap.add_argument("--batched", action="store_true", help="also measure the batched multi-RHS workload")
     return ap.parse_args()
 
 
@@ -98,6 +117,131 @@ def cpu_baseline(dims, U, b, kappa, csw):
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
             "sample": "%d applications of the FP64 Wilson hopping term (one parity) on the full %s lattice, "
                       "%.2f s each" % (reps, "x".join(map(str, dims)), dt)}
+
+
+def learned_solve(args, torch, L, ops, ctx, o64, o32, bp, block, mr, dims):
+    """Flexible GCR with the trained PTC network as preconditioner (Schwarz as
+    fallback), FP64 restarts, FP32 Krylov; and the cost of one network
+    application (BF16 matrix-core flops of its channel mixing)."""
+    import ctypes
+    import numpy as np
+    from paper_1109_2935_amd import ptc
+    net = ptc.Network(ctx)
+    net.load(args.learned)
+    prm = ops.gcr_params(1e-10, 16, 1e-3, max_iter=2000, precond=L.LQCD_PRECOND_LEARNED, block=block, mr_steps=mr)
+    prm.learned = ctypes.pointer(net.net)
+    best = None
+    for _ in range(2):
+        x = o64.spinor(full=True)
+        st, info = L.lqcd_gcr_solve(ctx, o64.op, o32.op, o32.op, prm, x, bp)
+        assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+        if best is None or info.seconds < best.seconds:
+            best = info
+    r = o32.spinor()
+    out = o32.spinor()
+    L.lqcd_spinor_convert(ctx, o32.op, r, o64.op, bp, 0)
+    dt = time_kernel(torch, lambda: net.apply(o32, out, r), 3)
+    V = int(np.prod(dims))
+    ch = net.channels
+    # complex multiply-adds per site: cout*4 x cin*9*4 for each of 3 colours; both parities except the last layer
+    macs = sum(co * 4 * ci * 36 * 3 * (V // 2 if k == len(ch) - 2 else V) for k, (ci, co) in enumerate(zip(ch[:-1], ch[1:])))
+    log("FGCR(PTC): %d steps, %d applies, %.3f s; one application %.2f ms, %.1f TFLOP/s" % (
+        best.iters, best.precond_applies, best.seconds, dt * 1e3, 8 * macs / dt / 1e12))
+    return {"fgcr_learned_seconds": round(best.seconds, 4), "fgcr_learned_steps": best.iters,
+            "fgcr_learned_true_residual": best.true_residual, "ptc_apply_ms": round(dt * 1e3, 3),
+            "ptc_apply_tflops": round(8 * macs / dt / 1e12, 1)}
+
+
+def staggered_workload(args, torch, L, ops, ctx):
+    """48^3x96 improved staggered (m = 0.01, eps = 0.2): dslash bandwidth per
+    precision and long-link format, reliable-update CG (FP32 / FP16 sloppy)
+    against plain FP64 CG."""
+    import numpy as np
+    import synth
+    dims, mass = (48, 48, 48, 96), 0.01
+    t = time.time()
+    U = synth.gauge_field(dims, 0.2, 3001)
+    fat = synth.fat_links(dims, U, seed=3003)
+    chi = synth.gaussian_spinor(dims, 3002, inner=(3,))
+    log("staggered fields %.1fs" % (time.time() - t))
+    Ud, Fd = torch.from_numpy(U).cuda(), torch.from_numpy(fat).cuda()
+    vh = int(np.prod(dims)) // 2
+    out = {"dims": list(dims), "kernels": {}}
+    inst = {}
+    for prec, recon in [(0, 18), (1, 18), (1, 12), (1, 8), (2, 12)]:
+        o = ops.staggered(ctx, fat, U, dims, mass, prec, recon, U_device=Ud, fat_device=Fd)
+        inst[(prec, recon)] = o
+        inp = o.import_spinor(np.where(synth.parity_of_sites(dims)[..., None] == 1, chi, 0), 1)
+        res = o.spinor()
+        dt = time_kernel(torch, lambda: L.lqcd_dslash(ctx, o.op, res, inp, 0), 20)
+        byts = vh * (12 + 8 * 18 + 8 * recon) * PREC_BYTES[prec]
+        out["kernels"]["stag_dslash_%s_r%d" % (PREC_NAME[prec], recon)] = {
+            "us": round(dt * 1e6, 1), "GB/s": round(byts / dt / 1e9, 1), "frac": round(byts / dt / 1e9 / HBM_PEAK_GBS, 4)}
+        log("staggered %s r%d: %.1f us %.1f GB/s" % (PREC_NAME[prec], recon, dt * 1e6, byts / dt / 1e9))
+    del Ud, Fd
+    hi = inst[(0, 18)]
+    b = hi.import_spinor(np.where(synth.parity_of_sites(dims)[..., None] == 0, chi, 0), 0)
+    for name, lo in (("fp64", None), ("fp32_sloppy", inst[(1, 12)]), ("fp16_sloppy", inst[(2, 12)])):
+        x = hi.spinor()
+        st, info = L.lqcd_cg_solve(ctx, hi.op, lo.op if lo else None,
+                                   ops.cg_params(1e-10, 20000, 0.1, L.LQCD_CG_STAG_NORMAL), x, b)
+        out["cg_" + name] = {"status": st, "iters": info.iters, "updates": info.restarts,
+                             "seconds": round(info.seconds, 4), "true_residual": info.true_residual}
+        log("staggered CG %s: %d it, %.3f s, res %.2e" % (name, info.iters, info.seconds, info.true_residual))
+    return out
+
+
+def batched_workload(args, torch, L, ops, ctx):
+    """Multi-RHS Wilson hopping term: 12 point sources (spin x colour) on
+    24^3x48, and one persistent launch over 16^3x32, 20^3x40 and 24^3x48 with
+    4 Gaussian sources each (kappa 0.122). Bytes per site and right-hand side:
+    spinor in + out (48 reals) plus the site's 8 links shared by its nrhs."""
+    import numpy as np
+    import synth
+    out = {}
+    for prec, recon in ((1, 12), (2, 12)):
+        pb = PREC_BYTES[prec]
+        # 12 point sources on 24^3x48
+        dims = (24, 24, 24, 48)
+        U = synth.gauge_field(dims, 0.25, 4001)
+        o = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon)
+        srcs = np.stack([synth.point_source(dims, sc // 3, sc % 3) for sc in range(12)])
+        # point sources sit on the even origin: apply D_oe to them
+        inp = o.import_spinor(srcs, 0, nrhs=12)
+        res_ = o.spinor(nrhs=12)
+        vh = int(np.prod(dims)) // 2
+        dt = time_kernel(torch, lambda: L.lqcd_dslash(ctx, o.op, res_, inp, 1, nrhs=12), 20)
+        byts = vh * (12 * 48 + 8 * recon) * pb
+        single_in = o.import_spinor(srcs[0], 0)
+        single_out = o.spinor()
+        dt1 = time_kernel(torch, lambda: L.lqcd_dslash(ctx, o.op, single_out, single_in, 1), 20)
+        out["point12_24x48_%s" % PREC_NAME[prec]] = {
+            "us": round(dt * 1e6, 1), "GB/s": round(byts / dt / 1e9, 1),
+            "us_per_rhs": round(dt * 1e6 / 12, 2), "single_rhs_us": round(dt1 * 1e6, 1),
+            "speedup_vs_sequential": round(12 * dt1 / dt, 2)}
+        # mixed batch, one persistent launch
+        jobs, keep, tot_bytes, seq = [], [], 0, 0.0
+        for k, dims in enumerate(((16, 16, 16, 32), (20, 20, 20, 40), (24, 24, 24, 48))):
+            U = synth.gauge_field(dims, 0.25, 4011 + 10 * k)
+            ok = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon)
+            srcs = np.stack([np.where(synth.parity_of_sites(dims)[..., None, None] == 1,
+                                      synth.gaussian_spinor(dims, 4012 + 10 * k + r), 0) for r in range(4)])
+            i_ = ok.import_spinor(srcs, 1, nrhs=4)
+            o_ = ok.spinor(nrhs=4)
+            jobs.append((ok.op, o_, i_, 0, 4))
+            keep.append((ok, i_, o_))
+            vhk = int(np.prod(dims)) // 2
+            tot_bytes += vhk * (4 * 48 + 8 * recon) * pb
+            seq += time_kernel(torch, lambda: L.lqcd_dslash(ctx, ok.op, o_, i_, 0, nrhs=4), 10)
+        dtb = time_kernel(torch, lambda: L.lqcd_dslash_batch(ctx, jobs), 20)
+        out["mixed3x4_%s" % PREC_NAME[prec]] = {
+            "us": round(dtb * 1e6, 1), "GB/s": round(tot_bytes / dtb / 1e9, 1),
+            "separate_launches_us": round(seq * 1e6, 1)}
+        log("batched %s: 12 point sources %.1f us (%.1f GB/s, x%.2f vs sequential); mixed batch %.1f us "
+            "(%.1f GB/s, separate launches %.1f us)" % (
+                PREC_NAME[prec], dt * 1e6, byts / dt / 1e9, 12 * dt1 / dt, dtb * 1e6, tot_bytes / dtb / 1e9,
+                seq * 1e6))
+    return out
 
 
 def main():
@@ -205,6 +349,8 @@ def main():
         tts.update({"fp64_cg_seconds": round(cg.seconds, 4), "fp64_cg_iters": cg.iters,
                     "fp64_cg_true_residual": cg.true_residual,
                     "speedup_vs_fp64_cg": round(cg.seconds / tts["gcr_dd_seconds"], 2)})
+    if os.path.exists(args.learned):
+        tts.update(learned_solve(args, torch, L, ops, ctx, o64, o32, bp, block, mr, dims))
     res = {
         "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 2), "higher_is_better": True,
@@ -215,11 +361,18 @@ def main():
                    "dims": list(dims), "kernel": "wilson dslash f32 recon12, one parity",
                    "dslash_launches_per_step": args.dslash_launches},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": (PROFILED_TRAFFIC["bytes_per_launch"]
+                                 if kernel_sources_sha1() == PROFILED_TRAFFIC["sources_sha1"] else None),
+                     "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": byts},
         "time_to_solution": tts,
         "device_copy": copy,
         "kernels": kernels,
     }
+    if args.staggered:
+        res["staggered"] = staggered_workload(args, torch, L, ops, ctx)
+    if args.batched:
+        res["batched"] = batched_workload(args, torch, L, ops, ctx)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline(dims, U, b, kappa, csw)

@@ -93,7 +93,8 @@ class Network:
         self.pack()
 
     def save(self, path):
-        np.savez(path, channels=np.array(self.channels), **{"w%d" % k: W for k, W in enumerate(self.get_weights())})
+        np.savez_compressed(path, channels=np.array(self.channels),
+                            **{"w%d" % k: W.astype(np.complex64) for k, W in enumerate(self.get_weights())})
 
     def load(self, path):
         z = np.load(path, allow_pickle=False)
