@@ -3,6 +3,8 @@
 // operator, additive Schwarz). Solvers live in solvers.cpp.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -159,6 +161,15 @@ const void *clover_block(const OpInfo &info, const void *clov, int parity) {
 // ---------------------------------------------------------------------------
 // operator compositions used by the entry points and the solvers
 
+// With LQCD_MRHS_MFMA=1 the link products of 16-bit operators with a multiple
+// of 4 right-hand sides run on the matrix cores. The hopping term is bound by
+// memory traffic, and on gfx950 the vector-ALU form measures faster, so it is
+// the default. Read on every call.
+static bool use_mfma(int prec, int nrhs, const double *partials) {
+  const char *e = std::getenv("LQCD_MRHS_MFMA");
+  return e && e[0] == '1' && (prec == LQCD_F16 || prec == LQCD_BF16) && nrhs % 4 == 0 && !partials;
+}
+
 lqcd_status wilson_hop(lqcd_context *ctx, const OpInfo &info, const Geom &g, int mode, void *out, const void *in,
                        const void *xin, const void *clov, int parity, double coef, int dagger, double *partials,
                        hipStream_t st, int nrhs) {
@@ -177,13 +188,15 @@ lqcd_status wilson_hop(lqcd_context *ctx, const OpInfo &info, const Geom &g, int
   w.mode = mode;
   w.partials = partials;
   w.nrhs = nrhs;
+  w.mfma = use_mfma(info.prec, nrhs, partials) ? 1 : 0;
   w.block_threads = 256;
   // Workgroup size picked by the autotuner per (kernel, precision, links,
   // geometry, rhs). Calls that overwrite one of their inputs are not re-run
   // for timing; they use the tuned value if there is one, else 128.
   const bool rerunnable = out != in && out != xin;
   const std::string key = "wilson m" + std::to_string(mode) + (partials ? "r" : "") + " p" + std::to_string(info.prec) +
-                          " r" + std::to_string(info.recon) + " " + geom_key(g) + " n" + std::to_string(nrhs);
+                          " r" + std::to_string(info.recon) + " " + geom_key(g) + " n" + std::to_string(nrhs) +
+                          (w.mfma ? " mf" : "");
   w.block_threads = tune_pick(ctx, key, {64, 128, 256}, 128, rerunnable, st, [&](int bt) {
     WilsonLaunch v = w;
     v.block_threads = bt;
@@ -581,10 +594,13 @@ lqcd_status lqcd_dslash_batch(lqcd_context *ctx, const lqcd_dslash_job *jobs, in
   for (int a = 0; a < njobs; ++a)
     for (int b = 0; b < njobs; ++b)
       if (bj[a].out == bj[b].in || (a != b && bj[a].out == bj[b].out)) distinct = false;
+  // the same link-product path as lqcd_dslash for each job
+  const int mf = use_mfma(prec, 4, nullptr) ? 1 : 0;
+  if (mf) key += " mf";
   const int pick = tune_pick(ctx, key, idx, 2, distinct, st, [&](int i) {
-    return launch_wilson_batch(prec, recon, bj, njobs, dagger, cands[i], (unsigned *)counter, st);
+    return launch_wilson_batch(prec, recon, bj, njobs, dagger, cands[i], mf, (unsigned *)counter, st);
   });
-  return hip_check(ctx, launch_wilson_batch(prec, recon, bj, njobs, dagger, cands[pick], (unsigned *)counter, st),
+  return hip_check(ctx, launch_wilson_batch(prec, recon, bj, njobs, dagger, cands[pick], mf, (unsigned *)counter, st),
                    "batched dslash launch");
 }
 

@@ -82,6 +82,7 @@ struct WilsonLaunch {
   double *partials;  // if non-null: per-segment <out,xin> (re, im) and <out,out> (nrhs = 1)
   int block_threads;
   int nrhs;          // right-hand sides interleaved per site
+  int mfma;          // link products on the matrix cores (16-bit, nrhs % 4 == 0, no partials)
 };
 hipError_t launch_wilson(const WilsonLaunch &w, hipStream_t st);
 
@@ -99,8 +100,9 @@ struct BatchTune {
   int chunk;          // (site, rhs) pairs per work item
   int grid;           // workgroups of the persistent launch
 };
+// mfma: 16-bit jobs whose source count is a multiple of 4 use the matrix-core link products
 hipError_t launch_wilson_batch(int prec, int recon, const BatchJob *jobs, int njobs, int dagger, const BatchTune &t,
-                               unsigned *counter, hipStream_t st);
+                               int mfma, unsigned *counter, hipStream_t st);
 
 hipError_t launch_clover_apply(const Geom &g, int prec, void *out, const void *in, const void *clov, int nrhs,
                                hipStream_t st);

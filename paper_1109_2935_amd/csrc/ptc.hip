@@ -67,19 +67,19 @@ __device__ __forceinline__ void transport_one(const PtcGeo &q, const float *__re
     load_site<float, RECON, float>(q.gauge + (int64_t)(2 * mu + par) * vh * RECON, vh, s, lv);
   else
     load_site<float, RECON, float>(q.gauge + (int64_t)(2 * mu + 1 - par) * vh * RECON, vh, n, lv);
-  const Link<float> U = unpack_link<RECON, float>(lv);
+  const Link<float> U0 = unpack_link<RECON, float>(lv);
   const float ph = (mu == 3 && (w & 1) && q.g.bc_t < 0) ? -1.f : 1.f;
+  Link<float> U;  // U or U^+, times the boundary sign
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) U.m[a][b] = ph * (fwd ? U0.m[a][b] : conj(U0.m[b][a]));
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp) {
-    cpx<float> v[3], u[3];
+    cpx<float> v[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) v[c] = mk<float>(r[6 * sp + 2 * c], r[6 * sp + 2 * c + 1]);
-    if (fwd)
-      su3_mv(U, v, u);
-    else
-      su3_adj_mv(U, v, u);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) out[sp][c] = ph * u[c];
+    su3_mv(U, v, out[sp]);
   }
 }
 
@@ -97,94 +97,227 @@ __device__ __forceinline__ void transport_any(const PtcGeo &q, const float *act,
     transport_dispatch<18>(q, act, C, ch, p, x, s, out);
 }
 
+// Neighbour table of the transport paths: entry [par][p-1][s] (p = 1..8) is
+// the index of the site reached by path p from site s of parity par, with
+// bit 31 set where the hop crosses the antiperiodic time boundary.
+__global__ void ptc_nbr_kernel(Geom g, int *tab) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int par = blockIdx.y;
+  if (s >= g.Vh) return;
+  const Site x = decode_site(g, s, par);
+  int *t = tab + (int64_t)par * 8 * g.Vh + s;
+  int w, n;
+#define PTC_NBR(MU)                                                              \
+  n = hop<MU>(g, x, 1, &w);                                                      \
+  t[(2 * MU) * (int64_t)g.Vh] = n | ((MU == 3 && (w & 1) && g.bc_t < 0) << 31);  \
+  n = hop<MU>(g, x, -1, &w);                                                     \
+  t[(2 * MU + 1) * (int64_t)g.Vh] = n | ((MU == 3 && (w & 1) && g.bc_t < 0) << 31);
+  PTC_NBR(0)
+  PTC_NBR(1)
+  PTC_NBR(2)
+  PTC_NBR(3)
+#undef PTC_NBR
+}
+
+// Transport of NCH consecutive channels i0 .. i0+NCH-1 of one path p at site s
+// of parity par, written to LDS as BF16 (row stride `cstride` between colours,
+// 8 K values per channel: spin-major, re/im interleaved). The link and the
+// neighbour are read once; the NCH channel loads are issued together.
+template <int RECON, int NCH>
+__device__ __forceinline__ void transportn_lds(const PtcGeo &q, const int *__restrict__ nbr, const float *__restrict__ act,
+                                               int C, int i0, int p, int par, int s, __bf16 *dst, int cstride) {
+  const int64_t vh = q.g.Vh, vs = vh * C;
+  int n = s;
+  float ph = 1.f;
+  if (p != 0) {
+    const int e = nbr[((int64_t)par * 8 + p - 1) * vh + s];
+    n = e & 0x7fffffff;
+    ph = e < 0 ? -1.f : 1.f;
+  }
+  const float *blk = act + (int64_t)(p == 0 ? par : 1 - par) * vs * 24;
+  float r[NCH][24];
+#pragma unroll
+  for (int k = 0; k < NCH; ++k) load_spinor_reals<float, 24, float>(blk, vs, (int64_t)n * C + i0 + k, r[k]);
+  if (p != 0) {
+    const int mu = (p - 1) >> 1;
+    const bool fwd = ((p - 1) & 1) == 0;
+    float lv[RECON];
+    // forward: U_mu(x) at x; backward: U_mu(x - mu)^+ at the neighbour
+    load_site<float, RECON, float>(q.gauge + (int64_t)(2 * mu + (fwd ? par : 1 - par)) * vh * RECON, vh, fwd ? s : n,
+                                   lv);
+    const Link<float> U0 = unpack_link<RECON, float>(lv);
+    // the matrix applied: U, or U^+ for a backward hop (selected once), times the boundary sign
+    Link<float> U;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const cpx<float> e = fwd ? U0.m[a][b] : conj(U0.m[b][a]);
+        U.m[a][b] = ph * e;
+      }
+#pragma unroll
+    for (int k = 0; k < NCH; ++k)
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) {
+        cpx<float> v[3], u[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = mk<float>(r[k][6 * sp + 2 * c], r[k][6 * sp + 2 * c + 1]);
+        su3_mv(U, v, u);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          r[k][6 * sp + 2 * c] = u[c].re;
+          r[k][6 * sp + 2 * c + 1] = u[c].im;
+        }
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < NCH; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bf16x8_t v;
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) {
+        v[2 * sp] = (__bf16)r[k][6 * sp + 2 * c];
+        v[2 * sp + 1] = (__bf16)r[k][6 * sp + 2 * c + 1];
+      }
+      *reinterpret_cast<bf16x8_t *>(dst + c * cstride + 8 * k) = v;
+    }
+}
+
 __device__ __forceinline__ bf16x8_t lds_frag(const __bf16 *row) {
   return *reinterpret_cast<const bf16x8_t *>(row);
 }
 
 // ---------------------------------------------------------------------------
 // forward: out (Cout channels, parity par) = sum W (T psi_in)
+//
+// A workgroup owns NS sites, i.e. N = 3 * NS GEMM columns
+// (n = colour * NS + site). Per K chunk its 256 threads transport
+// kFwSites x fw_ipc items into LDS (BF16, row n holds the chunk's K values),
+// then each wave multiplies its block of 16x16 output tiles: m-tiles
+// {mbase + 4j} by n-tiles [nbase, nbase + nn), so each B fragment read from
+// LDS feeds up to two MFMAs and each A fragment (pre-packed, one 16-byte load
+// per lane) up to 3 NS / 16. NS = 64 halves the weight traffic per site of
+// NS = 32 but needs twice the accumulators; the launch picks one by timing
+// (both give identical results: the K order of every output is the same).
 
-__global__ void __launch_bounds__(kPtcThreads) ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const float *in,
-                                                                   float *out, int par) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int krow = L.kchunk + kLdsPad;                  // bf16 per LDS row
-  __bf16 *Bt = reinterpret_cast<__bf16 *>(smem);        // [48][krow]
-  float *Ot = reinterpret_cast<float *>(smem + 48 * krow * 2);  // [16][Cout][24]
-  const int tile = blockIdx.x;
-  const int s0 = tile * kTile;
+constexpr int kFwRow = 16 * 8 + kLdsPad;  // bf16 per LDS row: 16 items x 8 K values + padding
+
+template <int NS, int WPE>
+__global__ void __launch_bounds__(kPtcThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
+ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const float *in, float *out, int par) {
+  constexpr int kFwSites = NS, NT = 3 * NS / 16;
+  __shared__ __align__(16) __bf16 Bt[3 * NS * kFwRow];
+  const int s0 = blockIdx.x * kFwSites;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ntile_total = L.mtiles * 3;
-  f32x4_t acc[6];
+  // this wave's output tiles
+  int mbase, nm, nbase, nn;
+  if (L.mtiles >= 4) {
+    mbase = wave;
+    nm = (L.mtiles - wave + 3) / 4;
+    nbase = 0;
+    nn = NT;
+  } else {
+    const int split = 4 / L.mtiles;  // waves per m-tile
+    mbase = wave % L.mtiles;
+    nm = 1;
+    nn = (NT + split - 1) / split;
+    nbase = (wave / L.mtiles) * nn;
+    nn = max(0, min(nn, NT - nbase));
+  }
+  f32x4_t acc[2][NT];
 #pragma unroll
-  for (int t = 0; t < 6; ++t) acc[t] = f32x4_t{0, 0, 0, 0};
-  for (int e = threadIdx.x; e < 48 * krow; e += kPtcThreads) Bt[e] = (__bf16)0.f;
-  for (int ck = 0; ck < L.nchunk; ++ck) {
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[j][t] = f32x4_t{0, 0, 0, 0};
+  const bf16x8_t *A = (const bf16x8_t *)L.A;
+  for (int q0 = 0; q0 < 4 * L.fw_ks; q0 += L.fw_ipc) {
+    const int ipc = min(L.fw_ipc, 4 * L.fw_ks - q0);
     __syncthreads();
-    const int nitem = kTile * L.chunk_ch * 9;
-    for (int it = threadIdx.x; it < nitem; it += kPtcThreads) {
-      const int sl = it % kTile, rem = it / kTile, p = rem % 9, il = rem / 9;
-      const int i = ck * L.chunk_ch + il;
-      const int s = s0 + sl;
-      cpx<float> y[4][3];
-      if (s < q.g.Vh && i < L.cin) {
-        const Site x = decode_site(q.g, s, par);
-        transport_any(q, in, L.cin, i, p, x, s, y);
-      } else {
+    if (L.cin % 4 == 0) {
+      // kNch consecutive items (one site and path, kNch channels) per thread
+      constexpr int kNch = 2;
+      const int gn = ipc / kNch;
+#pragma unroll 1
+      for (int w = threadIdx.x; w < kFwSites * gn; w += kPtcThreads) {
+        const int un = w % gn, sl = w / gn;
+        const int qi = q0 + kNch * un, s = s0 + sl;
+        __bf16 *dst = Bt + sl * kFwRow + 8 * kNch * un;
+        if (s < q.g.Vh && qi < L.fw_items) {
+          const int p = qi / L.cin, i0 = qi - p * L.cin;
+          if (q.recon == 12)
+            transportn_lds<12, kNch>(q, nbr, in, L.cin, i0, p, par, s, dst, kFwSites * kFwRow);
+          else
+            transportn_lds<18, kNch>(q, nbr, in, L.cin, i0, p, par, s, dst, kFwSites * kFwRow);
+        } else {
+          const bf16x8_t zero = {};
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+          for (int k = 0; k < kNch; ++k)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) y[a][c] = mk<float>(0, 0);
-      }
-      const int k0 = 2 * ((il * 9 + p) * 4);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        bf16x8_t v;
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp) {
-          v[2 * sp] = (__bf16)y[sp][c].re;
-          v[2 * sp + 1] = (__bf16)y[sp][c].im;
+            for (int c = 0; c < 3; ++c) *reinterpret_cast<bf16x8_t *>(dst + c * kFwSites * kFwRow + 8 * k) = zero;
         }
-        *reinterpret_cast<bf16x8_t *>(Bt + (c * kTile + sl) * krow + k0) = v;
+      }
+    } else {
+      // one item per thread, sites fastest (narrow activations)
+#pragma unroll 1
+      for (int w = threadIdx.x; w < kFwSites * ipc; w += kPtcThreads) {
+        const int sl = w % kFwSites, u = w / kFwSites;
+        const int qi = q0 + u, s = s0 + sl;
+        __bf16 *dst = Bt + sl * kFwRow + 8 * u;
+        if (s < q.g.Vh && qi < L.fw_items) {
+          const int p = qi / L.cin, i = qi - p * L.cin;
+          if (q.recon == 12)
+            transportn_lds<12, 1>(q, nbr, in, L.cin, i, p, par, s, dst, kFwSites * kFwRow);
+          else
+            transportn_lds<18, 1>(q, nbr, in, L.cin, i, p, par, s, dst, kFwSites * kFwRow);
+        } else {
+          const bf16x8_t zero = {};
+#pragma unroll
+          for (int c = 0; c < 3; ++c) *reinterpret_cast<bf16x8_t *>(dst + c * kFwSites * kFwRow) = zero;
+        }
       }
     }
     __syncthreads();
-    const bf16x8_t *A = (const bf16x8_t *)L.A + (size_t)ck * L.mtiles * (L.kchunk / 32) * 64;
-    for (int ks = 0; ks < L.kchunk / 32; ++ks) {
+    for (int kl = 0; kl < ipc / 4; ++kl) {
+      const int ks = q0 / 4 + kl;
+      bf16x8_t a[2];
 #pragma unroll
-      for (int t = 0; t < 6; ++t) {
-        const int tid = wave + 4 * t;
-        if (tid < ntile_total) {
-          const int mt = tid / 3, nt = tid % 3;
-          const bf16x8_t a = A[((size_t)mt * (L.kchunk / 32) + ks) * 64 + lane];
-          const bf16x8_t b = lds_frag(Bt + (nt * kTile + (lane & 15)) * krow + ks * 32 + 8 * (lane >> 4));
-          acc[t] = mfma_bf16(a, b, acc[t]);
+      for (int j = 0; j < 2; ++j)
+        if (j < nm) a[j] = A[((size_t)(mbase + 4 * j) * L.fw_ks + ks) * 64 + lane];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (t < nn) {
+          const bf16x8_t b = lds_frag(Bt + ((nbase + t) * 16 + (lane & 15)) * kFwRow + kl * 32 + 8 * (lane >> 4));
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            if (j < nm) acc[j][t] = mfma_bf16(a[j], b, acc[j][t]);
         }
       }
     }
   }
-  __syncthreads();
-  // accumulators -> LDS [site][o][spin*6 + colour*2 + re/im]
-#pragma unroll
-  for (int t = 0; t < 6; ++t) {
-    const int tid = wave + 4 * t;
-    if (tid < ntile_total) {
-      const int mt = tid / 3, nt = tid % 3;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int m = mt * 16 + 4 * (lane >> 4) + j;
-        const int mp = m >> 1, ri = m & 1;
-        const int o = mp >> 2, sp = mp & 3;
-        if (o < L.cout) Ot[((lane & 15) * L.cout + o) * 24 + sp * 6 + nt * 2 + ri] = acc[t][j];
-      }
-    }
-  }
-  __syncthreads();
+  // Row m = 16 mt + 4 g + jj (g = lane / 16) of a tile is channel o = 2 mt + g / 2,
+  // spin 2 (g % 2) + jj / 2, real/imaginary part jj % 2; column n = 16 nt + lane % 16.
   const int64_t vs = (int64_t)q.g.Vh * L.cout;
   float *blk = out + (int64_t)par * vs * 24;
-  for (int it = threadIdx.x; it < kTile * L.cout; it += kPtcThreads) {
-    const int sl = it / L.cout, o = it % L.cout;
-    const int s = s0 + sl;
-    if (s < q.g.Vh) store_spinor_reals<float, 24, float>(blk, vs, (int64_t)s * L.cout + o, Ot + it * 24);
+  const int g = lane >> 4;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (j >= nm) continue;
+    const int o = 2 * (mbase + 4 * j) + (g >> 1);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (t >= nn) continue;
+      const int n = (nbase + t) * 16 + (lane & 15);
+      const int c = n / kFwSites, s = s0 + n % kFwSites;
+      if (o < L.cout && s < q.g.Vh) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int r = (2 * (g & 1) + h) * 6 + 2 * c;  // real index of the (re, im) pair
+          float *dst = blk + ((int64_t)(r >> 2) * vs + (int64_t)s * L.cout + o) * 4 + (r & 3);
+          *reinterpret_cast<float2 *>(dst) = make_float2(acc[j][t][2 * h], acc[j][t][2 * h + 1]);
+        }
+      }
+    }
   }
 }
 
@@ -445,24 +578,22 @@ __device__ __forceinline__ float wval(const float *W, int cin, int o, int i, int
   return W[2 * ((((o * cin + i) * 9 + p) * 4 + s) * 4 + s2) + im];
 }
 
-// forward A: row m = 2*(o*4+s) + r, col k (within chunk) = 2*((il*9+p)*4+s') + r'
+// forward A: row m = 2*(o*4+s) + r, col k = 2*(q*4+s') + r' with q = p*Cin + i.
 __global__ void ptc_pack_forward_kernel(PtcLayerDev L, const float *W, bf16x8_t *A) {
-  const int ks_n = L.kchunk / 32;
-  const int total = L.nchunk * L.mtiles * ks_n * 64;
+  const int total = L.mtiles * L.fw_ks * 64;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int lane = idx % 64, ks = (idx / 64) % ks_n, mt = (idx / (64 * ks_n)) % L.mtiles;
-  const int ck = idx / (64 * ks_n * L.mtiles);
+  const int lane = idx % 64, ks = (idx / 64) % L.fw_ks, mt = idx / (64 * L.fw_ks);
   const int m = mt * 16 + (lane & 15);
   const int mp = m >> 1, r = m & 1, o = mp >> 2, s = mp & 3;
   bf16x8_t v;
   for (int j = 0; j < 8; ++j) {
     const int k = ks * 32 + 8 * (lane >> 4) + j;
     const int kp = k >> 1, r2 = k & 1;
-    const int il = kp / 36, p = (kp / 4) % 9, s2 = kp & 3;
-    const int i = ck * L.chunk_ch + il;
+    const int qi = kp >> 2, s2 = kp & 3;
+    const int p = qi / L.cin, i = qi % L.cin;
     float val = 0.f;
-    if (o < L.cout && il < L.chunk_ch && i < L.cin && kp < L.chunk_ch * 36) {
+    if (o < L.cout && qi < L.fw_items) {
       const float wr = wval(W, L.cin, o, i, p, s, s2, 0), wi = wval(W, L.cin, o, i, p, s, s2, 1);
       val = (r == 0) ? (r2 == 0 ? wr : -wi) : (r2 == 0 ? wi : wr);
     }
@@ -499,17 +630,30 @@ __global__ void ptc_pack_adjoint_kernel(PtcLayerDev L, const float *W, bf16x8_t 
 // ---------------------------------------------------------------------------
 // host launchers
 
-size_t ptc_forward_lds(const PtcLayerDev &L) { return 48 * (L.kchunk + kLdsPad) * 2 + kTile * L.cout * 24 * 4; }
 size_t ptc_bwd_data_lds(const PtcLayerDev &L) { return 48 * (L.kadj + kLdsPad) * 2; }
 size_t ptc_bwd_weight_lds(const PtcLayerDev &L) {
   const int ncol = L.chunk_ch * 36, ntn = (ncol + 15) / 16;
   return (size_t)(L.mw_tiles * 16 + ntn * 16) * (2 * 48 + kLdsPad) * 2;
 }
 
-hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const float *in, float *out, int par,
-                              hipStream_t st) {
-  const int nt = (q.g.Vh + kTile - 1) / kTile;
-  hipLaunchKernelGGL(ptc_forward_kernel, dim3(nt), dim3(kPtcThreads), ptc_forward_lds(L), st, q, L, in, out, par);
+hipError_t launch_ptc_nbr(const Geom &g, int *tab, hipStream_t st) {
+  if (g.Vh == 0) return hipSuccess;
+  hipLaunchKernelGGL(ptc_nbr_kernel, dim3((g.Vh + 255) / 256, 2), dim3(256), 0, st, g, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *nbr, const float *in, float *out,
+                              int par, int variant, hipStream_t st) {
+  switch (variant) {
+    case 642:
+      hipLaunchKernelGGL((ptc_forward_kernel<64, 2>), dim3((q.g.Vh + 63) / 64), dim3(kPtcThreads), 0, st, q, L, nbr,
+                         in, out, par);
+      break;
+    default:
+      hipLaunchKernelGGL((ptc_forward_kernel<32, 2>), dim3((q.g.Vh + 31) / 32), dim3(kPtcThreads), 0, st, q, L, nbr,
+                         in, out, par);
+      break;
+  }
   return hipGetLastError();
 }
 
@@ -544,7 +688,7 @@ hipError_t launch_ptc_weight_reduce(const PtcLayerDev &L, const float *partial, 
 
 hipError_t launch_ptc_pack(const PtcLayerDev &L, const float *W, hipStream_t st) {
   const int bt = 256;
-  const int nf = L.nchunk * L.mtiles * (L.kchunk / 32) * 64;
+  const int nf = L.mtiles * L.fw_ks * 64;
   hipLaunchKernelGGL(ptc_pack_forward_kernel, dim3((nf + bt - 1) / bt), dim3(bt), 0, st, L, W, (bf16x8_t *)L.A);
   const int na = L.madj_tiles * (L.kadj / 32) * 64;
   hipLaunchKernelGGL(ptc_pack_adjoint_kernel, dim3((na + bt - 1) / bt), dim3(bt), 0, st, L, W, (bf16x8_t *)L.Aadj);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -79,13 +80,24 @@ static lqcd_status ptc_geo(lqcd_context *ctx, const lqcd_operator *op, OpInfo *i
 static lqcd_status ptc_forward_all(lqcd_context *ctx, const PtcPlan &plan, const PtcGeo &q, const OpInfo &info,
                                    const void *in_even, std::vector<float *> &acts, hipStream_t st) {
   const size_t vh = info.vh;
+  void *nbr;
+  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 5, 2 * 8 * vh * sizeof(int), &nbr));
+  TRY(hip_check(ctx, launch_ptc_nbr(q.g, (int *)nbr, st), "ptc neighbour table"));
   // layer-0 input: r on even sites, zero on odd sites
   TRY(hip_check(ctx, hipMemcpyAsync(acts[0], in_even, vh * 24 * sizeof(float), hipMemcpyDeviceToDevice, st), "copy"));
   TRY(hip_check(ctx, hipMemsetAsync(acts[0] + vh * 24, 0, vh * 24 * sizeof(float), st), "memset"));
   for (int l = 0; l < plan.nl; ++l) {
     const bool last = l == plan.nl - 1;
+    const PtcLayerDev &L = plan.layers[l];
+    // sites per workgroup: timed once per layer shape and geometry
+    std::ostringstream key;
+    key << "ptc_fwd/" << L.cin << "-" << L.cout << "/" << geom_key(q.g);
+    const int variant = tune_pick(ctx, key.str(), {642, 322}, 642, true, st, [&](int v) {
+      return launch_ptc_forward(q, L, (const int *)nbr, acts[l], acts[l + 1], 0, v, st);
+    });
     for (int par = 0; par < (last ? 1 : 2); ++par)
-      TRY(hip_check(ctx, launch_ptc_forward(q, plan.layers[l], acts[l], acts[l + 1], par, st), "ptc forward"));
+      TRY(hip_check(ctx, launch_ptc_forward(q, L, (const int *)nbr, acts[l], acts[l + 1], par, variant, st),
+                    "ptc forward"));
   }
   return LQCD_OK;
 }

@@ -183,6 +183,138 @@ __device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// Link products of several right-hand sides on the matrix cores (16-bit
+// storage). With N sources per site the products of one hop are
+// U [3 x 2N] (3 colours x (2 half-spinor rows x N sources)), in real form
+// [[Ur, -Ui], [Ui, Ur]] (6 x 6) times (h_re; h_im) (6 x 2N). They run on
+// v_mfma_f32_4x4x4_16b_{f16,bf16}: 16 independent 4x4x4 products per
+// instruction, FP32 accumulation. A block is one site and 4 of its sources
+// (lanes 4b .. 4b+3): lane j supplies row j of the link (A operand) and the
+// half spinor of its own source (B column j), and receives U h for its own
+// source (D column j). Rows and K both run (c0 re, c0 im, c1 re, c1 im | c2 re,
+// c2 im, 0, 0): 2 M blocks x 2 K steps x 2 half-spinor rows = 8 instructions
+// per hop. Link and half-spinor entries are rounded to the storage format
+// (a reconstructed third row and the projection sums are the only new
+// roundings), products are exact and sums are FP32.
+
+typedef _Float16 mf_h4 __attribute__((ext_vector_type(4)));
+typedef short mf_s4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+template <typename S> struct Mf4;
+template <> struct Mf4<_Float16> {
+  typedef mf_h4 T;
+  __device__ __forceinline__ static T pack(float a, float b, float c, float d) {
+    return T{(_Float16)a, (_Float16)b, (_Float16)c, (_Float16)d};
+  }
+  __device__ __forceinline__ static mf_f4 mma(T a, T b, mf_f4 c) {
+    return __builtin_amdgcn_mfma_f32_4x4x4f16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mf4<bf16> {
+  typedef mf_s4 T;
+  __device__ __forceinline__ static short cv(float x) { return (short)Store<bf16>::from(x).bits; }
+  __device__ __forceinline__ static T pack(float a, float b, float c, float d) { return T{cv(a), cv(b), cv(c), cv(d)}; }
+  __device__ __forceinline__ static mf_f4 mma(T a, T b, mf_f4 c) {
+    return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+
+// A operands [M block][K step] of row j (0..3) of U (ADJ: of U^+).
+template <typename S, bool ADJ>
+__device__ __forceinline__ void mf_link_rows(const Link<float> &U, int j, typename Mf4<S>::T (&a)[2][2]) {
+  using M = Mf4<S>;
+  cpx<float> r0[3], r2[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cpx<float> e0 = ADJ ? conj(U.m[c][0]) : U.m[0][c];
+    const cpx<float> e1 = ADJ ? conj(U.m[c][1]) : U.m[1][c];
+    r0[c] = (j >> 1) ? e1 : e0;  // M block 0: colour j / 2
+    r2[c] = ADJ ? conj(U.m[c][2]) : U.m[2][c];
+  }
+  // row (colour, re) = (Re e_c, -Im e_c)_c; row (colour, im) = (Im e_c, Re e_c)_c
+  const bool im0 = j & 1;
+  a[0][0] = im0 ? M::pack(r0[0].im, r0[0].re, r0[1].im, r0[1].re) : M::pack(r0[0].re, -r0[0].im, r0[1].re, -r0[1].im);
+  a[0][1] = im0 ? M::pack(r0[2].im, r0[2].re, 0.f, 0.f) : M::pack(r0[2].re, -r0[2].im, 0.f, 0.f);
+  // M block 1: rows (c2 re, c2 im, 0, 0)
+  const float z = j < 2 ? 1.f : 0.f;
+  a[1][0] = (j == 1) ? M::pack(r2[0].im, r2[0].re, r2[1].im, r2[1].re)
+                     : M::pack(z * r2[0].re, -z * r2[0].im, z * r2[1].re, -z * r2[1].im);
+  a[1][1] = (j == 1) ? M::pack(r2[2].im, r2[2].re, 0.f, 0.f) : M::pack(z * r2[2].re, -z * r2[2].im, 0.f, 0.f);
+}
+
+template <typename S>
+__device__ __forceinline__ void mf_mul(const typename Mf4<S>::T (&a)[2][2], const cpx<float> (&h)[2][3],
+                                       cpx<float> (&u)[2][3]) {
+  using M = Mf4<S>;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const typename M::T b0 = M::pack(h[k][0].re, h[k][0].im, h[k][1].re, h[k][1].im);
+    const typename M::T b1 = M::pack(h[k][2].re, h[k][2].im, 0.f, 0.f);
+    mf_f4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+    d0 = M::mma(a[0][0], b0, d0);
+    d0 = M::mma(a[0][1], b1, d0);
+    d1 = M::mma(a[1][0], b0, d1);
+    d1 = M::mma(a[1][1], b1, d1);
+    u[k][0] = mk<float>(d0[0], d0[1]);
+    u[k][1] = mk<float>(d0[2], d0[3]);
+    u[k][2] = mk<float>(d1[0], d1[1]);
+  }
+}
+
+// Both hops of direction MU for (site s, source rhs) with the link products on
+// the matrix cores. Every lane takes part in the products (a lane without a
+// contribution supplies zeros), so there is no divergence around them.
+template <int MU, typename S, int RECON>
+__device__ __forceinline__ void wilson_dir_mf(const WArgs<S> &a, const Site &x, int s, int rhs, bool valid, float sgn,
+                                              cpx<float> (&acc)[4][3]) {
+  const int64_t vh = a.g.Vh, vs = vh * a.nrhs;
+  const int j = threadIdx.x & 3;
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {
+    const int step = dir == 0 ? 1 : -1;
+    const float g = dir == 0 ? -sgn : sgn;
+    const bool kept = valid && hop_kept<MU>(a.g, x, step);
+    int w = 0;
+    cpx<float> h[2][3];
+    Link<float> U;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) U.m[r][c] = mk<float>(0, 0);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) h[k][c] = mk<float>(0, 0);
+    if (kept) {
+      const int n = hop<MU>(a.g, x, step, &w);
+      cpx<float> psi[4][3];
+      load_spinor<S, float>(a.in, vs, (int64_t)n * a.nrhs + rhs, psi);
+      project<MU, float>(psi, g, h);
+      U = dir == 0 ? load_link<S, float, RECON>(a.gauge, vh, MU, x.p, s)
+                   : load_link<S, float, RECON>(a.gauge, vh, MU, 1 - x.p, n);
+    }
+    typename Mf4<S>::T A[2][2];
+    if (dir == 0)
+      mf_link_rows<S, false>(U, j, A);
+    else
+      mf_link_rows<S, true>(U, j, A);
+    cpx<float> u[2][3];
+    mf_mul<S>(A, h, u);
+    if (MU == 3 && (w & 1) && a.g.bc_t < 0) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) u[k][c] = -1.f * u[k][c];
+    }
+    if (dir == 0)
+      expand_acc<MU, float>(acc, u, -sgn);
+    else
+      expand_acc<MU, float>(acc, u, sgn);
+  }
+}
+
 // Per-segment sums of 3 values for the Schwarz block solver. A segment is
 // seg = min(sites per tile and parity, 64) consecutive sites (a power of two:
 // the tile's site count divides 64 or is a multiple of it), so a segment never
@@ -199,8 +331,10 @@ __device__ __forceinline__ void segment_reduce_store(double (&v)[3], int seg, in
 }
 
 // One output (site s, right-hand side rhs) of the hopping term and its epilogue.
-template <typename S, typename R, int RECON, int MODE, bool REDUCE>
-__device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, double (&red)[3]) {
+// MF: link products on the matrix cores (16-bit storage, sources in groups of
+// 4 lanes); then every lane of the wave calls this, `valid` marks real work.
+template <typename S, typename R, int RECON, int MODE, bool REDUCE, bool MF = false>
+__device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, double (&red)[3], bool valid = true) {
   const Site x = decode_site(a.g, s, a.parity);
   const R sgn = a.dagger ? R(-1) : R(1);
   cpx<R> acc[4][3];
@@ -208,10 +342,18 @@ __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, 
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[i][c] = mk<R>(0, 0);
-  wilson_dir<0, S, R, RECON>(a, x, s, rhs, sgn, acc);
-  wilson_dir<1, S, R, RECON>(a, x, s, rhs, sgn, acc);
-  wilson_dir<2, S, R, RECON>(a, x, s, rhs, sgn, acc);
-  wilson_dir<3, S, R, RECON>(a, x, s, rhs, sgn, acc);
+  if constexpr (MF) {
+    wilson_dir_mf<0, S, RECON>(a, x, s, rhs, valid, sgn, acc);
+    wilson_dir_mf<1, S, RECON>(a, x, s, rhs, valid, sgn, acc);
+    wilson_dir_mf<2, S, RECON>(a, x, s, rhs, valid, sgn, acc);
+    wilson_dir_mf<3, S, RECON>(a, x, s, rhs, valid, sgn, acc);
+    if (!valid) return;
+  } else {
+    wilson_dir<0, S, R, RECON>(a, x, s, rhs, sgn, acc);
+    wilson_dir<1, S, R, RECON>(a, x, s, rhs, sgn, acc);
+    wilson_dir<2, S, R, RECON>(a, x, s, rhs, sgn, acc);
+    wilson_dir<3, S, R, RECON>(a, x, s, rhs, sgn, acc);
+  }
   const R coef = (R)a.coef;
   const int64_t vh = a.g.Vh, vs = vh * a.nrhs, v = (int64_t)s * a.nrhs + rhs;
   cpx<R> res[4][3];
@@ -274,6 +416,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
   }
 }
 
+// Matrix-core variant for 16-bit storage and a multiple of 4 right-hand sides:
+// the same (site, rhs) pairs as wilson_kernel, 4 consecutive pairs (one site,
+// 4 sources) per 4x4x4 block. All lanes stay active through the products.
+template <typename S, int RECON, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) wilson_mf_kernel(WArgs<S> a) {
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int pidx = wg * blockDim.x + threadIdx.x;
+  const bool valid = pidx < a.g.Vh * a.nrhs;
+  const int s = valid ? (int)fdiv((uint32_t)pidx, a.dN) : 0;
+  double red[3];
+  wilson_point<S, float, RECON, MODE, false, true>(a, s, valid ? pidx - s * a.nrhs : 0, red, valid);
+}
+
 // Persistent launch over several operators (uneven lattices, several
 // right-hand sides each): workgroups take work items of `chunk` (site, rhs)
 // pairs from a global counter until every item of every job is done.
@@ -283,6 +438,7 @@ template <typename S> struct BatchArgs {
   int begin[kMaxBatchJobs + 1];  // first work item of each job (prefix sums)
   int njobs;
   int chunk;
+  int mfma;           // 16-bit jobs with a multiple of 4 sources: link products on the matrix cores
   unsigned *counter;  // zero at launch
 };
 
@@ -303,8 +459,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     const int npairs = a.g.Vh * a.nrhs;
     for (int q = threadIdx.x; q < b.chunk; q += blockDim.x) {
       const int pidx = first + q;
+      double red[3];
+      if constexpr (sizeof(S) == 2) {
+        if (b.mfma && a.nrhs % 4 == 0) {  // uniform over the workgroup; the chunk is a multiple of 64
+          const bool valid = pidx < npairs;
+          const int s = valid ? (int)fdiv((uint32_t)pidx, a.dN) : 0;
+          wilson_point<S, R, RECON, W_HOP, false, true>(a, s, valid ? pidx - s * a.nrhs : 0, red, valid);
+          continue;
+        }
+      }
       if (pidx < npairs) {
-        double red[3];
         const int s = (int)fdiv((uint32_t)pidx, a.dN);
         wilson_point<S, R, RECON, W_HOP, false>(a, s, pidx - s * a.nrhs, red);
       }
@@ -403,6 +567,14 @@ static hipError_t launch_w3(const WilsonLaunch &w, hipStream_t st) {
   a.nrhs = w.nrhs;
   a.dN = make_fastdiv(w.nrhs);
   const int nwg = (int)(((int64_t)w.g.Vh * w.nrhs + w.block_threads - 1) / w.block_threads);
+  if constexpr ((P == LQCD_F16 || P == LQCD_BF16) && !RED) {
+    if (w.mfma) {
+      if (w.nrhs % 4 || w.block_threads % 64) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((wilson_mf_kernel<S, RECON, MODE>), dim3(nwg), dim3(w.block_threads), 0, st, a);
+      return hipGetLastError();
+    }
+  }
+  if (w.mfma) return hipErrorInvalidValue;
   hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED>), dim3(nwg), dim3(w.block_threads), 0, st, a);
   return hipGetLastError();
 }
@@ -464,13 +636,15 @@ hipError_t launch_clover_apply(const Geom &g, int prec, void *out, const void *i
 }
 
 template <int P, int RECON>
-static hipError_t launch_b2(const BatchJob *jobs, int njobs, int dagger, const BatchTune &t, unsigned *counter,
-                            hipStream_t st) {
+static hipError_t launch_b2(const BatchJob *jobs, int njobs, int dagger, const BatchTune &t, int mfma,
+                            unsigned *counter, hipStream_t st) {
   using S = typename Prec<P>::S;
   using R = typename Prec<P>::R;
   BatchArgs<S> b;
   b.njobs = njobs;
   b.chunk = t.chunk;
+  b.mfma = mfma;
+  if (mfma && (t.chunk % 64 || t.block_threads % 64)) return hipErrorInvalidValue;
   b.counter = counter;
   b.begin[0] = 0;
   for (int j = 0; j < njobs; ++j) {
@@ -496,26 +670,27 @@ static hipError_t launch_b2(const BatchJob *jobs, int njobs, int dagger, const B
 }
 
 template <int P>
-static hipError_t launch_b1(int recon, const BatchJob *jobs, int njobs, int dagger, const BatchTune &t, unsigned *c,
-                            hipStream_t st) {
+static hipError_t launch_b1(int recon, const BatchJob *jobs, int njobs, int dagger, const BatchTune &t, int mf,
+                            unsigned *c, hipStream_t st) {
   switch (recon) {
-    case 18: return launch_b2<P, 18>(jobs, njobs, dagger, t, c, st);
-    case 12: return launch_b2<P, 12>(jobs, njobs, dagger, t, c, st);
+    case 18: return launch_b2<P, 18>(jobs, njobs, dagger, t, mf, c, st);
+    case 12: return launch_b2<P, 12>(jobs, njobs, dagger, t, mf, c, st);
     case 8:
-      if constexpr (P == LQCD_F64 || P == LQCD_F32) return launch_b2<P, 8>(jobs, njobs, dagger, t, c, st);
+      if constexpr (P == LQCD_F64 || P == LQCD_F32) return launch_b2<P, 8>(jobs, njobs, dagger, t, mf, c, st);
       break;
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_wilson_batch(int prec, int recon, const BatchJob *jobs, int njobs, int dagger, const BatchTune &t,
-                               unsigned *counter, hipStream_t st) {
+                               int mfma, unsigned *counter, hipStream_t st) {
   if (njobs < 1 || njobs > kMaxBatchJobs) return hipErrorInvalidValue;
+  if (mfma && prec != LQCD_F16 && prec != LQCD_BF16) return hipErrorInvalidValue;
   switch (prec) {
-    case LQCD_F64: return launch_b1<LQCD_F64>(recon, jobs, njobs, dagger, t, counter, st);
-    case LQCD_F32: return launch_b1<LQCD_F32>(recon, jobs, njobs, dagger, t, counter, st);
-    case LQCD_F16: return launch_b1<LQCD_F16>(recon, jobs, njobs, dagger, t, counter, st);
-    case LQCD_BF16: return launch_b1<LQCD_BF16>(recon, jobs, njobs, dagger, t, counter, st);
+    case LQCD_F64: return launch_b1<LQCD_F64>(recon, jobs, njobs, dagger, t, mfma, counter, st);
+    case LQCD_F32: return launch_b1<LQCD_F32>(recon, jobs, njobs, dagger, t, mfma, counter, st);
+    case LQCD_F16: return launch_b1<LQCD_F16>(recon, jobs, njobs, dagger, t, mfma, counter, st);
+    case LQCD_BF16: return launch_b1<LQCD_BF16>(recon, jobs, njobs, dagger, t, mfma, counter, st);
   }
   return hipErrorInvalidValue;
 }

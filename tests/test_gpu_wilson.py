@@ -197,10 +197,74 @@ def test_multi_rhs_equals_single(ctx, prec, recon):
         assert np.array_equal(np_of(o.export_spinor(es, 0)), cmulti[r])
 
 
+@pytest.fixture
+def matrix_cores(monkeypatch):
+    """Link products of 16-bit multi-source hops on the matrix cores."""
+    monkeypatch.setenv("LQCD_MRHS_MFMA", "1")
+
+
+@pytest.mark.parametrize("prec,recon", [(2, 18), (2, 12), (3, 18), (3, 12)])
+@pytest.mark.parametrize("dims,nr", [((6, 6, 2, 2), 4), ((4, 4, 6, 8), 8), ((4, 4, 4, 4), 12)])
+def test_multi_rhs_matrix_cores(ctx, matrix_cores, prec, recon, dims, nr):
+    """16-bit operators with a multiple of 4 sources take the link products on
+    the matrix cores: every source of dslash (both parities, dagger) and of the
+    Schur operator against the oracle, and against its single-source result,
+    within the storage-precision bound. (6,6,2,2) with 4 sources leaves half a
+    wave of idle lanes at the end."""
+    U = synth.gauge_field(dims, 0.25, 31)
+    o = ops.wilson_clover(ctx, U, dims, 0.124, 1.0, prec, recon)
+    ref_op = oracle.WilsonClover(dims, U, 0.124, 1.0, bc_t=-1)
+    for p in (0, 1):
+        srcs = np.stack([on_parity(synth.gaussian_spinor(dims, 300 + r), oracle.parity_mask(dims, 1 - p))
+                         for r in range(nr)])
+        inp = o.import_spinor(srcs, 1 - p, nrhs=nr)
+        for dagger in (0, 1):
+            out = o.spinor(nrhs=nr)
+            L.lqcd_dslash(ctx, o.op, out, inp, p, dagger, nrhs=nr)
+            multi = np_of(o.export_spinor(out, p, nrhs=nr))
+            for r in (0, nr // 2, nr - 1):
+                ref = oracle.wilson_dslash(dims, U, srcs[r], out_parity=p, dagger=bool(dagger))
+                assert rel(multi[r], ref) < TOL[prec], (p, dagger, r)
+                single = o.spinor()
+                L.lqcd_dslash(ctx, o.op, single, o.import_spinor(srcs[r], 1 - p), p, dagger)
+                assert rel(multi[r], np_of(o.export_spinor(single, p))) < TOL[prec]
+    esrc = np.stack([on_parity(synth.gaussian_spinor(dims, 400 + r), ref_op.even) for r in range(nr)])
+    eout = o.spinor(nrhs=nr)
+    L.lqcd_schur_apply(ctx, o.op, eout, o.import_spinor(esrc, 0, nrhs=nr), nrhs=nr)
+    emulti = np_of(o.export_spinor(eout, 0, nrhs=nr))
+    for r in (0, nr - 1):
+        assert rel(emulti[r], ref_op.schur(esrc[r])) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_multi_rhs_matrix_cores_dirichlet_cut(ctx, matrix_cores, prec):
+    dims, block, nr = (8, 8, 8, 8), (4, 4, 4, 4), 4
+    U, psi, _ = Fields.get(dims)
+    o = make_op(ctx, dims, prec, 12, tile=(4, 4, 4, 4))
+    srcs = np.stack([on_parity(synth.gaussian_spinor(dims, 500 + r), oracle.parity_mask(dims, 1)) for r in range(nr)])
+    out = o.spinor(nrhs=nr)
+    L.lqcd_dslash(ctx, o.op, out, o.import_spinor(srcs, 1, nrhs=nr), 0, 1, block=block, nrhs=nr)
+    multi = np_of(o.export_spinor(out, 0, nrhs=nr))
+    for r in range(nr):
+        ref = oracle.wilson_dslash(dims, U, srcs[r], out_parity=0, dagger=True, block=block)
+        assert rel(multi[r], ref) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec,recon", [(0, 18), (1, 12), (2, 12), (3, 12)])
 def test_batched_persistent_uneven_lattices(ctx, prec, recon):
     """One persistent launch over lattices of different size and rhs count
     equals the per-operator dslash (bitwise) and the oracle (per-precision bound)."""
+    run_batch(ctx, prec, recon)
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_batched_persistent_matrix_cores(ctx, matrix_cores, prec):
+    """The persistent launch takes the same matrix-core path per job as the
+    per-operator dslash (4- and 12-source jobs), the vector path for 1 source."""
+    run_batch(ctx, prec, 12)
+
+
+def run_batch(ctx, prec, recon):
     shapes = [((4, 4, 4, 8), 4), ((6, 6, 6, 12), 4), ((8, 8, 8, 8), 12), ((4, 6, 4, 6), 1)]
     jobs, ref_single, refs = [], [], []
     keep = []
@@ -218,6 +282,10 @@ def test_batched_persistent_uneven_lattices(ctx, prec, recon):
     L.lqcd_dslash_batch(ctx, jobs)
     L.lqcd_dslash_batch(ctx, jobs)  # second call: tuned parameters
     torch.cuda.synchronize()
+    check_batch(keep, prec)
+
+
+def check_batch(keep, prec):
     for o, out, inp, single, srcs, U, dims, nr in keep:
         assert torch.equal(out, single)
         got = np_of(o.export_spinor(out, 0, nrhs=nr))
