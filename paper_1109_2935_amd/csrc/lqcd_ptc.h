@@ -59,12 +59,15 @@ inline size_t ptc_adj_frag_bytes(const PtcLayerDev &L) { return (size_t)L.madj_t
 // neighbour table of the 8 hop paths, 2 * 8 * Vh ints (see ptc_nbr_kernel)
 hipError_t launch_ptc_nbr(const Geom &g, int *tab, hipStream_t st);
 // variant: 10 x sites per workgroup + waves per SIMD hint: 642 or 322
-hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *nbr, const float *in, float *out,
-                              int par, int variant, hipStream_t st);
+// in: BF16 activations; out: BF16 activations, or (out_f32, one channel) an FP32 packed spinor
+hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *nbr, const void *in, void *out,
+                              int out_f32, int par, int variant, hipStream_t st);
+// layer-0 activations from an FP32 packed even field
+hipError_t launch_ptc_input(int64_t vh, const void *in_even, void *act, hipStream_t st);
 hipError_t launch_ptc_bwd_data(const PtcGeo &q, const PtcLayerDev &L, const float *delta, float *gy, int par,
                                hipStream_t st);
 hipError_t launch_ptc_adjoint_gather(const PtcGeo &q, int cin, const float *gy, float *gpsi, int par, hipStream_t st);
-hipError_t launch_ptc_bwd_weight(const PtcGeo &q, const PtcLayerDev &L, const float *in, const float *delta,
+hipError_t launch_ptc_bwd_weight(const PtcGeo &q, const PtcLayerDev &L, const void *in, const float *delta,
                                  float *partial, int par, int groups, hipStream_t st);
 hipError_t launch_ptc_weight_reduce(const PtcLayerDev &L, const float *partial, int groups, float *gw, int accumulate,
                                     hipStream_t st);

@@ -7,8 +7,10 @@
 // no such network; it is used as a learned preconditioner of flexible GCR
 // (Section III-B: the outer solver must be flexible).
 //
-// Activations are FP32, channel-interleaved per site (packed spinor index
-// site * C + channel). The channel mixing is a complex GEMM
+// Activations between layers are BF16, channel-interleaved per site (packed
+// index site * C + channel) in 16-byte chunks of 8 reals, chunk-major within
+// each parity block (act_load / act_store); the network output is an FP32
+// packed spinor. The channel mixing is a complex GEMM
 //   O[(o,s)][(c,x)] = sum_{(i,p,s')} W[(o,s)][(i,p,s')] Y[(i,p,s')][(c,x)],
 // Y = T_p psi_i, run on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
 // accumulation) in real form with interleaved real/imaginary rows:
@@ -29,23 +31,28 @@ constexpr int kTile = 16;      // sites per workgroup tile
 constexpr int kPtcThreads = 256;
 constexpr int kLdsPad = 8;     // bf16 padding per LDS row (bank spread)
 
+// activation access: 24 reals of packed index idx in a parity block of vs entries
+__device__ __forceinline__ void act_load(const bf16 *__restrict__ blk, int64_t vs, int64_t idx, float *r) {
+  load_chunks<bf16, 24, 8, float>(blk, vs, idx, r);
+}
+
 __device__ __forceinline__ f32x4_t mfma_bf16(const bf16x8_t &a, const bf16x8_t &b, const f32x4_t &c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// (T_p psi)(x) for one channel of a channel-interleaved FP32 field.
+// (T_p psi)(x) for one channel of a channel-interleaved activation field.
 // x: site index of parity `par`; the identity path reads parity par, the hops
 // read parity 1 - par. Boundary phases as in the Dirac operator.
 template <int RECON>
-__device__ __forceinline__ void transport_one(const PtcGeo &q, const float *__restrict__ act, int C, int ch, int p,
+__device__ __forceinline__ void transport_one(const PtcGeo &q, const bf16 *__restrict__ act, int C, int ch, int p,
                                               const Site &x, int s, cpx<float> (&out)[4][3]) {
   const int par = x.p;
   const int64_t vh = q.g.Vh, vs = vh * C;
-  const float *blk_same = act + (int64_t)par * vs * 24;
-  const float *blk_other = act + (int64_t)(1 - par) * vs * 24;
+  const bf16 *blk_same = act + (int64_t)par * vs * 24;
+  const bf16 *blk_other = act + (int64_t)(1 - par) * vs * 24;
   float r[24];
   if (p == 0) {
-    load_spinor_reals<float, 24, float>(blk_same, vs, (int64_t)s * C + ch, r);
+    act_load(blk_same, vs, (int64_t)s * C + ch, r);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -61,7 +68,7 @@ __device__ __forceinline__ void transport_one(const PtcGeo &q, const float *__re
     case 2: n = hop<2>(q.g, x, fwd ? 1 : -1, &w); break;
     default: n = hop<3>(q.g, x, fwd ? 1 : -1, &w); break;
   }
-  load_spinor_reals<float, 24, float>(blk_other, vs, (int64_t)n * C + ch, r);
+  act_load(blk_other, vs, (int64_t)n * C + ch, r);
   float lv[RECON];
   if (fwd)
     load_site<float, RECON, float>(q.gauge + (int64_t)(2 * mu + par) * vh * RECON, vh, s, lv);
@@ -84,12 +91,12 @@ __device__ __forceinline__ void transport_one(const PtcGeo &q, const float *__re
 }
 
 template <int RECON>
-__device__ __forceinline__ void transport_dispatch(const PtcGeo &q, const float *act, int C, int ch, int p,
+__device__ __forceinline__ void transport_dispatch(const PtcGeo &q, const bf16 *act, int C, int ch, int p,
                                                    const Site &x, int s, cpx<float> (&out)[4][3]) {
   transport_one<RECON>(q, act, C, ch, p, x, s, out);
 }
 
-__device__ __forceinline__ void transport_any(const PtcGeo &q, const float *act, int C, int ch, int p, const Site &x,
+__device__ __forceinline__ void transport_any(const PtcGeo &q, const bf16 *act, int C, int ch, int p, const Site &x,
                                               int s, cpx<float> (&out)[4][3]) {
   if (q.recon == 12)
     transport_dispatch<12>(q, act, C, ch, p, x, s, out);
@@ -119,13 +126,15 @@ __global__ void ptc_nbr_kernel(Geom g, int *tab) {
 #undef PTC_NBR
 }
 
-// Transport of NCH consecutive channels i0 .. i0+NCH-1 of one path p at site s
-// of parity par, written to LDS as BF16 (row stride `cstride` between colours,
-// 8 K values per channel: spin-major, re/im interleaved). The link and the
-// neighbour are read once; the NCH channel loads are issued together.
+// Transport of NCH channels i0, i0 + kstep, ... of one path p at site s of
+// parity par, written to LDS as BF16 (row stride `cstride` between colours, 8
+// K values per channel: spin-major, re/im interleaved; channel i0 + k kstep at
+// column 8 k kstep). The link and the neighbour are read once; the NCH
+// channel loads are issued together.
 template <int RECON, int NCH>
-__device__ __forceinline__ void transportn_lds(const PtcGeo &q, const int *__restrict__ nbr, const float *__restrict__ act,
-                                               int C, int i0, int p, int par, int s, __bf16 *dst, int cstride) {
+__device__ __forceinline__ void transportn_lds(const PtcGeo &q, const int *__restrict__ nbr, const bf16 *__restrict__ act,
+                                               int C, int i0, int kstep, int p, int par, int s, __bf16 *dst,
+                                               int cstride) {
   const int64_t vh = q.g.Vh, vs = vh * C;
   int n = s;
   float ph = 1.f;
@@ -134,10 +143,10 @@ __device__ __forceinline__ void transportn_lds(const PtcGeo &q, const int *__res
     n = e & 0x7fffffff;
     ph = e < 0 ? -1.f : 1.f;
   }
-  const float *blk = act + (int64_t)(p == 0 ? par : 1 - par) * vs * 24;
+  const bf16 *blk = act + (int64_t)(p == 0 ? par : 1 - par) * vs * 24;
   float r[NCH][24];
 #pragma unroll
-  for (int k = 0; k < NCH; ++k) load_spinor_reals<float, 24, float>(blk, vs, (int64_t)n * C + i0 + k, r[k]);
+  for (int k = 0; k < NCH; ++k) act_load(blk, vs, (int64_t)n * C + i0 + k * kstep, r[k]);
   if (p != 0) {
     const int mu = (p - 1) >> 1;
     const bool fwd = ((p - 1) & 1) == 0;
@@ -180,7 +189,7 @@ __device__ __forceinline__ void transportn_lds(const PtcGeo &q, const int *__res
         v[2 * sp] = (__bf16)r[k][6 * sp + 2 * c];
         v[2 * sp + 1] = (__bf16)r[k][6 * sp + 2 * c + 1];
       }
-      *reinterpret_cast<bf16x8_t *>(dst + c * cstride + 8 * k) = v;
+      *reinterpret_cast<bf16x8_t *>(dst + c * cstride + 8 * k * kstep) = v;
     }
 }
 
@@ -205,7 +214,7 @@ constexpr int kFwRow = 16 * 8 + kLdsPad;  // bf16 per LDS row: 16 items x 8 K va
 
 template <int NS, int WPE>
 __global__ void __launch_bounds__(kPtcThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
-ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const float *in, float *out, int par) {
+ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void *out, int out_f32, int par) {
   constexpr int kFwSites = NS, NT = 3 * NS / 16;
   __shared__ __align__(16) __bf16 Bt[3 * NS * kFwRow];
   const int s0 = blockIdx.x * kFwSites;
@@ -231,53 +240,8 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const float *in, flo
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[j][t] = f32x4_t{0, 0, 0, 0};
   const bf16x8_t *A = (const bf16x8_t *)L.A;
-  for (int q0 = 0; q0 < 4 * L.fw_ks; q0 += L.fw_ipc) {
-    const int ipc = min(L.fw_ipc, 4 * L.fw_ks - q0);
-    __syncthreads();
-    if (L.cin % 4 == 0) {
-      // kNch consecutive items (one site and path, kNch channels) per thread
-      constexpr int kNch = 2;
-      const int gn = ipc / kNch;
-#pragma unroll 1
-      for (int w = threadIdx.x; w < kFwSites * gn; w += kPtcThreads) {
-        const int un = w % gn, sl = w / gn;
-        const int qi = q0 + kNch * un, s = s0 + sl;
-        __bf16 *dst = Bt + sl * kFwRow + 8 * kNch * un;
-        if (s < q.g.Vh && qi < L.fw_items) {
-          const int p = qi / L.cin, i0 = qi - p * L.cin;
-          if (q.recon == 12)
-            transportn_lds<12, kNch>(q, nbr, in, L.cin, i0, p, par, s, dst, kFwSites * kFwRow);
-          else
-            transportn_lds<18, kNch>(q, nbr, in, L.cin, i0, p, par, s, dst, kFwSites * kFwRow);
-        } else {
-          const bf16x8_t zero = {};
-#pragma unroll
-          for (int k = 0; k < kNch; ++k)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) *reinterpret_cast<bf16x8_t *>(dst + c * kFwSites * kFwRow + 8 * k) = zero;
-        }
-      }
-    } else {
-      // one item per thread, sites fastest (narrow activations)
-#pragma unroll 1
-      for (int w = threadIdx.x; w < kFwSites * ipc; w += kPtcThreads) {
-        const int sl = w % kFwSites, u = w / kFwSites;
-        const int qi = q0 + u, s = s0 + sl;
-        __bf16 *dst = Bt + sl * kFwRow + 8 * u;
-        if (s < q.g.Vh && qi < L.fw_items) {
-          const int p = qi / L.cin, i = qi - p * L.cin;
-          if (q.recon == 12)
-            transportn_lds<12, 1>(q, nbr, in, L.cin, i, p, par, s, dst, kFwSites * kFwRow);
-          else
-            transportn_lds<18, 1>(q, nbr, in, L.cin, i, p, par, s, dst, kFwSites * kFwRow);
-        } else {
-          const bf16x8_t zero = {};
-#pragma unroll
-          for (int c = 0; c < 3; ++c) *reinterpret_cast<bf16x8_t *>(dst + c * kFwSites * kFwRow) = zero;
-        }
-      }
-    }
-    __syncthreads();
+  // one K chunk (items q0 .. q0+ipc-1) from LDS into the accumulators
+  auto mma_chunk = [&](int q0, int ipc) {
     for (int kl = 0; kl < ipc / 4; ++kl) {
       const int ks = q0 / 4 + kl;
       bf16x8_t a[2];
@@ -294,29 +258,248 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const float *in, flo
         }
       }
     }
+  };
+  if (L.cin == 16 && kFwSites * 8 == kPtcThreads) {
+    // 16 input channels, one thread per (site, channel pair un, un + 8), one
+    // path per chunk; the loads of path p + 1 are issued before the matrix
+    // products of path p, so their latency overlaps them.
+    __shared__ int nbL[kFwSites][8];
+    const int un = threadIdx.x & 7, sl = threadIdx.x >> 3, s = s0 + sl;
+    const bool valid = s < q.g.Vh;
+    const int64_t vh = q.g.Vh, vs = vh * 16;
+    nbL[sl][un] = valid ? nbr[((int64_t)par * 8 + un) * vh + s] : 0;
+    __syncthreads();
+    uint4 raw[2][3];
+    float lv[18] = {};
+    auto issue = [&](int p) {
+      if (!valid) return;
+      const int n = p == 0 ? s : (nbL[sl][p - 1] & 0x7fffffff);
+      const bf16 *blk = in + (int64_t)(p == 0 ? par : 1 - par) * vs * 24;
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          raw[k][c] = *reinterpret_cast<const uint4 *>(blk + ((int64_t)c * vs + (int64_t)n * 16 + un + 8 * k) * 8);
+      if (p != 0) {
+        const int mu = (p - 1) >> 1;
+        const bool fwd = ((p - 1) & 1) == 0;
+        const int lsite = fwd ? s : n, lpar = fwd ? par : 1 - par;
+        if (q.recon == 12) {
+          float t[12];
+          load_site<float, 12, float>(q.gauge + (int64_t)(2 * mu + lpar) * vh * 12, vh, lsite, t);
+#pragma unroll
+          for (int i = 0; i < 12; ++i) lv[i] = t[i];
+        } else {
+          float t[18];
+          load_site<float, 18, float>(q.gauge + (int64_t)(2 * mu + lpar) * vh * 18, vh, lsite, t);
+#pragma unroll
+          for (int i = 0; i < 18; ++i) lv[i] = t[i];
+        }
+      }
+    };
+    auto compute = [&](int p) {
+      __bf16 *dst = Bt + sl * kFwRow + 8 * un;
+      if (!valid) {
+        const bf16x8_t zero = {};
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) *reinterpret_cast<bf16x8_t *>(dst + c * kFwSites * kFwRow + 64 * k) = zero;
+        return;
+      }
+      float r[2][24];
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const uint4 w4 = raw[k][c];
+          r[k][8 * c + 0] = __uint_as_float(w4.x << 16);
+          r[k][8 * c + 1] = __uint_as_float(w4.x & 0xffff0000u);
+          r[k][8 * c + 2] = __uint_as_float(w4.y << 16);
+          r[k][8 * c + 3] = __uint_as_float(w4.y & 0xffff0000u);
+          r[k][8 * c + 4] = __uint_as_float(w4.z << 16);
+          r[k][8 * c + 5] = __uint_as_float(w4.z & 0xffff0000u);
+          r[k][8 * c + 6] = __uint_as_float(w4.w << 16);
+          r[k][8 * c + 7] = __uint_as_float(w4.w & 0xffff0000u);
+        }
+      if (p != 0) {
+        const bool fwd = ((p - 1) & 1) == 0;
+        const float ph = nbL[sl][p - 1] < 0 ? -1.f : 1.f;
+        Link<float> U0;
+        if (q.recon == 12)
+          U0 = unpack_link<12, float>(lv);
+        else
+          U0 = unpack_link<18, float>(lv);
+        Link<float> U;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) U.m[a][b] = ph * (fwd ? U0.m[a][b] : conj(U0.m[b][a]));
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+          for (int sp = 0; sp < 4; ++sp) {
+            cpx<float> v[3], u[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[c] = mk<float>(r[k][6 * sp + 2 * c], r[k][6 * sp + 2 * c + 1]);
+            su3_mv(U, v, u);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              r[k][6 * sp + 2 * c] = u[c].re;
+              r[k][6 * sp + 2 * c + 1] = u[c].im;
+            }
+          }
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          bf16x8_t v;
+#pragma unroll
+          for (int sp = 0; sp < 4; ++sp) {
+            v[2 * sp] = (__bf16)r[k][6 * sp + 2 * c];
+            v[2 * sp + 1] = (__bf16)r[k][6 * sp + 2 * c + 1];
+          }
+          *reinterpret_cast<bf16x8_t *>(dst + c * kFwSites * kFwRow + 64 * k) = v;
+        }
+    };
+    issue(0);
+#pragma unroll 1
+    for (int p = 0; p < 9; ++p) {
+      __syncthreads();
+      compute(p);
+      if (p + 1 < 9) issue(p + 1);
+      __syncthreads();
+      mma_chunk(16 * p, 16);
+    }
+  } else {
+  for (int q0 = 0; q0 < 4 * L.fw_ks; q0 += L.fw_ipc) {
+    const int ipc = min(L.fw_ipc, 4 * L.fw_ks - q0);
+    __syncthreads();
+    if (L.cin % 4 == 0) {
+      // kNch items (one site and path) per thread: channels un and un + gn of
+      // the chunk when it is one path (lanes of a site then read whole cache
+      // lines), else kNch consecutive channels
+      constexpr int kNch = 2;
+      const int gn = ipc / kNch;
+      const bool one_path = ipc == L.cin;
+#pragma unroll 1
+      for (int w = threadIdx.x; w < kFwSites * gn; w += kPtcThreads) {
+        const int un = w % gn, sl = w / gn;
+        const int u0 = one_path ? un : kNch * un, kstep = one_path ? gn : 1;
+        const int qi = q0 + u0, s = s0 + sl;
+        __bf16 *dst = Bt + sl * kFwRow + 8 * u0;
+        if (s < q.g.Vh && qi < L.fw_items) {
+          const int p = qi / L.cin, i0 = qi - p * L.cin;
+          if (q.recon == 12)
+            transportn_lds<12, kNch>(q, nbr, in, L.cin, i0, kstep, p, par, s, dst, kFwSites * kFwRow);
+          else
+            transportn_lds<18, kNch>(q, nbr, in, L.cin, i0, kstep, p, par, s, dst, kFwSites * kFwRow);
+        } else {
+          const bf16x8_t zero = {};
+#pragma unroll
+          for (int k = 0; k < kNch; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              *reinterpret_cast<bf16x8_t *>(dst + c * kFwSites * kFwRow + 8 * k * kstep) = zero;
+        }
+      }
+    } else {
+      // one item per thread, sites fastest (narrow activations)
+#pragma unroll 1
+      for (int w = threadIdx.x; w < kFwSites * ipc; w += kPtcThreads) {
+        const int sl = w % kFwSites, u = w / kFwSites;
+        const int qi = q0 + u, s = s0 + sl;
+        __bf16 *dst = Bt + sl * kFwRow + 8 * u;
+        if (s < q.g.Vh && qi < L.fw_items) {
+          const int p = qi / L.cin, i = qi - p * L.cin;
+          if (q.recon == 12)
+            transportn_lds<12, 1>(q, nbr, in, L.cin, i, 1, p, par, s, dst, kFwSites * kFwRow);
+          else
+            transportn_lds<18, 1>(q, nbr, in, L.cin, i, 1, p, par, s, dst, kFwSites * kFwRow);
+        } else {
+          const bf16x8_t zero = {};
+#pragma unroll
+          for (int c = 0; c < 3; ++c) *reinterpret_cast<bf16x8_t *>(dst + c * kFwSites * kFwRow) = zero;
+        }
+      }
+    }
+    __syncthreads();
+    mma_chunk(q0, ipc);
+  }
   }
   // Row m = 16 mt + 4 g + jj (g = lane / 16) of a tile is channel o = 2 mt + g / 2,
   // spin 2 (g % 2) + jj / 2, real/imaginary part jj % 2; column n = 16 nt + lane % 16.
-  const int64_t vs = (int64_t)q.g.Vh * L.cout;
-  float *blk = out + (int64_t)par * vs * 24;
+  // The tile is staged in LDS as [site][channel][24 reals] (rows padded by 16
+  // bytes against bank conflicts), then stored in whole 16-byte chunks.
+  __syncthreads();
   const int g = lane >> 4;
+  const int64_t vs = (int64_t)q.g.Vh * L.cout;
+  if (!out_f32) {
+    __bf16 *St = Bt;
+    const int srow = L.cout * 24 + 8;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    if (j >= nm) continue;
-    const int o = 2 * (mbase + 4 * j) + (g >> 1);
+    for (int j = 0; j < 2; ++j) {
+      if (j >= nm) continue;
+      const int o = 2 * (mbase + 4 * j) + (g >> 1);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (t >= nn) continue;
-      const int n = (nbase + t) * 16 + (lane & 15);
-      const int c = n / kFwSites, s = s0 + n % kFwSites;
-      if (o < L.cout && s < q.g.Vh) {
+      for (int t = 0; t < NT; ++t) {
+        if (t >= nn) continue;
+        const int n = (nbase + t) * 16 + (lane & 15);
+        const int c = n / kFwSites, sl = n % kFwSites;
+        if (o < L.cout) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int r = (2 * (g & 1) + h) * 6 + 2 * c;  // real index of the (re, im) pair
-          float *dst = blk + ((int64_t)(r >> 2) * vs + (int64_t)s * L.cout + o) * 4 + (r & 3);
-          *reinterpret_cast<float2 *>(dst) = make_float2(acc[j][t][2 * h], acc[j][t][2 * h + 1]);
+          for (int h = 0; h < 2; ++h) {
+            const int r = (2 * (g & 1) + h) * 6 + 2 * c;
+            St[sl * srow + o * 24 + r] = (__bf16)acc[j][t][2 * h];
+            St[sl * srow + o * 24 + r + 1] = (__bf16)acc[j][t][2 * h + 1];
+          }
         }
       }
+    }
+    __syncthreads();
+    bf16 *blk = (bf16 *)out + (int64_t)par * vs * 24;
+    const int per_chunk = kFwSites * L.cout;
+    for (int w = threadIdx.x; w < 3 * per_chunk; w += kPtcThreads) {
+      const int k = w / per_chunk, rem = w - k * per_chunk;
+      const int sl = rem / L.cout, o = rem - sl * L.cout;
+      const int s = s0 + sl;
+      if (s < q.g.Vh)
+        *reinterpret_cast<uint4 *>(blk + ((int64_t)k * vs + (int64_t)s * L.cout + o) * 8) =
+            *reinterpret_cast<const uint4 *>(St + sl * srow + o * 24 + 8 * k);
+    }
+  } else {
+    // FP32 packed spinor (chunks of 4 reals); the network's last layer (one channel)
+    float *Sf = reinterpret_cast<float *>(Bt);
+    const int srow = L.cout * 24 + 4;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (j >= nm) continue;
+      const int o = 2 * (mbase + 4 * j) + (g >> 1);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (t >= nn) continue;
+        const int n = (nbase + t) * 16 + (lane & 15);
+        const int c = n / kFwSites, sl = n % kFwSites;
+        if (o < L.cout) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int r = (2 * (g & 1) + h) * 6 + 2 * c;
+            *reinterpret_cast<float2 *>(Sf + sl * srow + o * 24 + r) = make_float2(acc[j][t][2 * h], acc[j][t][2 * h + 1]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    float *blk = (float *)out + (int64_t)par * vs * 24;
+    const int per_chunk = kFwSites * L.cout;
+    for (int w = threadIdx.x; w < 6 * per_chunk; w += kPtcThreads) {
+      const int k = w / per_chunk, rem = w - k * per_chunk;
+      const int sl = rem / L.cout, o = rem - sl * L.cout;
+      const int s = s0 + sl;
+      if (s < q.g.Vh)
+        *reinterpret_cast<float4 *>(blk + ((int64_t)k * vs + (int64_t)s * L.cout + o) * 4) =
+            *reinterpret_cast<const float4 *>(Sf + sl * srow + o * 24 + 4 * k);
     }
   }
 }
@@ -453,7 +636,7 @@ __global__ void __launch_bounds__(256) ptc_adjoint_gather_kernel(PtcGeo q, int c
 // i.e. G = (Re, Im) of sum_x delta (T psi)^+. A workgroup owns one input
 // channel chunk and a strided set of site tiles of parity par.
 
-__global__ void __launch_bounds__(kPtcThreads) ptc_bwd_weight_kernel(PtcGeo q, PtcLayerDev L, const float *in,
+__global__ void __launch_bounds__(kPtcThreads) ptc_bwd_weight_kernel(PtcGeo q, PtcLayerDev L, const bf16 *in,
                                                                       const float *delta, float *partial, int par,
                                                                       int groups) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -642,18 +825,39 @@ hipError_t launch_ptc_nbr(const Geom &g, int *tab, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *nbr, const float *in, float *out,
-                              int par, int variant, hipStream_t st) {
+hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *nbr, const void *in, void *out,
+                              int out_f32, int par, int variant, hipStream_t st) {
+  // LDS staging of the output tile: BF16 up to 16 channels; FP32 one channel
+  if (out_f32 && L.cout != 1) return hipErrorInvalidValue;
   switch (variant) {
     case 642:
       hipLaunchKernelGGL((ptc_forward_kernel<64, 2>), dim3((q.g.Vh + 63) / 64), dim3(kPtcThreads), 0, st, q, L, nbr,
-                         in, out, par);
+                         (const bf16 *)in, out, out_f32, par);
       break;
     default:
       hipLaunchKernelGGL((ptc_forward_kernel<32, 2>), dim3((q.g.Vh + 31) / 32), dim3(kPtcThreads), 0, st, q, L, nbr,
-                         in, out, par);
+                         (const bf16 *)in, out, out_f32, par);
       break;
   }
+  return hipGetLastError();
+}
+
+// Layer-0 input: the even field (FP32 packed spinor) as BF16 activations
+// with one channel, zero on odd sites.
+__global__ void ptc_input_kernel(int64_t vh, const float *in_even, bf16 *act) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= vh) return;
+  float r[24];
+  load_spinor_reals<float, 24, float>(in_even, vh, s, r);
+  store_chunks<bf16, 24, 8, float>(act, vh, s, r);
+  float z[24] = {};
+  store_chunks<bf16, 24, 8, float>(act + vh * 24, vh, s, z);
+}
+
+hipError_t launch_ptc_input(int64_t vh, const void *in_even, void *act, hipStream_t st) {
+  if (vh == 0) return hipSuccess;
+  hipLaunchKernelGGL(ptc_input_kernel, dim3((unsigned)((vh + 255) / 256)), dim3(256), 0, st, vh, (const float *)in_even,
+                     (bf16 *)act);
   return hipGetLastError();
 }
 
@@ -671,10 +875,10 @@ hipError_t launch_ptc_adjoint_gather(const PtcGeo &q, int cin, const float *gy, 
   return hipGetLastError();
 }
 
-hipError_t launch_ptc_bwd_weight(const PtcGeo &q, const PtcLayerDev &L, const float *in, const float *delta,
+hipError_t launch_ptc_bwd_weight(const PtcGeo &q, const PtcLayerDev &L, const void *in, const float *delta,
                                  float *partial, int par, int groups, hipStream_t st) {
   hipLaunchKernelGGL(ptc_bwd_weight_kernel, dim3(groups, L.nchunk), dim3(kPtcThreads), ptc_bwd_weight_lds(L), st, q,
-                     L, in, delta, partial, par, groups);
+                     L, (const bf16 *)in, delta, partial, par, groups);
   return hipGetLastError();
 }
 

@@ -76,42 +76,43 @@ static lqcd_status ptc_geo(lqcd_context *ctx, const lqcd_operator *op, OpInfo *i
 }
 
 // Forward pass; activation k (input of layer k) is kept in acts[k] (full
-// lattice, channel-interleaved FP32); the output y (even sites) in acts[nl].
+// lattice, channel-interleaved BF16), the output y (even sites, FP32 packed
+// spinor) goes to y_even.
 static lqcd_status ptc_forward_all(lqcd_context *ctx, const PtcPlan &plan, const PtcGeo &q, const OpInfo &info,
-                                   const void *in_even, std::vector<float *> &acts, hipStream_t st) {
+                                   const void *in_even, std::vector<void *> &acts, void *y_even, hipStream_t st) {
   const size_t vh = info.vh;
   void *nbr;
   TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 5, 2 * 8 * vh * sizeof(int), &nbr));
   TRY(hip_check(ctx, launch_ptc_nbr(q.g, (int *)nbr, st), "ptc neighbour table"));
   // layer-0 input: r on even sites, zero on odd sites
-  TRY(hip_check(ctx, hipMemcpyAsync(acts[0], in_even, vh * 24 * sizeof(float), hipMemcpyDeviceToDevice, st), "copy"));
-  TRY(hip_check(ctx, hipMemsetAsync(acts[0] + vh * 24, 0, vh * 24 * sizeof(float), st), "memset"));
+  TRY(hip_check(ctx, launch_ptc_input((int64_t)vh, in_even, acts[0], st), "ptc input"));
   for (int l = 0; l < plan.nl; ++l) {
     const bool last = l == plan.nl - 1;
     const PtcLayerDev &L = plan.layers[l];
+    void *out = last ? y_even : acts[l + 1];
     // sites per workgroup: timed once per layer shape and geometry
     std::ostringstream key;
     key << "ptc_fwd/" << L.cin << "-" << L.cout << "/" << geom_key(q.g);
     const int variant = tune_pick(ctx, key.str(), {642, 322}, 642, true, st, [&](int v) {
-      return launch_ptc_forward(q, L, (const int *)nbr, acts[l], acts[l + 1], 0, v, st);
+      return launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, 0, v, st);
     });
     for (int par = 0; par < (last ? 1 : 2); ++par)
-      TRY(hip_check(ctx, launch_ptc_forward(q, L, (const int *)nbr, acts[l], acts[l + 1], par, variant, st),
+      TRY(hip_check(ctx, launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, par, variant, st),
                     "ptc forward"));
   }
   return LQCD_OK;
 }
 
-// Scratch: activation buffers start at slot `slot0`.
+// Scratch: activation buffers start at slot `slot0` (BF16, both parities); the
+// output slot (FP32, even sites) follows them.
 static lqcd_status ptc_buffers(lqcd_context *ctx, const PtcPlan &plan, const OpInfo &info, int slot0,
-                               std::vector<float *> &acts) {
+                               std::vector<void *> &acts) {
   acts.assign(plan.nl + 1, nullptr);
-  for (int l = 0; l <= plan.nl; ++l) {
+  for (int l = 0; l < plan.nl; ++l) {
     const int c = l == 0 ? 1 : plan.layers[l - 1].cout;
-    void *p;
-    TRY(scratch(ctx, slot0 + l, 2 * info.vh * 24 * c * sizeof(float), &p));
-    acts[l] = (float *)p;
+    TRY(scratch(ctx, slot0 + l, 2 * info.vh * 24 * c * sizeof(uint16_t), &acts[l]));
   }
+  TRY(scratch(ctx, slot0 + plan.nl, info.vh * 24 * sizeof(float), &acts[plan.nl]));
   return LQCD_OK;
 }
 
@@ -125,11 +126,9 @@ lqcd_status ptc_apply(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc
   OpInfo info;
   PtcGeo q;
   TRY(ptc_geo(ctx, op, &info, &q));
-  std::vector<float *> acts;
+  std::vector<void *> acts;
   TRY(ptc_buffers(ctx, plan, info, kSlotPtc, acts));
-  TRY(ptc_forward_all(ctx, plan, q, info, in_even, acts, st));
-  return hip_check(ctx, hipMemcpyAsync(out_even, acts[plan.nl], info.vh * 24 * sizeof(float), hipMemcpyDeviceToDevice, st),
-                   "copy");
+  return ptc_forward_all(ctx, plan, q, info, in_even, acts, out_even, st);
 }
 
 }  // namespace lqcd
@@ -178,9 +177,9 @@ lqcd_status lqcd_ptc_gradient(lqcd_context *ctx, const lqcd_operator *op, const 
   PtcGeo q;
   TRY(ptc_geo(ctx, op, &info, &q));
   const size_t vh = info.vh;
-  std::vector<float *> acts;
+  std::vector<void *> acts;
   TRY(ptc_buffers(ctx, plan, info, kSlotPtc, acts));
-  TRY(ptc_forward_all(ctx, plan, q, info, r_even, acts, st));
+  TRY(ptc_forward_all(ctx, plan, q, info, r_even, acts, acts[plan.nl], st));
   // loss = |y - e|^2 / |e|^2 on even sites; delta = (y - e) / |e|^2
   int maxc = 1, maxc9 = 9;
   for (auto &L : plan.layers) {
