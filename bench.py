@@ -61,8 +61,8 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true", help="time kernels only (for profiling runs)")
     ap.add_argument("--learned", default=os.path.join(ROOT, "paper_1109_2935_amd", "data", "ptc_16x4.npz"),
                     help="trained network weights; FGCR with it is timed when the file exists")
-    ap.add_argument("--staggered", action="store_true", help="also measure the 48^3x96 staggered workload")
-    ap.add_argument("--batched", action="store_true", help="also measure the batched multi-RHS workload")
+    ap.add_argument("--no-staggered", action="store_true", help="skip the 48^3x96 staggered workload")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-RHS workload")
     return ap.parse_args()
 
 
@@ -137,6 +137,12 @@ def learned_solve(args, torch, L, ops, ctx, o64, o32, bp, block, mr, dims):
         assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
         if best is None or info.seconds < best.seconds:
             best = info
+    # the same outer solver without a preconditioner, for the network's gain
+    x = o64.spinor(full=True)
+    st, plain = L.lqcd_gcr_solve(ctx, o64.op, o32.op, None, ops.gcr_params(1e-10, 16, 1e-3, max_iter=5000), x, bp)
+    assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+    log("GCR without preconditioner: %d steps, %.3f s, true residual %.2e" % (plain.iters, plain.seconds,
+                                                                           plain.true_residual))
     r = o32.spinor()
     out = o32.spinor()
     L.lqcd_spinor_convert(ctx, o32.op, r, o64.op, bp, 0)
@@ -147,7 +153,8 @@ def learned_solve(args, torch, L, ops, ctx, o64, o32, bp, block, mr, dims):
     macs = sum(co * 4 * ci * 36 * 3 * (V // 2 if k == len(ch) - 2 else V) for k, (ci, co) in enumerate(zip(ch[:-1], ch[1:])))
     log("FGCR(PTC): %d steps, %d applies, %.3f s; one application %.2f ms, %.1f TFLOP/s" % (
         best.iters, best.precond_applies, best.seconds, dt * 1e3, 8 * macs / dt / 1e12))
-    return {"fgcr_learned_seconds": round(best.seconds, 4), "fgcr_learned_steps": best.iters,
+    return {"gcr_unpreconditioned_seconds": round(plain.seconds, 4), "gcr_unpreconditioned_steps": plain.iters,
+            "fgcr_learned_seconds": round(best.seconds, 4), "fgcr_learned_steps": best.iters,
             "fgcr_learned_true_residual": best.true_residual, "ptc_apply_ms": round(dt * 1e3, 3),
             "ptc_apply_tflops": round(8 * macs / dt / 1e12, 1)}
 
@@ -195,32 +202,49 @@ def batched_workload(args, torch, L, ops, ctx):
     """Multi-RHS Wilson hopping term: 12 point sources (spin x colour) on
     24^3x48, and one persistent launch over 16^3x32, 20^3x40 and 24^3x48 with
     4 Gaussian sources each (kappa 0.122). Bytes per site and right-hand side:
-    spinor in + out (48 reals) plus the site's 8 links shared by its nrhs."""
+    spinor in + out (48 reals) plus the site's 8 links shared by its nrhs.
+    16-bit operators are also timed with the link products on the matrix cores
+    (LQCD_MRHS_MFMA=1)."""
     import numpy as np
     import synth
     out = {}
+
+    def with_mfma(on, fn):
+        old = os.environ.get("LQCD_MRHS_MFMA")
+        os.environ["LQCD_MRHS_MFMA"] = "1" if on else "0"
+        try:
+            return fn()
+        finally:
+            if old is None:
+                del os.environ["LQCD_MRHS_MFMA"]
+            else:
+                os.environ["LQCD_MRHS_MFMA"] = old
+
     for prec, recon in ((1, 12), (2, 12)):
         pb = PREC_BYTES[prec]
-        # 12 point sources on 24^3x48
+        variants = (False, True) if prec in (2, 3) else (False,)
+        # 12 point sources on 24^3x48 (the origin is even: D_oe acts on them)
         dims = (24, 24, 24, 48)
         U = synth.gauge_field(dims, 0.25, 4001)
         o = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon)
         srcs = np.stack([synth.point_source(dims, sc // 3, sc % 3) for sc in range(12)])
-        # point sources sit on the even origin: apply D_oe to them
         inp = o.import_spinor(srcs, 0, nrhs=12)
         res_ = o.spinor(nrhs=12)
         vh = int(np.prod(dims)) // 2
-        dt = time_kernel(torch, lambda: L.lqcd_dslash(ctx, o.op, res_, inp, 1, nrhs=12), 20)
         byts = vh * (12 * 48 + 8 * recon) * pb
         single_in = o.import_spinor(srcs[0], 0)
         single_out = o.spinor()
         dt1 = time_kernel(torch, lambda: L.lqcd_dslash(ctx, o.op, single_out, single_in, 1), 20)
-        out["point12_24x48_%s" % PREC_NAME[prec]] = {
-            "us": round(dt * 1e6, 1), "GB/s": round(byts / dt / 1e9, 1),
-            "us_per_rhs": round(dt * 1e6 / 12, 2), "single_rhs_us": round(dt1 * 1e6, 1),
-            "speedup_vs_sequential": round(12 * dt1 / dt, 2)}
+        for mf in variants:
+            dt = with_mfma(mf, lambda: time_kernel(torch, lambda: L.lqcd_dslash(ctx, o.op, res_, inp, 1, nrhs=12), 20))
+            key = "point12_24x48_%s%s" % (PREC_NAME[prec], "_mfma" if mf else "")
+            out[key] = {"us": round(dt * 1e6, 1), "GB/s": round(byts / dt / 1e9, 1), "bytes": byts,
+                        "us_per_rhs": round(dt * 1e6 / 12, 2), "single_rhs_us": round(dt1 * 1e6, 1),
+                        "speedup_vs_sequential": round(12 * dt1 / dt, 2)}
+            log("batched %s%s: 12 point sources %.1f us (%.1f GB/s, x%.2f vs 12 single-source launches)" % (
+                PREC_NAME[prec], " mfma" if mf else "", dt * 1e6, byts / dt / 1e9, 12 * dt1 / dt))
         # mixed batch, one persistent launch
-        jobs, keep, tot_bytes, seq = [], [], 0, 0.0
+        jobs, keep, tot_bytes = [], [], 0
         for k, dims in enumerate(((16, 16, 16, 32), (20, 20, 20, 40), (24, 24, 24, 48))):
             U = synth.gauge_field(dims, 0.25, 4011 + 10 * k)
             ok = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon)
@@ -230,17 +254,18 @@ def batched_workload(args, torch, L, ops, ctx):
             o_ = ok.spinor(nrhs=4)
             jobs.append((ok.op, o_, i_, 0, 4))
             keep.append((ok, i_, o_))
-            vhk = int(np.prod(dims)) // 2
-            tot_bytes += vhk * (4 * 48 + 8 * recon) * pb
-            seq += time_kernel(torch, lambda: L.lqcd_dslash(ctx, ok.op, o_, i_, 0, nrhs=4), 10)
-        dtb = time_kernel(torch, lambda: L.lqcd_dslash_batch(ctx, jobs), 20)
-        out["mixed3x4_%s" % PREC_NAME[prec]] = {
-            "us": round(dtb * 1e6, 1), "GB/s": round(tot_bytes / dtb / 1e9, 1),
-            "separate_launches_us": round(seq * 1e6, 1)}
-        log("batched %s: 12 point sources %.1f us (%.1f GB/s, x%.2f vs sequential); mixed batch %.1f us "
-            "(%.1f GB/s, separate launches %.1f us)" % (
-                PREC_NAME[prec], dt * 1e6, byts / dt / 1e9, 12 * dt1 / dt, dtb * 1e6, tot_bytes / dtb / 1e9,
-                seq * 1e6))
+            tot_bytes += int(np.prod(dims)) // 2 * (4 * 48 + 8 * recon) * pb
+        for mf in variants:
+            def separate():  # the three launches in turn, as a caller without batching would run them
+                for j in jobs:
+                    L.lqcd_dslash(ctx, j[0], j[1], j[2], 0, nrhs=4)
+            seq = with_mfma(mf, lambda: time_kernel(torch, separate, 10))
+            dtb = with_mfma(mf, lambda: time_kernel(torch, lambda: L.lqcd_dslash_batch(ctx, jobs), 20))
+            key = "mixed3x4_%s%s" % (PREC_NAME[prec], "_mfma" if mf else "")
+            out[key] = {"us": round(dtb * 1e6, 1), "GB/s": round(tot_bytes / dtb / 1e9, 1), "bytes": tot_bytes,
+                        "separate_launches_us": round(seq * 1e6, 1)}
+            log("batched %s%s: mixed batch %.1f us (%.1f GB/s; separate launches %.1f us)" % (
+                PREC_NAME[prec], " mfma" if mf else "", dtb * 1e6, tot_bytes / dtb / 1e9, seq * 1e6))
     return out
 
 
@@ -369,9 +394,9 @@ def main():
         "device_copy": copy,
         "kernels": kernels,
     }
-    if args.staggered:
+    if not args.no_staggered:
         res["staggered"] = staggered_workload(args, torch, L, ops, ctx)
-    if args.batched:
+    if not args.no_batched:
         res["batched"] = batched_workload(args, torch, L, ops, ctx)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

@@ -219,9 +219,10 @@ lqcd_status lqcd_clover_build(lqcd_context *ctx, const lqcd_operator *op, void *
  * parity -1: both (packed = LQCD_FIELD_SPINOR_FULL). Export writes only the
  * natural sites of the parities it covers.
  * nrhs > 1: `natural` holds nrhs consecutive natural fields, and the packed
- * field stores the right-hand sides interleaved per site (packed site index
- * site * nrhs + rhs), the layout every nrhs > 1 call below expects; its size
- * is lqcd_field_bytes(op, kind, nrhs).
+ * field stores them source-major (packed index rhs * (sites per parity) +
+ * site, i.e. nrhs single-source blocks one after another, within each parity
+ * block), the layout every nrhs > 1 call below expects; its size is
+ * lqcd_field_bytes(op, kind, nrhs).
  */
 lqcd_status lqcd_spinor_import(lqcd_context *ctx, const lqcd_operator *op, void *packed,
                                const void *natural, int32_t parity, int32_t nrhs, lqcd_stream stream);
@@ -231,7 +232,7 @@ lqcd_status lqcd_spinor_export(lqcd_context *ctx, const lqcd_operator *op, void 
 /*
  * out = scale * in between two instances of the same action, geometry and
  * tile (any precisions): parity 0 or 1 (single-parity fields) or -1 (full
- * fields), nrhs interleaved right-hand sides. out and in may be the same
+ * fields), nrhs right-hand sides (source-major). out and in may be the same
  * buffer only if the precisions are equal.
  */
 lqcd_status lqcd_spinor_convert(lqcd_context *ctx, const lqcd_operator *op_out, void *out,
@@ -250,8 +251,11 @@ lqcd_status lqcd_spinor_convert(lqcd_context *ctx, const lqcd_operator *op_out, 
  * every hop whose two sites lie in different blocks is dropped (Section III-B,
  * Section VIII-A); an axis with one block keeps its periodic hop.
  * out and in are packed single-parity spinors with nrhs right-hand sides
- * interleaved per site (one launch; the link of a site is shared by its
- * right-hand sides). out must not alias in.
+ * (source-major; one launch whose workgroups for the sources of a site block
+ * run together, so a link is fetched from memory once for all of them).
+ * With LQCD_MRHS_MFMA=1, 16-bit operators with a multiple of 4 sources take
+ * the link products on the matrix cores (the default vector form measures
+ * faster on gfx950). out must not alias in.
  */
 lqcd_status lqcd_dslash(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in,
                         int32_t out_parity, int32_t dagger, const int32_t *block, int32_t nrhs,
@@ -259,7 +263,7 @@ lqcd_status lqcd_dslash(lqcd_context *ctx, const lqcd_operator *op, void *out, c
 
 /*
  * Clover term of eq. (2): out_p = A_p in_p (inverse = 0) or A_p^-1 in_p
- * (inverse = 1), single-parity packed spinors, nrhs interleaved right-hand sides.
+ * (inverse = 1), single-parity packed spinors, nrhs right-hand sides (source-major).
  */
 lqcd_status lqcd_clover_apply(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in,
                               int32_t parity, int32_t inverse, int32_t nrhs, lqcd_stream stream);
@@ -276,12 +280,14 @@ lqcd_status lqcd_schur_apply(lqcd_context *ctx, const lqcd_operator *op, void *o
 /*
  * Batched Wilson hopping term over several operators in one persistent
  * launch (the lattices may differ in size): for every job,
- * out = D_{p,1-p} in (dagger: D^+) with nrhs interleaved right-hand sides.
- * All jobs share precision and link compression; at most 8 jobs. Workgroups
- * take work items from a queue until every job is done; the work-item size,
- * workgroup size and grid come from the autotuner (timed on first use of a
- * batch shape, see LQCD_TUNE / LQCD_TUNE_CACHE). The paper is silent on
- * batching; each job computes exactly lqcd_dslash.
+ * out = D_{p,1-p} in (dagger: D^+) with nrhs right-hand sides (source-major).
+ * All jobs share precision and link compression; at most 8 jobs. Work items
+ * are one workgroup's worth of site x source pairs; either a fixed grid of
+ * workgroups takes them from per-XCD queues until every job is done, or one
+ * workgroup runs per item. The form, workgroup size and grid come from the
+ * autotuner (timed on first use of a batch shape, see LQCD_TUNE /
+ * LQCD_TUNE_CACHE). The paper is silent on batching; each job computes
+ * exactly lqcd_dslash (the same arithmetic, bit for bit).
  */
 typedef struct {
   const lqcd_operator *op;

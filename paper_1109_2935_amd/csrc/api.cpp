@@ -584,9 +584,10 @@ lqcd_status lqcd_dslash_batch(lqcd_context *ctx, const lqcd_dslash_job *jobs, in
   lqcd_status s = scratch(ctx, kSlotBatchCounter, 256, &counter);
   if (s) return s;
   hipStream_t st = (hipStream_t)stream;
-  // candidates: workgroup size x (site, rhs) pairs per work item x persistent grid
-  static const BatchTune cands[] = {{128, 1024, 2048}, {128, 2048, 2048}, {256, 2048, 1024}, {256, 4096, 1024},
-                                    {256, 1024, 2048}, {128, 512, 4096},   {256, 8192, 1024}, {64, 512, 4096}};
+  // candidates: workgroup size (= pairs per work item) x persistent grid (0: one workgroup per item)
+  static const BatchTune cands[] = {{128, 128, 2048}, {128, 128, 4096}, {256, 256, 1024}, {256, 256, 2048},
+                                    {64, 64, 4096},   {128, 128, 8192}, {128, 128, 0},    {256, 256, 0},
+                                    {64, 64, 0}};
   const int ncand = sizeof(cands) / sizeof(cands[0]);
   std::vector<int> idx(ncand);
   for (int i = 0; i < ncand; ++i) idx[i] = i;

@@ -136,6 +136,18 @@ __device__ __forceinline__ void store_site(S *__restrict__ base, int64_t stride,
   store_chunks<S, N, chunk_reals<S, N>(), R>(base, stride, s, in);
 }
 
+// Per-site field that is read once per launch when stream is true (one
+// right-hand side: non-temporal loads keep it from displacing reused data in
+// the caches) and by several workgroups otherwise (cached loads).
+template <typename S, int N, typename R>
+__device__ __forceinline__ void load_site_once(const S *__restrict__ base, int64_t stride, int64_t s, R *out,
+                                               bool stream) {
+  if (stream)
+    load_site<S, N, R, true>(base, stride, s, out);
+  else
+    load_site<S, N, R, false>(base, stride, s, out);
+}
+
 // Spinors: the chunk is 4 reals (Wilson, 24 reals per site) or 2 reals
 // (staggered, 6) in every precision, so the k-th real of a packed spinor is
 // the same spin-colour component at the same site whatever the precision and
@@ -379,6 +391,39 @@ __device__ __forceinline__ int xcd_remap(int wg, int nwg) {
   constexpr int NXCD = 8;
   if (nwg % NXCD) return wg;
   return (wg % NXCD) * (nwg / NXCD) + wg / NXCD;
+}
+
+// Fields of several right-hand sides are stored in blocks of R sources
+// (R = 4, 2 or 1: the largest of these dividing nrhs): within a parity block
+// the packed index of (site s, source r) is ((r / R) Vh + s) R + r % R, so the
+// R sources of a site are adjacent (the lanes of a wave that share a site
+// share its link loads) and each group of R sources is one contiguous field
+// (neighbour accesses keep the locality of a single field). R = 1 for one
+// source is the plain layout.
+__host__ __device__ __forceinline__ int rhs_group(int nrhs) { return (nrhs & 3) == 0 ? 4 : ((nrhs & 1) == 0 ? 2 : 1); }
+__device__ __forceinline__ int64_t rhs_index(int rhs, int64_t s, int64_t vh, int R) {
+  return ((int64_t)(rhs / R) * vh + s) * R + (rhs & (R - 1));
+}
+
+// A launch covers ceil(Vh / (blockDim / R)) site blocks x (nrhs / R) source
+// groups, source group fastest after the XCD remap: the workgroups of one site
+// block run together on one XCD and read its links and clover terms from that
+// XCD's L2 rather than from memory. Lane l takes site s0 + l / R and source
+// R * group + l % R.
+struct RhsBlock {
+  int rhs;  // source of this lane
+  int s;    // site of this lane
+};
+__device__ __forceinline__ RhsBlock rhs_block_at(int w, int nrhs, int R) {
+  const int ng = nrhs / R, spb = blockDim.x / R;
+  return RhsBlock{R * (w % ng) + (int)(threadIdx.x & (R - 1)), (w / ng) * spb + (int)(threadIdx.x / R)};
+}
+__device__ __forceinline__ RhsBlock rhs_block(int nrhs, int R) {
+  return rhs_block_at(xcd_remap(blockIdx.x, gridDim.x), nrhs, R);
+}
+inline int rhs_grid(int vh, int nrhs, int block_threads) {
+  const int R = rhs_group(nrhs), spb = block_threads / R;
+  return ((vh + spb - 1) / spb) * (nrhs / R);
 }
 
 }  // namespace lqcd

@@ -81,7 +81,7 @@ struct WilsonLaunch {
   int mode;
   double *partials;  // if non-null: per-segment <out,xin> (re, im) and <out,out> (nrhs = 1)
   int block_threads;
-  int nrhs;          // right-hand sides interleaved per site
+  int nrhs;          // right-hand sides (source-major)
   int mfma;          // link products on the matrix cores (16-bit, nrhs % 4 == 0, no partials)
 };
 hipError_t launch_wilson(const WilsonLaunch &w, hipStream_t st);
@@ -97,8 +97,8 @@ struct BatchJob {
 };
 struct BatchTune {
   int block_threads;  // 64..256
-  int chunk;          // (site, rhs) pairs per work item
-  int grid;           // workgroups of the persistent launch
+  int chunk;          // (site, rhs) pairs per work item: equal to block_threads
+  int grid;           // workgroups of the persistent launch; 0: one workgroup per item, no queue
 };
 // mfma: 16-bit jobs whose source count is a multiple of 4 use the matrix-core link products
 hipError_t launch_wilson_batch(int prec, int recon, const BatchJob *jobs, int njobs, int dagger, const BatchTune &t,

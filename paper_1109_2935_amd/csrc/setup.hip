@@ -17,14 +17,14 @@ __device__ __forceinline__ void site_global(const Geom &g, const Site &x, int X[
 // ---------------------------------------------------------------------------
 // spinors
 
-// nrhs natural fields (consecutive, V sites each) <-> one packed field with the
-// right-hand sides interleaved per site (packed index site * nrhs + rhs).
+// nrhs natural fields (consecutive, V sites each) <-> one packed field in the
+// multi-source layout (rhs_index: blocks of rhs_group(nrhs) sources).
 template <typename S, int NSP>
 __global__ void __launch_bounds__(256) spinor_import_kernel(Geom g, S *packed, const double *nat, int parity,
                                                             int nrhs) {
   const int pidx = blockIdx.x * blockDim.x + threadIdx.x;
   if (pidx >= g.Vh * nrhs) return;
-  const int s = pidx / nrhs, r = pidx - s * nrhs;
+  const int R = rhs_group(nrhs), q = pidx / R, blk = q / g.Vh, s = q - blk * g.Vh, r = blk * R + pidx % R;
   const Site x = decode_site(g, s, parity);
   int X[4];
   site_global(g, x, X);
@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(256) spinor_export_kernel(Geom g, double *nat,
                                                             int nrhs) {
   const int pidx = blockIdx.x * blockDim.x + threadIdx.x;
   if (pidx >= g.Vh * nrhs) return;
-  const int s = pidx / nrhs, r = pidx - s * nrhs;
+  const int R = rhs_group(nrhs), q = pidx / R, blk = q / g.Vh, s = q - blk * g.Vh, r = blk * R + pidx % R;
   const Site x = decode_site(g, s, parity);
   int X[4];
   site_global(g, x, X);

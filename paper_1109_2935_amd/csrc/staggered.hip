@@ -18,8 +18,8 @@ template <typename S> struct SArgs {
   const S *xin;
   int parity;
   double coef, xcoef, c_long;
-  int nrhs;
-  FastDiv dN;
+  int nrhs;  // sources
+  int rg;    // sources per block of the multi-source layout (rhs_group(nrhs))
 };
 
 template <typename S, typename R>
@@ -44,15 +44,15 @@ __device__ __forceinline__ void stag_dir(const SArgs<S> &a, const Site &x, int s
       int w;
       const int n = hop<MU>(a.g, x, +k, &w);
       cpx<R> v[3], u[3];
-      load_cvec<S, R>(a.in, vs, (int64_t)n * a.nrhs + rhs, v);
+      load_cvec<S, R>(a.in, vs, rhs_index(rhs, n, vh, a.rg), v);
       Link<R> U;
       if (h == 0) {
         R r[18];
-        load_site<S, 18, R, true>(a.fat + (int64_t)(2 * MU + x.p) * vh * 18, vh, s, r);
+        load_site_once<S, 18, R>(a.fat + (int64_t)(2 * MU + x.p) * vh * 18, vh, s, r, a.nrhs == 1);
         U = unpack_link<18, R>(r);
       } else {
         R r[RECON];
-        load_site<S, RECON, R, true>(a.lng + (int64_t)(2 * MU + x.p) * vh * RECON, vh, s, r);
+        load_site_once<S, RECON, R>(a.lng + (int64_t)(2 * MU + x.p) * vh * RECON, vh, s, r, a.nrhs == 1);
         U = unpack_link<RECON, R>(r);
       }
       su3_mv(U, v, u);
@@ -64,15 +64,15 @@ __device__ __forceinline__ void stag_dir(const SArgs<S> &a, const Site &x, int s
       int w;
       const int n = hop<MU>(a.g, x, -k, &w);
       cpx<R> v[3], u[3];
-      load_cvec<S, R>(a.in, vs, (int64_t)n * a.nrhs + rhs, v);
+      load_cvec<S, R>(a.in, vs, rhs_index(rhs, n, vh, a.rg), v);
       Link<R> U;
       if (h == 0) {
         R r[18];
-        load_site<S, 18, R, true>(a.fat + (int64_t)(2 * MU + 1 - x.p) * vh * 18, vh, n, r);
+        load_site_once<S, 18, R>(a.fat + (int64_t)(2 * MU + 1 - x.p) * vh * 18, vh, n, r, a.nrhs == 1);
         U = unpack_link<18, R>(r);
       } else {
         R r[RECON];
-        load_site<S, RECON, R, true>(a.lng + (int64_t)(2 * MU + 1 - x.p) * vh * RECON, vh, n, r);
+        load_site_once<S, RECON, R>(a.lng + (int64_t)(2 * MU + 1 - x.p) * vh * RECON, vh, n, r, a.nrhs == 1);
         U = unpack_link<RECON, R>(r);
       }
       su3_adj_mv(U, v, u);
@@ -85,10 +85,11 @@ __device__ __forceinline__ void stag_dir(const SArgs<S> &a, const Site &x, int s
 
 template <typename S, typename R, int RECON, bool XPAY>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) stag_kernel(SArgs<S> a) {
-  const int pidx = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (pidx >= a.g.Vh * a.nrhs) return;
-  const int s = (int)fdiv((uint32_t)pidx, a.dN), rhs = pidx - s * a.nrhs;
+  const RhsBlock rb = rhs_block(a.nrhs, a.rg);
+  const int s = rb.s, rhs = rb.rhs;
+  if (s >= a.g.Vh) return;
   const int64_t vs = (int64_t)a.g.Vh * a.nrhs;
+  const int pidx = (int)rhs_index(rhs, s, a.g.Vh, a.rg);  // below 2^31 (checked on the host)
   const Site x = decode_site(a.g, s, a.parity);
   const int X0 = x.t[0] * a.g.B[0] + x.l[0], X1 = x.t[1] * a.g.B[1] + x.l[1], X2 = x.t[2] * a.g.B[2] + x.l[2];
   const R e1 = (X0 & 1) ? R(-1) : R(1);
@@ -137,8 +138,8 @@ static hipError_t launch_s2(const StagLaunch &l, hipStream_t st) {
   a.xcoef = l.xcoef;
   a.c_long = l.c_long;
   a.nrhs = l.nrhs;
-  a.dN = make_fastdiv(l.nrhs);
-  const int bt = l.block_threads, nwg = (int)(((int64_t)l.g.Vh * l.nrhs + bt - 1) / bt);
+  a.rg = rhs_group(l.nrhs);
+  const int bt = l.block_threads, nwg = rhs_grid(l.g.Vh, l.nrhs, bt);
   if (l.xin)
     hipLaunchKernelGGL((stag_kernel<S, R, RECON, true>), dim3(nwg), dim3(bt), 0, st, a);
   else

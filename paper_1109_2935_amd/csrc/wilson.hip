@@ -88,10 +88,12 @@ __device__ __forceinline__ void store_spinor(S *__restrict__ f, int64_t vh, int 
 // Round to the storage precision and back (what a store followed by a load returns).
 template <typename S, typename R> __device__ __forceinline__ R quantize(R v) { return to_real<R>(Store<S>::from(v)); }
 
+// stream: the link is read once per launch (one right-hand side)
 template <typename S, typename R, int RECON>
-__device__ __forceinline__ Link<R> load_link(const S *__restrict__ gauge, int64_t vh, int mu, int parity, int s) {
+__device__ __forceinline__ Link<R> load_link(const S *__restrict__ gauge, int64_t vh, int mu, int parity, int s,
+                                             bool stream) {
   R v[RECON];
-  load_site<S, RECON, R, true>(gauge + (int64_t)(2 * mu + parity) * vh * RECON, vh, s, v);
+  load_site_once<S, RECON, R>(gauge + (int64_t)(2 * mu + parity) * vh * RECON, vh, s, v, stream);
   return unpack_link<RECON, R>(v);
 }
 
@@ -100,9 +102,9 @@ __device__ __forceinline__ Link<R> load_link(const S *__restrict__ gauge, int64_
 // order as (re, im); block 0 = spins 0,1, block 1 = spins 2,3 (72 reals).
 template <typename S, typename R>
 __device__ __forceinline__ void clover_mul(const S *__restrict__ clov, int64_t vh, int s, const cpx<R> (&in)[4][3],
-                                           cpx<R> (&out)[4][3]) {
+                                           cpx<R> (&out)[4][3], bool stream) {
   R a[72];
-  load_site<S, 72, R, true>(clov, vh, s, a);
+  load_site_once<S, 72, R>(clov, vh, s, a, stream);
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const R *A = a + 36 * b;
@@ -137,8 +139,8 @@ template <typename S> struct WArgs {
   double coef;
   int parity;
   int dagger;
-  int nrhs;    // right-hand sides interleaved per site (spinor index site * nrhs + rhs)
-  FastDiv dN;  // division by nrhs
+  int nrhs;  // right-hand sides
+  int rg;    // sources per block of the multi-source layout (rhs_group(nrhs))
 };
 
 template <int MU, typename S, typename R, int RECON>
@@ -150,9 +152,9 @@ __device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int
     int w;
     const int n = hop<MU>(a.g, x, +1, &w);
     cpx<R> psi[4][3], h[2][3], u[2][3];
-    load_spinor<S, R>(a.in, vs, (int64_t)n * a.nrhs + rhs, psi);
+    load_spinor<S, R>(a.in, vs, rhs_index(rhs, n, vh, a.rg), psi);
     project<MU, R>(psi, -sgn, h);
-    const Link<R> U = load_link<S, R, RECON>(a.gauge, vh, MU, x.p, s);
+    const Link<R> U = load_link<S, R, RECON>(a.gauge, vh, MU, x.p, s, a.nrhs == 1);
     su3_mv(U, h[0], u[0]);
     su3_mv(U, h[1], u[1]);
     if (MU == 3 && (w & 1) && a.g.bc_t < 0) {
@@ -168,9 +170,9 @@ __device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int
     int w;
     const int n = hop<MU>(a.g, x, -1, &w);
     cpx<R> psi[4][3], h[2][3], u[2][3];
-    load_spinor<S, R>(a.in, vs, (int64_t)n * a.nrhs + rhs, psi);
+    load_spinor<S, R>(a.in, vs, rhs_index(rhs, n, vh, a.rg), psi);
     project<MU, R>(psi, sgn, h);
-    const Link<R> U = load_link<S, R, RECON>(a.gauge, vh, MU, 1 - x.p, n);
+    const Link<R> U = load_link<S, R, RECON>(a.gauge, vh, MU, 1 - x.p, n, a.nrhs == 1);
     su3_adj_mv(U, h[0], u[0]);
     su3_adj_mv(U, h[1], u[1]);
     if (MU == 3 && (w & 1) && a.g.bc_t < 0) {
@@ -290,10 +292,10 @@ __device__ __forceinline__ void wilson_dir_mf(const WArgs<S> &a, const Site &x, 
     if (kept) {
       const int n = hop<MU>(a.g, x, step, &w);
       cpx<float> psi[4][3];
-      load_spinor<S, float>(a.in, vs, (int64_t)n * a.nrhs + rhs, psi);
+      load_spinor<S, float>(a.in, vs, rhs_index(rhs, n, vh, a.rg), psi);
       project<MU, float>(psi, g, h);
-      U = dir == 0 ? load_link<S, float, RECON>(a.gauge, vh, MU, x.p, s)
-                   : load_link<S, float, RECON>(a.gauge, vh, MU, 1 - x.p, n);
+      U = dir == 0 ? load_link<S, float, RECON>(a.gauge, vh, MU, x.p, s, false)
+                   : load_link<S, float, RECON>(a.gauge, vh, MU, 1 - x.p, n, false);
     }
     typename Mf4<S>::T A[2][2];
     if (dir == 0)
@@ -355,7 +357,7 @@ __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, 
     wilson_dir<3, S, R, RECON>(a, x, s, rhs, sgn, acc);
   }
   const R coef = (R)a.coef;
-  const int64_t vh = a.g.Vh, vs = vh * a.nrhs, v = (int64_t)s * a.nrhs + rhs;
+  const int64_t vh = a.g.Vh, vs = vh * a.nrhs, v = rhs_index(rhs, s, vh, a.rg);
   cpx<R> res[4][3];
   if constexpr (MODE == W_HOP) {
 #pragma unroll
@@ -367,12 +369,12 @@ __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, 
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[i][c] = coef * acc[i][c];
-    clover_mul<S, R>(a.clov, vh, s, acc, res);
+    clover_mul<S, R>(a.clov, vh, s, acc, res, a.nrhs == 1);
   } else {
     cpx<R> xv[4][3];
     load_spinor<S, R>(a.xin, vs, v, xv);
     if constexpr (MODE == W_XPAY_CLOV) {
-      clover_mul<S, R>(a.clov, vh, s, xv, res);
+      clover_mul<S, R>(a.clov, vh, s, xv, res, a.nrhs == 1);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -400,94 +402,107 @@ __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, 
   store_spinor<S, R, true>(a.out, vs, v, res);
 }
 
-// One thread per (site, rhs) pair, rhs fastest, so the lanes of one site share
-// its link and clover loads. Workgroup ids are remapped per XCD.
+// One thread per (site, rhs): the lanes of a site block's source group are
+// adjacent in the workgroup and the workgroups of its groups are adjacent in
+// the launch (rhs_block), so link and clover loads are shared.
 template <typename S, typename R, int RECON, int MODE, bool REDUCE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) wilson_kernel(WArgs<S> a) {
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int pidx = wg * blockDim.x + threadIdx.x;
+  const RhsBlock rb = rhs_block(a.nrhs, a.rg);
   double red[3] = {0, 0, 0};
-  if (pidx < a.g.Vh * a.nrhs) {
-    const int s = (int)fdiv((uint32_t)pidx, a.dN);
-    wilson_point<S, R, RECON, MODE, REDUCE>(a, s, pidx - s * a.nrhs, red);
-  }
+  if (rb.s < a.g.Vh) wilson_point<S, R, RECON, MODE, REDUCE>(a, rb.s, rb.rhs, red);
   if constexpr (REDUCE) {  // single right-hand side only
-    segment_reduce_store(red, a.g.Vt2 < 64 ? a.g.Vt2 : 64, pidx, a.g.Vh, a.partials);
+    segment_reduce_store(red, a.g.Vt2 < 64 ? a.g.Vt2 : 64, rb.s, a.g.Vh, a.partials);
   }
 }
 
 // Matrix-core variant for 16-bit storage and a multiple of 4 right-hand sides:
-// the same (site, rhs) pairs as wilson_kernel, 4 consecutive pairs (one site,
-// 4 sources) per 4x4x4 block. All lanes stay active through the products.
+// lanes 4b .. 4b+3 (one 4x4x4 block) are one site and its 4 sources of one
+// group (the lane mapping of wilson_kernel with 4 sources per group). All
+// lanes stay active through the products.
 template <typename S, int RECON, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) wilson_mf_kernel(WArgs<S> a) {
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int pidx = wg * blockDim.x + threadIdx.x;
-  const bool valid = pidx < a.g.Vh * a.nrhs;
-  const int s = valid ? (int)fdiv((uint32_t)pidx, a.dN) : 0;
+  const RhsBlock rb = rhs_block(a.nrhs, 4);  // rg == 4 here
+  const bool valid = rb.s < a.g.Vh;
   double red[3];
-  wilson_point<S, float, RECON, MODE, false, true>(a, s, valid ? pidx - s * a.nrhs : 0, red, valid);
+  wilson_point<S, float, RECON, MODE, false, true>(a, valid ? rb.s : 0, rb.rhs, red, valid);
 }
 
 // Persistent launch over several operators (uneven lattices, several
-// right-hand sides each): workgroups take work items of `chunk` (site, rhs)
-// pairs from a global counter until every item of every job is done.
+// right-hand sides each): a fixed grid of workgroups takes work items from a
+// global counter until every item of every job is done. An item is one
+// workgroup's worth of (site, rhs) pairs, numbered job after job and, within a
+// job, in the order of the non-persistent launch (source fastest).
 constexpr int kMaxBatchJobs = 8;
+constexpr int kBatchQueues = 8;  // one work queue per XCD
 template <typename S> struct BatchArgs {
   WArgs<S> job[kMaxBatchJobs];
   int begin[kMaxBatchJobs + 1];  // first work item of each job (prefix sums)
   int njobs;
   int chunk;
   int mfma;           // 16-bit jobs with a multiple of 4 sources: link products on the matrix cores
-  unsigned *counter;  // zero at launch
+  unsigned *counter;  // kBatchQueues counters, zero at launch
 };
+
+// Items are split into kBatchQueues contiguous ranges; workgroup b serves queue
+// b % kBatchQueues, i.e. the XCD it runs on, so the items of one site block
+// (its source groups, adjacent in the numbering) share that XCD's L2. The grid
+// is a multiple of kBatchQueues, so every queue is drained.
+template <typename S, typename R, int RECON>
+__device__ __forceinline__ void batch_item(const BatchArgs<S> &b, int it) {
+  int j = 0;
+  while (j + 1 < b.njobs && it >= b.begin[j + 1]) ++j;
+  const WArgs<S> &a = b.job[j];
+  const RhsBlock rb = rhs_block_at(it - b.begin[j], a.nrhs, a.rg);
+  const bool valid = rb.s < a.g.Vh;
+  double red[3];
+  if constexpr (sizeof(S) == 2) {
+    if (b.mfma && a.nrhs % 4 == 0) {  // uniform over the workgroup
+      wilson_point<S, R, RECON, W_HOP, false, true>(a, valid ? rb.s : 0, rb.rhs, red, valid);
+      return;
+    }
+  }
+  if (valid) wilson_point<S, R, RECON, W_HOP, false>(a, rb.s, rb.rhs, red);
+}
+
+// Single launch with one workgroup per item (items remapped per XCD like the
+// single-operator launch): the alternative the autotuner weighs against the
+// persistent queue.
+template <typename S, typename R, int RECON>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) wilson_batch_flat_kernel(BatchArgs<S> b) {
+  batch_item<S, R, RECON>(b, xcd_remap(blockIdx.x, gridDim.x));
+}
 
 template <typename S, typename R, int RECON>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) wilson_batch_kernel(BatchArgs<S> b) {
-  __shared__ int item;
+  __shared__ int next;
   const int total = b.begin[b.njobs];
-  for (;;) {
-    if (threadIdx.x == 0) item = (int)atomicAdd(b.counter, 1u);
-    __syncthreads();
-    const int it = item;
-    __syncthreads();
-    if (it >= total) break;
-    int j = 0;
-    while (j + 1 < b.njobs && it >= b.begin[j + 1]) ++j;
-    const WArgs<S> &a = b.job[j];
-    const int first = (it - b.begin[j]) * b.chunk;
-    const int npairs = a.g.Vh * a.nrhs;
-    for (int q = threadIdx.x; q < b.chunk; q += blockDim.x) {
-      const int pidx = first + q;
-      double red[3];
-      if constexpr (sizeof(S) == 2) {
-        if (b.mfma && a.nrhs % 4 == 0) {  // uniform over the workgroup; the chunk is a multiple of 64
-          const bool valid = pidx < npairs;
-          const int s = valid ? (int)fdiv((uint32_t)pidx, a.dN) : 0;
-          wilson_point<S, R, RECON, W_HOP, false, true>(a, s, valid ? pidx - s * a.nrhs : 0, red, valid);
-          continue;
-        }
-      }
-      if (pidx < npairs) {
-        const int s = (int)fdiv((uint32_t)pidx, a.dN);
-        wilson_point<S, R, RECON, W_HOP, false>(a, s, pidx - s * a.nrhs, red);
-      }
-    }
+  const int q = blockIdx.x % kBatchQueues;
+  const int lo = (int)((int64_t)q * total / kBatchQueues), hi = (int)((int64_t)(q + 1) * total / kBatchQueues);
+  // the index of the following item is fetched while the current one runs
+  if (threadIdx.x == 0) next = lo + (int)atomicAdd(b.counter + q, 1u);
+  __syncthreads();
+  int it = next;
+  while (it < hi) {
+    __syncthreads();  // every thread has read `next`
+    if (threadIdx.x == 0) next = lo + (int)atomicAdd(b.counter + q, 1u);
+    batch_item<S, R, RECON>(b, it);
+    __syncthreads();  // `next` is written
+    it = next;
   }
 }
 
-__global__ void zero_counter_kernel(unsigned *c) { c[threadIdx.x] = 0u; }
+__global__ void zero_counter_kernel(unsigned *c) { c[threadIdx.x] = 0u; }  // one workgroup, one thread per counter
 
 template <typename S, typename R>
-__global__ void __launch_bounds__(256) clover_apply_kernel(Geom g, S *out, const S *in, const S *clov, int nrhs,
-                                                           FastDiv dN) {
-  const int pidx = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (pidx >= g.Vh * nrhs) return;
-  const int s = (int)fdiv((uint32_t)pidx, dN);
+__global__ void __launch_bounds__(256) clover_apply_kernel(Geom g, S *out, const S *in, const S *clov, int nrhs) {
+  const RhsBlock rb = rhs_block(nrhs, rhs_group(nrhs));
+  const int s = rb.s;
+  if (s >= g.Vh) return;
+  const int64_t pidx = rhs_index(rb.rhs, s, g.Vh, rhs_group(nrhs));
   const int64_t vs = (int64_t)g.Vh * nrhs;
   cpx<R> x[4][3], y[4][3];
   load_spinor<S, R>(in, vs, pidx, x);
-  clover_mul<S, R>(clov, g.Vh, s, x, y);
+  clover_mul<S, R>(clov, g.Vh, s, x, y, nrhs == 1);
   store_spinor<S, R, true>(out, vs, pidx, y);
 }
 
@@ -565,8 +580,8 @@ static hipError_t launch_w3(const WilsonLaunch &w, hipStream_t st) {
   a.parity = w.parity;
   a.dagger = w.dagger;
   a.nrhs = w.nrhs;
-  a.dN = make_fastdiv(w.nrhs);
-  const int nwg = (int)(((int64_t)w.g.Vh * w.nrhs + w.block_threads - 1) / w.block_threads);
+  a.rg = rhs_group(w.nrhs);
+  const int nwg = rhs_grid(w.g.Vh, w.nrhs, w.block_threads);
   if constexpr ((P == LQCD_F16 || P == LQCD_BF16) && !RED) {
     if (w.mfma) {
       if (w.nrhs % 4 || w.block_threads % 64) return hipErrorInvalidValue;
@@ -617,14 +632,13 @@ hipError_t launch_wilson(const WilsonLaunch &w, hipStream_t st) {
 
 hipError_t launch_clover_apply(const Geom &g, int prec, void *out, const void *in, const void *clov, int nrhs,
                                hipStream_t st) {
-  const int bt = 256, nwg = (int)(((int64_t)g.Vh * nrhs + bt - 1) / bt);
+  const int bt = 256, nwg = rhs_grid(g.Vh, nrhs, bt);
   if (g.Vh == 0) return hipSuccess;
-  const FastDiv dN = make_fastdiv(nrhs);
   switch (prec) {
 #define CASE(P)                                                                                           \
   case P:                                                                                                 \
     hipLaunchKernelGGL((clover_apply_kernel<Prec<P>::S, Prec<P>::R>), dim3(nwg), dim3(bt), 0, st, g,      \
-                       (Prec<P>::S *)out, (const Prec<P>::S *)in, (const Prec<P>::S *)clov, nrhs, dN);    \
+                       (Prec<P>::S *)out, (const Prec<P>::S *)in, (const Prec<P>::S *)clov, nrhs);        \
     return hipGetLastError();
     CASE(LQCD_F64)
     CASE(LQCD_F32)
@@ -644,7 +658,7 @@ static hipError_t launch_b2(const BatchJob *jobs, int njobs, int dagger, const B
   b.njobs = njobs;
   b.chunk = t.chunk;
   b.mfma = mfma;
-  if (mfma && (t.chunk % 64 || t.block_threads % 64)) return hipErrorInvalidValue;
+  if (t.chunk != t.block_threads || t.block_threads % 64) return hipErrorInvalidValue;
   b.counter = counter;
   b.begin[0] = 0;
   for (int j = 0; j < njobs; ++j) {
@@ -660,11 +674,16 @@ static hipError_t launch_b2(const BatchJob *jobs, int njobs, int dagger, const B
     a.parity = jobs[j].parity;
     a.dagger = dagger;
     a.nrhs = jobs[j].nrhs;
-    a.dN = make_fastdiv(jobs[j].nrhs);
-    const int64_t pairs = (int64_t)jobs[j].g.Vh * jobs[j].nrhs;
-    b.begin[j + 1] = b.begin[j] + (int)((pairs + t.chunk - 1) / t.chunk);
+    a.rg = rhs_group(jobs[j].nrhs);
+    // items of this job: one per workgroup of the non-persistent launch
+    b.begin[j + 1] = b.begin[j] + rhs_grid(jobs[j].g.Vh, jobs[j].nrhs, t.block_threads);
   }
-  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+  if (t.grid == 0) {  // one workgroup per item
+    hipLaunchKernelGGL((wilson_batch_flat_kernel<S, R, RECON>), dim3(b.begin[njobs]), dim3(t.block_threads), 0, st, b);
+    return hipGetLastError();
+  }
+  if (t.grid % kBatchQueues) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(kBatchQueues), 0, st, counter);
   hipLaunchKernelGGL((wilson_batch_kernel<S, R, RECON>), dim3(t.grid), dim3(t.block_threads), 0, st, b);
   return hipGetLastError();
 }

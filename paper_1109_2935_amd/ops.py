@@ -59,7 +59,7 @@ class Operator:
     # -- spinor exchange ----------------------------------------------------
     def import_spinor(self, natural, parity, out=None, nrhs=1):
         """Pack natural field(s); nrhs > 1: natural is [nrhs, t, z, y, x, ...] and the
-        right-hand sides are interleaved per site in the packed field."""
+        right-hand sides are stored one after another (source-major) in the packed field."""
         nat = _device_complex(natural, self.device)
         if out is None:
             out = self.spinor(full=(parity < 0), zero=False, nrhs=nrhs)
