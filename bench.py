@@ -70,6 +70,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def stencil_tile(dims, block):
+    """Tile of the stencil operators: the full x extent, 8 sites along y, z and t
+    where they divide (else the Schwarz block)."""
+    t = (dims[0],) + tuple(8 if d % 8 == 0 else b for d, b in zip(dims[1:], block[1:]))
+    return t if all(d % e == 0 and e % 2 == 0 for d, e in zip(dims, t)) else tuple(block)
+
+
 def time_kernel(torch, fn, launches):
     """Average duration of `fn` (one kernel launch or a fixed sequence) with
     HIP events on the current stream."""
@@ -119,7 +126,7 @@ def cpu_baseline(dims, U, b, kappa, csw):
                       "%.2f s each" % (reps, "x".join(map(str, dims)), dt)}
 
 
-def learned_solve(args, torch, L, ops, ctx, o64, o32, bp, block, mr, dims):
+def learned_solve(args, torch, L, ops, ctx, o64, o32, o32b, bp, block, mr, dims):
     """Flexible GCR with the trained PTC network as preconditioner (Schwarz as
     fallback), FP64 restarts, FP32 Krylov; and the cost of one network
     application (BF16 matrix-core flops of its channel mixing)."""
@@ -133,7 +140,7 @@ def learned_solve(args, torch, L, ops, ctx, o64, o32, bp, block, mr, dims):
     best = None
     for _ in range(2):
         x = o64.spinor(full=True)
-        st, info = L.lqcd_gcr_solve(ctx, o64.op, o32.op, o32.op, prm, x, bp)
+        st, info = L.lqcd_gcr_solve(ctx, o64.op, o32.op, o32b.op, prm, x, bp)
         assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
         if best is None or info.seconds < best.seconds:
             best = info
@@ -291,11 +298,18 @@ def main():
     log("fields ready %.1fs" % (time.time() - t))
     ctx = L.lqcd_context_create()
     Ud = torch.from_numpy(U).cuda()
+    # Stencil operators use tiles spanning the full x extent (the site order
+    # with the least neighbour re-fetch from memory); the FP16 Schwarz operator
+    # is tiled by its Dirichlet blocks, and the solver re-lays out K's input
+    # and output.
+    tile = stencil_tile(dims, block)
     inst = {}
     for prec, recon in [(0, 18), (0, 12), (1, 18), (1, 12), (1, 8), (2, 18), (2, 12), (3, 12)]:
-        inst[(prec, recon)] = ops.wilson_clover(ctx, U, dims, kappa, csw, prec, recon, tile=block, U_device=Ud)
+        inst[(prec, recon)] = ops.wilson_clover(ctx, U, dims, kappa, csw, prec, recon, tile=tile, U_device=Ud)
+    o16b = ops.wilson_clover(ctx, U, dims, kappa, csw, 2, 12, tile=block, U_device=Ud)
+    o32b = ops.wilson_clover(ctx, U, dims, kappa, csw, 1, 12, tile=block, U_device=Ud)
     torch.cuda.synchronize()
-    log("operators ready")
+    log("operators ready (stencil tile %s, Schwarz tile %s)" % (tile, block))
 
     # ---- kernel table: Wilson dslash and Schur matvec, every precision/recon
     kernels = {}
@@ -319,13 +333,21 @@ def main():
             "frac": round(sb / dts / 1e9 / HBM_PEAK_GBS, 4), "bytes": sb}
         log("%-18s %8.1f us %7.1f GB/s | schur %8.1f us %7.1f GB/s" % (
             "%s r%d" % (PREC_NAME[prec], recon), dt * 1e6, byts / dt / 1e9, dts * 1e6, sb / dts / 1e9))
+    # the same kernel in the Schwarz block tiling, for comparison
+    inp = o32b.import_spinor(np.where(synth.parity_of_sites(dims)[..., None, None] == 1, b, 0), 1)
+    out = o32b.spinor()
+    dt = time_kernel(torch, lambda: L.lqcd_dslash(ctx, o32b.op, out, inp, 0, 0), args.dslash_launches)
+    byts = vh * WILSON_REALS[12] * PREC_BYTES[1]
+    kernels["dslash_f32_r12_block_tile"] = {"us": round(dt * 1e6, 2), "GB/s": round(byts / dt / 1e9, 1),
+                                            "frac": round(byts / dt / 1e9 / HBM_PEAK_GBS, 4), "bytes": byts}
+    log("f32 r12 in %s tiles %8.1f us %7.1f GB/s" % (block, dt * 1e6, byts / dt / 1e9))
     copy = device_copy(torch)
     log("device copy %.1f GB/s" % copy["GB/s"])
     if args.kernels_only:
         print(json.dumps({"kernels": kernels, "device_copy": copy}))
         return
 
-    o64, o32, o16 = inst[(0, 18)], inst[(1, 12)], inst[(2, 12)]
+    o64, o32, o16 = inst[(0, 18)], inst[(1, 12)], o16b
     bp = o64.import_spinor(b, -1)
     prm = ops.gcr_params(1e-10, k_max=16, delta=1e-3, max_iter=2000, precond=L.LQCD_PRECOND_SCHWARZ,
                          block=block, mr_steps=mr)
@@ -375,7 +397,7 @@ def main():
                     "fp64_cg_true_residual": cg.true_residual,
                     "speedup_vs_fp64_cg": round(cg.seconds / tts["gcr_dd_seconds"], 2)})
     if os.path.exists(args.learned):
-        tts.update(learned_solve(args, torch, L, ops, ctx, o64, o32, bp, block, mr, dims))
+        tts.update(learned_solve(args, torch, L, ops, ctx, o64, o32, o32b, bp, block, mr, dims))
     res = {
         "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 2), "higher_is_better": True,
@@ -383,7 +405,8 @@ def main():
         "config": {"workload": "wilson-clover %s, kappa %.3f, c_sw %.1f, eps %.2f, antiperiodic t; GCR-DD "
                                "FP64/FP32/FP16, Schwarz 8^4 blocks, %d MR steps" % (
                                    "x".join(map(str, dims)), kappa, csw, eps, mr),
-                   "dims": list(dims), "kernel": "wilson dslash f32 recon12, one parity",
+                   "dims": list(dims), "tile": list(tile), "schwarz_tile": list(block),
+                   "kernel": "wilson dslash f32 recon12, one parity",
                    "dslash_launches_per_step": args.dslash_launches},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4),

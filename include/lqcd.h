@@ -230,10 +230,11 @@ lqcd_status lqcd_spinor_export(lqcd_context *ctx, const lqcd_operator *op, void 
                                const void *packed, int32_t parity, int32_t nrhs, lqcd_stream stream);
 
 /*
- * out = scale * in between two instances of the same action, geometry and
- * tile (any precisions): parity 0 or 1 (single-parity fields) or -1 (full
- * fields), nrhs right-hand sides (source-major). out and in may be the same
- * buffer only if the precisions are equal.
+ * out = scale * in between two instances of the same action and lattice
+ * (any precisions and tiles; fields are re-laid out when the tiles differ):
+ * parity 0 or 1 (single-parity fields) or -1 (full fields), nrhs right-hand
+ * sides. out and in may be the same buffer only if precisions and tiles are
+ * equal.
  */
 lqcd_status lqcd_spinor_convert(lqcd_context *ctx, const lqcd_operator *op_out, void *out,
                                 const lqcd_operator *op_in, const void *in, int32_t parity, int32_t nrhs,
@@ -320,6 +321,8 @@ lqcd_status lqcd_schwarz_precond(lqcd_context *ctx, const lqcd_operator *op_prec
  * x_o = A_oo^-1 (b_o + kappa D_oe x_e)). The Krylov space (p, z) is built
  * in op_krylov's precision, K in op_precond's, and every restart recomputes
  * r = bhat - Mhat x with op_hi (FP64), where the solution accumulates.
+ * op_hi and op_krylov share one tile; op_precond may use another (the Schwarz
+ * blocks equal its tile), and K's input and output are then re-laid out.
  * x_full (in: initial guess, out: solution) and b_full are packed
  * LQCD_FIELD_SPINOR_FULL fields of op_hi. Returns LQCD_ERR_NOT_CONVERGED
  * (best iterate in x_full, info filled) when max_iter is reached.

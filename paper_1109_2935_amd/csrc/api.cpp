@@ -469,17 +469,30 @@ lqcd_status lqcd_spinor_convert(lqcd_context *ctx, const lqcd_operator *op_out, 
   if (s) return s;
   if ((s = check_op(ctx, op_in, &ii))) return s;
   if (op_out->action != op_in->action) return set_error(ctx, LQCD_ERR_INVALID_ARG, "actions differ");
-  for (int m = 0; m < 4; ++m)
-    if (op_out->dims[m] != op_in->dims[m] || op_out->tile[m] != op_in->tile[m])
-      return set_error(ctx, LQCD_ERR_INVALID_ARG, "geometry or tile differs");
+  bool same_tile = true;
+  for (int m = 0; m < 4; ++m) {
+    if (op_out->dims[m] != op_in->dims[m]) return set_error(ctx, LQCD_ERR_INVALID_ARG, "lattices differ");
+    same_tile = same_tile && op_out->tile[m] == op_in->tile[m];
+  }
   if (parity < -1 || parity > 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "parity must be 0, 1 or -1");
   if ((s = check_nrhs(ctx, io, nrhs))) return s;
   if (!aligned16(out) || !aligned16(in)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
-  if (out == in && op_out->prec != op_in->prec)
-    return set_error(ctx, LQCD_ERR_INVALID_ARG, "in-place conversion needs equal precisions");
-  // the packed spinor layout does not depend on the precision: element-wise
-  const size_t n = io.vh * io.nsp / 2 * (parity < 0 ? 2 : 1) * (size_t)nrhs;
-  return hip_check(ctx, blas_convert(op_in->prec, in, op_out->prec, out, n, scale, (hipStream_t)stream), "convert");
+  if (out == in && (op_out->prec != op_in->prec || !same_tile))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "in-place conversion needs equal precisions and tiles");
+  hipStream_t st = (hipStream_t)stream;
+  if (same_tile) {  // the packed spinor layout does not depend on the precision: element-wise
+    const size_t n = io.vh * io.nsp / 2 * (parity < 0 ? 2 : 1) * (size_t)nrhs;
+    return hip_check(ctx, blas_convert(op_in->prec, in, op_out->prec, out, n, scale, st), "convert");
+  }
+  for (int p = 0; p < 2; ++p) {
+    if (parity >= 0 && p != parity) continue;
+    const size_t off_o = parity < 0 ? p * io.spinor_bytes * nrhs : 0, off_i = parity < 0 ? p * ii.spinor_bytes * nrhs : 0;
+    if ((s = hip_check(ctx, launch_spinor_relayout(io.g, op_out->prec, (char *)out + off_o, ii.g, op_in->prec,
+                                                   (const char *)in + off_i, io.nsp, p, nrhs, scale, st),
+                       "relayout")))
+      return s;
+  }
+  return LQCD_OK;
 }
 
 static lqcd_status check_fields(lqcd_context *ctx, const lqcd_operator *op, bool need_clover) {

@@ -112,6 +112,10 @@ hipError_t launch_spinor_import(const Geom &g, int prec, int nsp, void *packed, 
                                 int parity, int nrhs, hipStream_t st);
 hipError_t launch_spinor_export(const Geom &g, int prec, int nsp, double *natural, const void *packed,
                                 int parity, int nrhs, hipStream_t st);
+// out (layout go, precision pout) = scale * in (layout gi, precision pin): one
+// parity block of the same lattice in two tilings
+hipError_t launch_spinor_relayout(const Geom &go, int pout, void *out, const Geom &gi, int pin, const void *in, int nsp,
+                                  int parity, int nrhs, double scale, hipStream_t st);
 hipError_t launch_gauge_import(const Geom &g, int prec, int recon, void *packed, const double *natural,
                                int form_long, hipStream_t st);
 hipError_t launch_clover_build(const Geom &g, int prec, double kappa, double csw, void *clov, void *clov_inv,

@@ -53,6 +53,70 @@ __global__ void __launch_bounds__(256) spinor_export_kernel(Geom g, double *nat,
   for (int k = 0; k < NSP; ++k) dst[k] = v[k];
 }
 
+// out = scale * in between two tiled layouts of the same lattice (one parity
+// block each, nrhs sources in the multi-source layout), any precisions: one
+// thread per output (site, source), which finds its site in the input layout.
+template <typename So, typename Si, int NSP>
+__global__ void __launch_bounds__(256) spinor_relayout_kernel(Geom go, So *out, Geom gi, const Si *in, int parity,
+                                                              int nrhs, double scale) {
+  const int64_t pidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t vh = go.Vh;
+  if (pidx >= vh * nrhs) return;
+  const int R = rhs_group(nrhs);
+  const int64_t q = pidx / R, blk = q / vh;
+  const int s = (int)(q - blk * vh), r = (int)(blk * R + pidx % R);
+  int X[4], t[4], l[4];
+  site_global(go, decode_site(go, s, parity), X);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    t[m] = X[m] / gi.B[m];
+    l[m] = X[m] - t[m] * gi.B[m];
+  }
+  const int si = encode_site(gi, t, l);
+  double v[NSP];
+  load_spinor_reals<Si, NSP, double>(in, vh * nrhs, rhs_index(r, si, vh, R), v);
+#pragma unroll
+  for (int k = 0; k < NSP; ++k) v[k] *= scale;
+  store_spinor_reals<So, NSP, double>(out, vh * nrhs, pidx, v);
+}
+
+template <typename So, int NSP>
+static hipError_t relayout_in(const Geom &go, So *out, const Geom &gi, int pin, const void *in, int parity, int nrhs,
+                              double scale, hipStream_t st) {
+  const int bt = 256;
+  const int nwg = (int)(((int64_t)go.Vh * nrhs + bt - 1) / bt);
+  switch (pin) {
+#define CASE(P)                                                                                                     \
+  case P:                                                                                                           \
+    hipLaunchKernelGGL((spinor_relayout_kernel<So, Prec<P>::S, NSP>), dim3(nwg), dim3(bt), 0, st, go, out, gi,      \
+                       (const Prec<P>::S *)in, parity, nrhs, scale);                                                \
+    return hipGetLastError();
+    CASE(LQCD_F64)
+    CASE(LQCD_F32)
+    CASE(LQCD_F16)
+    CASE(LQCD_BF16)
+#undef CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_spinor_relayout(const Geom &go, int pout, void *out, const Geom &gi, int pin, const void *in, int nsp,
+                                  int parity, int nrhs, double scale, hipStream_t st) {
+  if (go.Vh == 0) return hipSuccess;
+  switch (pout) {
+#define CASE(P)                                                                                                     \
+  case P:                                                                                                           \
+    return nsp == 24 ? relayout_in<Prec<P>::S, 24>(go, (Prec<P>::S *)out, gi, pin, in, parity, nrhs, scale, st)    \
+                     : relayout_in<Prec<P>::S, 6>(go, (Prec<P>::S *)out, gi, pin, in, parity, nrhs, scale, st);
+    CASE(LQCD_F64)
+    CASE(LQCD_F32)
+    CASE(LQCD_F16)
+    CASE(LQCD_BF16)
+#undef CASE
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int NSP>
 static hipError_t spinor_io(const Geom &g, int prec, void *packed, double *natural, int parity, int nrhs, bool imp,
                             hipStream_t st) {

@@ -25,12 +25,19 @@ using cd = std::complex<double>;
 
 namespace {
 
-bool same_system(const lqcd_operator *a, const lqcd_operator *b) {
+// The same physical system; `any_tile`: the memory tiles may differ.
+bool same_system(const lqcd_operator *a, const lqcd_operator *b, bool any_tile = false) {
   if (a->action != b->action || a->bc_t != b->bc_t) return false;
   for (int m = 0; m < 4; ++m)
-    if (a->dims[m] != b->dims[m] || a->tile[m] != b->tile[m]) return false;
+    if (a->dims[m] != b->dims[m] || (!any_tile && a->tile[m] != b->tile[m])) return false;
   if (a->action == LQCD_WILSON_CLOVER) return a->kappa == b->kappa && a->csw == b->csw;
   return a->mass == b->mass && a->c_long == b->c_long;
+}
+
+bool same_tile(const OpInfo &a, const OpInfo &b) {
+  for (int m = 0; m < 4; ++m)
+    if (a.op->tile[m] != b.op->tile[m]) return false;
+  return true;
 }
 
 struct Solver {
@@ -118,12 +125,12 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
   const int pk = prm->precond;
   if (pk == LQCD_PRECOND_SCHWARZ) {
     TRY(check_op(ctx, op_precond, &pc));
-    if (!same_system(op_hi, op_precond))
+    if (!same_system(op_hi, op_precond, true))
       return set_error(ctx, LQCD_ERR_INVALID_ARG, "op_precond describes another system");
     TRY(check_schwarz(ctx, pc, &prm->schwarz));
   } else if (pk == LQCD_PRECOND_LEARNED) {
     TRY(check_op(ctx, op_precond, &pc));
-    if (!same_system(op_hi, op_precond))
+    if (!same_system(op_hi, op_precond, true))
       return set_error(ctx, LQCD_ERR_INVALID_ARG, "op_precond describes another system");
     if (op_precond->prec != LQCD_F32 || op_krylov->prec != LQCD_F32)
       return set_error(ctx, LQCD_ERR_UNSUPPORTED, "the learned preconditioner runs with FP32 op_krylov and op_precond");
@@ -149,10 +156,17 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
   std::vector<void *> P(kmax), Z(kmax);
   for (int i = 0; i < kmax; ++i) TRY(S.vec(kr.spinor_bytes, &P[i]));
   for (int i = 0; i < kmax; ++i) TRY(S.vec(kr.spinor_bytes, &Z[i]));
-  if (pk == LQCD_PRECOND_SCHWARZ || (pk == LQCD_PRECOND_LEARNED && prm->schwarz.mr_steps > 0)) {
+  // K works in op_precond's precision and tile; its input and output are
+  // converted (and re-laid out when the tiles differ)
+  const bool k_relayout = pk != LQCD_PRECOND_NONE && !same_tile(kr, pc);
+  if (pk == LQCD_PRECOND_SCHWARZ || (pk == LQCD_PRECOND_LEARNED && (prm->schwarz.mr_steps > 0 || k_relayout))) {
     TRY(S.vec(pc.spinor_bytes, &pin));
     TRY(S.vec(pc.spinor_bytes, &pout));
   }
+  auto to_layout = [&](const OpInfo &a, const void *in, const OpInfo &b, void *out, double scale) -> lqcd_status {
+    if (same_tile(a, b)) return S.hip(blas_convert(a.prec, in, b.prec, out, ncomplex(a), scale, S.st), "convert");
+    return S.hip(launch_spinor_relayout(b.g, b.prec, out, a.g, a.prec, in, a.nsp, 0, 1, scale, S.st), "relayout");
+  };
   // LEARNED: a step whose residual reduction stalls (or whose network output
   // is not finite) makes the next step use the Schwarz preconditioner.
   bool use_fallback = false;
@@ -194,13 +208,19 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
     const bool schwarz_now = pk == LQCD_PRECOND_SCHWARZ || (pk == LQCD_PRECOND_LEARNED && use_fallback);
     if (schwarz_now) {
       const double sc = unit_rms_scale(rhn, 2 * n);
-      TRY(S.hip(blas_convert(kr.prec, rhat, pc.prec, pin, n, sc, S.st), "convert"));
+      TRY(to_layout(kr, rhat, pc, pin, sc));
       TRY(schwarz_apply(ctx, pc, &prm->schwarz, pout, pin, kSlotSchwarz, S.st));
-      TRY(S.hip(blas_convert(pc.prec, pout, kr.prec, P[k], n, 1.0 / sc, S.st), "convert"));
+      TRY(to_layout(pc, pout, kr, P[k], 1.0 / sc));
       inf.precond_applies++;
       use_fallback = false;
     } else if (pk == LQCD_PRECOND_LEARNED) {
-      TRY(ptc_apply(ctx, op_precond, prm->learned, P[k], rhat, S.st));
+      if (k_relayout) {
+        TRY(to_layout(kr, rhat, pc, pin, 1.0));
+        TRY(ptc_apply(ctx, op_precond, prm->learned, pout, pin, S.st));
+        TRY(to_layout(pc, pout, kr, P[k], 1.0));
+      } else {
+        TRY(ptc_apply(ctx, op_precond, prm->learned, P[k], rhat, S.st));
+      }
       inf.precond_applies++;
     } else {
       TRY(S.hip(hipMemcpyAsync(P[k], rhat, kr.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));

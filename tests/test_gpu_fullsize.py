@@ -52,10 +52,16 @@ def sample_sites(dims, parity, n, seed):
     return np.sort(keep[:n])
 
 
-@pytest.mark.parametrize("prec,recon", [(1, 12), (2, 12), (0, 18)])
-def test_wilson_dslash_sampled_sites_32x64(ctx, prec, recon):
+# the benchmark's tilings: stencil operators span the full x extent, the FP16
+# Schwarz operator is tiled by its 8^4 Dirichlet blocks
+STENCIL_TILE, BLOCK = (32, 8, 8, 8), (8, 8, 8, 8)
+
+
+@pytest.mark.parametrize("prec,recon,tile", [(1, 12, STENCIL_TILE), (2, 12, STENCIL_TILE), (0, 18, STENCIL_TILE),
+                                             (1, 12, BLOCK)])
+def test_wilson_dslash_sampled_sites_32x64(ctx, prec, recon, tile):
     dims, U, b, Ud = wilson_fields()
-    o = ops.wilson_clover(ctx, U, dims, 0.124, 1.0, prec, recon, tile=(8, 8, 8, 8), U_device=Ud)
+    o = ops.wilson_clover(ctx, U, dims, 0.124, 1.0, prec, recon, tile=tile, U_device=Ud)
     src = np.where(oracle.parity_mask(dims, 1)[..., None, None], b, 0)
     out = o.spinor()
     L.lqcd_dslash(ctx, o.op, out, o.import_spinor(src, 1), 0)
@@ -68,9 +74,10 @@ def test_wilson_dslash_sampled_sites_32x64(ctx, prec, recon):
 
 def test_gcr_dd_full_32x64(ctx):
     """The benchmark's solve: FP64 restarts, FP32 Krylov, FP16 Schwarz on 8^4
-    blocks, 8 MR steps; the oracle recomputes ||b - M x|| / ||b|| in FP64."""
+    blocks (its own tiling), 8 MR steps; the oracle recomputes ||b - M x|| / ||b||
+    in FP64."""
     dims, U, b, Ud = wilson_fields()
-    o = {p: ops.wilson_clover(ctx, U, dims, 0.124, 1.0, p, r, tile=(8, 8, 8, 8), U_device=Ud)
+    o = {p: ops.wilson_clover(ctx, U, dims, 0.124, 1.0, p, r, tile=STENCIL_TILE if p < 2 else BLOCK, U_device=Ud)
          for p, r in ((0, 18), (1, 12), (2, 12))}
     bp = o[0].import_spinor(b, -1)
     x = o[0].spinor(full=True)

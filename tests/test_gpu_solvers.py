@@ -147,3 +147,50 @@ def test_cgne_mixed_precision_reliable_updates(ctx):
     assert info.restarts >= 2
     res, _ = oracle_residual(dims, U, kappa, csw, np_of(o[0].export_spinor(x, -1)), b)
     assert res <= 1.05e-10
+
+
+def test_gcr_dd_preconditioner_in_its_own_tile(ctx):
+    """FP64/FP32 operators tiled for the fastest stencil, the FP16 Schwarz
+    operator tiled by its Dirichlet blocks: the solver re-lays out K's input and
+    output; same FP64 residual and (up to reduction order) the same steps as
+    with one tiling throughout."""
+    dims, kappa, csw, block = (8, 8, 8, 8), 0.124, 1.0, (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.25, 301)
+    b = synth.gaussian_spinor(dims, 302)
+    Ud = torch.from_numpy(U).cuda()
+    fast = (8, 4, 4, 4)
+    hi = ops.wilson_clover(ctx, U, dims, kappa, csw, 0, 18, tile=fast, U_device=Ud)
+    kr = ops.wilson_clover(ctx, U, dims, kappa, csw, 1, 12, tile=fast, U_device=Ud)
+    pc = ops.wilson_clover(ctx, U, dims, kappa, csw, 2, 12, tile=block, U_device=Ud)
+    same = {p: ops.wilson_clover(ctx, U, dims, kappa, csw, p, 18 if p < 2 else 12, tile=block, U_device=Ud)
+            for p in (0, 1)}
+    prm = ops.gcr_params(1e-10, 16, 1e-3, precond=L.LQCD_PRECOND_SCHWARZ, block=block, mr_steps=8)
+    x = hi.spinor(full=True)
+    st, info = L.lqcd_gcr_solve(ctx, hi.op, kr.op, pc.op, prm, x, hi.import_spinor(b, -1))
+    assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+    x2 = same[0].spinor(full=True)
+    st2, info2 = L.lqcd_gcr_solve(ctx, same[0].op, same[1].op, pc.op, prm, x2, same[0].import_spinor(b, -1))
+    assert st2 == L.LQCD_OK
+    xs = np_of(hi.export_spinor(x, -1))
+    res, _ = oracle_residual(dims, U, kappa, csw, xs, b)
+    assert res <= 1.05e-10
+    assert abs(info.iters - info2.iters) <= 2
+
+
+@pytest.mark.parametrize("prec_out", [0, 1, 2])
+def test_spinor_convert_between_tiles(ctx, prec_out):
+    dims = (8, 8, 4, 8)
+    U = synth.gauge_field(dims, 0.25, 311)
+    psi = synth.gaussian_spinor(dims, 312)
+    a = ops.wilson_clover(ctx, U, dims, 0.124, 1.0, 0, 18, tile=(4, 4, 2, 2))
+    bop = ops.wilson_clover(ctx, U, dims, 0.124, 1.0, prec_out, 18 if prec_out < 2 else 12, tile=(8, 2, 4, 4))
+    for parity in (-1, 0, 1):
+        src = psi if parity < 0 else on_parity(psi, oracle.parity_mask(dims, parity))
+        pa = a.import_spinor(src, parity)
+        pb = bop.spinor(full=parity < 0)
+        L.lqcd_spinor_convert(ctx, bop.op, pb, a.op, pa, parity, scale=2.0)
+        got = np_of(bop.export_spinor(pb, parity))
+        if prec_out == 0:
+            assert np.array_equal(got, 2.0 * src)
+        else:
+            assert rel(got, 2.0 * src) < {1: 1e-7, 2: 1e-3}[prec_out]
