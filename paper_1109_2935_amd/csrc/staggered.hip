@@ -30,14 +30,15 @@ __device__ __forceinline__ void load_cvec(const S *__restrict__ f, int64_t vh, i
   for (int c = 0; c < 3; ++c) v[c] = mk<R>(r[2 * c], r[2 * c + 1]);
 }
 
-template <int MU, typename S, typename R, int RECON>
+// Hops along MU: h = 0 the fat (one-site) hops, h = 1 the long (three-site)
+// hops; H0 .. H1 selects which.
+template <int MU, int H0, int H1, typename S, typename R, int RECON>
 __device__ __forceinline__ void stag_dir(const SArgs<S> &a, const Site &x, int s, int rhs, R eta, R cl,
                                          cpx<R> (&acc)[3]) {
   const int64_t vh = a.g.Vh, vs = vh * a.nrhs;
   const int neg = a.g.bc_t < 0;
-  // one hop: fat; three hops: long
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = H0; h <= H1; ++h) {
     const int k = h == 0 ? 1 : 3;
     const R wgt = h == 0 ? eta : eta * cl;
     {
@@ -83,7 +84,13 @@ __device__ __forceinline__ void stag_dir(const SArgs<S> &a, const Site &x, int s
   }
 }
 
-template <typename S, typename R, int RECON, bool XPAY>
+// One pass computes the hops of types H0 .. H1 (0 fat, 1 long) along the
+// directions M0 .. M1. 16-bit storage runs all 16 hops in one pass; FP32 runs
+// two passes (fat, long) and FP64 four (fat and long, x/y and z/t), so that the
+// loads of one pass fit in registers (16 hops in one pass spill). The FIRST
+// pass writes coef * its hops (plus the xpay term); the others add theirs to
+// the output in place.
+template <typename S, typename R, int RECON, bool XPAY, int H0, int H1, int M0, int M1, bool FIRST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) stag_kernel(SArgs<S> a) {
   const RhsBlock rb = rhs_block(a.nrhs, a.rg);
   const int s = rb.s, rhs = rb.rhs;
@@ -97,13 +104,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
   const R e3 = ((X0 + X1 + X2) & 1) ? R(-1) : R(1);
   const R cl = (R)a.c_long;
   cpx<R> acc[3] = {mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0)};
-  stag_dir<0, S, R, RECON>(a, x, s, rhs, R(1), cl, acc);
-  stag_dir<1, S, R, RECON>(a, x, s, rhs, e1, cl, acc);
-  stag_dir<2, S, R, RECON>(a, x, s, rhs, e2, cl, acc);
-  stag_dir<3, S, R, RECON>(a, x, s, rhs, e3, cl, acc);
+  if constexpr (M0 <= 0 && 0 <= M1) stag_dir<0, H0, H1, S, R, RECON>(a, x, s, rhs, R(1), cl, acc);
+  if constexpr (M0 <= 1 && 1 <= M1) stag_dir<1, H0, H1, S, R, RECON>(a, x, s, rhs, e1, cl, acc);
+  if constexpr (M0 <= 2 && 2 <= M1) stag_dir<2, H0, H1, S, R, RECON>(a, x, s, rhs, e2, cl, acc);
+  if constexpr (M0 <= 3 && 3 <= M1) stag_dir<3, H0, H1, S, R, RECON>(a, x, s, rhs, e3, cl, acc);
   const R coef = (R)a.coef;
   R out[6];
-  if constexpr (XPAY) {
+  if constexpr (!FIRST) {
+    cpx<R> prev[3];
+    load_cvec<S, R>(a.out, vs, pidx, prev);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      out[2 * c] = fma(coef, acc[c].re, prev[c].re);
+      out[2 * c + 1] = fma(coef, acc[c].im, prev[c].im);
+    }
+  } else if constexpr (XPAY) {
     cpx<R> xv[3];
     load_cvec<S, R>(a.xin, vs, pidx, xv);
     const R xc = (R)a.xcoef;
@@ -140,10 +155,26 @@ static hipError_t launch_s2(const StagLaunch &l, hipStream_t st) {
   a.nrhs = l.nrhs;
   a.rg = rhs_group(l.nrhs);
   const int bt = l.block_threads, nwg = rhs_grid(l.g.Vh, l.nrhs, bt);
-  if (l.xin)
-    hipLaunchKernelGGL((stag_kernel<S, R, RECON, true>), dim3(nwg), dim3(bt), 0, st, a);
-  else
-    hipLaunchKernelGGL((stag_kernel<S, R, RECON, false>), dim3(nwg), dim3(bt), 0, st, a);
+  if constexpr (sizeof(S) == 2) {
+    if (l.xin)
+      hipLaunchKernelGGL((stag_kernel<S, R, RECON, true, 0, 1, 0, 3, true>), dim3(nwg), dim3(bt), 0, st, a);
+    else
+      hipLaunchKernelGGL((stag_kernel<S, R, RECON, false, 0, 1, 0, 3, true>), dim3(nwg), dim3(bt), 0, st, a);
+  } else if constexpr (sizeof(S) == 4) {
+    if (l.xin)
+      hipLaunchKernelGGL((stag_kernel<S, R, RECON, true, 0, 0, 0, 3, true>), dim3(nwg), dim3(bt), 0, st, a);
+    else
+      hipLaunchKernelGGL((stag_kernel<S, R, RECON, false, 0, 0, 0, 3, true>), dim3(nwg), dim3(bt), 0, st, a);
+    hipLaunchKernelGGL((stag_kernel<S, R, RECON, false, 1, 1, 0, 3, false>), dim3(nwg), dim3(bt), 0, st, a);
+  } else {
+    if (l.xin)
+      hipLaunchKernelGGL((stag_kernel<S, R, RECON, true, 0, 0, 0, 1, true>), dim3(nwg), dim3(bt), 0, st, a);
+    else
+      hipLaunchKernelGGL((stag_kernel<S, R, RECON, false, 0, 0, 0, 1, true>), dim3(nwg), dim3(bt), 0, st, a);
+    hipLaunchKernelGGL((stag_kernel<S, R, RECON, false, 0, 0, 2, 3, false>), dim3(nwg), dim3(bt), 0, st, a);
+    hipLaunchKernelGGL((stag_kernel<S, R, RECON, false, 1, 1, 0, 1, false>), dim3(nwg), dim3(bt), 0, st, a);
+    hipLaunchKernelGGL((stag_kernel<S, R, RECON, false, 1, 1, 2, 3, false>), dim3(nwg), dim3(bt), 0, st, a);
+  }
   return hipGetLastError();
 }
 
