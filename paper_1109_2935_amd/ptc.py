@@ -126,9 +126,11 @@ def solver_pairs(ctx, op64, b_even_natural, every, max_pairs, xstar_tol=1e-12, t
     return [(rec_r[k * sb:(k + 1) * sb], rec_e[k * sb:(k + 1) * sb]) for k in range(n)]
 
 
-def train(ctx, net, op64, op32, dims, nsources, every=2, pairs_per_source=100, lr=2e-3, seed0=5100, log=None):
+def train(ctx, net, op64, op32, dims, nsources, every=2, pairs_per_source=100, lr=2e-3, seed0=5100, log=None,
+          lr_end=None):
     """Online training: for each Gaussian source (seeds seed0 + j) the solver's
-    pairs are generated on the GPU, converted to FP32 and used once each."""
+    pairs are generated on the GPU, converted to FP32 and used once each. With
+    lr_end the step size decays geometrically from lr to lr_end over the sources."""
     import synth
     r32, e32 = op32.spinor(), op32.spinor()
     losses = []
@@ -137,11 +139,12 @@ def train(ctx, net, op64, op32, dims, nsources, every=2, pairs_per_source=100, l
     for j in range(nsources):
         b = synth.gaussian_spinor(dims, seed0 + j)
         b = np.where(even[..., None, None], b, 0)
+        lr_j = lr if lr_end is None else lr * (lr_end / lr) ** (j / max(1, nsources - 1))
         for r64, e64 in solver_pairs(ctx, op64, b, every, pairs_per_source):
             L.lqcd_spinor_convert(ctx, op32.op, r32, op64.op, r64, 0)
             L.lqcd_spinor_convert(ctx, op32.op, e32, op64.op, e64, 0)
             losses.append(net.gradient(op32, r32, e32))
-            net.adam(lr)
+            net.adam(lr_j)
         if log:
             log("source %d: pairs %d, mean loss (last 50) %.4f, %.1fs" % (
                 j, len(losses), float(np.mean(losses[-50:])), time.time() - t0))
