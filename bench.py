@@ -158,11 +158,12 @@ def learned_solve(args, torch, L, ops, ctx, o64, o32, o32b, bp, block, mr, dims)
     ch = net.channels
     # complex multiply-adds per site: cout*4 x cin*9*4 for each of 3 colours; both parities except the last layer
     macs = sum(co * 4 * ci * 36 * 3 * (V // 2 if k == len(ch) - 2 else V) for k, (ci, co) in enumerate(zip(ch[:-1], ch[1:])))
-    log("FGCR(PTC): %d steps, %d applies, %.3f s; one application %.2f ms, %.1f TFLOP/s" % (
-        best.iters, best.precond_applies, best.seconds, dt * 1e3, 8 * macs / dt / 1e12))
+    log("FGCR(PTC): %d steps, %d applies (%d Schwarz fallback), %.3f s; one application %.2f ms, %.1f TFLOP/s" % (
+        best.iters, best.precond_applies, best.fallback_applies, best.seconds, dt * 1e3, 8 * macs / dt / 1e12))
     return {"gcr_unpreconditioned_seconds": round(plain.seconds, 4), "gcr_unpreconditioned_steps": plain.iters,
             "fgcr_learned_seconds": round(best.seconds, 4), "fgcr_learned_steps": best.iters,
-            "fgcr_learned_true_residual": best.true_residual, "ptc_apply_ms": round(dt * 1e3, 3),
+            "fgcr_learned_true_residual": best.true_residual,
+            "fgcr_learned_fallback_applies": best.fallback_applies, "ptc_apply_ms": round(dt * 1e3, 3),
             "ptc_apply_tflops": round(8 * macs / dt / 1e12, 1)}
 
 

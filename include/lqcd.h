@@ -109,6 +109,8 @@ typedef struct {
   int32_t restarts;          /* high-precision restarts / reliable updates */
   int32_t matvecs;           /* operator applications in the Krylov precision */
   int32_t precond_applies;   /* applications of K */
+  int32_t fallback_applies;  /* of those, Schwarz steps taken in place of the learned K */
+  int32_t reserved;          /* zero */
   double true_residual;      /* ||b - M x|| / ||b||, recomputed in FP64 at the end */
   double seconds;            /* wall time of the call */
 } lqcd_solve_info;
@@ -370,6 +372,27 @@ lqcd_status lqcd_ptc_apply(lqcd_context *ctx, const lqcd_operator *op, const lqc
  */
 lqcd_status lqcd_ptc_gradient(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc_net *net,
                               const void *r_even, const void *e_even, void *grad, double *loss, lqcd_stream stream);
+
+/*
+ * Residual loss L = |Mhat N(r) - r|^2 / |r|^2 over even sites (Mhat the even-odd
+ * Schur operator of op, which must carry its clover fields) and its gradient
+ * grad = dL/d conj(W); *loss (host) is set. The network then approximates
+ * Mhat^-1 on the directions r it is shown, weighted as GCR weights them: the
+ * residual left after a preconditioned step.
+ */
+lqcd_status lqcd_ptc_residual_gradient(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc_net *net,
+                                       const void *r_even, void *grad, double *loss, lqcd_stream stream);
+
+/*
+ * Vector-Jacobian product: grad = dL/d conj(W) for any real loss L whose
+ * derivative with respect to the network output y = N(r_even) is
+ * dy_even = dL/d conj(y) (FP32 packed even spinor of op; dL = 2 Re <dy, dy'>
+ * to first order). The forward pass on r_even is recomputed. Used to train on
+ * losses that involve the Dirac operator, e.g. |Mhat N(r) - r|^2 / |r|^2 with
+ * dy = Mhat^+ (Mhat N(r) - r) / |r|^2.
+ */
+lqcd_status lqcd_ptc_vjp(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc_net *net, const void *r_even,
+                         const void *dy_even, void *grad, lqcd_stream stream);
 
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the FP32 master weights. */
 lqcd_status lqcd_ptc_adam(lqcd_context *ctx, const lqcd_ptc_shape *shape, void *weights, void *m, void *v,

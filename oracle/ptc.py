@@ -16,6 +16,8 @@ G = dL/d(conj W), so that dL = 2 Re <G, dW>. With
 L = sum_even |y - e|^2 / |e|^2, delta = dL/d(conj y) = (y - e)/|e|^2 on even sites,
     dL/d(conj W[o,i,p]) = sum_x delta_o(x) (T_p psi_i(x))^+   (spin outer product, traced over colour)
     dL/d(conj psi_i)    = sum_{o,p} T_p^+ (W[o,i,p]^+ delta_o).
+With the residual loss L = |Mhat y - r|^2 / |r|^2 (Mhat the even-odd Schur
+operator) the output cotangent is delta = Mhat^+ (Mhat y - r) / |r|^2.
 """
 import numpy as np
 
@@ -71,14 +73,39 @@ def forward(dims, U, r, Ws, even_mask, bc_t=-1):
     return y, acts
 
 
+def backprop(dims, U, acts, Ws, delta, bc_t=-1):
+    """dL/d conj W for every layer from the output cotangent delta = dL/d conj y
+    (even sites) and the layer inputs of the forward pass."""
+    delta = delta[None]
+    grads = [None] * len(Ws)
+    for k in range(len(Ws) - 1, -1, -1):
+        grads[k], delta = layer_backward(dims, U, acts[k], Ws[k], delta, bc_t)
+    return grads
+
+
 def loss_and_grads(dims, U, r, e, Ws, even_mask, bc_t=-1):
     """L = |y - e|^2 / |e|^2 on even sites and dL/d conj W for every layer."""
     y, acts = forward(dims, U, r, Ws, even_mask, bc_t)
     en2 = np.vdot(e, e).real
     diff = y - np.where(even_mask[..., None, None], e, 0)
     L = np.vdot(diff, diff).real / en2
-    delta = (diff / en2)[None]
-    grads = [None] * len(Ws)
-    for k in range(len(Ws) - 1, -1, -1):
-        grads[k], delta = layer_backward(dims, U, acts[k], Ws[k], delta, bc_t)
-    return L, grads
+    return L, backprop(dims, U, acts, Ws, diff / en2, bc_t)
+
+
+def vjp(dims, U, r, dy, Ws, even_mask, bc_t=-1):
+    """dL/d conj W for a loss whose cotangent at the output is dy (even sites)."""
+    _, acts = forward(dims, U, r, Ws, even_mask, bc_t)
+    return backprop(dims, U, acts, Ws, np.where(even_mask[..., None, None], dy, 0), bc_t)
+
+
+def residual_loss_and_grads(dims, U, r, Ws, even_mask, schur, bc_t=-1):
+    """L = |Mhat y - r|^2 / |r|^2 over even sites, y = N(r), and dL/d conj W.
+    schur(x, dagger) applies Mhat (or its adjoint) to a field read on even
+    sites; the cotangent is dL/d conj y = Mhat^+ (Mhat y - r) / |r|^2."""
+    y, acts = forward(dims, U, r, Ws, even_mask, bc_t)
+    re = np.where(even_mask[..., None, None], r, 0)
+    rn2 = np.vdot(re, re).real
+    z = np.where(even_mask[..., None, None], schur(y, False), 0) - re
+    L = np.vdot(z, z).real / rn2
+    delta = np.where(even_mask[..., None, None], schur(z, True), 0) / rn2
+    return L, backprop(dims, U, acts, Ws, delta, bc_t)

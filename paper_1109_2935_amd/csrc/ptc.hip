@@ -19,6 +19,8 @@
 // input channels in LDS (parallel transport, converted to BF16), then each of
 // its 4 waves runs the MFMA tiles it owns; weights come pre-packed in the
 // per-lane A-operand order, so each A fragment is one coalesced 16-byte load.
+#include <type_traits>
+
 #include "lqcd_internal.h"
 #include "lqcd_ptc.h"
 
@@ -26,6 +28,13 @@ namespace lqcd {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// (x, y) rounded to nearest-even BF16, x in the low half
+__device__ __forceinline__ bf16x2_t pack_bf16x2(float x, float y) {
+  return __builtin_convertvector(f32x2_t{x, y}, bf16x2_t);
+}
 
 constexpr int kTile = 16;      // sites per workgroup tile
 constexpr int kPtcThreads = 256;
@@ -212,12 +221,14 @@ __device__ __forceinline__ bf16x8_t lds_frag(const __bf16 *row) {
 
 constexpr int kFwRow = 16 * 8 + kLdsPad;  // bf16 per LDS row: 16 items x 8 K values + padding
 
-template <int NS, int WPE>
+template <int NS, int WPE, bool PIPE>
 __global__ void __launch_bounds__(kPtcThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
 ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void *out, int out_f32, int par) {
   constexpr int kFwSites = NS, NT = 3 * NS / 16;
   __shared__ __align__(16) __bf16 Bt[3 * NS * kFwRow];
-  const int s0 = blockIdx.x * kFwSites;
+  // each XCD takes a contiguous range of site tiles, so that the neighbours'
+  // activations are read from its own L2
+  const int s0 = xcd_remap(blockIdx.x, gridDim.x) * kFwSites;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // this wave's output tiles
   int mbase, nm, nbase, nn;
@@ -259,7 +270,27 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
       }
     }
   };
-  if (L.cin == 16 && kFwSites * 8 == kPtcThreads) {
+  // the same product with compile-time tile counts (all loads of a K step
+  // issued before its MFMAs, no per-tile branches): SM m-tiles x SN n-tiles
+  auto mma_static = [&](auto smc, auto snc, int q0) {
+    constexpr int SM = decltype(smc)::value, SN = decltype(snc)::value;
+#pragma unroll
+    for (int kl = 0; kl < 4; ++kl) {
+      const int ks = q0 / 4 + kl;
+      bf16x8_t a[SM], b[SN];
+#pragma unroll
+      for (int j = 0; j < SM; ++j) a[j] = A[((size_t)(mbase + 4 * j) * L.fw_ks + ks) * 64 + lane];
+#pragma unroll
+      for (int t = 0; t < SN; ++t)
+        b[t] = lds_frag(Bt + ((nbase + t) * 16 + (lane & 15)) * kFwRow + kl * 32 + 8 * (lane >> 4));
+#pragma unroll
+      for (int t = 0; t < SN; ++t)
+#pragma unroll
+        for (int j = 0; j < SM; ++j) acc[j][t] = mfma_bf16(a[j], b[t], acc[j][t]);
+    }
+  };
+  if constexpr (PIPE) {
+    static_assert(kFwSites * 8 == kPtcThreads, "pipelined path: 8 threads per site");
     // 16 input channels, one thread per (site, channel pair un, un + 8), one
     // path per chunk; the loads of path p + 1 are issued before the matrix
     // products of path p, so their latency overlaps them.
@@ -307,20 +338,16 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
           for (int c = 0; c < 3; ++c) *reinterpret_cast<bf16x8_t *>(dst + c * kFwSites * kFwRow + 64 * k) = zero;
         return;
       }
-      float r[2][24];
+      // word 3 sp + col of a channel: the (re, im) BF16 pair of spin sp, colour col
+      uint32_t w[2][12];
 #pragma unroll
       for (int k = 0; k < 2; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const uint4 w4 = raw[k][c];
-          r[k][8 * c + 0] = __uint_as_float(w4.x << 16);
-          r[k][8 * c + 1] = __uint_as_float(w4.x & 0xffff0000u);
-          r[k][8 * c + 2] = __uint_as_float(w4.y << 16);
-          r[k][8 * c + 3] = __uint_as_float(w4.y & 0xffff0000u);
-          r[k][8 * c + 4] = __uint_as_float(w4.z << 16);
-          r[k][8 * c + 5] = __uint_as_float(w4.z & 0xffff0000u);
-          r[k][8 * c + 6] = __uint_as_float(w4.w << 16);
-          r[k][8 * c + 7] = __uint_as_float(w4.w & 0xffff0000u);
+          w[k][4 * c + 0] = raw[k][c].x;
+          w[k][4 * c + 1] = raw[k][c].y;
+          w[k][4 * c + 2] = raw[k][c].z;
+          w[k][4 * c + 3] = raw[k][c].w;
         }
       if (p != 0) {
         const bool fwd = ((p - 1) & 1) == 0;
@@ -330,39 +357,52 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
           U0 = unpack_link<12, float>(lv);
         else
           U0 = unpack_link<18, float>(lv);
-        Link<float> U;
+        // the applied matrix (U, or U^+ for a backward hop, times the boundary
+        // sign) as BF16 pairs: re(u v) = dot((Ur, -Ui), (vr, vi)),
+        // im(u v) = dot((Ui, Ur), (vr, vi)), products exact, FP32 sums
+        bf16x2_t Pr[3][3], Pi[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-          for (int b = 0; b < 3; ++b) U.m[a][b] = ph * (fwd ? U0.m[a][b] : conj(U0.m[b][a]));
+          for (int b = 0; b < 3; ++b) {
+            const cpx<float> e = fwd ? U0.m[a][b] : conj(U0.m[b][a]);
+            Pr[a][b] = pack_bf16x2(ph * e.re, -ph * e.im);
+            Pi[a][b] = pack_bf16x2(ph * e.im, ph * e.re);
+          }
 #pragma unroll
         for (int k = 0; k < 2; ++k)
 #pragma unroll
           for (int sp = 0; sp < 4; ++sp) {
-            cpx<float> v[3], u[3];
+            bf16x2_t v[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) v[c] = mk<float>(r[k][6 * sp + 2 * c], r[k][6 * sp + 2 * c + 1]);
-            su3_mv(U, v, u);
+            for (int b = 0; b < 3; ++b) v[b] = __builtin_bit_cast(bf16x2_t, w[k][3 * sp + b]);
+            uint32_t o[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              r[k][6 * sp + 2 * c] = u[c].re;
-              r[k][6 * sp + 2 * c + 1] = u[c].im;
+            for (int a = 0; a < 3; ++a) {
+              float re = 0.f, im = 0.f;
+#pragma unroll
+              for (int b = 0; b < 3; ++b) {
+                re = __builtin_amdgcn_fdot2_f32_bf16(Pr[a][b], v[b], re, false);
+                im = __builtin_amdgcn_fdot2_f32_bf16(Pi[a][b], v[b], im, false);
+              }
+              o[a] = __builtin_bit_cast(uint32_t, pack_bf16x2(re, im));
             }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) w[k][3 * sp + a] = o[a];
           }
       }
+      // colour c: the four spins' (re, im) words
 #pragma unroll
       for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          bf16x8_t v;
-#pragma unroll
-          for (int sp = 0; sp < 4; ++sp) {
-            v[2 * sp] = (__bf16)r[k][6 * sp + 2 * c];
-            v[2 * sp + 1] = (__bf16)r[k][6 * sp + 2 * c + 1];
-          }
-          *reinterpret_cast<bf16x8_t *>(dst + c * kFwSites * kFwRow + 64 * k) = v;
-        }
+        for (int c = 0; c < 3; ++c)
+          *reinterpret_cast<uint4 *>(dst + c * kFwSites * kFwRow + 64 * k) =
+              make_uint4(w[k][c], w[k][3 + c], w[k][6 + c], w[k][9 + c]);
     };
+    // per path: transport into LDS, issue the next path's loads, then the
+    // matrix products (their latency overlaps the products)
+    constexpr int kSplitN = (NT + 3) / 4;  // n-tiles per wave when one m-tile is split over 4 waves
+    const int form = (nm == 2 && nn == NT) ? 2 : (nm == 1 && nn == kSplitN) ? 1 : (nn > 0 ? 0 : -1);
     issue(0);
 #pragma unroll 1
     for (int p = 0; p < 9; ++p) {
@@ -370,7 +410,12 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
       compute(p);
       if (p + 1 < 9) issue(p + 1);
       __syncthreads();
-      mma_chunk(16 * p, 16);
+      if (form == 2)
+        mma_static(std::integral_constant<int, 2>(), std::integral_constant<int, NT>(), 16 * p);
+      else if (form == 1)
+        mma_static(std::integral_constant<int, 1>(), std::integral_constant<int, kSplitN>(), 16 * p);
+      else if (form == 0)
+        mma_chunk(16 * p, 16);
     }
   } else {
   for (int q0 = 0; q0 < 4 * L.fw_ks; q0 += L.fw_ipc) {
@@ -513,7 +558,7 @@ __global__ void __launch_bounds__(kPtcThreads) ptc_bwd_data_kernel(PtcGeo q, Ptc
   extern __shared__ __align__(16) unsigned char smem[];
   const int krow = L.kadj + kLdsPad;
   __bf16 *Bt = reinterpret_cast<__bf16 *>(smem);  // [48][krow]: delta, k = 2*(o*4+s) + r
-  const int s0 = blockIdx.x * kTile;
+  const int s0 = xcd_remap(blockIdx.x, gridDim.x) * kTile;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int e = threadIdx.x; e < 48 * krow; e += kPtcThreads) Bt[e] = (__bf16)0.f;
   __syncthreads();
@@ -573,7 +618,7 @@ __global__ void __launch_bounds__(kPtcThreads) ptc_bwd_data_kernel(PtcGeo q, Ptc
 // (site, channel) of parity par.
 __global__ void __launch_bounds__(256) ptc_adjoint_gather_kernel(PtcGeo q, int cin, const float *gy, float *gpsi,
                                                                   int par) {
-  const int pidx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pidx = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (pidx >= q.g.Vh * cin) return;
   const int s = pidx / cin, i = pidx - s * cin;
   const Site x = decode_site(q.g, s, par);
@@ -830,14 +875,18 @@ hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *
   // LDS staging of the output tile: BF16 up to 16 channels; FP32 one channel
   if (out_f32 && L.cout != 1) return hipErrorInvalidValue;
   switch (variant) {
-    case 642:
-      hipLaunchKernelGGL((ptc_forward_kernel<64, 2>), dim3((q.g.Vh + 63) / 64), dim3(kPtcThreads), 0, st, q, L, nbr,
-                         (const bf16 *)in, out, out_f32, par);
-      break;
-    default:
-      hipLaunchKernelGGL((ptc_forward_kernel<32, 2>), dim3((q.g.Vh + 31) / 32), dim3(kPtcThreads), 0, st, q, L, nbr,
-                         (const bf16 *)in, out, out_f32, par);
-      break;
+#define PTC_FWD(NS, WPE, PIPE)                                                                            \
+  hipLaunchKernelGGL((ptc_forward_kernel<NS, WPE, PIPE>), dim3((q.g.Vh + NS - 1) / NS), dim3(kPtcThreads), 0, st, q, \
+                     L, nbr, (const bf16 *)in, out, out_f32, par);                                                  \
+  break;
+    case 642: PTC_FWD(64, 2, false)
+    case 322: PTC_FWD(32, 2, false)
+    // the pipelined 16-channel path at 2, 3 or 4 waves per SIMD
+    case 3221: if (L.cin != 16) return hipErrorInvalidValue; PTC_FWD(32, 2, true)
+    case 3231: if (L.cin != 16) return hipErrorInvalidValue; PTC_FWD(32, 3, true)
+    case 3241: if (L.cin != 16) return hipErrorInvalidValue; PTC_FWD(32, 4, true)
+    default: return hipErrorInvalidValue;
+#undef PTC_FWD
   }
   return hipGetLastError();
 }

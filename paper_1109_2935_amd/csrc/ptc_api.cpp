@@ -90,10 +90,12 @@ static lqcd_status ptc_forward_all(lqcd_context *ctx, const PtcPlan &plan, const
     const bool last = l == plan.nl - 1;
     const PtcLayerDev &L = plan.layers[l];
     void *out = last ? y_even : acts[l + 1];
-    // sites per workgroup: timed once per layer shape and geometry
+    // sites per workgroup (and, for 16 input channels, the pipelined form and
+    // its waves per SIMD): timed once per layer shape and geometry
     std::ostringstream key;
     key << "ptc_fwd/" << L.cin << "-" << L.cout << "/" << geom_key(q.g);
-    const int variant = tune_pick(ctx, key.str(), {642, 322}, 642, true, st, [&](int v) {
+    const std::vector<int> cands = L.cin == 16 ? std::vector<int>{642, 3221, 3231, 3241} : std::vector<int>{642, 322};
+    const int variant = tune_pick(ctx, key.str(), cands, 642, true, st, [&](int v) {
       return launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, 0, v, st);
     });
     for (int par = 0; par < (last ? 1 : 2); ++par)
@@ -129,6 +131,101 @@ lqcd_status ptc_apply(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc
   std::vector<void *> acts;
   TRY(ptc_buffers(ctx, plan, info, kSlotPtc, acts));
   return ptc_forward_all(ctx, plan, q, info, in_even, acts, out_even, st);
+}
+
+enum PtcLoss { kLossError, kLossResidual, kLossCotangent };
+
+// Forward pass of the network on r_even, then back-propagation of an output
+// cotangent delta = dL/d conj(y) (y = N(r_even), even sites) to the weights:
+// grad = dL/d conj(W). The cotangent is
+//   kLossError:     (y - e) / |e|^2 for L = |y - e|^2 / |e|^2 (aux = e_even),
+//   kLossResidual:  Mhat^+ z / |r|^2, z = Mhat y - r, for L = |z|^2 / |r|^2,
+//   kLossCotangent: aux itself (dy_even),
+// and *loss (if given) is set for the first two.
+static lqcd_status ptc_backprop(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc_net *net,
+                                const void *r_even, PtcLoss kind, const void *aux, void *grad, double *loss,
+                                hipStream_t st) {
+  PtcPlan plan;
+  TRY(ptc_plan(ctx, &net->shape, &plan));
+  bind_packed(plan, net->packed);
+  OpInfo info;
+  PtcGeo q;
+  TRY(ptc_geo(ctx, op, &info, &q));
+  const size_t vh = info.vh;
+  std::vector<void *> acts;
+  TRY(ptc_buffers(ctx, plan, info, kSlotPtc, acts));
+  TRY(ptc_forward_all(ctx, plan, q, info, r_even, acts, acts[plan.nl], st));
+  int maxc = 1, maxc9 = 9;
+  for (auto &L : plan.layers) {
+    maxc = std::max(maxc, std::max(L.cin, L.cout));
+    maxc9 = std::max(maxc9, 9 * L.cin);
+  }
+  void *d0, *d1, *gy, *part;
+  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 1, 2 * vh * 24 * maxc * sizeof(float), &d0));
+  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 2, 2 * vh * 24 * maxc * sizeof(float), &d1));
+  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 3, 2 * vh * 24 * (size_t)maxc9 * sizeof(float), &gy));
+  const int groups = 128;
+  size_t pbytes = 0;
+  for (auto &L : plan.layers) {
+    const size_t ldc = (size_t)((L.chunk_ch * 36 + 15) / 16) * 16;
+    pbytes = std::max(pbytes, (size_t)L.nchunk * groups * L.mw_tiles * 16 * ldc * sizeof(float));
+  }
+  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 4, pbytes, &part));
+  RedScratch red = red_scratch(ctx);
+  const size_t n = vh * 12;  // complex entries of one even field
+  float *delta = (float *)d0;
+  TRY(hip_check(ctx, hipMemsetAsync(delta, 0, 2 * vh * 24 * sizeof(float), st), "memset"));
+  if (kind == kLossError) {
+    // loss = |y - e|^2 / |e|^2 on even sites; delta = dL/d conj(y) = (y - e) / |e|^2
+    const void *e_even = aux;
+    double en2 = 0, dn2 = 0;
+    TRY(hip_check(ctx, blas_norm2(LQCD_F32, e_even, n, red, st), "norm"));
+    TRY(read_result(ctx, st, 1, &en2));
+    if (!(en2 > 0)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "target has zero norm");
+    TRY(hip_check(ctx, hipMemcpyAsync(delta, acts[plan.nl], vh * 24 * sizeof(float), hipMemcpyDeviceToDevice, st),
+                  "copy"));
+    TRY(hip_check(ctx, blas_axpby(LQCD_F32, e_even, LQCD_F32, delta, n, -1.0, 0.0, 1.0, 0.0, &red, st), "axpby"));
+    TRY(read_result(ctx, st, 1, &dn2));
+    TRY(hip_check(ctx, blas_convert(LQCD_F32, delta, LQCD_F32, delta, n, 1.0 / en2, st), "scale"));
+    if (loss) *loss = dn2 / en2;
+  } else if (kind == kLossResidual) {
+    // z = Mhat y - r; loss = |z|^2 / |r|^2; delta = Mhat^+ z / |r|^2
+    void *z, *tmp;
+    TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 6, info.spinor_bytes, &z));
+    TRY(scratch(ctx, kSlotSchurTmp, info.spinor_bytes, &tmp));
+    double rn2 = 0, zn2 = 0;
+    TRY(hip_check(ctx, blas_norm2(LQCD_F32, r_even, n, red, st), "norm"));
+    TRY(read_result(ctx, st, 1, &rn2));
+    if (!(rn2 > 0)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "input has zero norm");
+    TRY(schur_apply(ctx, info, info.g, z, acts[plan.nl], tmp, 0, nullptr, st));
+    TRY(hip_check(ctx, blas_axpby(LQCD_F32, r_even, LQCD_F32, z, n, -1.0, 0.0, 1.0, 0.0, &red, st), "axpby"));
+    TRY(read_result(ctx, st, 1, &zn2));
+    TRY(schur_apply(ctx, info, info.g, delta, z, tmp, 1, nullptr, st));
+    TRY(hip_check(ctx, blas_convert(LQCD_F32, delta, LQCD_F32, delta, n, 1.0 / rn2, st), "scale"));
+    if (loss) *loss = zn2 / rn2;
+  } else {
+    // the caller's cotangent dL/d conj(y) on even sites
+    TRY(hip_check(ctx, hipMemcpyAsync(delta, aux, vh * 24 * sizeof(float), hipMemcpyDeviceToDevice, st), "copy"));
+  }
+  // backward through the layers
+  float *dcur = (float *)d0, *dnext = (float *)d1;
+  for (int l = plan.nl - 1; l >= 0; --l) {
+    const PtcLayerDev &L = plan.layers[l];
+    const bool last = l == plan.nl - 1;
+    float *gw = (float *)grad + 2 * plan.woff[l];
+    for (int par = 0; par < (last ? 1 : 2); ++par) {
+      TRY(hip_check(ctx, launch_ptc_bwd_weight(q, L, acts[l], dcur, (float *)part, par, groups, st), "ptc dW"));
+      TRY(hip_check(ctx, launch_ptc_weight_reduce(L, (const float *)part, groups, gw, par, st), "ptc dW reduce"));
+    }
+    if (l == 0) break;
+    TRY(hip_check(ctx, hipMemsetAsync(gy, 0, 2 * vh * 24 * (size_t)(9 * L.cin) * sizeof(float), st), "memset"));
+    for (int par = 0; par < (last ? 1 : 2); ++par)
+      TRY(hip_check(ctx, launch_ptc_bwd_data(q, L, dcur, (float *)gy, par, st), "ptc dY"));
+    for (int par = 0; par < 2; ++par)
+      TRY(hip_check(ctx, launch_ptc_adjoint_gather(q, L.cin, (const float *)gy, dnext, par, st), "ptc adjoint"));
+    std::swap(dcur, dnext);
+  }
+  return LQCD_OK;
 }
 
 }  // namespace lqcd
@@ -169,66 +266,22 @@ lqcd_status lqcd_ptc_gradient(lqcd_context *ctx, const lqcd_operator *op, const 
                               const void *r_even, const void *e_even, void *grad, double *loss, lqcd_stream stream) {
   if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
   if (!net || !r_even || !e_even || !grad) return set_error(ctx, LQCD_ERR_INVALID_ARG, "NULL argument");
-  hipStream_t st = (hipStream_t)stream;
-  PtcPlan plan;
-  TRY(ptc_plan(ctx, &net->shape, &plan));
-  bind_packed(plan, net->packed);
-  OpInfo info;
-  PtcGeo q;
-  TRY(ptc_geo(ctx, op, &info, &q));
-  const size_t vh = info.vh;
-  std::vector<void *> acts;
-  TRY(ptc_buffers(ctx, plan, info, kSlotPtc, acts));
-  TRY(ptc_forward_all(ctx, plan, q, info, r_even, acts, acts[plan.nl], st));
-  // loss = |y - e|^2 / |e|^2 on even sites; delta = (y - e) / |e|^2
-  int maxc = 1, maxc9 = 9;
-  for (auto &L : plan.layers) {
-    maxc = std::max(maxc, std::max(L.cin, L.cout));
-    maxc9 = std::max(maxc9, 9 * L.cin);
-  }
-  void *d0, *d1, *gy, *part;
-  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 1, 2 * vh * 24 * maxc * sizeof(float), &d0));
-  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 2, 2 * vh * 24 * maxc * sizeof(float), &d1));
-  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 3, 2 * vh * 24 * (size_t)maxc9 * sizeof(float), &gy));
-  const int groups = 128;
-  size_t pbytes = 0;
-  for (auto &L : plan.layers) {
-    const size_t ldc = (size_t)((L.chunk_ch * 36 + 15) / 16) * 16;
-    pbytes = std::max(pbytes, (size_t)L.nchunk * groups * L.mw_tiles * 16 * ldc * sizeof(float));
-  }
-  TRY(scratch(ctx, kSlotPtc + kPtcMaxLayers + 4, pbytes, &part));
-  RedScratch red = red_scratch(ctx);
-  const size_t n = vh * 12;  // complex entries of one even field
-  double en2 = 0, dn2 = 0;
-  TRY(hip_check(ctx, blas_norm2(LQCD_F32, e_even, n, red, st), "norm"));
-  TRY(read_result(ctx, st, 1, &en2));
-  if (!(en2 > 0)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "target has zero norm");
-  float *delta = (float *)d0;
-  TRY(hip_check(ctx, hipMemsetAsync(delta, 0, 2 * vh * 24 * sizeof(float), st), "memset"));
-  TRY(hip_check(ctx, hipMemcpyAsync(delta, acts[plan.nl], vh * 24 * sizeof(float), hipMemcpyDeviceToDevice, st), "copy"));
-  TRY(hip_check(ctx, blas_axpby(LQCD_F32, e_even, LQCD_F32, delta, n, -1.0, 0.0, 1.0, 0.0, &red, st), "axpby"));
-  TRY(read_result(ctx, st, 1, &dn2));
-  TRY(hip_check(ctx, blas_convert(LQCD_F32, delta, LQCD_F32, delta, n, 1.0 / en2, st), "scale"));
-  if (loss) *loss = dn2 / en2;
-  // backward through the layers
-  float *dcur = (float *)d0, *dnext = (float *)d1;
-  for (int l = plan.nl - 1; l >= 0; --l) {
-    const PtcLayerDev &L = plan.layers[l];
-    const bool last = l == plan.nl - 1;
-    float *gw = (float *)grad + 2 * plan.woff[l];
-    for (int par = 0; par < (last ? 1 : 2); ++par) {
-      TRY(hip_check(ctx, launch_ptc_bwd_weight(q, L, acts[l], dcur, (float *)part, par, groups, st), "ptc dW"));
-      TRY(hip_check(ctx, launch_ptc_weight_reduce(L, (const float *)part, groups, gw, par, st), "ptc dW reduce"));
-    }
-    if (l == 0) break;
-    TRY(hip_check(ctx, hipMemsetAsync(gy, 0, 2 * vh * 24 * (size_t)(9 * L.cin) * sizeof(float), st), "memset"));
-    for (int par = 0; par < (last ? 1 : 2); ++par)
-      TRY(hip_check(ctx, launch_ptc_bwd_data(q, L, dcur, (float *)gy, par, st), "ptc dY"));
-    for (int par = 0; par < 2; ++par)
-      TRY(hip_check(ctx, launch_ptc_adjoint_gather(q, L.cin, (const float *)gy, dnext, par, st), "ptc adjoint"));
-    std::swap(dcur, dnext);
-  }
-  return LQCD_OK;
+  return ptc_backprop(ctx, op, net, r_even, kLossError, e_even, grad, loss, (hipStream_t)stream);
+}
+
+lqcd_status lqcd_ptc_residual_gradient(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc_net *net,
+                                       const void *r_even, void *grad, double *loss, lqcd_stream stream) {
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  if (!op || !net || !r_even || !grad) return set_error(ctx, LQCD_ERR_INVALID_ARG, "NULL argument");
+  TRY(check_fields_internal(ctx, op));
+  return ptc_backprop(ctx, op, net, r_even, kLossResidual, nullptr, grad, loss, (hipStream_t)stream);
+}
+
+lqcd_status lqcd_ptc_vjp(lqcd_context *ctx, const lqcd_operator *op, const lqcd_ptc_net *net, const void *r_even,
+                         const void *dy_even, void *grad, lqcd_stream stream) {
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  if (!net || !r_even || !dy_even || !grad) return set_error(ctx, LQCD_ERR_INVALID_ARG, "NULL argument");
+  return ptc_backprop(ctx, op, net, r_even, kLossCotangent, dy_even, grad, nullptr, (hipStream_t)stream);
 }
 
 lqcd_status lqcd_ptc_adam(lqcd_context *ctx, const lqcd_ptc_shape *shape, void *weights, void *m, void *v,

@@ -212,6 +212,7 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
       TRY(schwarz_apply(ctx, pc, &prm->schwarz, pout, pin, kSlotSchwarz, S.st));
       TRY(to_layout(pc, pout, kr, P[k], 1.0 / sc));
       inf.precond_applies++;
+      if (pk == LQCD_PRECOND_LEARNED) inf.fallback_applies++;
       use_fallback = false;
     } else if (pk == LQCD_PRECOND_LEARNED) {
       if (k_relayout) {

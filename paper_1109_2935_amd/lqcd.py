@@ -48,7 +48,8 @@ class lqcd_operator(ctypes.Structure):
 
 class lqcd_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("matvecs", ctypes.c_int32),
-                ("precond_applies", ctypes.c_int32), ("true_residual", ctypes.c_double),
+                ("precond_applies", ctypes.c_int32), ("fallback_applies", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("true_residual", ctypes.c_double),
                 ("seconds", ctypes.c_double)]
 
     def as_dict(self):
@@ -113,6 +114,8 @@ _SIGNATURES = {
     "lqcd_ptc_pack": [_P, ctypes.POINTER(lqcd_ptc_shape), _P, _P, _P],
     "lqcd_ptc_apply": [_P, _OPP, ctypes.POINTER(lqcd_ptc_net), _P, _P, _P],
     "lqcd_ptc_gradient": [_P, _OPP, ctypes.POINTER(lqcd_ptc_net), _P, _P, _P, ctypes.POINTER(ctypes.c_double), _P],
+    "lqcd_ptc_residual_gradient": [_P, _OPP, ctypes.POINTER(lqcd_ptc_net), _P, _P, ctypes.POINTER(ctypes.c_double), _P],
+    "lqcd_ptc_vjp": [_P, _OPP, ctypes.POINTER(lqcd_ptc_net), _P, _P, _P, _P],
     "lqcd_ptc_adam": [_P, ctypes.POINTER(lqcd_ptc_shape), _P, _P, _P, _P, _I, ctypes.c_double, _P],
 }
 EXPORTED = tuple(_SIGNATURES)
@@ -283,6 +286,18 @@ def lqcd_ptc_gradient(ctx, op, net, r_even, e_even, grad, stream=None):
     _check(lib().lqcd_ptc_gradient(ctx, ctypes.byref(op), ctypes.byref(net), _ptr(r_even), _ptr(e_even), _ptr(grad),
                                    ctypes.byref(loss), _stream(stream)), ctx)
     return loss.value
+
+
+def lqcd_ptc_residual_gradient(ctx, op, net, r_even, grad, stream=None):
+    loss = ctypes.c_double()
+    _check(lib().lqcd_ptc_residual_gradient(ctx, ctypes.byref(op), ctypes.byref(net), _ptr(r_even), _ptr(grad),
+                                            ctypes.byref(loss), _stream(stream)), ctx)
+    return loss.value
+
+
+def lqcd_ptc_vjp(ctx, op, net, r_even, dy_even, grad, stream=None):
+    _check(lib().lqcd_ptc_vjp(ctx, ctypes.byref(op), ctypes.byref(net), _ptr(r_even), _ptr(dy_even), _ptr(grad),
+                              _stream(stream)), ctx)
 
 
 def lqcd_ptc_adam(ctx, shape, weights, m, v, grad, step, lr, stream=None):

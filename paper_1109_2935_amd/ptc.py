@@ -87,6 +87,13 @@ class Network:
     def gradient(self, op32, r_even, e_even):
         return L.lqcd_ptc_gradient(self.ctx, op32.op, self.net, r_even, e_even, self.grad)
 
+    def residual_gradient(self, op32, r_even):
+        """|Mhat N(r) - r|^2 / |r|^2 and its gradient (into self.grad)."""
+        return L.lqcd_ptc_residual_gradient(self.ctx, op32.op, self.net, r_even, self.grad)
+
+    def vjp(self, op32, r_even, dy_even):
+        L.lqcd_ptc_vjp(self.ctx, op32.op, self.net, r_even, dy_even, self.grad)
+
     def adam(self, lr):
         self.step += 1
         L.lqcd_ptc_adam(self.ctx, self.shape, self.weights, self.m, self.v, self.grad, self.step, lr)
@@ -127,25 +134,48 @@ def solver_pairs(ctx, op64, b_even_natural, every, max_pairs, xstar_tol=1e-12, t
 
 
 def train(ctx, net, op64, op32, dims, nsources, every=2, pairs_per_source=100, lr=2e-3, seed0=5100, log=None,
-          lr_end=None):
+          lr_end=None, objective="error", max_pairs=None):
     """Online training: for each Gaussian source (seeds seed0 + j) the solver's
-    pairs are generated on the GPU, converted to FP32 and used once each. With
-    lr_end the step size decays geometrically from lr to lr_end over the sources."""
+    pairs are generated on the GPU, converted to FP32 and used once each.
+    nsources sources, or, with max_pairs, as many sources as it takes to reach
+    max_pairs pairs (a solve that converges early yields fewer than
+    pairs_per_source). With lr_end the step size decays geometrically from lr
+    to lr_end, over the sources, or over the pairs when max_pairs is given.
+    objective "error": |N(r) - e|^2 / |e|^2; "residual": |Mhat N(r) - r|^2 / |r|^2
+    (only the residual of each pair is used)."""
+    if objective not in ("error", "residual"):
+        raise ValueError("objective must be 'error' or 'residual'")
     import synth
     r32, e32 = op32.spinor(), op32.spinor()
     losses = []
     t0 = time.time()
     even = synth.parity_of_sites(dims) == 0
-    for j in range(nsources):
+
+    def step_size(j):
+        if lr_end is None:
+            return lr
+        if max_pairs:
+            return lr * (lr_end / lr) ** (len(losses) / max(1, max_pairs - 1))
+        return lr * (lr_end / lr) ** (j / max(1, nsources - 1))
+
+    j = 0
+    while (len(losses) < max_pairs) if max_pairs else (j < nsources):
         b = synth.gaussian_spinor(dims, seed0 + j)
         b = np.where(even[..., None, None], b, 0)
-        lr_j = lr if lr_end is None else lr * (lr_end / lr) ** (j / max(1, nsources - 1))
-        for r64, e64 in solver_pairs(ctx, op64, b, every, pairs_per_source):
+        want = pairs_per_source if not max_pairs else min(pairs_per_source, max_pairs - len(losses))
+        pairs = solver_pairs(ctx, op64, b, every, want)
+        if not pairs:
+            raise RuntimeError("the solve for source %d produced no pairs" % j)
+        for r64, e64 in pairs:
             L.lqcd_spinor_convert(ctx, op32.op, r32, op64.op, r64, 0)
-            L.lqcd_spinor_convert(ctx, op32.op, e32, op64.op, e64, 0)
-            losses.append(net.gradient(op32, r32, e32))
-            net.adam(lr_j)
+            if objective == "residual":
+                losses.append(net.residual_gradient(op32, r32))
+            else:
+                L.lqcd_spinor_convert(ctx, op32.op, e32, op64.op, e64, 0)
+                losses.append(net.gradient(op32, r32, e32))
+            net.adam(step_size(j))
         if log:
             log("source %d: pairs %d, mean loss (last 50) %.4f, %.1fs" % (
                 j, len(losses), float(np.mean(losses[-50:])), time.time() - t0))
+        j += 1
     return losses

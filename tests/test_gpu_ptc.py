@@ -88,6 +88,60 @@ def test_ptc_gradient_matches_oracle(ctx, channels):
         assert rel(gk, G) < 6e-2, k
 
 
+def _flat_grads(net, gref):
+    flat = net.grad.cpu().numpy().view(np.complex64).astype(np.complex128)
+    out, off = [], 0
+    for G in gref:
+        out.append(flat[off:off + G.size].reshape(G.shape))
+        off += G.size
+    return out
+
+
+@pytest.mark.parametrize("channels", [(1, 4, 4, 1), (1, 16, 16, 16, 1)])
+def test_ptc_residual_gradient_matches_oracle(ctx, channels):
+    """|Mhat N(r) - r|^2 / |r|^2 and its gradient: network, FP32 Schur operator
+    and its adjoint on the GPU against the FP64 oracle."""
+    U, o = system(ctx, DIMS, 101)
+    op32 = o[1]
+    even = oracle.parity_mask(DIMS, 0)
+    net = ptc.Network(ctx, channels)
+    Ws = weights_c64(optc.init_weights(102, channels=channels))
+    net.set_weights(Ws)
+    r = on_parity(synth.gaussian_spinor(DIMS, 103), even)
+    loss = net.residual_gradient(op32, op32.import_spinor(r, 0))
+    M = oracle.WilsonClover(DIMS, U, 0.124, 1.0)
+    Lref, gref = optc.residual_loss_and_grads(DIMS, U, r, Ws, even, M.schur)
+    assert abs(loss - Lref) < 2e-2 * Lref
+    for k, (g, G) in enumerate(zip(_flat_grads(net, gref), gref)):
+        assert rel(g, G) < 6e-2, k
+
+
+def test_ptc_vjp_matches_oracle(ctx):
+    channels = (1, 4, 4, 1)
+    U, o = system(ctx, DIMS, 111)
+    op32 = o[1]
+    even = oracle.parity_mask(DIMS, 0)
+    net = ptc.Network(ctx, channels)
+    Ws = weights_c64(optc.init_weights(112, channels=channels))
+    net.set_weights(Ws)
+    r = on_parity(synth.gaussian_spinor(DIMS, 113), even)
+    dy = on_parity(synth.gaussian_spinor(DIMS, 114), even)
+    net.vjp(op32, op32.import_spinor(r, 0), op32.import_spinor(dy, 0))
+    gref = optc.vjp(DIMS, U, r, dy, Ws, even)
+    for k, (g, G) in enumerate(zip(_flat_grads(net, gref), gref)):
+        assert rel(g, G) < 6e-2, k
+
+
+def test_ptc_residual_training_reduces_loss(ctx):
+    dims = (8, 8, 8, 8)
+    U, o = system(ctx, dims, 121, precs=(0, 1))
+    net = ptc.Network(ctx, (1, 16, 16, 16, 1), seed=122)
+    losses = ptc.train(ctx, net, o[0], o[1], dims, nsources=3, every=1, pairs_per_source=60, lr=3e-3, seed0=9200,
+                       objective="residual")
+    assert len(losses) >= 100
+    assert np.mean(losses[-30:]) < 0.7 * np.mean(losses[:10])
+
+
 def test_ptc_training_and_fgcr_gain(ctx):
     """Trained on solver pairs, the network preconditions flexible GCR: fewer
     Krylov steps than GCR without it, same FP64 residual (the gain is not
