@@ -223,7 +223,8 @@ constexpr int kFwRow = 16 * 8 + kLdsPad;  // bf16 per LDS row: 16 items x 8 K va
 
 template <int NS, int WPE, bool PIPE>
 __global__ void __launch_bounds__(kPtcThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
-ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void *out, int out_f32, int par) {
+ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void *out, int out_f32, int par,
+                   int zero_par) {
   constexpr int kFwSites = NS, NT = 3 * NS / 16;
   __shared__ __align__(16) __bf16 Bt[3 * NS * kFwRow];
   // each XCD takes a contiguous range of site tiles, so that the neighbours'
@@ -418,8 +419,13 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
         mma_chunk(16 * p, 16);
     }
   } else {
-  for (int q0 = 0; q0 < 4 * L.fw_ks; q0 += L.fw_ipc) {
-    const int ipc = min(L.fw_ipc, 4 * L.fw_ks - q0);
+  // input known to vanish on parity zero_par (the network input lives on even
+  // sites): the items reading that parity are zero, and when every hop is
+  // zero only the identity items' K steps are multiplied
+  const int hop_par = 1 - par;
+  const int q_end = zero_par == hop_par ? 4 * ((L.cin + 3) / 4) : 4 * L.fw_ks;
+  for (int q0 = 0; q0 < q_end; q0 += L.fw_ipc) {
+    const int ipc = min(L.fw_ipc, q_end - q0);
     __syncthreads();
     if (L.cin % 4 == 0) {
       // kNch items (one site and path) per thread: channels un and un + gn of
@@ -434,8 +440,9 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
         const int u0 = one_path ? un : kNch * un, kstep = one_path ? gn : 1;
         const int qi = q0 + u0, s = s0 + sl;
         __bf16 *dst = Bt + sl * kFwRow + 8 * u0;
-        if (s < q.g.Vh && qi < L.fw_items) {
-          const int p = qi / L.cin, i0 = qi - p * L.cin;
+        const int pq = qi / L.cin;
+        if (s < q.g.Vh && qi < L.fw_items && (pq == 0 ? par : hop_par) != zero_par) {
+          const int p = pq, i0 = qi - p * L.cin;
           if (q.recon == 12)
             transportn_lds<12, kNch>(q, nbr, in, L.cin, i0, kstep, p, par, s, dst, kFwSites * kFwRow);
           else
@@ -456,8 +463,9 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
         const int sl = w % kFwSites, u = w / kFwSites;
         const int qi = q0 + u, s = s0 + sl;
         __bf16 *dst = Bt + sl * kFwRow + 8 * u;
-        if (s < q.g.Vh && qi < L.fw_items) {
-          const int p = qi / L.cin, i = qi - p * L.cin;
+        const int pq = qi / L.cin;
+        if (s < q.g.Vh && qi < L.fw_items && (pq == 0 ? par : hop_par) != zero_par) {
+          const int p = pq, i = qi - p * L.cin;
           if (q.recon == 12)
             transportn_lds<12, 1>(q, nbr, in, L.cin, i, 1, p, par, s, dst, kFwSites * kFwRow);
           else
@@ -871,20 +879,21 @@ hipError_t launch_ptc_nbr(const Geom &g, int *tab, hipStream_t st) {
 }
 
 hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *nbr, const void *in, void *out,
-                              int out_f32, int par, int variant, hipStream_t st) {
+                              int out_f32, int par, int variant, int zero_par, hipStream_t st) {
   // LDS staging of the output tile: BF16 up to 16 channels; FP32 one channel
   if (out_f32 && L.cout != 1) return hipErrorInvalidValue;
   switch (variant) {
 #define PTC_FWD(NS, WPE, PIPE)                                                                            \
   hipLaunchKernelGGL((ptc_forward_kernel<NS, WPE, PIPE>), dim3((q.g.Vh + NS - 1) / NS), dim3(kPtcThreads), 0, st, q, \
-                     L, nbr, (const bf16 *)in, out, out_f32, par);                                                  \
+                     L, nbr, (const bf16 *)in, out, out_f32, par, zero_par);                                                  \
   break;
     case 642: PTC_FWD(64, 2, false)
     case 322: PTC_FWD(32, 2, false)
     // the pipelined 16-channel path at 2, 3 or 4 waves per SIMD
-    case 3221: if (L.cin != 16) return hipErrorInvalidValue; PTC_FWD(32, 2, true)
-    case 3231: if (L.cin != 16) return hipErrorInvalidValue; PTC_FWD(32, 3, true)
-    case 3241: if (L.cin != 16) return hipErrorInvalidValue; PTC_FWD(32, 4, true)
+    // (the pipelined path reads every path: no input parity may be known zero)
+    case 3221: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 2, true)
+    case 3231: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, true)
+    case 3241: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, true)
     default: return hipErrorInvalidValue;
 #undef PTC_FWD
   }

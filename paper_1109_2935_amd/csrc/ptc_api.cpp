@@ -94,12 +94,15 @@ static lqcd_status ptc_forward_all(lqcd_context *ctx, const PtcPlan &plan, const
     // its waves per SIMD): timed once per layer shape and geometry
     std::ostringstream key;
     key << "ptc_fwd/" << L.cin << "-" << L.cout << "/" << geom_key(q.g);
-    const std::vector<int> cands = L.cin == 16 ? std::vector<int>{642, 3221, 3231, 3241} : std::vector<int>{642, 322};
+    // the layer-0 input (r on even sites) vanishes on odd sites
+    const int zero_par = l == 0 ? 1 : -1;
+    const std::vector<int> cands =
+        L.cin == 16 && zero_par < 0 ? std::vector<int>{642, 3221, 3231, 3241} : std::vector<int>{642, 322};
     const int variant = tune_pick(ctx, key.str(), cands, 642, true, st, [&](int v) {
-      return launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, 0, v, st);
+      return launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, 0, v, zero_par, st);
     });
     for (int par = 0; par < (last ? 1 : 2); ++par)
-      TRY(hip_check(ctx, launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, par, variant, st),
+      TRY(hip_check(ctx, launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, par, variant, zero_par, st),
                     "ptc forward"));
   }
   return LQCD_OK;
