@@ -63,6 +63,8 @@ def parse():
                     help="trained network weights; FGCR with it is timed when the file exists")
     ap.add_argument("--no-staggered", action="store_true", help="skip the 48^3x96 staggered workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-RHS workload")
+    ap.add_argument("--only", choices=("staggered", "batched", "learned"), default=None,
+                    help="run one secondary workload alone and print its JSON (for profiling runs)")
     return ap.parse_args()
 
 
@@ -116,7 +118,8 @@ def cpu_baseline(dims, U, b, kappa, csw):
     while True:
         oracle.wilson_dslash(dims, U, src, bc_t=-1, out_parity=0)
         reps += 1
-        if time.perf_counter() - t0 > 10.0 or reps >= 5:
+        # about 10 s of host work (bounded in count for slow hosts)
+        if time.perf_counter() - t0 > 10.0 or reps >= 1000:
             break
     dt = (time.perf_counter() - t0) / reps
     gbs = (V // 2) * 1536 / dt / 1e9
@@ -126,16 +129,10 @@ def cpu_baseline(dims, U, b, kappa, csw):
                       "%.2f s each" % (reps, "x".join(map(str, dims)), dt)}
 
 
-def learned_solve(args, torch, L, ops, ctx, o64, o32, o32b, bp, block, mr, dims):
-    """Flexible GCR with the trained PTC network as preconditioner (Schwarz as
-    fallback), FP64 restarts, FP32 Krylov; and the cost of one network
-    application (BF16 matrix-core flops of its channel mixing)."""
+def learned_solves(args, L, ops, ctx, o64, o32, o32b, bp, net, prm):
+    """Two FGCR solves with the network (the faster one reported) and GCR
+    without a preconditioner."""
     import ctypes
-    import numpy as np
-    from paper_1109_2935_amd import ptc
-    net = ptc.Network(ctx)
-    net.load(args.learned)
-    prm = ops.gcr_params(1e-10, 16, 1e-3, max_iter=2000, precond=L.LQCD_PRECOND_LEARNED, block=block, mr_steps=mr)
     prm.learned = ctypes.pointer(net.net)
     best = None
     for _ in range(2):
@@ -150,21 +147,40 @@ def learned_solve(args, torch, L, ops, ctx, o64, o32, o32b, bp, block, mr, dims)
     assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
     log("GCR without preconditioner: %d steps, %.3f s, true residual %.2e" % (plain.iters, plain.seconds,
                                                                            plain.true_residual))
-    r = o32.spinor()
-    out = o32.spinor()
-    L.lqcd_spinor_convert(ctx, o32.op, r, o64.op, bp, 0)
-    dt = time_kernel(torch, lambda: net.apply(o32, out, r), 3)
+    log("FGCR(PTC): %d steps (%d Schwarz fallback), %.3f s, true residual %.2e" % (
+        best.iters, best.fallback_applies, best.seconds, best.true_residual))
+    return {"gcr_unpreconditioned_seconds": round(plain.seconds, 4), "gcr_unpreconditioned_steps": plain.iters,
+            "fgcr_learned_seconds": round(best.seconds, 4), "fgcr_learned_steps": best.iters,
+            "fgcr_learned_true_residual": best.true_residual,
+            "fgcr_learned_fallback_applies": best.fallback_applies}
+
+
+def learned_solve(args, torch, L, ops, ctx, o64, o32, o32b, bp, block, mr, dims):
+    """Flexible GCR with the trained PTC network as preconditioner (Schwarz as
+    fallback), FP64 restarts, FP32 Krylov; and the cost of one network
+    application (BF16 matrix-core flops of its channel mixing). With
+    --kernels-only, the application alone."""
+    import numpy as np
+    from paper_1109_2935_amd import ptc
+    net = ptc.Network(ctx)
+    net.load(args.learned)
+    prm = ops.gcr_params(1e-10, 16, 1e-3, max_iter=2000, precond=L.LQCD_PRECOND_LEARNED, block=block, mr_steps=mr)
+    res = {}
+    if not args.kernels_only:
+        res = learned_solves(args, L, ops, ctx, o64, o32, o32b, bp, net, prm)
+    # one application in the layout the solver applies it in (the Schwarz block tiling)
+    r = o32b.spinor()
+    out = o32b.spinor()
+    L.lqcd_spinor_convert(ctx, o32b.op, r, o64.op, bp, 0)
+    dt = time_kernel(torch, lambda: net.apply(o32b, out, r), 3)
     V = int(np.prod(dims))
     ch = net.channels
     # complex multiply-adds per site: cout*4 x cin*9*4 for each of 3 colours; both parities except the last layer
     macs = sum(co * 4 * ci * 36 * 3 * (V // 2 if k == len(ch) - 2 else V) for k, (ci, co) in enumerate(zip(ch[:-1], ch[1:])))
-    log("FGCR(PTC): %d steps, %d applies (%d Schwarz fallback), %.3f s; one application %.2f ms, %.1f TFLOP/s" % (
-        best.iters, best.precond_applies, best.fallback_applies, best.seconds, dt * 1e3, 8 * macs / dt / 1e12))
-    return {"gcr_unpreconditioned_seconds": round(plain.seconds, 4), "gcr_unpreconditioned_steps": plain.iters,
-            "fgcr_learned_seconds": round(best.seconds, 4), "fgcr_learned_steps": best.iters,
-            "fgcr_learned_true_residual": best.true_residual,
-            "fgcr_learned_fallback_applies": best.fallback_applies, "ptc_apply_ms": round(dt * 1e3, 3),
-            "ptc_apply_tflops": round(8 * macs / dt / 1e12, 1)}
+    log("PTC network: one application %.2f ms, %.1f TFLOP/s (BF16 channel mixing)" % (
+        dt * 1e3, 8 * macs / dt / 1e12))
+    res.update({"ptc_apply_ms": round(dt * 1e3, 3), "ptc_apply_tflops": round(8 * macs / dt / 1e12, 1)})
+    return res
 
 
 def staggered_workload(args, torch, L, ops, ctx):
@@ -194,6 +210,8 @@ def staggered_workload(args, torch, L, ops, ctx):
             "us": round(dt * 1e6, 1), "GB/s": round(byts / dt / 1e9, 1), "frac": round(byts / dt / 1e9 / HBM_PEAK_GBS, 4)}
         log("staggered %s r%d: %.1f us %.1f GB/s" % (PREC_NAME[prec], recon, dt * 1e6, byts / dt / 1e9))
     del Ud, Fd
+    if args.kernels_only:
+        return out
     hi = inst[(0, 18)]
     b = hi.import_spinor(np.where(synth.parity_of_sites(dims)[..., None] == 0, chi, 0), 0)
     for name, lo in (("fp64", None), ("fp32_sloppy", inst[(1, 12)]), ("fp16_sloppy", inst[(2, 12)])):
@@ -291,6 +309,15 @@ def main():
 
     dims = tuple(int(v) for v in args.dims.split(","))
     kappa, csw, eps, block, mr = 0.124, 1.0, 0.25, (8, 8, 8, 8), 8
+    if args.only in ("staggered", "batched"):
+        ctx = L.lqcd_context_create()
+        fn = staggered_workload if args.only == "staggered" else batched_workload
+        res = {args.only: fn(args, torch, L, ops, ctx)}
+        if args.kernels_only:
+            res["device_copy"] = device_copy(torch)  # calibrates the profiler's byte counters
+        print(json.dumps(res))
+        L.lqcd_context_destroy(ctx)
+        return
     vh = int(np.prod(dims)) // 2
     log("generating fields", dims)
     t = time.time()
@@ -299,6 +326,18 @@ def main():
     log("fields ready %.1fs" % (time.time() - t))
     ctx = L.lqcd_context_create()
     Ud = torch.from_numpy(U).cuda()
+    if args.only == "learned":
+        tile = stencil_tile(dims, block)
+        o64 = ops.wilson_clover(ctx, U, dims, kappa, csw, 0, 18, tile=tile, U_device=Ud)
+        o32 = ops.wilson_clover(ctx, U, dims, kappa, csw, 1, 12, tile=tile, U_device=Ud)
+        o32b = ops.wilson_clover(ctx, U, dims, kappa, csw, 1, 12, tile=block, U_device=Ud)
+        res = {"learned": learned_solve(args, torch, L, ops, ctx, o64, o32, o32b, o64.import_spinor(b, -1), block, mr,
+                                        dims)}
+        if args.kernels_only:
+            res["device_copy"] = device_copy(torch)  # calibrates the profiler's byte counters
+        print(json.dumps(res))
+        L.lqcd_context_destroy(ctx)
+        return
     # Stencil operators use tiles spanning the full x extent (the site order
     # with the least neighbour re-fetch from memory); the FP16 Schwarz operator
     # is tiled by its Dirichlet blocks, and the solver re-lays out K's input
