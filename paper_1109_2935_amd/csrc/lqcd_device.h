@@ -426,4 +426,62 @@ inline int rhs_grid(int vh, int nrhs, int block_threads) {
   return ((vh + spb - 1) / spb) * (nrhs / R);
 }
 
+// v_mfma_f32_4x4x4_16b_{f16,bf16}: 16 independent 4x4x4 products per
+// instruction, FP32 accumulation. Block b is lanes 4b .. 4b+3; lane j of a
+// block supplies row j of its A (4 K values), column j of its B (4 K values)
+// and receives column j of D (4 rows). A complex 3x3 matrix U times a colour
+// vector v runs in real form on two M blocks x two K steps: rows and K both
+// run (c0 re, c0 im, c1 re, c1 im | c2 re, c2 im, 0, 0), the A rows being
+// (Re u, -Im u) for a real row and (Im u, Re u) for an imaginary row.
+typedef _Float16 mf_h4 __attribute__((ext_vector_type(4)));
+typedef short mf_s4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+template <typename S> struct Mf4;
+template <> struct Mf4<_Float16> {
+  typedef mf_h4 T;
+  __device__ __forceinline__ static T pack(float a, float b, float c, float d) {
+    return T{(_Float16)a, (_Float16)b, (_Float16)c, (_Float16)d};
+  }
+  __device__ __forceinline__ static mf_f4 mma(T a, T b, mf_f4 c) {
+    return __builtin_amdgcn_mfma_f32_4x4x4f16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mf4<bf16> {
+  typedef mf_s4 T;
+  // hardware round-to-nearest-even (v_cvt_pk_bf16_f32): for finite values
+  // the same result as Store<bf16>::from
+  __device__ __forceinline__ static T pack(float a, float b, float c, float d) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+    return __builtin_bit_cast(T, __builtin_convertvector(f4{a, b, c, d}, b4));
+  }
+  __device__ __forceinline__ static mf_f4 mma(T a, T b, mf_f4 c) {
+    return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+
+// A operands [M block][K step] of row j (0..3) of U (ADJ: of U^+).
+template <typename S, bool ADJ>
+__device__ __forceinline__ void mf_link_rows(const Link<float> &U, int j, typename Mf4<S>::T (&a)[2][2]) {
+  using M = Mf4<S>;
+  cpx<float> r0[3], r2[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cpx<float> e0 = ADJ ? conj(U.m[c][0]) : U.m[0][c];
+    const cpx<float> e1 = ADJ ? conj(U.m[c][1]) : U.m[1][c];
+    r0[c] = (j >> 1) ? e1 : e0;  // M block 0: colour j / 2
+    r2[c] = ADJ ? conj(U.m[c][2]) : U.m[2][c];
+  }
+  // row (colour, re) = (Re e_c, -Im e_c)_c; row (colour, im) = (Im e_c, Re e_c)_c
+  const bool im0 = j & 1;
+  a[0][0] = im0 ? M::pack(r0[0].im, r0[0].re, r0[1].im, r0[1].re) : M::pack(r0[0].re, -r0[0].im, r0[1].re, -r0[1].im);
+  a[0][1] = im0 ? M::pack(r0[2].im, r0[2].re, 0.f, 0.f) : M::pack(r0[2].re, -r0[2].im, 0.f, 0.f);
+  // M block 1: rows (c2 re, c2 im, 0, 0)
+  const float z = j < 2 ? 1.f : 0.f;
+  a[1][0] = (j == 1) ? M::pack(r2[0].im, r2[0].re, r2[1].im, r2[1].re)
+                     : M::pack(z * r2[0].re, -z * r2[0].im, z * r2[1].re, -z * r2[1].im);
+  a[1][1] = (j == 1) ? M::pack(r2[2].im, r2[2].re, 0.f, 0.f) : M::pack(z * r2[2].re, -z * r2[2].im, 0.f, 0.f);
+}
+
 }  // namespace lqcd

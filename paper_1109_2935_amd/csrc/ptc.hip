@@ -30,6 +30,7 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
 
 // (x, y) rounded to nearest-even BF16, x in the low half
 __device__ __forceinline__ bf16x2_t pack_bf16x2(float x, float y) {
@@ -221,7 +222,9 @@ __device__ __forceinline__ bf16x8_t lds_frag(const __bf16 *row) {
 
 constexpr int kFwRow = 16 * 8 + kLdsPad;  // bf16 per LDS row: 16 items x 8 K values + padding
 
-template <int NS, int WPE, bool PIPE>
+// PIPE: 0 generic; 1 and 2 the pipelined 16-channel form with the colour
+// products on BF16 dot2 (1) or on 4x4x4 matrix-core blocks (2)
+template <int NS, int WPE, int PIPE>
 __global__ void __launch_bounds__(kPtcThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
 ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void *out, int out_f32, int par,
                    int zero_par) {
@@ -290,7 +293,7 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
         for (int j = 0; j < SM; ++j) acc[j][t] = mfma_bf16(a[j], b[t], acc[j][t]);
     }
   };
-  if constexpr (PIPE) {
+  if constexpr (PIPE != 0) {
     static_assert(kFwSites * 8 == kPtcThreads, "pipelined path: 8 threads per site");
     // 16 input channels, one thread per (site, channel pair un, un + 8), one
     // path per chunk; the loads of path p + 1 are issued before the matrix
@@ -331,7 +334,9 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
     };
     auto compute = [&](int p) {
       __bf16 *dst = Bt + sl * kFwRow + 8 * un;
-      if (!valid) {
+      // (the matrix-core form keeps every lane in its products: a lane of a
+      // site beyond Vh multiplies zeros and stores zeros)
+      if (PIPE != 2 && !valid) {
         const bf16x8_t zero = {};
 #pragma unroll
         for (int k = 0; k < 2; ++k)
@@ -345,10 +350,10 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
       for (int k = 0; k < 2; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          w[k][4 * c + 0] = raw[k][c].x;
-          w[k][4 * c + 1] = raw[k][c].y;
-          w[k][4 * c + 2] = raw[k][c].z;
-          w[k][4 * c + 3] = raw[k][c].w;
+          w[k][4 * c + 0] = valid ? raw[k][c].x : 0u;
+          w[k][4 * c + 1] = valid ? raw[k][c].y : 0u;
+          w[k][4 * c + 2] = valid ? raw[k][c].z : 0u;
+          w[k][4 * c + 3] = valid ? raw[k][c].w : 0u;
         }
       if (p != 0) {
         const bool fwd = ((p - 1) & 1) == 0;
@@ -358,39 +363,71 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
           U0 = unpack_link<12, float>(lv);
         else
           U0 = unpack_link<18, float>(lv);
-        // the applied matrix (U, or U^+ for a backward hop, times the boundary
-        // sign) as BF16 pairs: re(u v) = dot((Ur, -Ui), (vr, vi)),
-        // im(u v) = dot((Ui, Ur), (vr, vi)), products exact, FP32 sums
-        bf16x2_t Pr[3][3], Pi[3][3];
+        if constexpr (PIPE == 2) {
+          // matrix cores: lanes 4b .. 4b+3 are one site (8 lanes per site), so
+          // a 4x4x4 block is one site's link times 4 of its (channel, spin)
+          // vectors; a vector's 3 words are its own B operand (K = c0 re, c0 im,
+          // c1 re, c1 im | c2 re, c2 im, 0, 0) and its D column is U v in FP32
+          Link<float> U;  // U, or U^+ for a backward hop, times the boundary sign
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+          for (int a = 0; a < 3; ++a)
 #pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            const cpx<float> e = fwd ? U0.m[a][b] : conj(U0.m[b][a]);
-            Pr[a][b] = pack_bf16x2(ph * e.re, -ph * e.im);
-            Pi[a][b] = pack_bf16x2(ph * e.im, ph * e.re);
-          }
+            for (int b = 0; b < 3; ++b) {
+              const cpx<float> e = fwd ? U0.m[a][b] : conj(U0.m[b][a]);
+              U.m[a][b] = ph * e;
+            }
+          mf_s4 A4[2][2];
+          mf_link_rows<bf16, false>(U, lane & 3, A4);
+          const mf_f4 zero4 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
+          for (int k = 0; k < 2; ++k)
 #pragma unroll
-          for (int sp = 0; sp < 4; ++sp) {
-            bf16x2_t v[3];
+            for (int sp = 0; sp < 4; ++sp) {
+              const mf_s4 b0 = __builtin_bit_cast(mf_s4, u32x2_t{w[k][3 * sp], w[k][3 * sp + 1]});
+              const mf_s4 b1 = __builtin_bit_cast(mf_s4, u32x2_t{w[k][3 * sp + 2], 0u});
+              mf_f4 d0 = Mf4<bf16>::mma(A4[0][0], b0, zero4);
+              d0 = Mf4<bf16>::mma(A4[0][1], b1, d0);
+              mf_f4 d1 = Mf4<bf16>::mma(A4[1][0], b0, zero4);
+              d1 = Mf4<bf16>::mma(A4[1][1], b1, d1);
+              w[k][3 * sp + 0] = __builtin_bit_cast(uint32_t, pack_bf16x2(d0[0], d0[1]));
+              w[k][3 * sp + 1] = __builtin_bit_cast(uint32_t, pack_bf16x2(d0[2], d0[3]));
+              w[k][3 * sp + 2] = __builtin_bit_cast(uint32_t, pack_bf16x2(d1[0], d1[1]));
+            }
+        } else {
+          // the applied matrix (U, or U^+ for a backward hop, times the boundary
+          // sign) as BF16 pairs: re(u v) = dot((Ur, -Ui), (vr, vi)),
+          // im(u v) = dot((Ui, Ur), (vr, vi)), products exact, FP32 sums
+          bf16x2_t Pr[3][3], Pi[3][3];
 #pragma unroll
-            for (int b = 0; b < 3; ++b) v[b] = __builtin_bit_cast(bf16x2_t, w[k][3 * sp + b]);
-            uint32_t o[3];
+          for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              float re = 0.f, im = 0.f;
-#pragma unroll
-              for (int b = 0; b < 3; ++b) {
-                re = __builtin_amdgcn_fdot2_f32_bf16(Pr[a][b], v[b], re, false);
-                im = __builtin_amdgcn_fdot2_f32_bf16(Pi[a][b], v[b], im, false);
-              }
-              o[a] = __builtin_bit_cast(uint32_t, pack_bf16x2(re, im));
+            for (int b = 0; b < 3; ++b) {
+              const cpx<float> e = fwd ? U0.m[a][b] : conj(U0.m[b][a]);
+              Pr[a][b] = pack_bf16x2(ph * e.re, -ph * e.im);
+              Pi[a][b] = pack_bf16x2(ph * e.im, ph * e.re);
             }
 #pragma unroll
-            for (int a = 0; a < 3; ++a) w[k][3 * sp + a] = o[a];
-          }
+          for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+              bf16x2_t v[3];
+#pragma unroll
+              for (int b = 0; b < 3; ++b) v[b] = __builtin_bit_cast(bf16x2_t, w[k][3 * sp + b]);
+              uint32_t o[3];
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                float re = 0.f, im = 0.f;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                  re = __builtin_amdgcn_fdot2_f32_bf16(Pr[a][b], v[b], re, false);
+                  im = __builtin_amdgcn_fdot2_f32_bf16(Pi[a][b], v[b], im, false);
+                }
+                o[a] = __builtin_bit_cast(uint32_t, pack_bf16x2(re, im));
+              }
+#pragma unroll
+              for (int a = 0; a < 3; ++a) w[k][3 * sp + a] = o[a];
+            }
+        }
       }
       // colour c: the four spins' (re, im) words
 #pragma unroll
@@ -887,13 +924,17 @@ hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *
   hipLaunchKernelGGL((ptc_forward_kernel<NS, WPE, PIPE>), dim3((q.g.Vh + NS - 1) / NS), dim3(kPtcThreads), 0, st, q, \
                      L, nbr, (const bf16 *)in, out, out_f32, par, zero_par);                                                  \
   break;
-    case 642: PTC_FWD(64, 2, false)
-    case 322: PTC_FWD(32, 2, false)
-    // the pipelined 16-channel path at 2, 3 or 4 waves per SIMD
-    // (the pipelined path reads every path: no input parity may be known zero)
-    case 3221: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 2, true)
-    case 3231: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, true)
-    case 3241: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, true)
+    case 642: PTC_FWD(64, 2, 0)
+    case 322: PTC_FWD(32, 2, 0)
+    // the pipelined 16-channel path at 2, 3 or 4 waves per SIMD, colour
+    // products on dot2 (..1) or on the matrix cores (..2); it reads every
+    // path, so no input parity may be known zero
+    case 3221: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 2, 1)
+    case 3231: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, 1)
+    case 3241: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, 1)
+    case 3222: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 2, 2)
+    case 3232: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, 2)
+    case 3242: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, 2)
     default: return hipErrorInvalidValue;
 #undef PTC_FWD
   }

@@ -97,7 +97,8 @@ static lqcd_status ptc_forward_all(lqcd_context *ctx, const PtcPlan &plan, const
     // the layer-0 input (r on even sites) vanishes on odd sites
     const int zero_par = l == 0 ? 1 : -1;
     const std::vector<int> cands =
-        L.cin == 16 && zero_par < 0 ? std::vector<int>{642, 3221, 3231, 3241} : std::vector<int>{642, 322};
+        L.cin == 16 && zero_par < 0 ? std::vector<int>{642, 3221, 3231, 3241, 3222, 3232, 3242}
+                                    : std::vector<int>{642, 322};
     const int variant = tune_pick(ctx, key.str(), cands, 642, true, st, [&](int v) {
       return launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, 0, v, zero_par, st);
     });
