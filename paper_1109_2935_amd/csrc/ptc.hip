@@ -224,11 +224,14 @@ constexpr int kFwRow = 16 * 8 + kLdsPad;  // bf16 per LDS row: 16 items x 8 K va
 
 // PIPE: 0 generic; 1 and 2 the pipelined 16-channel form with the colour
 // products on BF16 dot2 (1) or on 4x4x4 matrix-core blocks (2)
-template <int NS, int WPE, int PIPE>
-__global__ void __launch_bounds__(kPtcThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
+// NTH threads (NTH / 64 waves) per workgroup.
+template <int NS, int WPE, int PIPE, int NTH = kPtcThreads>
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(WPE)))
 ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void *out, int out_f32, int par,
                    int zero_par) {
   constexpr int kFwSites = NS, NT = 3 * NS / 16;
+  constexpr int NW = NTH / 64;           // waves
+  constexpr int JM = (8 + NW - 1) / NW;  // m-tiles per wave at most (8 m-tiles for 16 output channels)
   __shared__ __align__(16) __bf16 Bt[3 * NS * kFwRow];
   // each XCD takes a contiguous range of site tiles, so that the neighbours'
   // activations are read from its own L2
@@ -236,22 +239,22 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // this wave's output tiles
   int mbase, nm, nbase, nn;
-  if (L.mtiles >= 4) {
+  if (L.mtiles >= NW) {
     mbase = wave;
-    nm = (L.mtiles - wave + 3) / 4;
+    nm = (L.mtiles - wave + NW - 1) / NW;
     nbase = 0;
     nn = NT;
   } else {
-    const int split = 4 / L.mtiles;  // waves per m-tile
+    const int split = NW / L.mtiles;  // waves per m-tile
     mbase = wave % L.mtiles;
     nm = 1;
     nn = (NT + split - 1) / split;
     nbase = (wave / L.mtiles) * nn;
     nn = max(0, min(nn, NT - nbase));
   }
-  f32x4_t acc[2][NT];
+  f32x4_t acc[JM][NT];
 #pragma unroll
-  for (int j = 0; j < 2; ++j)
+  for (int j = 0; j < JM; ++j)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[j][t] = f32x4_t{0, 0, 0, 0};
   const bf16x8_t *A = (const bf16x8_t *)L.A;
@@ -259,16 +262,16 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
   auto mma_chunk = [&](int q0, int ipc) {
     for (int kl = 0; kl < ipc / 4; ++kl) {
       const int ks = q0 / 4 + kl;
-      bf16x8_t a[2];
+      bf16x8_t a[JM];
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        if (j < nm) a[j] = A[((size_t)(mbase + 4 * j) * L.fw_ks + ks) * 64 + lane];
+      for (int j = 0; j < JM; ++j)
+        if (j < nm) a[j] = A[((size_t)(mbase + NW * j) * L.fw_ks + ks) * 64 + lane];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         if (t < nn) {
           const bf16x8_t b = lds_frag(Bt + ((nbase + t) * 16 + (lane & 15)) * kFwRow + kl * 32 + 8 * (lane >> 4));
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+          for (int j = 0; j < JM; ++j)
             if (j < nm) acc[j][t] = mfma_bf16(a[j], b, acc[j][t]);
         }
       }
@@ -283,7 +286,7 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
       const int ks = q0 / 4 + kl;
       bf16x8_t a[SM], b[SN];
 #pragma unroll
-      for (int j = 0; j < SM; ++j) a[j] = A[((size_t)(mbase + 4 * j) * L.fw_ks + ks) * 64 + lane];
+      for (int j = 0; j < SM; ++j) a[j] = A[((size_t)(mbase + NW * j) * L.fw_ks + ks) * 64 + lane];
 #pragma unroll
       for (int t = 0; t < SN; ++t)
         b[t] = lds_frag(Bt + ((nbase + t) * 16 + (lane & 15)) * kFwRow + kl * 32 + 8 * (lane >> 4));
@@ -294,27 +297,28 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
     }
   };
   if constexpr (PIPE != 0) {
-    static_assert(kFwSites * 8 == kPtcThreads, "pipelined path: 8 threads per site");
-    // 16 input channels, one thread per (site, channel pair un, un + 8), one
-    // path per chunk; the loads of path p + 1 are issued before the matrix
-    // products of path p, so their latency overlaps them.
+    // 16 input channels: TPS threads per site, thread un taking channels
+    // un + TPS k (k < KC); one path per chunk; the loads of path p + 1 are
+    // issued before the matrix products of path p, so their latency overlaps them.
+    constexpr int TPS = NTH / kFwSites, KC = 16 / TPS;
+    static_assert(TPS * KC == 16 && (TPS == 8 || TPS == 16), "pipelined path: 8 or 16 threads per site");
     __shared__ int nbL[kFwSites][8];
-    const int un = threadIdx.x & 7, sl = threadIdx.x >> 3, s = s0 + sl;
+    const int un = threadIdx.x % TPS, sl = threadIdx.x / TPS, s = s0 + sl;
     const bool valid = s < q.g.Vh;
     const int64_t vh = q.g.Vh, vs = vh * 16;
-    nbL[sl][un] = valid ? nbr[((int64_t)par * 8 + un) * vh + s] : 0;
+    if (un < 8) nbL[sl][un] = valid ? nbr[((int64_t)par * 8 + un) * vh + s] : 0;
     __syncthreads();
-    uint4 raw[2][3];
+    uint4 raw[KC][3];
     float lv[18] = {};
     auto issue = [&](int p) {
       if (!valid) return;
       const int n = p == 0 ? s : (nbL[sl][p - 1] & 0x7fffffff);
       const bf16 *blk = in + (int64_t)(p == 0 ? par : 1 - par) * vs * 24;
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < KC; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          raw[k][c] = *reinterpret_cast<const uint4 *>(blk + ((int64_t)c * vs + (int64_t)n * 16 + un + 8 * k) * 8);
+          raw[k][c] = *reinterpret_cast<const uint4 *>(blk + ((int64_t)c * vs + (int64_t)n * 16 + un + TPS * k) * 8);
       if (p != 0) {
         const int mu = (p - 1) >> 1;
         const bool fwd = ((p - 1) & 1) == 0;
@@ -339,15 +343,16 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
       if (PIPE != 2 && !valid) {
         const bf16x8_t zero = {};
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
+        for (int k = 0; k < KC; ++k)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) *reinterpret_cast<bf16x8_t *>(dst + c * kFwSites * kFwRow + 64 * k) = zero;
+          for (int c = 0; c < 3; ++c)
+            *reinterpret_cast<bf16x8_t *>(dst + c * kFwSites * kFwRow + 8 * TPS * k) = zero;
         return;
       }
       // word 3 sp + col of a channel: the (re, im) BF16 pair of spin sp, colour col
-      uint32_t w[2][12];
+      uint32_t w[KC][12];
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < KC; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           w[k][4 * c + 0] = valid ? raw[k][c].x : 0u;
@@ -380,7 +385,7 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
           mf_link_rows<bf16, false>(U, lane & 3, A4);
           const mf_f4 zero4 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int k = 0; k < 2; ++k)
+          for (int k = 0; k < KC; ++k)
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp) {
               const mf_s4 b0 = __builtin_bit_cast(mf_s4, u32x2_t{w[k][3 * sp], w[k][3 * sp + 1]});
@@ -407,7 +412,7 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
               Pi[a][b] = pack_bf16x2(ph * e.im, ph * e.re);
             }
 #pragma unroll
-          for (int k = 0; k < 2; ++k)
+          for (int k = 0; k < KC; ++k)
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp) {
               bf16x2_t v[3];
@@ -431,16 +436,16 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
       }
       // colour c: the four spins' (re, im) words
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < KC; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          *reinterpret_cast<uint4 *>(dst + c * kFwSites * kFwRow + 64 * k) =
+          *reinterpret_cast<uint4 *>(dst + c * kFwSites * kFwRow + 8 * TPS * k) =
               make_uint4(w[k][c], w[k][3 + c], w[k][6 + c], w[k][9 + c]);
     };
     // per path: transport into LDS, issue the next path's loads, then the
     // matrix products (their latency overlaps the products)
-    constexpr int kSplitN = (NT + 3) / 4;  // n-tiles per wave when one m-tile is split over 4 waves
-    const int form = (nm == 2 && nn == NT) ? 2 : (nm == 1 && nn == kSplitN) ? 1 : (nn > 0 ? 0 : -1);
+    constexpr int kSplitN = (NT + NW - 1) / NW;  // n-tiles per wave when one m-tile is split over all waves
+    const int form = (nm == JM && nn == NT) ? 2 : (nm == 1 && nn == kSplitN) ? 1 : (nn > 0 ? 0 : -1);
     issue(0);
 #pragma unroll 1
     for (int p = 0; p < 9; ++p) {
@@ -449,7 +454,7 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
       if (p + 1 < 9) issue(p + 1);
       __syncthreads();
       if (form == 2)
-        mma_static(std::integral_constant<int, 2>(), std::integral_constant<int, NT>(), 16 * p);
+        mma_static(std::integral_constant<int, JM>(), std::integral_constant<int, NT>(), 16 * p);
       else if (form == 1)
         mma_static(std::integral_constant<int, 1>(), std::integral_constant<int, kSplitN>(), 16 * p);
       else if (form == 0)
@@ -531,7 +536,7 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       if (j >= nm) continue;
-      const int o = 2 * (mbase + 4 * j) + (g >> 1);
+      const int o = 2 * (mbase + NW * j) + (g >> 1);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         if (t >= nn) continue;
@@ -565,7 +570,7 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       if (j >= nm) continue;
-      const int o = 2 * (mbase + 4 * j) + (g >> 1);
+      const int o = 2 * (mbase + NW * j) + (g >> 1);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         if (t >= nn) continue;
@@ -920,21 +925,24 @@ hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *
   // LDS staging of the output tile: BF16 up to 16 channels; FP32 one channel
   if (out_f32 && L.cout != 1) return hipErrorInvalidValue;
   switch (variant) {
-#define PTC_FWD(NS, WPE, PIPE)                                                                            \
-  hipLaunchKernelGGL((ptc_forward_kernel<NS, WPE, PIPE>), dim3((q.g.Vh + NS - 1) / NS), dim3(kPtcThreads), 0, st, q, \
-                     L, nbr, (const bf16 *)in, out, out_f32, par, zero_par);                                                  \
+#define PTC_FWD(NS, WPE, PIPE, NTH)                                                                           \
+  hipLaunchKernelGGL((ptc_forward_kernel<NS, WPE, PIPE, NTH>), dim3((q.g.Vh + NS - 1) / NS), dim3(NTH), 0, st, q, L, \
+                     nbr, (const bf16 *)in, out, out_f32, par, zero_par);                                           \
   break;
-    case 642: PTC_FWD(64, 2, 0)
-    case 322: PTC_FWD(32, 2, 0)
-    // the pipelined 16-channel path at 2, 3 or 4 waves per SIMD, colour
-    // products on dot2 (..1) or on the matrix cores (..2); it reads every
-    // path, so no input parity may be known zero
-    case 3221: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 2, 1)
-    case 3231: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, 1)
-    case 3241: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, 1)
-    case 3222: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 2, 2)
-    case 3232: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, 2)
-    case 3242: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, 2)
+    case 642: PTC_FWD(64, 2, 0, 256)
+    case 322: PTC_FWD(32, 2, 0, 256)
+    // the pipelined 16-channel path: 256 threads (8 per site) at 2 or 3 waves
+    // per SIMD, or 512 threads (16 per site) at 3 or 4; colour products on
+    // dot2 (..1) or on the matrix cores (..2). It reads every path, so no
+    // input parity may be known zero.
+    case 3221: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 2, 1, 256)
+    case 3231: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, 1, 256)
+    case 3222: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 2, 2, 256)
+    case 3232: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, 2, 256)
+    case 5031: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, 1, 512)
+    case 5041: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, 1, 512)
+    case 5032: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, 2, 512)
+    case 5042: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, 2, 512)
     default: return hipErrorInvalidValue;
 #undef PTC_FWD
   }

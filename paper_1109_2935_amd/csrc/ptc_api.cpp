@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -97,11 +98,17 @@ static lqcd_status ptc_forward_all(lqcd_context *ctx, const PtcPlan &plan, const
     // the layer-0 input (r on even sites) vanishes on odd sites
     const int zero_par = l == 0 ? 1 : -1;
     const std::vector<int> cands =
-        L.cin == 16 && zero_par < 0 ? std::vector<int>{642, 3221, 3231, 3241, 3222, 3232, 3242}
+        L.cin == 16 && zero_par < 0 ? std::vector<int>{642, 3221, 3231, 3222, 3232, 5031, 5041, 5032, 5042}
                                     : std::vector<int>{642, 322};
-    const int variant = tune_pick(ctx, key.str(), cands, 642, true, st, [&](int v) {
-      return launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, 0, v, zero_par, st);
-    });
+    // LQCD_PTC_VARIANT=<form> forces the form of the 16-input-channel layers
+    // (so that tests can check every form against the oracle)
+    const char *forced = std::getenv("LQCD_PTC_VARIANT");
+    const int variant =
+        (forced && L.cin == 16 && zero_par < 0)
+            ? std::atoi(forced)
+            : tune_pick(ctx, key.str(), cands, 642, true, st, [&](int v) {
+                return launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, 0, v, zero_par, st);
+              });
     for (int par = 0; par < (last ? 1 : 2); ++par)
       TRY(hip_check(ctx, launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, par, variant, zero_par, st),
                     "ptc forward"));

@@ -49,6 +49,31 @@ def test_ptc_forward_matches_oracle(ctx, channels, tol):
     assert rel(got, ref) < tol
 
 
+# every form of the 16-input-channel layers (256 or 512 threads, waves per
+# SIMD, colour products on dot2 or on 4x4x4 matrix-core blocks), on a lattice
+# whose sites fill whole workgroups and on one that leaves 16 of 32 sites of a
+# workgroup empty
+PTC_FORMS = (3221, 3231, 3222, 3232, 5031, 5041, 5032, 5042)
+
+
+@pytest.mark.parametrize("dims", [DIMS, (4, 2, 2, 2)])
+@pytest.mark.parametrize("form", PTC_FORMS)
+def test_ptc_forward_every_form(ctx, form, dims, monkeypatch):
+    channels = (1, 16, 16, 16, 1)
+    U = synth.gauge_field(dims, 0.25, 131)
+    op32 = ops.wilson_clover(ctx, U, dims, 0.124, 1.0, 1, 12)
+    net = ptc.Network(ctx, channels)
+    Ws = weights_c64(optc.init_weights(132, channels=channels))
+    net.set_weights(Ws)
+    r = on_parity(synth.gaussian_spinor(dims, 133), oracle.parity_mask(dims, 0))
+    out = op32.spinor()
+    monkeypatch.setenv("LQCD_PTC_VARIANT", str(form))
+    net.apply(op32, out, op32.import_spinor(r, 0))
+    got = np_of(op32.export_spinor(out, 0))
+    ref, _ = optc.forward(dims, U, r, Ws, oracle.parity_mask(dims, 0))
+    assert rel(got, ref) < 4e-2
+
+
 def test_ptc_gauge_equivariance_on_gpu(ctx):
     channels = (1, 4, 4, 1)
     U = synth.gauge_field(DIMS, 0.25, 71)
