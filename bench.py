@@ -81,6 +81,12 @@ def stencil_tile(dims, block):
     return t if all(d % e == 0 and e % 2 == 0 for d, e in zip(dims, t)) else tuple(block)
 
 
+def full_x_tile(dims):
+    """The full x extent and, along y, z and t, the largest of 8, 6, 4, 2 that
+    divides the extent (the batched lattices include 20^3x40)."""
+    return (dims[0],) + tuple(next(e for e in (8, 6, 4, 2) if d % e == 0) for d in dims[1:])
+
+
 def time_kernel(torch, fn, launches):
     """Average duration of `fn` (one kernel launch or a fixed sequence) with
     HIP events on the current stream."""
@@ -229,7 +235,7 @@ def staggered_workload(args, torch, L, ops, ctx):
 def batched_workload(args, torch, L, ops, ctx):
     """Multi-RHS Wilson hopping term: 12 point sources (spin x colour) on
     24^3x48, and one persistent launch over 16^3x32, 20^3x40 and 24^3x48 with
-    4 Gaussian sources each (kappa 0.122). Bytes per site and right-hand side:
+    4 Gaussian sources each (kappa 0.122), in full-x tiles. Bytes per site and right-hand side:
     spinor in + out (48 reals) plus the site's 8 links shared by its nrhs.
     16-bit operators are also timed with the link products on the matrix cores
     (LQCD_MRHS_MFMA=1)."""
@@ -254,7 +260,7 @@ def batched_workload(args, torch, L, ops, ctx):
         # 12 point sources on 24^3x48 (the origin is even: D_oe acts on them)
         dims = (24, 24, 24, 48)
         U = synth.gauge_field(dims, 0.25, 4001)
-        o = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon)
+        o = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon, tile=full_x_tile(dims))
         srcs = np.stack([synth.point_source(dims, sc // 3, sc % 3) for sc in range(12)])
         inp = o.import_spinor(srcs, 0, nrhs=12)
         res_ = o.spinor(nrhs=12)
@@ -275,7 +281,7 @@ def batched_workload(args, torch, L, ops, ctx):
         jobs, keep, tot_bytes = [], [], 0
         for k, dims in enumerate(((16, 16, 16, 32), (20, 20, 20, 40), (24, 24, 24, 48))):
             U = synth.gauge_field(dims, 0.25, 4011 + 10 * k)
-            ok = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon)
+            ok = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon, tile=full_x_tile(dims))
             srcs = np.stack([np.where(synth.parity_of_sites(dims)[..., None, None] == 1,
                                       synth.gaussian_spinor(dims, 4012 + 10 * k + r), 0) for r in range(4)])
             i_ = ok.import_spinor(srcs, 1, nrhs=4)
