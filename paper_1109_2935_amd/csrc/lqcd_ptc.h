@@ -60,7 +60,9 @@ inline size_t ptc_adj_frag_bytes(const PtcLayerDev &L) { return (size_t)L.madj_t
 hipError_t launch_ptc_nbr(const Geom &g, int *tab, hipStream_t st);
 // variant: 10 x sites per workgroup + waves per SIMD hint: 642 or 322
 // in: BF16 activations; out: BF16 activations, or (out_f32, one channel) an FP32 packed spinor
-// zero_par: parity on which the input is known to vanish (-1: none)
+// par: output parity, or -1 for both in one launch (workgroups of the two
+// parities interleaved); zero_par: parity on which the input is known to
+// vanish (-1: none)
 hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *nbr, const void *in, void *out,
                               int out_f32, int par, int variant, int zero_par, hipStream_t st);
 // layer-0 activations from an FP32 packed even field

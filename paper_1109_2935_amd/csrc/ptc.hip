@@ -223,33 +223,49 @@ __device__ __forceinline__ bf16x8_t lds_frag(const __bf16 *row) {
 constexpr int kFwRow = 16 * 8 + kLdsPad;  // bf16 per LDS row: 16 items x 8 K values + padding
 
 // PIPE: 0 generic; 1 and 2 the pipelined 16-channel form with the colour
-// products on BF16 dot2 (1) or on 4x4x4 matrix-core blocks (2)
+// products on BF16 dot2 (1) or on 4x4x4 matrix-core blocks (2); 3 and 4 the
+// same split between waves: the first half of the waves transport path p + 1
+// into one LDS buffer while the second half multiply path p from the other
+// (one barrier per path, so the vector and matrix work of a workgroup overlap).
 // NTH threads (NTH / 64 waves) per workgroup.
 template <int NS, int WPE, int PIPE, int NTH = kPtcThreads>
 __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(WPE)))
-ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void *out, int out_f32, int par,
+ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void *out, int out_f32, int par_arg,
                    int zero_par) {
   constexpr int kFwSites = NS, NT = 3 * NS / 16;
-  constexpr int NW = NTH / 64;           // waves
-  constexpr int JM = (8 + NW - 1) / NW;  // m-tiles per wave at most (8 m-tiles for 16 output channels)
-  __shared__ __align__(16) __bf16 Bt[3 * NS * kFwRow];
+  constexpr bool SPLIT = PIPE >= 3;
+  constexpr int TRANS = (PIPE == 2 || PIPE == 4) ? 2 : 1;  // colour products: 1 dot2, 2 matrix cores
+  constexpr int NW = NTH / 64;                // waves
+  constexpr int NWC = SPLIT ? NW / 2 : NW;    // waves doing the matrix products
+  constexpr int JM = (8 + NWC - 1) / NWC;     // m-tiles per wave at most (8 m-tiles for 16 output channels)
+  constexpr int kBuf = 3 * NS * kFwRow;       // bf16 per LDS buffer of transported inputs
+  __shared__ __align__(16) __bf16 Bt[(SPLIT ? 2 : 1) * kBuf];
   // each XCD takes a contiguous range of site tiles, so that the neighbours'
-  // activations are read from its own L2
-  const int s0 = xcd_remap(blockIdx.x, gridDim.x) * kFwSites;
+  // activations are read from its own L2; with par_arg < 0 both output
+  // parities are computed, workgroups 2t and 2t + 1 taking tile t of the even
+  // and the odd sites, so that an input site's reads as a hop input (by one
+  // parity) and as its own identity input (by the other) come close in time
+  int wl = xcd_remap(blockIdx.x, gridDim.x);
+  const int par = par_arg < 0 ? (wl & 1) : par_arg;
+  if (par_arg < 0) wl >>= 1;
+  const int s0 = wl * kFwSites;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool producer = SPLIT && wave < NW / 2;  // (split forms) transports only
+  const int cw = SPLIT ? wave - NW / 2 : wave;   // index among the waves doing products
   // this wave's output tiles
-  int mbase, nm, nbase, nn;
-  if (L.mtiles >= NW) {
-    mbase = wave;
-    nm = (L.mtiles - wave + NW - 1) / NW;
+  int mbase = 0, nm = 0, nbase = 0, nn = 0;
+  if (producer) {
+  } else if (L.mtiles >= NWC) {
+    mbase = cw;
+    nm = (L.mtiles - cw + NWC - 1) / NWC;
     nbase = 0;
     nn = NT;
   } else {
-    const int split = NW / L.mtiles;  // waves per m-tile
-    mbase = wave % L.mtiles;
+    const int split = NWC / L.mtiles;  // waves per m-tile
+    mbase = cw % L.mtiles;
     nm = 1;
     nn = (NT + split - 1) / split;
-    nbase = (wave / L.mtiles) * nn;
+    nbase = (cw / L.mtiles) * nn;
     nn = max(0, min(nn, NT - nbase));
   }
   f32x4_t acc[JM][NT];
@@ -259,54 +275,115 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
     for (int t = 0; t < NT; ++t) acc[j][t] = f32x4_t{0, 0, 0, 0};
   const bf16x8_t *A = (const bf16x8_t *)L.A;
   // one K chunk (items q0 .. q0+ipc-1) from LDS into the accumulators
-  auto mma_chunk = [&](int q0, int ipc) {
+  auto mma_chunk = [&](auto &ac, const __bf16 *Bb, int q0, int ipc) {
     for (int kl = 0; kl < ipc / 4; ++kl) {
       const int ks = q0 / 4 + kl;
       bf16x8_t a[JM];
 #pragma unroll
       for (int j = 0; j < JM; ++j)
-        if (j < nm) a[j] = A[((size_t)(mbase + NW * j) * L.fw_ks + ks) * 64 + lane];
+        if (j < nm) a[j] = A[((size_t)(mbase + NWC * j) * L.fw_ks + ks) * 64 + lane];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         if (t < nn) {
-          const bf16x8_t b = lds_frag(Bt + ((nbase + t) * 16 + (lane & 15)) * kFwRow + kl * 32 + 8 * (lane >> 4));
+          const bf16x8_t b = lds_frag(Bb + ((nbase + t) * 16 + (lane & 15)) * kFwRow + kl * 32 + 8 * (lane >> 4));
 #pragma unroll
           for (int j = 0; j < JM; ++j)
-            if (j < nm) acc[j][t] = mfma_bf16(a[j], b, acc[j][t]);
+            if (j < nm) ac[j][t] = mfma_bf16(a[j], b, ac[j][t]);
         }
       }
     }
   };
   // the same product with compile-time tile counts (all loads of a K step
   // issued before its MFMAs, no per-tile branches): SM m-tiles x SN n-tiles
-  auto mma_static = [&](auto smc, auto snc, int q0) {
+  auto mma_static = [&](auto smc, auto snc, auto &ac, const __bf16 *Bb, int q0) {
     constexpr int SM = decltype(smc)::value, SN = decltype(snc)::value;
 #pragma unroll
     for (int kl = 0; kl < 4; ++kl) {
       const int ks = q0 / 4 + kl;
       bf16x8_t a[SM], b[SN];
 #pragma unroll
-      for (int j = 0; j < SM; ++j) a[j] = A[((size_t)(mbase + NW * j) * L.fw_ks + ks) * 64 + lane];
+      for (int j = 0; j < SM; ++j) a[j] = A[((size_t)(mbase + NWC * j) * L.fw_ks + ks) * 64 + lane];
 #pragma unroll
       for (int t = 0; t < SN; ++t)
-        b[t] = lds_frag(Bt + ((nbase + t) * 16 + (lane & 15)) * kFwRow + kl * 32 + 8 * (lane >> 4));
+        b[t] = lds_frag(Bb + ((nbase + t) * 16 + (lane & 15)) * kFwRow + kl * 32 + 8 * (lane >> 4));
 #pragma unroll
       for (int t = 0; t < SN; ++t)
 #pragma unroll
-        for (int j = 0; j < SM; ++j) acc[j][t] = mfma_bf16(a[j], b[t], acc[j][t]);
+        for (int j = 0; j < SM; ++j) ac[j][t] = mfma_bf16(a[j], b[t], ac[j][t]);
+    }
+  };
+  // Output. Row m = 16 mt + 4 g + jj (g = lane / 16) of a tile is channel
+  // o = 2 mt + g / 2, spin 2 (g % 2) + jj / 2, real/imaginary part jj % 2;
+  // column n = 16 nt + lane % 16. The tile is staged in LDS as
+  // [site][channel][24 reals] (rows padded against bank conflicts) by stage(),
+  // then stored in whole 16-byte chunks by store_out() (after a barrier).
+  const int g = lane >> 4;
+  const int64_t vs = (int64_t)q.g.Vh * L.cout;
+  const int srow = L.cout * 24 + (out_f32 ? 4 : 8);  // staging row, in elements of the output type
+  auto stage = [&](const f32x4_t (&ac)[JM][NT]) {
+#pragma unroll
+    for (int j = 0; j < JM; ++j) {
+      if (j >= nm) continue;
+      const int o = 2 * (mbase + NWC * j) + (g >> 1);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (t >= nn) continue;
+        const int n = (nbase + t) * 16 + (lane & 15);
+        const int c = n / kFwSites, sl = n % kFwSites;
+        if (o < L.cout) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int r = (2 * (g & 1) + h) * 6 + 2 * c;
+            if (!out_f32) {
+              Bt[sl * srow + o * 24 + r] = (__bf16)ac[j][t][2 * h];
+              Bt[sl * srow + o * 24 + r + 1] = (__bf16)ac[j][t][2 * h + 1];
+            } else {
+              *reinterpret_cast<float2 *>(reinterpret_cast<float *>(Bt) + sl * srow + o * 24 + r) =
+                  make_float2(ac[j][t][2 * h], ac[j][t][2 * h + 1]);
+            }
+          }
+        }
+      }
+    }
+  };
+  auto store_out = [&]() {
+    const int per_chunk = kFwSites * L.cout;
+    if (!out_f32) {
+      bf16 *blk = (bf16 *)out + (int64_t)par * vs * 24;
+      for (int w = threadIdx.x; w < 3 * per_chunk; w += NTH) {
+        const int k = w / per_chunk, rem = w - k * per_chunk;
+        const int sl = rem / L.cout, o = rem - sl * L.cout;
+        const int s = s0 + sl;
+        if (s < q.g.Vh)
+          *reinterpret_cast<uint4 *>(blk + ((int64_t)k * vs + (int64_t)s * L.cout + o) * 8) =
+              *reinterpret_cast<const uint4 *>(Bt + sl * srow + o * 24 + 8 * k);
+      }
+    } else {
+      // FP32 packed spinor (chunks of 4 reals); the network's last layer (one channel)
+      const float *Sf = reinterpret_cast<const float *>(Bt);
+      float *blk = (float *)out + (int64_t)par * vs * 24;
+      for (int w = threadIdx.x; w < 6 * per_chunk; w += NTH) {
+        const int k = w / per_chunk, rem = w - k * per_chunk;
+        const int sl = rem / L.cout, o = rem - sl * L.cout;
+        const int s = s0 + sl;
+        if (s < q.g.Vh)
+          *reinterpret_cast<float4 *>(blk + ((int64_t)k * vs + (int64_t)s * L.cout + o) * 4) =
+              *reinterpret_cast<const float4 *>(Sf + sl * srow + o * 24 + 4 * k);
+      }
     }
   };
   if constexpr (PIPE != 0) {
     // 16 input channels: TPS threads per site, thread un taking channels
     // un + TPS k (k < KC); one path per chunk; the loads of path p + 1 are
     // issued before the matrix products of path p, so their latency overlaps them.
-    constexpr int TPS = NTH / kFwSites, KC = 16 / TPS;
+    constexpr int TPS = (SPLIT ? NTH / 2 : NTH) / kFwSites, KC = 16 / TPS;
     static_assert(TPS * KC == 16 && (TPS == 8 || TPS == 16), "pipelined path: 8 or 16 threads per site");
     __shared__ int nbL[kFwSites][8];
-    const int un = threadIdx.x % TPS, sl = threadIdx.x / TPS, s = s0 + sl;
+    // (in the split forms the transporting threads are 0 .. NTH / 2 - 1)
+    const int un = threadIdx.x % TPS, sl = (threadIdx.x / TPS) % kFwSites, s = s0 + sl;
     const bool valid = s < q.g.Vh;
     const int64_t vh = q.g.Vh, vs = vh * 16;
-    if (un < 8) nbL[sl][un] = valid ? nbr[((int64_t)par * 8 + un) * vh + s] : 0;
+    if (un < 8 && (!SPLIT || producer)) nbL[sl][un] = valid ? nbr[((int64_t)par * 8 + un) * vh + s] : 0;
     __syncthreads();
     uint4 raw[KC][3];
     float lv[18] = {};
@@ -336,11 +413,11 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
         }
       }
     };
-    auto compute = [&](int p) {
-      __bf16 *dst = Bt + sl * kFwRow + 8 * un;
+    auto compute = [&](__bf16 *Bb, int p) {
+      __bf16 *dst = Bb + sl * kFwRow + 8 * un;
       // (the matrix-core form keeps every lane in its products: a lane of a
       // site beyond Vh multiplies zeros and stores zeros)
-      if (PIPE != 2 && !valid) {
+      if (TRANS != 2 && !valid) {
         const bf16x8_t zero = {};
 #pragma unroll
         for (int k = 0; k < KC; ++k)
@@ -368,7 +445,7 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
           U0 = unpack_link<12, float>(lv);
         else
           U0 = unpack_link<18, float>(lv);
-        if constexpr (PIPE == 2) {
+        if constexpr (TRANS == 2) {
           // matrix cores: lanes 4b .. 4b+3 are one site (8 lanes per site), so
           // a 4x4x4 block is one site's link times 4 of its (channel, spin)
           // vectors; a vector's 3 words are its own B operand (K = c0 re, c0 im,
@@ -444,21 +521,58 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
     };
     // per path: transport into LDS, issue the next path's loads, then the
     // matrix products (their latency overlaps the products)
-    constexpr int kSplitN = (NT + NW - 1) / NW;  // n-tiles per wave when one m-tile is split over all waves
+    constexpr int kSplitN = (NT + NWC - 1) / NWC;  // n-tiles per wave when one m-tile is split over all waves
     const int form = (nm == JM && nn == NT) ? 2 : (nm == 1 && nn == kSplitN) ? 1 : (nn > 0 ? 0 : -1);
-    issue(0);
-#pragma unroll 1
-    for (int p = 0; p < 9; ++p) {
-      __syncthreads();
-      compute(p);
-      if (p + 1 < 9) issue(p + 1);
-      __syncthreads();
+    auto products = [&](auto &ac, const __bf16 *Bb, int p) {
       if (form == 2)
-        mma_static(std::integral_constant<int, JM>(), std::integral_constant<int, NT>(), 16 * p);
+        mma_static(std::integral_constant<int, JM>(), std::integral_constant<int, NT>(), ac, Bb, 16 * p);
       else if (form == 1)
-        mma_static(std::integral_constant<int, 1>(), std::integral_constant<int, kSplitN>(), 16 * p);
+        mma_static(std::integral_constant<int, 1>(), std::integral_constant<int, kSplitN>(), ac, Bb, 16 * p);
       else if (form == 0)
-        mma_chunk(16 * p, 16);
+        mma_chunk(ac, Bb, 16 * p, 16);
+    };
+    if constexpr (SPLIT) {
+      // iteration i: the transporting waves fill buffer i % 2 with path i while
+      // the others multiply path i - 1 from buffer (i - 1) % 2; the barrier
+      // ending iteration i publishes path i and frees buffer (i - 1) % 2. The
+      // accumulators live in the multiplying waves' branch only (they are not
+      // held while transporting), which also stages the output tile.
+      if (producer) {
+        issue(0);
+#pragma unroll 1
+        for (int i = 0; i < 10; ++i) {
+          if (i < 9) {
+            compute(Bt + (i & 1) * kBuf, i);
+            if (i + 1 < 9) issue(i + 1);
+          }
+          __syncthreads();
+        }
+      } else {
+        f32x4_t cacc[JM][NT];
+#pragma unroll
+        for (int j = 0; j < JM; ++j)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) cacc[j][t] = f32x4_t{0, 0, 0, 0};
+#pragma unroll 1
+        for (int i = 0; i < 10; ++i) {
+          if (i > 0) products(cacc, Bt + ((i - 1) & 1) * kBuf, i - 1);
+          __syncthreads();
+        }
+        stage(cacc);
+      }
+      __syncthreads();
+      store_out();
+      return;
+    } else {
+      issue(0);
+#pragma unroll 1
+      for (int p = 0; p < 9; ++p) {
+        __syncthreads();
+        compute(Bt, p);
+        if (p + 1 < 9) issue(p + 1);
+        __syncthreads();
+        products(acc, Bt, p);
+      }
     }
   } else {
   // input known to vanish on parity zero_par (the network input lives on even
@@ -520,83 +634,13 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
       }
     }
     __syncthreads();
-    mma_chunk(q0, ipc);
+    mma_chunk(acc, Bt, q0, ipc);
   }
   }
-  // Row m = 16 mt + 4 g + jj (g = lane / 16) of a tile is channel o = 2 mt + g / 2,
-  // spin 2 (g % 2) + jj / 2, real/imaginary part jj % 2; column n = 16 nt + lane % 16.
-  // The tile is staged in LDS as [site][channel][24 reals] (rows padded by 16
-  // bytes against bank conflicts), then stored in whole 16-byte chunks.
   __syncthreads();
-  const int g = lane >> 4;
-  const int64_t vs = (int64_t)q.g.Vh * L.cout;
-  if (!out_f32) {
-    __bf16 *St = Bt;
-    const int srow = L.cout * 24 + 8;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      if (j >= nm) continue;
-      const int o = 2 * (mbase + NW * j) + (g >> 1);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        if (t >= nn) continue;
-        const int n = (nbase + t) * 16 + (lane & 15);
-        const int c = n / kFwSites, sl = n % kFwSites;
-        if (o < L.cout) {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int r = (2 * (g & 1) + h) * 6 + 2 * c;
-            St[sl * srow + o * 24 + r] = (__bf16)acc[j][t][2 * h];
-            St[sl * srow + o * 24 + r + 1] = (__bf16)acc[j][t][2 * h + 1];
-          }
-        }
-      }
-    }
-    __syncthreads();
-    bf16 *blk = (bf16 *)out + (int64_t)par * vs * 24;
-    const int per_chunk = kFwSites * L.cout;
-    for (int w = threadIdx.x; w < 3 * per_chunk; w += kPtcThreads) {
-      const int k = w / per_chunk, rem = w - k * per_chunk;
-      const int sl = rem / L.cout, o = rem - sl * L.cout;
-      const int s = s0 + sl;
-      if (s < q.g.Vh)
-        *reinterpret_cast<uint4 *>(blk + ((int64_t)k * vs + (int64_t)s * L.cout + o) * 8) =
-            *reinterpret_cast<const uint4 *>(St + sl * srow + o * 24 + 8 * k);
-    }
-  } else {
-    // FP32 packed spinor (chunks of 4 reals); the network's last layer (one channel)
-    float *Sf = reinterpret_cast<float *>(Bt);
-    const int srow = L.cout * 24 + 4;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      if (j >= nm) continue;
-      const int o = 2 * (mbase + NW * j) + (g >> 1);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        if (t >= nn) continue;
-        const int n = (nbase + t) * 16 + (lane & 15);
-        const int c = n / kFwSites, sl = n % kFwSites;
-        if (o < L.cout) {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int r = (2 * (g & 1) + h) * 6 + 2 * c;
-            *reinterpret_cast<float2 *>(Sf + sl * srow + o * 24 + r) = make_float2(acc[j][t][2 * h], acc[j][t][2 * h + 1]);
-          }
-        }
-      }
-    }
-    __syncthreads();
-    float *blk = (float *)out + (int64_t)par * vs * 24;
-    const int per_chunk = kFwSites * L.cout;
-    for (int w = threadIdx.x; w < 6 * per_chunk; w += kPtcThreads) {
-      const int k = w / per_chunk, rem = w - k * per_chunk;
-      const int sl = rem / L.cout, o = rem - sl * L.cout;
-      const int s = s0 + sl;
-      if (s < q.g.Vh)
-        *reinterpret_cast<float4 *>(blk + ((int64_t)k * vs + (int64_t)s * L.cout + o) * 4) =
-            *reinterpret_cast<const float4 *>(Sf + sl * srow + o * 24 + 4 * k);
-    }
-  }
+  stage(acc);
+  __syncthreads();
+  store_out();
 }
 
 // ---------------------------------------------------------------------------
@@ -924,10 +968,12 @@ hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *
                               int out_f32, int par, int variant, int zero_par, hipStream_t st) {
   // LDS staging of the output tile: BF16 up to 16 channels; FP32 one channel
   if (out_f32 && L.cout != 1) return hipErrorInvalidValue;
+  if (par < -1 || par > 1) return hipErrorInvalidValue;
+  const int npar = par < 0 ? 2 : 1;  // par -1: both parities in one launch
   switch (variant) {
-#define PTC_FWD(NS, WPE, PIPE, NTH)                                                                           \
-  hipLaunchKernelGGL((ptc_forward_kernel<NS, WPE, PIPE, NTH>), dim3((q.g.Vh + NS - 1) / NS), dim3(NTH), 0, st, q, L, \
-                     nbr, (const bf16 *)in, out, out_f32, par, zero_par);                                           \
+#define PTC_FWD(NS, WPE, PIPE, NTH)                                                                      \
+  hipLaunchKernelGGL((ptc_forward_kernel<NS, WPE, PIPE, NTH>), dim3(npar * ((q.g.Vh + NS - 1) / NS)), dim3(NTH), \
+                     0, st, q, L, nbr, (const bf16 *)in, out, out_f32, par, zero_par);                         \
   break;
     case 642: PTC_FWD(64, 2, 0, 256)
     case 322: PTC_FWD(32, 2, 0, 256)
@@ -943,6 +989,11 @@ hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *
     case 5041: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, 1, 512)
     case 5032: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, 2, 512)
     case 5042: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, 2, 512)
+    // split forms (512 threads: 4 waves transport, 4 multiply), at 3 or 4 waves per SIMD
+    case 5033: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, 3, 512)
+    case 5043: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, 3, 512)
+    case 5034: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 3, 4, 512)
+    case 5044: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, 4, 512)
     default: return hipErrorInvalidValue;
 #undef PTC_FWD
   }

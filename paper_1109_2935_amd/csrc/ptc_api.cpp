@@ -98,7 +98,8 @@ static lqcd_status ptc_forward_all(lqcd_context *ctx, const PtcPlan &plan, const
     // the layer-0 input (r on even sites) vanishes on odd sites
     const int zero_par = l == 0 ? 1 : -1;
     const std::vector<int> cands =
-        L.cin == 16 && zero_par < 0 ? std::vector<int>{642, 3221, 3231, 3222, 3232, 5031, 5041, 5032, 5042}
+        L.cin == 16 && zero_par < 0 ? std::vector<int>{642,  3221, 3231, 3222, 3232, 5031, 5041,
+                                                      5032, 5042, 5033, 5043, 5034, 5044}
                                     : std::vector<int>{642, 322};
     // LQCD_PTC_VARIANT=<form> forces the form of the 16-input-channel layers
     // (so that tests can check every form against the oracle)
@@ -109,9 +110,17 @@ static lqcd_status ptc_forward_all(lqcd_context *ctx, const PtcPlan &plan, const
             : tune_pick(ctx, key.str(), cands, 642, true, st, [&](int v) {
                 return launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, 0, v, zero_par, st);
               });
-    for (int par = 0; par < (last ? 1 : 2); ++par)
-      TRY(hip_check(ctx, launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, par, variant, zero_par, st),
+    // the last layer's output lives on even sites; 16-channel layers compute
+    // both parities in one launch (a third less memory traffic, same time),
+    // the first layer (only one path per parity carries data) one per launch
+    if (last || zero_par >= 0) {
+      for (int par = 0; par < (last ? 1 : 2); ++par)
+        TRY(hip_check(ctx, launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, par, variant, zero_par, st),
+                      "ptc forward"));
+    } else {
+      TRY(hip_check(ctx, launch_ptc_forward(q, L, (const int *)nbr, acts[l], out, last, -1, variant, zero_par, st),
                     "ptc forward"));
+    }
   }
   return LQCD_OK;
 }

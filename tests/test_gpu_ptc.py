@@ -50,10 +50,11 @@ def test_ptc_forward_matches_oracle(ctx, channels, tol):
 
 
 # every form of the 16-input-channel layers (256 or 512 threads, waves per
-# SIMD, colour products on dot2 or on 4x4x4 matrix-core blocks), on a lattice
+# SIMD, colour products on dot2 or on 4x4x4 matrix-core blocks, transport and
+# products in the same or in separate waves), on a lattice
 # whose sites fill whole workgroups and on one that leaves 16 of 32 sites of a
 # workgroup empty
-PTC_FORMS = (3221, 3231, 3222, 3232, 5031, 5041, 5032, 5042)
+PTC_FORMS = (3221, 3231, 3222, 3232, 5031, 5041, 5032, 5042, 5033, 5043, 5034, 5044)
 
 
 @pytest.mark.parametrize("dims", [DIMS, (4, 2, 2, 2)])
