@@ -227,8 +227,9 @@ constexpr int kFwRow = 16 * 8 + kLdsPad;  // bf16 per LDS row: 16 items x 8 K va
 // same split between waves: the first half of the waves transport path p + 1
 // into one LDS buffer while the second half multiply path p from the other
 // (one barrier per path, so the vector and matrix work of a workgroup overlap).
-// NTH threads (NTH / 64 waves) per workgroup.
-template <int NS, int WPE, int PIPE, int NTH = kPtcThreads>
+// NTH threads (NTH / 64 waves) per workgroup; RC the link format (12 or 18
+// reals) of the pipelined forms.
+template <int NS, int WPE, int PIPE, int NTH = kPtcThreads, int RC = 18>
 __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(WPE)))
 ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void *out, int out_f32, int par_arg,
                    int zero_par) {
@@ -385,9 +386,13 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
     const int64_t vh = q.g.Vh, vs = vh * 16;
     if (un < 8 && (!SPLIT || producer)) nbL[sl][un] = valid ? nbr[((int64_t)par * 8 + un) * vh + s] : 0;
     __syncthreads();
-    uint4 raw[KC][3];
-    float lv[18] = {};
-    auto issue = [&](int p) {
+    // activation words and link reals of the path in flight
+    static_assert(RC == 12 || RC == 18, "link format");
+    uint4 rawA[KC][3];
+    float lvA[RC] = {};
+    // (always inlined: the register sets are passed by reference and must not
+    // go to memory)
+    auto issue = [&](uint4 (&raw)[KC][3], float (&lv)[RC], int p) __attribute__((always_inline)) {
       if (!valid) return;
       const int n = p == 0 ? s : (nbL[sl][p - 1] & 0x7fffffff);
       const bf16 *blk = in + (int64_t)(p == 0 ? par : 1 - par) * vs * 24;
@@ -400,20 +405,11 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
         const int mu = (p - 1) >> 1;
         const bool fwd = ((p - 1) & 1) == 0;
         const int lsite = fwd ? s : n, lpar = fwd ? par : 1 - par;
-        if (q.recon == 12) {
-          float t[12];
-          load_site<float, 12, float>(q.gauge + (int64_t)(2 * mu + lpar) * vh * 12, vh, lsite, t);
-#pragma unroll
-          for (int i = 0; i < 12; ++i) lv[i] = t[i];
-        } else {
-          float t[18];
-          load_site<float, 18, float>(q.gauge + (int64_t)(2 * mu + lpar) * vh * 18, vh, lsite, t);
-#pragma unroll
-          for (int i = 0; i < 18; ++i) lv[i] = t[i];
-        }
+        load_site<float, RC, float>(q.gauge + (int64_t)(2 * mu + lpar) * vh * RC, vh, lsite, lv);
       }
     };
-    auto compute = [&](__bf16 *Bb, int p) {
+    auto compute = [&](__bf16 *Bb, const uint4 (&raw)[KC][3], const float (&lv)[RC], int p)
+                       __attribute__((always_inline)) {
       __bf16 *dst = Bb + sl * kFwRow + 8 * un;
       // (the matrix-core form keeps every lane in its products: a lane of a
       // site beyond Vh multiplies zeros and stores zeros)
@@ -440,11 +436,7 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
       if (p != 0) {
         const bool fwd = ((p - 1) & 1) == 0;
         const float ph = nbL[sl][p - 1] < 0 ? -1.f : 1.f;
-        Link<float> U0;
-        if (q.recon == 12)
-          U0 = unpack_link<12, float>(lv);
-        else
-          U0 = unpack_link<18, float>(lv);
+        const Link<float> U0 = unpack_link<RC, float>(lv);
         if constexpr (TRANS == 2) {
           // matrix cores: lanes 4b .. 4b+3 are one site (8 lanes per site), so
           // a 4x4x4 block is one site's link times 4 of its (channel, spin)
@@ -538,12 +530,12 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
       // accumulators live in the multiplying waves' branch only (they are not
       // held while transporting), which also stages the output tile.
       if (producer) {
-        issue(0);
+        issue(rawA, lvA, 0);
 #pragma unroll 1
         for (int i = 0; i < 10; ++i) {
           if (i < 9) {
-            compute(Bt + (i & 1) * kBuf, i);
-            if (i + 1 < 9) issue(i + 1);
+            compute(Bt + (i & 1) * kBuf, rawA, lvA, i);
+            if (i + 1 < 9) issue(rawA, lvA, i + 1);
           }
           __syncthreads();
         }
@@ -564,12 +556,12 @@ ptc_forward_kernel(PtcGeo q, PtcLayerDev L, const int *nbr, const bf16 *in, void
       store_out();
       return;
     } else {
-      issue(0);
+      issue(rawA, lvA, 0);
 #pragma unroll 1
       for (int p = 0; p < 9; ++p) {
         __syncthreads();
-        compute(Bt, p);
-        if (p + 1 < 9) issue(p + 1);
+        compute(Bt, rawA, lvA, p);
+        if (p + 1 < 9) issue(rawA, lvA, p + 1);
         __syncthreads();
         products(acc, Bt, p);
       }
@@ -971,9 +963,17 @@ hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *
   if (par < -1 || par > 1) return hipErrorInvalidValue;
   const int npar = par < 0 ? 2 : 1;  // par -1: both parities in one launch
   switch (variant) {
-#define PTC_FWD(NS, WPE, PIPE, NTH)                                                                      \
-  hipLaunchKernelGGL((ptc_forward_kernel<NS, WPE, PIPE, NTH>), dim3(npar * ((q.g.Vh + NS - 1) / NS)), dim3(NTH), \
-                     0, st, q, L, nbr, (const bf16 *)in, out, out_f32, par, zero_par);                         \
+#define PTC_FWD_RC(NS, WPE, PIPE, NTH, RC)                                                                   \
+  hipLaunchKernelGGL((ptc_forward_kernel<NS, WPE, PIPE, NTH, RC>), dim3(npar * ((q.g.Vh + NS - 1) / NS)),         \
+                     dim3(NTH), 0, st, q, L, nbr, (const bf16 *)in, out, out_f32, par, zero_par)
+#define PTC_FWD(NS, WPE, PIPE, NTH)              \
+  if constexpr (PIPE == 0) {                     \
+    PTC_FWD_RC(NS, WPE, PIPE, NTH, 18);          \
+  } else if (q.recon == 18) {                    \
+    PTC_FWD_RC(NS, WPE, PIPE, NTH, 18);          \
+  } else {                                       \
+    PTC_FWD_RC(NS, WPE, PIPE, NTH, 12);          \
+  }                                              \
   break;
     case 642: PTC_FWD(64, 2, 0, 256)
     case 322: PTC_FWD(32, 2, 0, 256)
@@ -996,6 +996,7 @@ hipError_t launch_ptc_forward(const PtcGeo &q, const PtcLayerDev &L, const int *
     case 5044: if (L.cin != 16 || zero_par >= 0) return hipErrorInvalidValue; PTC_FWD(32, 4, 4, 512)
     default: return hipErrorInvalidValue;
 #undef PTC_FWD
+#undef PTC_FWD_RC
   }
   return hipGetLastError();
 }

@@ -51,18 +51,19 @@ def test_ptc_forward_matches_oracle(ctx, channels, tol):
 
 # every form of the 16-input-channel layers (256 or 512 threads, waves per
 # SIMD, colour products on dot2 or on 4x4x4 matrix-core blocks, transport and
-# products in the same or in separate waves), on a lattice
+# products in the same or in separate waves; both link formats), on a lattice
 # whose sites fill whole workgroups and on one that leaves 16 of 32 sites of a
 # workgroup empty
 PTC_FORMS = (3221, 3231, 3222, 3232, 5031, 5041, 5032, 5042, 5033, 5043, 5034, 5044)
 
 
+@pytest.mark.parametrize("recon", [12, 18])
 @pytest.mark.parametrize("dims", [DIMS, (4, 2, 2, 2)])
 @pytest.mark.parametrize("form", PTC_FORMS)
-def test_ptc_forward_every_form(ctx, form, dims, monkeypatch):
+def test_ptc_forward_every_form(ctx, form, dims, recon, monkeypatch):
     channels = (1, 16, 16, 16, 1)
     U = synth.gauge_field(dims, 0.25, 131)
-    op32 = ops.wilson_clover(ctx, U, dims, 0.124, 1.0, 1, 12)
+    op32 = ops.wilson_clover(ctx, U, dims, 0.124, 1.0, 1, recon)
     net = ptc.Network(ctx, channels)
     Ws = weights_c64(optc.init_weights(132, channels=channels))
     net.set_weights(Ws)
