@@ -40,6 +40,17 @@
  * launch and nothing is written when validation fails. LQCD_ERR_DEVICE wraps
  * HIP failures; lqcd_last_error() returns the text of the most recent error
  * of the context (or of the library, for calls without a context).
+ *
+ * Environment. LQCD_TUNE=0 disables the autotuner's timing (fixed fallback
+ * launch parameters); LQCD_TUNE_CACHE=<file> keeps its choices across
+ * processes; LQCD_MRHS_MFMA=1 selects the matrix-core form of the multi-source
+ * link products; LQCD_PTC_VARIANT=<form> forces the form of the network's
+ * 16-input-channel layers (for testing every form); LQCD_VERBOSE prints the
+ * solvers' residual history to stderr. The tuned launch parameters of the
+ * stencil and batch kernels never change a result; the network's forms differ
+ * in the order of their FP32 sums (dot2 or matrix-core colour products), so
+ * the form timed fastest can change its output by BF16 roundings (fix it with
+ * LQCD_PTC_VARIANT or a tuning cache for bit-reproducible runs).
  */
 #ifndef LQCD_H
 #define LQCD_H

@@ -100,18 +100,12 @@ __device__ __forceinline__ void transport_one(const PtcGeo &q, const bf16 *__res
   }
 }
 
-template <int RECON>
-__device__ __forceinline__ void transport_dispatch(const PtcGeo &q, const bf16 *act, int C, int ch, int p,
-                                                   const Site &x, int s, cpx<float> (&out)[4][3]) {
-  transport_one<RECON>(q, act, C, ch, p, x, s, out);
-}
-
 __device__ __forceinline__ void transport_any(const PtcGeo &q, const bf16 *act, int C, int ch, int p, const Site &x,
                                               int s, cpx<float> (&out)[4][3]) {
   if (q.recon == 12)
-    transport_dispatch<12>(q, act, C, ch, p, x, s, out);
+    transport_one<12>(q, act, C, ch, p, x, s, out);
   else
-    transport_dispatch<18>(q, act, C, ch, p, x, s, out);
+    transport_one<18>(q, act, C, ch, p, x, s, out);
 }
 
 // Neighbour table of the transport paths: entry [par][p-1][s] (p = 1..8) is

@@ -7,8 +7,11 @@
 // is kept in the context. With LQCD_TUNE_CACHE=<file> results are also read
 // from and appended to a text file ("key<TAB>value" lines) tagged with the
 // device architecture; LQCD_TUNE=0 disables timing (fallback values).
-// All candidates compute the same result: each output element is written by
-// one thread with a fixed summation order, so tuning never changes numerics.
+// The candidates of the stencil and batch kernels compute the same result
+// (each output element is written by one thread with a fixed summation
+// order). The network's forward forms differ in the order of their FP32 sums
+// (dot2 or matrix-core colour products), so there the choice can change an
+// output by BF16 roundings; LQCD_PTC_VARIANT or a cache file fixes it.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -42,8 +45,6 @@ static std::string arch_tag() {
 }
 
 static void load_file(lqcd_context *ctx) {
-  static bool env_read = false;
-  (void)env_read;
   const char *t = std::getenv("LQCD_TUNE");
   ctx->tune_enabled = !(t && t[0] == '0');
   const char *f = std::getenv("LQCD_TUNE_CACHE");

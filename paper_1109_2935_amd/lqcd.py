@@ -126,8 +126,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError("liblqcd.so is not built (%s); run __graft_entry__.build() or "
-                              "python paper_1109_2935_amd/build.py" % LIB_PATH)
+            raise ImportError("liblqcd.so is not built (%s); run python paper_1109_2935_amd/build.py" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
         for name, args in _SIGNATURES.items():
             fn = getattr(L, name)
