@@ -1,10 +1,12 @@
 """Textbook FP64 solvers of the oracle (test infrastructure only).
 
 Written from the paper (Babich et al., SC11): CG and CG on the normal
-equations (Section III-A), minimal residual for the Schwarz blocks and the
-additive Schwarz preconditioner (Section III-B, Section VIII-A), and the GCR-DD
-solver of Algorithm 1 (Section VIII-A), all in FP64 with numpy inner products
-<a,b> = sum conj(a) b. Every function takes the operator as a callable.
+equations (Section III-A), the multi-shift CG for eq. (4) (Section III-A; the
+method is cited there, not printed), minimal residual for the Schwarz blocks
+and the additive Schwarz preconditioner (Section III-B, Section VIII-A), and
+the GCR-DD solver of Algorithm 1 (Section VIII-A), all in FP64 with numpy
+inner products <a,b> = sum conj(a) b. Every function takes the operator as a
+callable.
 """
 import numpy as np
 
@@ -39,6 +41,61 @@ def cg(apply_A, b, tol=1e-10, maxiter=10000, x0=None):
         it += 1
         hist.append(np.sqrt(rr))
     return x, it, hist
+
+
+def multishift_cg(apply_A, b, shifts, tol=1e-10, maxiter=10000):
+    """All solutions of (A + s_i) x_i = b (eq. (4)) from the one Krylov space
+    of CG on A (A Hermitian positive definite, A + s_i too). The residual of
+    shifted system i stays collinear with the base residual, r_i = z_i r, and
+    the CG recurrences of the base fix every z_i:
+        z_{k+1} = z_k z_{k-1} a_{k-1} /
+                  (a_k b_{k-1} (z_{k-1} - z_k) + z_{k-1} a_{k-1} (1 + s a_k)),
+        a^s_k = a_k z_{k+1} / z_k,   b^s_k = b_k (z_{k+1} / z_k)^2,
+        x^s += a^s_k p^s,   p^s = z_{k+1} r_{k+1} + b^s_k p^s,
+    with z_0 = z_{-1} = 1, a_{-1} = 1, b_{-1} = 0. A shift stops being updated
+    once |z| ||r|| <= tol ||b||; the iteration ends when all have.
+    Returns (list of x_i, iterations, list of |z_i| ||r|| / ||b|| at each
+    shift's last update)."""
+    shifts = [float(s_) for s_ in shifts]
+    ns = len(shifts)
+    r = b.copy()
+    p = b.copy()
+    xs = [np.zeros_like(b) for _ in range(ns)]
+    ps = [b.copy() for _ in range(ns)]
+    z = [1.0] * ns        # z_k
+    z_prev = [1.0] * ns   # z_{k-1}
+    a_prev, b_prev = 1.0, 0.0
+    rr = dot(r, r).real
+    bn = norm(b)
+    active = [True] * ns
+    res = [1.0] * ns
+    it = 0
+    while any(active) and it < maxiter:
+        Ap = apply_A(p)
+        a = rr / dot(p, Ap).real
+        r = r - a * Ap
+        rr_new = dot(r, r).real
+        bk = rr_new / rr
+        for i in range(ns):
+            if not active[i]:
+                continue
+            s_ = shifts[i]
+            z_next = z[i] * z_prev[i] * a_prev / (a * b_prev * (z_prev[i] - z[i]) + z_prev[i] * a_prev * (1.0 + s_ * a))
+            a_s = a * z_next / z[i]
+            b_s = bk * (z_next / z[i]) ** 2
+            xs[i] = xs[i] + a_s * ps[i]
+            ps[i] = z_next * r + b_s * ps[i]
+            z_prev[i], z[i] = z[i], z_next
+        p = r + bk * p
+        a_prev, b_prev = a, bk
+        rr = rr_new
+        it += 1
+        for i in range(ns):
+            if active[i]:
+                res[i] = abs(z[i]) * np.sqrt(rr) / bn
+                if res[i] <= tol:
+                    active[i] = False
+    return xs, it, res
 
 
 def cgne(apply_A, apply_Adag, b, tol=1e-10, maxiter=10000, x0=None):
