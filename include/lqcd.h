@@ -352,11 +352,52 @@ lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op_hi,
  *   lattice through CG on the normal equations of Mhat (x, b packed FULL);
  * kind = LQCD_CG_STAG_NORMAL: solves N_e x_e = b_e on even sites (eq. (4)
  *   with one shift sigma = 0; x, b packed single-parity even).
- * op_sloppy may be NULL (pure op_hi).
+ * op_sloppy may be NULL (pure op_hi). x holds the starting guess on entry
+ * (zero for a cold start) and the solution on return.
  */
 lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_hi,
                           const lqcd_operator *op_sloppy, const lqcd_cg_params *params, void *x,
                           const void *b, lqcd_solve_info *info, lqcd_stream stream);
+
+/*
+ * Multi-shift CG for the shifted staggered systems of eq. (4),
+ *   (N_e + sigma_i) x_i = b,  i = 0 .. nshift - 1,  on even sites,
+ * N_e = m^2 - D_eo D_oe / 4 (so N_e + sigma is the same normal operator at mass
+ * sqrt(m^2 + sigma)). The strategy of Section VIII-B: one multi-shift CG in the
+ * precision of op_sloppy produces every x_i from the Krylov space of the
+ * smallest shift (Section III-A: the residuals of all shifted systems stay
+ * collinear), each shift stopping once its residual estimate is below
+ * tol_sloppy; then each x_i is refined to tol by the reliable-update CG of
+ * lqcd_cg_solve (op_hi FP64, op_sloppy) starting from it, its residual
+ * recomputed in FP64. op_sloppy: FP32, or NULL (multi-shift stage in FP64);
+ * 16-bit is refused (the multi-shift solutions would be too inaccurate to
+ * refine, as the paper notes). x: host array of nshift device pointers, each a
+ * packed even spinor of op_hi (written, not read); b: packed even spinor of
+ * op_hi. Both operators staggered, same system except precision and links.
+ */
+#define LQCD_MAX_SHIFTS 16
+
+typedef struct {
+  int32_t nshift;                 /* 1 .. LQCD_MAX_SHIFTS */
+  double shifts[LQCD_MAX_SHIFTS]; /* sigma_i, with m^2 + sigma_i > 0 */
+  double tol;                     /* final ||b - (N_e + sigma_i) x_i|| <= tol ||b||, recomputed in FP64 */
+  double tol_sloppy;              /* multi-shift stage, per shift (e.g. 1e-6 in FP32) */
+  int32_t max_iter;               /* per stage and per refinement */
+  double delta_reliable;          /* of the refinements (see lqcd_cg_params) */
+} lqcd_multishift_params;
+
+typedef struct {
+  int32_t ms_iters;                       /* iterations of the multi-shift stage */
+  int32_t ms_matvecs;                     /* its applications of N_e */
+  double ms_seconds;                      /* its wall time */
+  lqcd_solve_info shift[LQCD_MAX_SHIFTS]; /* refinement of each x_i: iters, reliable updates, matvecs,
+                                             final FP64 true residual, seconds */
+  double seconds;                         /* wall time of the call */
+} lqcd_multishift_info;
+
+lqcd_status lqcd_multishift_cg_solve(lqcd_context *ctx, const lqcd_operator *op_hi, const lqcd_operator *op_sloppy,
+                                     const lqcd_multishift_params *params, void *const *x, const void *b,
+                                     lqcd_multishift_info *info, lqcd_stream stream);
 
 /* ---------------------------------------------------------------------- */
 /* learned preconditioner                                                  */

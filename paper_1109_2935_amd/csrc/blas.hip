@@ -15,6 +15,7 @@ namespace lqcd {
 
 constexpr int kBT = 256;
 constexpr int kMaxVec = 32;
+constexpr int kMaxShiftVec = 17;  // 16 shifted systems and the base direction
 
 // 4 consecutive reals (2 complex numbers) of storage type S.
 template <typename S> struct Quad;
@@ -276,6 +277,39 @@ __global__ void __launch_bounds__(kBT) multi_axpy_acc_kernel(SX *x, VecPack p, s
   }
 }
 
+// Multi-shift CG update (eq. (4)): for every shifted system j,
+//   x_j += a_j p_j (skipped where x_j is NULL), then p_j = z_j r + b_j p_j,
+// all from one read of r. Real coefficients (Hermitian positive-definite
+// systems).
+struct ShiftPack {
+  void *x[kMaxShiftVec];
+  void *p[kMaxShiftVec];
+  double a[kMaxShiftVec], z[kMaxShiftVec], b[kMaxShiftVec];
+  int k;
+};
+
+template <typename S>
+__global__ void __launch_bounds__(kBT) multishift_update_kernel(ShiftPack sp, const S *r, size_t nq) {
+  for (size_t i = (size_t)blockIdx.x * kBT + threadIdx.x; i < nq; i += (size_t)gridDim.x * kBT) {
+    double rv[4];
+    ld4(r, i, rv);
+    for (int j = 0; j < sp.k; ++j) {
+      double pv[4];
+      ld4((const S *)sp.p[j], i, pv);
+      if (sp.x[j]) {
+        double xv[4];
+        ld4((const S *)sp.x[j], i, xv);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xv[c] += sp.a[j] * pv[c];
+        st4((S *)sp.x[j], i, xv);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) pv[c] = sp.z[j] * rv[c] + sp.b[j] * pv[c];
+      st4((S *)sp.p[j], i, pv);
+    }
+  }
+}
+
 // x += a p ; r -= a q ; reduce ||r||^2
 template <typename SX, typename SR>
 __global__ void __launch_bounds__(kBT) cg_update_kernel(SX *x, const SX *p, SR *rv, const SR *q, size_t nq, double a,
@@ -411,6 +445,25 @@ hipError_t blas_multi_axpy_acc(int px, void *x, int pp, const void *const *p, co
   const int g = grid_for(nq, 4096);
   return dispatch2(px, pp, [&](auto t1, auto t2) -> hipError_t {
     hipLaunchKernelGGL((multi_axpy_acc_kernel<T1, T2>), dim3(g), dim3(kBT), 0, st, (T1 *)x, pk, nq);
+    return hipGetLastError();});
+}
+
+hipError_t blas_multishift_update(int prec, void *const *x, void *const *p, const double *a, const double *z,
+                                  const double *b, int k, const void *r, size_t n, hipStream_t st) {
+  if (k < 1 || k > kMaxShiftVec) return hipErrorInvalidValue;
+  ShiftPack sp;
+  sp.k = k;
+  for (int j = 0; j < k; ++j) {
+    sp.x[j] = x[j];
+    sp.p[j] = p[j];
+    sp.a[j] = a[j];
+    sp.z[j] = z[j];
+    sp.b[j] = b[j];
+  }
+  const size_t nq = n / 2;
+  const int g = grid_for(nq, 4096);
+  return dispatch1(prec, [&](auto t1) -> hipError_t {
+    hipLaunchKernelGGL((multishift_update_kernel<T1>), dim3(g), dim3(kBT), 0, st, sp, (const T1 *)r, nq);
     return hipGetLastError();});
 }
 

@@ -519,3 +519,178 @@ extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
   if (!converged) return set_error(ctx, LQCD_ERR_NOT_CONVERGED, "CG reached max_iter");
   return LQCD_OK;
 }
+
+extern "C" lqcd_status lqcd_multishift_cg_solve(lqcd_context *ctx, const lqcd_operator *op_hi,
+                                                const lqcd_operator *op_sloppy, const lqcd_multishift_params *prm,
+                                                void *const *x, const void *b, lqcd_multishift_info *info,
+                                                lqcd_stream stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  if (!prm) return set_error(ctx, LQCD_ERR_INVALID_ARG, "params are NULL");
+  OpInfo hi, lo;
+  TRY(check_op(ctx, op_hi, &hi));
+  if (op_hi->action != LQCD_STAGGERED) return set_error(ctx, LQCD_ERR_INVALID_ARG, "multi-shift CG needs a staggered operator");
+  if (hi.prec != LQCD_F64) return set_error(ctx, LQCD_ERR_UNSUPPORTED, "op_hi must be FP64");
+  TRY(check_fields_internal(ctx, op_hi));
+  if (op_sloppy) {
+    TRY(check_op(ctx, op_sloppy, &lo));
+    if (!same_system(op_hi, op_sloppy)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "op_sloppy describes another system");
+    TRY(check_fields_internal(ctx, op_sloppy));
+    if (lo.prec != LQCD_F32 && lo.prec != LQCD_F64)
+      return set_error(ctx, LQCD_ERR_UNSUPPORTED, "the multi-shift stage runs in FP32 or FP64, not in 16-bit precision");
+  } else {
+    lo = hi;
+  }
+  const int ns = prm->nshift;
+  if (ns < 1 || ns > LQCD_MAX_SHIFTS) return set_error(ctx, LQCD_ERR_INVALID_ARG, "nshift must be 1 .. LQCD_MAX_SHIFTS");
+  if (!(prm->tol > 0) || !(prm->tol_sloppy > 0) || prm->max_iter < 1 || prm->delta_reliable < 0 ||
+      prm->delta_reliable >= 1)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "need tol > 0, tol_sloppy > 0, max_iter >= 1, 0 <= delta_reliable < 1");
+  const double m2 = op_hi->mass * op_hi->mass;
+  double smin = prm->shifts[0];
+  for (int i = 0; i < ns; ++i) {
+    if (!std::isfinite(prm->shifts[i]) || !(m2 + prm->shifts[i] > 0))
+      return set_error(ctx, LQCD_ERR_INVALID_ARG, "every shift needs m^2 + sigma > 0");
+    smin = std::min(smin, prm->shifts[i]);
+  }
+  if (!x || !b || ((uintptr_t)b & 15)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
+  for (int i = 0; i < ns; ++i) {
+    if (!x[i] || ((uintptr_t)x[i] & 15) || x[i] == b) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad solution pointer");
+    for (int j = 0; j < i; ++j)
+      if (x[j] == x[i]) return set_error(ctx, LQCD_ERR_INVALID_ARG, "solution pointers must be distinct");
+  }
+
+  Solver S{ctx, (hipStream_t)stream, kSlotSolver};
+  const size_t n = ncomplex(hi);  // complex entries of one even field
+  RedScratch red = S.red();
+  lqcd_multishift_info inf{};
+
+  double bn2;
+  TRY(S.hip(blas_norm2(hi.prec, b, n, red, S.st), "norm"));
+  TRY(S.result(1, &bn2));
+  if (!std::isfinite(bn2)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "source contains non-finite values");
+  if (bn2 == 0) {
+    for (int i = 0; i < ns; ++i) TRY(S.hip(hipMemsetAsync(x[i], 0, hi.spinor_bytes, S.st), "memset"));
+    TRY(S.hip(hipStreamSynchronize(S.st), "sync"));
+    inf.seconds = elapsed(t0);
+    if (info) *info = inf;
+    return LQCD_OK;
+  }
+  const double bn = std::sqrt(bn2);
+
+  // Multi-shift stage in the sloppy precision: CG on A = N_e + smin (the
+  // normal operator at mass sqrt(m^2 + smin)); the systems A + s_i with
+  // s_i = sigma_i - smin >= 0 follow from the collinear residuals r_i = z_i r.
+  lqcd_operator base_op = op_sloppy ? *op_sloppy : *op_hi;
+  base_op.mass = std::sqrt(m2 + smin);
+  OpInfo lb = lo;
+  lb.op = &base_op;
+  void *r, *q, *tmp, *p, *xs[LQCD_MAX_SHIFTS], *ps[LQCD_MAX_SHIFTS];
+  TRY(S.vec(lo.spinor_bytes, &r));
+  TRY(S.vec(lo.spinor_bytes, &q));
+  TRY(S.vec(lo.spinor_bytes, &tmp));
+  TRY(S.vec(lo.spinor_bytes, &p));
+  for (int i = 0; i < ns; ++i) {
+    TRY(S.vec(lo.spinor_bytes, &xs[i]));
+    TRY(S.vec(lo.spinor_bytes, &ps[i]));
+  }
+  TRY(S.hip(blas_convert(hi.prec, b, lo.prec, r, n, 1.0, S.st), "convert"));
+  TRY(S.hip(hipMemcpyAsync(p, r, lo.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
+  for (int i = 0; i < ns; ++i) {
+    TRY(S.hip(hipMemcpyAsync(ps[i], r, lo.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
+    TRY(S.hip(hipMemsetAsync(xs[i], 0, lo.spinor_bytes, S.st), "memset"));
+  }
+  double rr;
+  TRY(S.hip(blas_norm2(lo.prec, r, n, red, S.st), "norm"));
+  TRY(S.result(1, &rr));
+  double z[LQCD_MAX_SHIFTS], zp[LQCD_MAX_SHIFTS], res[LQCD_MAX_SHIFTS];
+  bool active[LQCD_MAX_SHIFTS];
+  for (int i = 0; i < ns; ++i) {
+    z[i] = zp[i] = 1.0;
+    res[i] = 1.0;
+    active[i] = true;
+  }
+  double a_prev = 1.0, b_prev = 0.0;
+  int it = 0;
+  auto any_active = [&] {
+    for (int i = 0; i < ns; ++i)
+      if (active[i]) return true;
+    return false;
+  };
+  while (any_active() && it < prm->max_iter) {
+    TRY(schur_apply(ctx, lb, lb.g, q, p, tmp, 0, nullptr, S.st));
+    inf.ms_matvecs++;
+    double d[2];
+    TRY(S.hip(blas_cdot(lo.prec, p, q, n, red, S.st), "dot"));
+    TRY(S.result(2, d));
+    if (!(d[0] > 0)) return set_error(ctx, LQCD_ERR_BREAKDOWN, "multi-shift CG breakdown: <p, A p> <= 0");
+    const double a = rr / d[0];
+    double rr_new;
+    TRY(S.hip(blas_axpby(lo.prec, q, lo.prec, r, n, -a, 0.0, 1.0, 0.0, &red, S.st), "axpby"));
+    TRY(S.result(1, &rr_new));
+    const double bk = rr_new / rr;
+    void *ux[LQCD_MAX_SHIFTS + 1], *up[LQCD_MAX_SHIFTS + 1];
+    double ua[LQCD_MAX_SHIFTS + 1], uz[LQCD_MAX_SHIFTS + 1], ub[LQCD_MAX_SHIFTS + 1];
+    int k = 0;
+    for (int i = 0; i < ns; ++i) {
+      if (!active[i]) continue;
+      const double s = prm->shifts[i] - smin;
+      const double den = a * b_prev * (zp[i] - z[i]) + zp[i] * a_prev * (1.0 + s * a);
+      const double zn = z[i] * zp[i] * a_prev / den;
+      if (!std::isfinite(zn) || zn == 0 || !(den != 0))
+        return set_error(ctx, LQCD_ERR_BREAKDOWN, "multi-shift CG breakdown in the shift recurrence");
+      ux[k] = xs[i];
+      up[k] = ps[i];
+      ua[k] = a * zn / z[i];
+      uz[k] = zn;
+      ub[k] = bk * (zn / z[i]) * (zn / z[i]);
+      ++k;
+      zp[i] = z[i];
+      z[i] = zn;
+    }
+    // the base direction p = r + bk p
+    ux[k] = nullptr;
+    up[k] = p;
+    ua[k] = 0.0;
+    uz[k] = 1.0;
+    ub[k] = bk;
+    ++k;
+    TRY(S.hip(blas_multishift_update(lo.prec, ux, up, ua, uz, ub, k, r, n, S.st), "multi-shift update"));
+    a_prev = a;
+    b_prev = bk;
+    rr = rr_new;
+    ++it;
+    for (int i = 0; i < ns; ++i) {
+      if (!active[i]) continue;
+      res[i] = std::fabs(z[i]) * std::sqrt(rr) / bn;
+      if (res[i] <= prm->tol_sloppy) active[i] = false;
+    }
+    if (verbose()) fprintf(stderr, "multi-shift it %d |r|/|b| %.3e (base shift)\n", it, std::sqrt(rr) / bn);
+  }
+  inf.ms_iters = it;
+  // hand the solutions over in FP64 (before the refinements reuse the scratch)
+  for (int i = 0; i < ns; ++i) TRY(S.hip(blas_convert(lo.prec, xs[i], hi.prec, x[i], n, 1.0, S.st), "convert"));
+  TRY(S.hip(hipStreamSynchronize(S.st), "sync"));
+  inf.ms_seconds = elapsed(t0);
+
+  // Refinement of each x_i: reliable-update CG on the normal operator at mass
+  // sqrt(m^2 + sigma_i), starting from the multi-shift solution.
+  lqcd_status status = LQCD_OK;
+  for (int i = 0; i < ns && status == LQCD_OK; ++i) {
+    lqcd_operator oh = *op_hi, ol{};
+    oh.mass = std::sqrt(m2 + prm->shifts[i]);
+    if (op_sloppy) {
+      ol = *op_sloppy;
+      ol.mass = oh.mass;
+    }
+    lqcd_cg_params cg{};
+    cg.tol = prm->tol;
+    cg.max_iter = prm->max_iter;
+    cg.delta_reliable = prm->delta_reliable;
+    cg.kind = LQCD_CG_STAG_NORMAL;
+    status = lqcd_cg_solve(ctx, &oh, op_sloppy ? &ol : nullptr, &cg, x[i], b, &inf.shift[i], stream);
+  }
+  inf.seconds = elapsed(t0);
+  if (info) *info = inf;
+  return status;
+}

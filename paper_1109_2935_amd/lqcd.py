@@ -86,6 +86,19 @@ class lqcd_cg_params(ctypes.Structure):
                 ("record_count", ctypes.POINTER(ctypes.c_int32))]
 
 
+LQCD_MAX_SHIFTS = 16
+
+
+class lqcd_multishift_params(ctypes.Structure):
+    _fields_ = [("nshift", ctypes.c_int32), ("shifts", ctypes.c_double * LQCD_MAX_SHIFTS), ("tol", ctypes.c_double),
+                ("tol_sloppy", ctypes.c_double), ("max_iter", ctypes.c_int32), ("delta_reliable", ctypes.c_double)]
+
+
+class lqcd_multishift_info(ctypes.Structure):
+    _fields_ = [("ms_iters", ctypes.c_int32), ("ms_matvecs", ctypes.c_int32), ("ms_seconds", ctypes.c_double),
+                ("shift", lqcd_solve_info * LQCD_MAX_SHIFTS), ("seconds", ctypes.c_double)]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -110,6 +123,8 @@ _SIGNATURES = {
     "lqcd_gcr_solve": [_P, _OPP, _OPP, _OPP, ctypes.POINTER(lqcd_gcr_params), _P, _P,
                        ctypes.POINTER(lqcd_solve_info), _P],
     "lqcd_cg_solve": [_P, _OPP, _OPP, ctypes.POINTER(lqcd_cg_params), _P, _P, ctypes.POINTER(lqcd_solve_info), _P],
+    "lqcd_multishift_cg_solve": [_P, _OPP, _OPP, ctypes.POINTER(lqcd_multishift_params), ctypes.POINTER(_P), _P,
+                                 ctypes.POINTER(lqcd_multishift_info), _P],
     "lqcd_ptc_sizes": [ctypes.POINTER(lqcd_ptc_shape), ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
     "lqcd_ptc_pack": [_P, ctypes.POINTER(lqcd_ptc_shape), _P, _P, _P],
     "lqcd_ptc_apply": [_P, _OPP, ctypes.POINTER(lqcd_ptc_net), _P, _P, _P],
@@ -260,6 +275,18 @@ def lqcd_cg_solve(ctx, op_hi, op_sloppy, params, x, b, stream=None):
     info = lqcd_solve_info()
     st = lib().lqcd_cg_solve(ctx, ctypes.byref(op_hi), ctypes.byref(op_sloppy) if op_sloppy is not None else None,
                              ctypes.byref(params), _ptr(x), _ptr(b), ctypes.byref(info), _stream(stream))
+    if st not in (LQCD_OK, LQCD_ERR_NOT_CONVERGED):
+        _check(st, ctx)
+    return st, info
+
+
+def lqcd_multishift_cg_solve(ctx, op_hi, op_sloppy, params, xs, b, stream=None):
+    """xs: sequence of params.nshift packed even fields of op_hi (outputs)."""
+    info = lqcd_multishift_info()
+    ptrs = (_P * max(1, len(xs)))(*[_ptr(x) for x in xs])
+    st = lib().lqcd_multishift_cg_solve(ctx, ctypes.byref(op_hi),
+                                        ctypes.byref(op_sloppy) if op_sloppy is not None else None,
+                                        ctypes.byref(params), ptrs, _ptr(b), ctypes.byref(info), _stream(stream))
     if st not in (LQCD_OK, LQCD_ERR_NOT_CONVERGED):
         _check(st, ctx)
     return st, info

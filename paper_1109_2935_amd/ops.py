@@ -126,6 +126,15 @@ def cg_params(tol=1e-10, max_iter=10000, delta_reliable=0.1, kind=L.LQCD_CG_CGNE
     return p
 
 
+def multishift_params(shifts, tol=1e-10, tol_sloppy=1e-6, max_iter=20000, delta_reliable=0.1):
+    p = L.lqcd_multishift_params()
+    p.nshift = len(shifts)
+    for i, s in enumerate(shifts):
+        p.shifts[i] = float(s)
+    p.tol, p.tol_sloppy, p.max_iter, p.delta_reliable = tol, tol_sloppy, max_iter, delta_reliable
+    return p
+
+
 def schwarz_params(block, mr_steps=8):
     p = L.lqcd_schwarz_params()
     p.block[:] = [int(b) for b in block]
