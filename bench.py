@@ -229,7 +229,40 @@ def staggered_workload(args, torch, L, ops, ctx):
         out["cg_" + name] = {"status": st, "iters": info.iters, "updates": info.restarts,
                              "seconds": round(info.seconds, 4), "true_residual": info.true_residual}
         log("staggered CG %s: %d it, %.3f s, res %.2e" % (name, info.iters, info.seconds, info.true_residual))
+    out["multishift"] = multishift_workload(L, ops, ctx, hi, inst[(1, 12)], b, mass)
     return out
+
+
+def multishift_workload(L, ops, ctx, hi, lo, b, mass):
+    """Eq. (4) for 8 shifts (sigma = 0 and 1e-4 .. 0.4 geometric) on 48^3x96:
+    the multi-shift CG in FP32 then reliable-update refinement of each solution
+    (Section VIII-B), against one mixed-precision CG per shift in sequence."""
+    import math
+    shifts = [0.0] + [1e-4 * 4 ** k for k in range(7)]
+    xs = [hi.spinor() for _ in shifts]
+    st, info = L.lqcd_multishift_cg_solve(ctx, hi.op, lo.op, ops.multishift_params(shifts, tol=1e-10, tol_sloppy=1e-8),
+                                          xs, b)
+    assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+    ref_iters = [info.shift[i].iters for i in range(len(shifts))]
+    worst = max(info.shift[i].true_residual for i in range(len(shifts)))
+    # the same systems one at a time: mixed-precision CG at mass sqrt(m^2 + sigma)
+    seq_seconds, seq_iters = 0.0, []
+    for s_ in shifts:
+        oh = L.lqcd_operator.from_buffer_copy(hi.op)
+        ol = L.lqcd_operator.from_buffer_copy(lo.op)
+        oh.mass = ol.mass = math.sqrt(mass * mass + s_)
+        x = hi.spinor()
+        st, ci = L.lqcd_cg_solve(ctx, oh, ol, ops.cg_params(1e-10, 20000, 0.1, L.LQCD_CG_STAG_NORMAL), x, b)
+        assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+        seq_seconds += ci.seconds
+        seq_iters.append(ci.iters)
+    log("multi-shift (%d shifts): FP32 stage %d it %.3f s, refinements %s it, total %.3f s (worst residual %.2e); "
+        "sequential mixed CG %.3f s (%s it)" % (len(shifts), info.ms_iters, info.ms_seconds, ref_iters, info.seconds,
+                                               worst, seq_seconds, seq_iters))
+    return {"shifts": shifts, "seconds": round(info.seconds, 4), "ms_iters": info.ms_iters,
+            "ms_seconds": round(info.ms_seconds, 4), "refine_iters": ref_iters, "worst_true_residual": worst,
+            "sequential_cg_seconds": round(seq_seconds, 4), "sequential_cg_iters": seq_iters,
+            "speedup_vs_sequential": round(seq_seconds / info.seconds, 2)}
 
 
 def batched_workload(args, torch, L, ops, ctx):

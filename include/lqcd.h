@@ -381,7 +381,8 @@ typedef struct {
   int32_t nshift;                 /* 1 .. LQCD_MAX_SHIFTS */
   double shifts[LQCD_MAX_SHIFTS]; /* sigma_i, with m^2 + sigma_i > 0 */
   double tol;                     /* final ||b - (N_e + sigma_i) x_i|| <= tol ||b||, recomputed in FP64 */
-  double tol_sloppy;              /* multi-shift stage, per shift (e.g. 1e-6 in FP32) */
+  double tol_sloppy;              /* multi-shift stage, per shift (in FP32, 1e-8: about where the
+                                     refinements stop getting shorter) */
   int32_t max_iter;               /* per stage and per refinement */
   double delta_reliable;          /* of the refinements (see lqcd_cg_params) */
 } lqcd_multishift_params;

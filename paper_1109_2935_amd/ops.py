@@ -126,7 +126,7 @@ def cg_params(tol=1e-10, max_iter=10000, delta_reliable=0.1, kind=L.LQCD_CG_CGNE
     return p
 
 
-def multishift_params(shifts, tol=1e-10, tol_sloppy=1e-6, max_iter=20000, delta_reliable=0.1):
+def multishift_params(shifts, tol=1e-10, tol_sloppy=1e-8, max_iter=20000, delta_reliable=0.1):
     p = L.lqcd_multishift_params()
     p.nshift = len(shifts)
     for i, s in enumerate(shifts):

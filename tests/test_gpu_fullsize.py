@@ -120,3 +120,33 @@ def test_staggered_cg_full_48x96(ctx):
     res = np.linalg.norm(b - op.normal_even(xs)) / np.linalg.norm(b)
     say("oracle residual %.3e (%.1fs)" % (res, time.time() - t))
     assert res <= 1.05e-10
+
+
+def test_staggered_multishift_full_48x96(ctx):
+    """Eq. (4) with three shifts at the benchmark's size: FP32 multi-shift
+    stage, FP64-verified refinements; the oracle recomputes each shifted
+    system's residual over all even sites."""
+    dims, mass = (48, 48, 48, 96), 0.01
+    U = synth.gauge_field(dims, 0.2, 3001)
+    fat = synth.fat_links(dims, U, seed=3003)
+    chi = synth.gaussian_spinor(dims, 3002, inner=(3,))
+    Ud, Fd = torch.from_numpy(U).cuda(), torch.from_numpy(fat).cuda()
+    hi = ops.staggered(ctx, fat, U, dims, mass, 0, 18, U_device=Ud, fat_device=Fd)
+    lo = ops.staggered(ctx, fat, U, dims, mass, 1, 12, U_device=Ud, fat_device=Fd)
+    del Ud, Fd
+    even = oracle.parity_mask(dims, 0)
+    b = np.where(even[..., None], chi, 0)
+    bp = hi.import_spinor(b, 0)
+    shifts = (0.0, 1e-3, 0.1)
+    xs = [hi.spinor() for _ in shifts]
+    st, info = L.lqcd_multishift_cg_solve(ctx, hi.op, lo.op, ops.multishift_params(shifts), xs, bp)
+    assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+    say("multi-shift %d it, refinements %s, %.3fs" % (info.ms_iters, [info.shift[i].iters for i in range(3)],
+                                                       info.seconds))
+    op = oracle.Staggered(dims, fat, oracle.long_links(dims, U), mass)
+    bn = np.linalg.norm(b)
+    for i, s in enumerate(shifts):
+        x = np_of(hi.export_spinor(xs[i], 0))
+        res = np.linalg.norm(b - op.normal_even(x) - s * np.where(even[..., None], x, 0)) / bn
+        say("shift %g: oracle residual %.3e" % (s, res))
+        assert res <= 1.05e-10

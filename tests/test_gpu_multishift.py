@@ -50,7 +50,7 @@ def test_multishift_parity(ctx, sloppy, dims, shifts):
     b = on_parity(chi, ref.even)
     bp = hi.import_spinor(b, 0)
     xs = [hi.spinor() for _ in shifts]
-    prm = ops.multishift_params(shifts, tol=1e-10, tol_sloppy=1e-6 if sloppy else 1e-10)
+    prm = ops.multishift_params(shifts, tol=1e-10, tol_sloppy=1e-8 if sloppy else 1e-10)
     st, info = L.lqcd_multishift_cg_solve(ctx, hi.op, lo.op if lo else None, prm, xs, bp)
     assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
     assert info.ms_iters > 0 and info.ms_matvecs == info.ms_iters
