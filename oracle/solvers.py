@@ -1,8 +1,9 @@
 """Textbook FP64 solvers of the oracle (test infrastructure only).
 
 Written from the paper (Babich et al., SC11): CG and CG on the normal
-equations (Section III-A), the multi-shift CG for eq. (4) (Section III-A; the
-method is cited there, not printed), minimal residual for the Schwarz blocks
+equations (Section III-A), BiCGstab (Section III-A cites it; the paper's
+baseline for GCR-DD, Section IX), the multi-shift CG for eq. (4) (Section
+III-A; the method is cited there, not printed), minimal residual for the Schwarz blocks
 and the additive Schwarz preconditioner (Section III-B, Section VIII-A), and
 the GCR-DD solver of Algorithm 1 (Section VIII-A), all in FP64 with numpy
 inner products <a,b> = sum conj(a) b. Every function takes the operator as a
@@ -40,6 +41,46 @@ def cg(apply_A, b, tol=1e-10, maxiter=10000, x0=None):
         rr = rr_new
         it += 1
         hist.append(np.sqrt(rr))
+    return x, it, hist
+
+
+def bicgstab(apply_A, b, tol=1e-10, maxiter=10000, x0=None):
+    """BiCGstab (van der Vorst) for a general non-singular A, shadow residual
+    r^ = r_0:
+        rho' = <r^, r>,  beta = (rho' / rho) (alpha / omega),
+        p = r + beta (p - omega v),  v = A p,  alpha = rho' / <r^, v>,
+        s = r - alpha v,  t = A s,  omega = <t, s> / <t, t>,
+        x += alpha p + omega s,  r = s - omega t,
+    starting from rho = alpha = omega = 1, p = v = 0. Stops when the
+    recursively updated ||r|| (or ||s||, after the half step) <= tol ||b||.
+    Returns (x, iterations, residual-norm history)."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - apply_A(x) if x0 is not None else b.copy()
+    rh = r.copy()
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    rho = alpha = omega = 1.0
+    bn = norm(b)
+    hist = [norm(r)]
+    it = 0
+    while hist[-1] > tol * bn and it < maxiter:
+        rho_new = dot(rh, r)
+        beta = (rho_new / rho) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        v = apply_A(p)
+        alpha = rho_new / dot(rh, v)
+        s_ = r - alpha * v
+        it += 1
+        if norm(s_) <= tol * bn:
+            x = x + alpha * p
+            hist.append(norm(s_))
+            break
+        t = apply_A(s_)
+        omega = dot(t, s_) / dot(t, t)
+        x = x + alpha * p + omega * s_
+        r = s_ - omega * t
+        rho = rho_new
+        hist.append(norm(r))
     return x, it, hist
 
 
