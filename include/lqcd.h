@@ -400,6 +400,38 @@ lqcd_status lqcd_multishift_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
                                      const lqcd_multishift_params *params, void *const *x, const void *b,
                                      lqcd_multishift_info *info, lqcd_stream stream);
 
+/*
+ * Mixed-precision BiCGstab (van der Vorst; Section III-A names it as the usual
+ * non-Hermitian method for Wilson-clover, and Section IX compares GCR-DD with
+ * its mixed-precision form): solves M x = b for the full Wilson-clover lattice
+ * through the even-odd system Mhat x_e = bhat (the same reduction and
+ * reconstruction as lqcd_gcr_solve). The iteration runs in op_sloppy's
+ * precision (FP32, FP16 or BF16; NULL: FP64), its shadow residual the first
+ * residual. Reliable updates (residual replacement): when ||r|| falls below
+ * delta_reliable times its largest value since the previous update, or the
+ * iterated residual claims convergence, the sloppy solution is added to the
+ * FP64 x_e and r = bhat - Mhat x_e is recomputed with op_hi; the search
+ * directions and the shadow residual are kept. If the half-step residual s
+ * meets tol but the recomputed one does not, or <rhat, v> vanishes, the
+ * iteration restarts with the current residual as the new shadow residual.
+ * x_full (in: initial guess, out: solution) and b_full are packed
+ * LQCD_FIELD_SPINOR_FULL fields of op_hi (FP64); op_sloppy: same system and
+ * tile. info: iters (BiCGstab steps, two applications of Mhat each),
+ * restarts (reliable updates), matvecs, true_residual (FP64, full lattice),
+ * seconds; the other fields zero. Returns LQCD_ERR_NOT_CONVERGED (best
+ * iterate in x_full, info filled) at max_iter, LQCD_ERR_BREAKDOWN if a
+ * restart breaks down again before any progress.
+ */
+typedef struct {
+  double tol;            /* stop when ||b - M x|| <= tol ||b|| (FP64) */
+  int32_t max_iter;      /* BiCGstab steps */
+  double delta_reliable; /* 0 <= delta < 1 (0: updates only at apparent convergence) */
+} lqcd_bicgstab_params;
+
+lqcd_status lqcd_bicgstab_solve(lqcd_context *ctx, const lqcd_operator *op_hi, const lqcd_operator *op_sloppy,
+                                const lqcd_bicgstab_params *params, void *x_full, const void *b_full,
+                                lqcd_solve_info *info, lqcd_stream stream);
+
 /* ---------------------------------------------------------------------- */
 /* learned preconditioner                                                  */
 

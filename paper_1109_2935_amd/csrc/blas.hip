@@ -277,6 +277,25 @@ __global__ void __launch_bounds__(kBT) multi_axpy_acc_kernel(SX *x, VecPack p, s
   }
 }
 
+// BiCGstab search direction: p = r + beta (p - omega v), i.e.
+// p = r + beta p + c v with c = -beta omega (complex coefficients).
+template <typename S>
+__global__ void __launch_bounds__(kBT) bicgstab_dir_kernel(const S *r, S *p, const S *v, size_t nq, double br,
+                                                          double bi, double cr, double ci) {
+  for (size_t i = (size_t)blockIdx.x * kBT + threadIdx.x; i < nq; i += (size_t)gridDim.x * kBT) {
+    double rv[4], pv[4], vv[4], o[4];
+    ld4(r, i, rv);
+    ld4(p, i, pv);
+    ld4(v, i, vv);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      o[2 * c] = rv[2 * c] + br * pv[2 * c] - bi * pv[2 * c + 1] + cr * vv[2 * c] - ci * vv[2 * c + 1];
+      o[2 * c + 1] = rv[2 * c + 1] + br * pv[2 * c + 1] + bi * pv[2 * c] + cr * vv[2 * c + 1] + ci * vv[2 * c];
+    }
+    st4(p, i, o);
+  }
+}
+
 // Multi-shift CG update (eq. (4)): for every shifted system j,
 //   x_j += a_j p_j (skipped where x_j is NULL), then p_j = z_j r + b_j p_j,
 // all from one read of r. Real coefficients (Hermitian positive-definite
@@ -445,6 +464,16 @@ hipError_t blas_multi_axpy_acc(int px, void *x, int pp, const void *const *p, co
   const int g = grid_for(nq, 4096);
   return dispatch2(px, pp, [&](auto t1, auto t2) -> hipError_t {
     hipLaunchKernelGGL((multi_axpy_acc_kernel<T1, T2>), dim3(g), dim3(kBT), 0, st, (T1 *)x, pk, nq);
+    return hipGetLastError();});
+}
+
+hipError_t blas_bicgstab_dir(int prec, const void *r, void *p, const void *v, size_t n, double br, double bi,
+                             double cr, double ci, hipStream_t st) {
+  const size_t nq = n / 2;
+  const int g = grid_for(nq, 4096);
+  return dispatch1(prec, [&](auto t1) -> hipError_t {
+    hipLaunchKernelGGL((bicgstab_dir_kernel<T1>), dim3(g), dim3(kBT), 0, st, (const T1 *)r, (T1 *)p, (const T1 *)v,
+                       nq, br, bi, cr, ci);
     return hipGetLastError();});
 }
 

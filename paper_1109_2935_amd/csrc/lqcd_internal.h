@@ -173,10 +173,13 @@ hipError_t blas_gcr_update(int p, void *z, void *r, size_t n, double inv_gamma, 
 // x (precision px) += sum_i chi_i p_i (precision pp)
 hipError_t blas_multi_axpy_acc(int px, void *x, int pp, const void *const *p, const double *chi, int k, size_t n,
                                hipStream_t st);
-// CG: x += a p; r -= a q; result ||r||^2 (x, p in px; r, q in pr)
 // multi-shift CG: x_j += a_j p_j (x_j may be NULL), p_j = z_j r + b_j p_j, k <= 17
 hipError_t blas_multishift_update(int prec, void *const *x, void *const *p, const double *a, const double *z,
                                   const double *b, int k, const void *r, size_t n, hipStream_t st);
+// BiCGstab: p = r + b p + c v (b, c complex), all of precision prec
+hipError_t blas_bicgstab_dir(int prec, const void *r, void *p, const void *v, size_t n, double br, double bi,
+                             double cr, double ci, hipStream_t st);
+// CG: x += a p; r -= a q; result ||r||^2 (x, p in px; r, q in pr)
 hipError_t blas_cg_update(int px, void *x, const void *p, int pr, void *r, const void *q, size_t n, double a,
                           const RedScratch &red, hipStream_t st);
 

@@ -694,3 +694,236 @@ extern "C" lqcd_status lqcd_multishift_cg_solve(lqcd_context *ctx, const lqcd_op
   if (info) *info = inf;
   return status;
 }
+
+// ---------------------------------------------------------------------------
+// Mixed-precision BiCGstab with reliable updates (Section III-A; the baseline
+// of the GCR-DD comparison in Section IX)
+
+extern "C" lqcd_status lqcd_bicgstab_solve(lqcd_context *ctx, const lqcd_operator *op_hi,
+                                           const lqcd_operator *op_sloppy, const lqcd_bicgstab_params *prm,
+                                           void *x_full, const void *b_full, lqcd_solve_info *info,
+                                           lqcd_stream stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!ctx) return set_error(ctx, LQCD_ERR_INVALID_ARG, "context is NULL");
+  if (!prm) return set_error(ctx, LQCD_ERR_INVALID_ARG, "params are NULL");
+  OpInfo hi, lo;
+  TRY(check_op(ctx, op_hi, &hi));
+  if (op_hi->action != LQCD_WILSON_CLOVER)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "BiCGstab solves Wilson-clover systems");
+  if (hi.prec != LQCD_F64) return set_error(ctx, LQCD_ERR_UNSUPPORTED, "op_hi must be FP64");
+  TRY(check_fields_internal(ctx, op_hi));
+  if (op_sloppy) {
+    TRY(check_op(ctx, op_sloppy, &lo));
+    if (!same_system(op_hi, op_sloppy)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "op_sloppy describes another system");
+    TRY(check_fields_internal(ctx, op_sloppy));
+  } else {
+    lo = hi;
+  }
+  if (!(prm->tol > 0) || prm->max_iter < 1 || prm->delta_reliable < 0 || prm->delta_reliable >= 1)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "need tol > 0, max_iter >= 1, 0 <= delta_reliable < 1");
+  if (!x_full || !b_full || ((uintptr_t)x_full & 15) || ((uintptr_t)b_full & 15))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
+
+  Solver S{ctx, (hipStream_t)stream, kSlotSolver};
+  const size_t n = ncomplex(hi);
+  const bool mixed = lo.prec != hi.prec;
+  const bool half = lo.prec == LQCD_F16 || lo.prec == LQCD_BF16;
+  const double delta = prm->delta_reliable;
+  void *bhat, *r, *y, *tmp_hi, *rs, *rh, *xs, *p, *v, *t, *tmp_lo;
+  TRY(S.vec(hi.spinor_bytes, &bhat));
+  TRY(S.vec(hi.spinor_bytes, &r));
+  TRY(S.vec(hi.spinor_bytes, &y));
+  TRY(S.vec(hi.spinor_bytes, &tmp_hi));
+  TRY(S.vec(lo.spinor_bytes, &rs));  // iterated residual; holds s after the half step
+  TRY(S.vec(lo.spinor_bytes, &rh));  // shadow residual
+  TRY(S.vec(lo.spinor_bytes, &xs));  // sloppy solution since the last reliable update
+  TRY(S.vec(lo.spinor_bytes, &p));
+  TRY(S.vec(lo.spinor_bytes, &v));
+  TRY(S.vec(lo.spinor_bytes, &t));
+  TRY(S.vec(lo.spinor_bytes, &tmp_lo));
+  RedScratch red = S.red();
+  lqcd_solve_info inf{};
+  void *xe = x_full;
+
+  double bn2;
+  TRY(S.hip(blas_norm2(hi.prec, b_full, 2 * n, red, S.st), "norm"));
+  TRY(S.result(1, &bn2));
+  if (!std::isfinite(bn2)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "source contains non-finite values");
+  if (bn2 == 0) {
+    TRY(S.hip(hipMemsetAsync(x_full, 0, 2 * hi.spinor_bytes, S.st), "memset"));
+    TRY(S.hip(hipStreamSynchronize(S.st), "sync"));
+    inf.seconds = elapsed(t0);
+    if (info) *info = inf;
+    return LQCD_OK;
+  }
+  const double bn = std::sqrt(bn2);
+  const double stop = prm->tol * prm->tol * bn2;
+  TRY(wilson_schur_source(S, hi, bhat, b_full, tmp_hi));
+
+  // r = bhat - Mhat x_e in FP64; returns ||r||^2
+  auto true_residual = [&](double *rr) -> lqcd_status {
+    TRY(schur_apply(ctx, hi, hi.g, y, xe, tmp_hi, 0, nullptr, S.st));
+    TRY(S.hip(hipMemcpyAsync(r, bhat, hi.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
+    TRY(S.hip(blas_axpby(hi.prec, y, hi.prec, r, n, -1.0, 0.0, 1.0, 0.0, &red, S.st), "axpby"));
+    return S.result(1, rr);
+  };
+  auto cdot = [&](const void *a, const void *b, cd *out) -> lqcd_status {
+    double d[2];
+    TRY(S.hip(blas_cdot(lo.prec, a, b, n, red, S.st), "dot"));
+    TRY(S.result(2, d));
+    *out = cd(d[0], d[1]);
+    return LQCD_OK;
+  };
+
+  // The sloppy vectors live in units of sc times the FP64 ones (sc != 1 only
+  // for 16-bit storage, which needs O(1) entries); every recurrence of
+  // BiCGstab is homogeneous in that scale except rho, which carries it.
+  double rr_true;
+  TRY(true_residual(&rr_true));
+  double sc = half ? unit_rms_scale(std::sqrt(rr_true), 2 * n) : 1.0;
+  TRY(S.hip(blas_convert(hi.prec, r, lo.prec, rs, n, sc, S.st), "convert"));
+  TRY(S.hip(hipMemsetAsync(xs, 0, lo.spinor_bytes, S.st), "memset"));
+
+  // (re)start: shadow residual = current residual, p = r
+  cd rho_new, rho(1, 0), alpha(1, 0), omega(1, 0);
+  bool fresh = true;
+  auto restart_shadow = [&]() -> lqcd_status {
+    TRY(S.hip(hipMemcpyAsync(rh, rs, lo.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
+    TRY(cdot(rh, rs, &rho_new));
+    fresh = true;
+    return LQCD_OK;
+  };
+  TRY(restart_shadow());
+  double maxrr = rr_true;
+  bool converged = rr_true <= stop;
+  bool progress_since_restart = true;
+  int shadow_restarts = 0;
+  lqcd_status status = LQCD_OK;
+
+  // fold the sloppy solution into x_e, recompute r in FP64 and replace the
+  // iterated residual with it (rescaling p, v and rho to the new units)
+  auto reliable_update = [&](double *rr_out) -> lqcd_status {
+    TRY(S.hip(blas_axpby(lo.prec, xs, hi.prec, xe, n, 1.0 / sc, 0.0, 1.0, 0.0, nullptr, S.st), "x update"));
+    TRY(true_residual(rr_out));
+    inf.restarts++;
+    const double sc_new = half ? unit_rms_scale(std::sqrt(*rr_out), 2 * n) : 1.0;
+    TRY(S.hip(blas_convert(hi.prec, r, lo.prec, rs, n, sc_new, S.st), "convert"));
+    TRY(S.hip(hipMemsetAsync(xs, 0, lo.spinor_bytes, S.st), "memset"));
+    if (sc_new != sc) {
+      const double f = sc_new / sc;
+      TRY(S.hip(blas_convert(lo.prec, p, lo.prec, p, n, f, S.st), "rescale"));
+      TRY(S.hip(blas_convert(lo.prec, v, lo.prec, v, n, f, S.st), "rescale"));
+      rho *= f;
+    }
+    sc = sc_new;
+    TRY(cdot(rh, rs, &rho_new));
+    maxrr = *rr_out;
+    if (verbose())
+      fprintf(stderr, "bicgstab reliable update %d true |r|/|b| %.3e\n", inf.restarts, std::sqrt(*rr_out) / bn);
+    return LQCD_OK;
+  };
+
+  int it = 0;
+  while (!converged && it < prm->max_iter) {
+    if (fresh) {
+      TRY(S.hip(hipMemcpyAsync(p, rs, lo.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
+      fresh = false;
+    } else {
+      const cd beta = (rho_new / rho) * (alpha / omega);
+      const cd c = -beta * omega;
+      TRY(S.hip(blas_bicgstab_dir(lo.prec, rs, p, v, n, beta.real(), beta.imag(), c.real(), c.imag(), S.st), "dir"));
+    }
+    rho = rho_new;
+    TRY(schur_apply(ctx, lo, lo.g, v, p, tmp_lo, 0, nullptr, S.st));
+    inf.matvecs++;
+    cd rhv;
+    TRY(cdot(rh, v, &rhv));
+    ++it;
+    if (!(std::abs(rhv) > 0) || !std::isfinite(std::abs(rhv)) || !(std::abs(rho) > 0)) {
+      // <rhat, v> = 0 (or rho = 0): fold in what we have and take a new shadow
+      if (!progress_since_restart) {
+        status = set_error(ctx, LQCD_ERR_BREAKDOWN, "BiCGstab breakdown: <rhat, A p> = 0 after a restart");
+        break;
+      }
+      double rrt;
+      TRY(reliable_update(&rrt));
+      if (rrt <= stop) { converged = true; break; }
+      TRY(restart_shadow());
+      ++shadow_restarts;
+      progress_since_restart = false;
+      continue;
+    }
+    alpha = rho / rhv;
+    // s = r - alpha v (in place of r)
+    double ss;
+    TRY(S.hip(blas_axpby(lo.prec, v, lo.prec, rs, n, -alpha.real(), -alpha.imag(), 1.0, 0.0, &red, S.st), "axpby"));
+    TRY(S.result(1, &ss));
+    if (ss / (sc * sc) <= stop) {
+      // converged at the half step: x += alpha p, then check in FP64
+      const double chi[2] = {alpha.real(), alpha.imag()};
+      const void *pp[1] = {p};
+      TRY(S.hip(blas_multi_axpy_acc(lo.prec, xs, lo.prec, pp, chi, 1, n, S.st), "x update"));
+      double rrt;
+      TRY(reliable_update(&rrt));
+      if (rrt <= stop) { converged = true; break; }
+      TRY(restart_shadow());
+      ++shadow_restarts;
+      continue;
+    }
+    TRY(schur_apply(ctx, lo, lo.g, t, rs, tmp_lo, 0, nullptr, S.st));
+    inf.matvecs++;
+    double d[4];  // <t, t>, <s, t>
+    {
+      const void *z[2] = {t, rs};
+      TRY(S.hip(blas_multi_cdot(lo.prec, z, 2, t, n, red, S.st), "dots"));
+      TRY(S.result(4, d));
+    }
+    if (!(d[0] > 0) || !std::isfinite(d[0])) {
+      status = set_error(ctx, LQCD_ERR_BREAKDOWN, "BiCGstab breakdown: A s = 0 with s != 0");
+      break;
+    }
+    omega = std::conj(cd(d[2], d[3])) / d[0];
+    {
+      const double chi[4] = {alpha.real(), alpha.imag(), omega.real(), omega.imag()};
+      const void *pp[2] = {p, rs};
+      TRY(S.hip(blas_multi_axpy_acc(lo.prec, xs, lo.prec, pp, chi, 2, n, S.st), "x update"));
+    }
+    // r = s - omega t; ||r||^2 and <r, rhat>
+    double e[3];
+    {
+      const void *z[1] = {t};
+      const double w[2] = {omega.real(), omega.imag()};
+      TRY(S.hip(blas_multi_caxpy_dots(lo.prec, z, w, 1, rs, rh, n, red, S.st), "r update"));
+      TRY(S.result(3, e));
+    }
+    rho_new = std::conj(cd(e[1], e[2]));
+    const double rr_now = e[0] / (sc * sc);
+    progress_since_restart = true;
+    if (verbose()) fprintf(stderr, "bicgstab it %d |r|/|b| %.3e\n", it, std::sqrt(rr_now) / bn);
+    if (!std::isfinite(rr_now)) {
+      status = set_error(ctx, LQCD_ERR_BREAKDOWN, "BiCGstab: the iterated residual is not finite");
+      break;
+    }
+    if (rr_now <= stop || (mixed && rr_now < delta * delta * maxrr)) {
+      double rrt;
+      TRY(reliable_update(&rrt));
+      if (rrt <= stop) { converged = true; break; }
+    } else {
+      maxrr = std::max(maxrr, rr_now);
+    }
+  }
+  if (!converged) {
+    // fold in the last sloppy correction (also after a breakdown: xs is valid)
+    TRY(S.hip(blas_axpby(lo.prec, xs, hi.prec, xe, n, 1.0 / sc, 0.0, 1.0, 0.0, nullptr, S.st), "x update"));
+  }
+  if (verbose()) fprintf(stderr, "bicgstab: %d steps, %d shadow restarts\n", it, shadow_restarts);
+  double tres;
+  TRY(wilson_finish(S, hi, x_full, b_full, tmp_hi, y, bn, &tres));
+  inf.iters = it;
+  inf.true_residual = tres;
+  inf.seconds = elapsed(t0);
+  if (info) *info = inf;
+  if (status != LQCD_OK) return status;
+  if (!converged) return set_error(ctx, LQCD_ERR_NOT_CONVERGED, "BiCGstab reached max_iter");
+  return LQCD_OK;
+}

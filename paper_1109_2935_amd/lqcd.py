@@ -94,6 +94,10 @@ class lqcd_multishift_params(ctypes.Structure):
                 ("tol_sloppy", ctypes.c_double), ("max_iter", ctypes.c_int32), ("delta_reliable", ctypes.c_double)]
 
 
+class lqcd_bicgstab_params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("delta_reliable", ctypes.c_double)]
+
+
 class lqcd_multishift_info(ctypes.Structure):
     _fields_ = [("ms_iters", ctypes.c_int32), ("ms_matvecs", ctypes.c_int32), ("ms_seconds", ctypes.c_double),
                 ("shift", lqcd_solve_info * LQCD_MAX_SHIFTS), ("seconds", ctypes.c_double)]
@@ -125,6 +129,8 @@ _SIGNATURES = {
     "lqcd_cg_solve": [_P, _OPP, _OPP, ctypes.POINTER(lqcd_cg_params), _P, _P, ctypes.POINTER(lqcd_solve_info), _P],
     "lqcd_multishift_cg_solve": [_P, _OPP, _OPP, ctypes.POINTER(lqcd_multishift_params), ctypes.POINTER(_P), _P,
                                  ctypes.POINTER(lqcd_multishift_info), _P],
+    "lqcd_bicgstab_solve": [_P, _OPP, _OPP, ctypes.POINTER(lqcd_bicgstab_params), _P, _P,
+                            ctypes.POINTER(lqcd_solve_info), _P],
     "lqcd_ptc_sizes": [ctypes.POINTER(lqcd_ptc_shape), ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
     "lqcd_ptc_pack": [_P, ctypes.POINTER(lqcd_ptc_shape), _P, _P, _P],
     "lqcd_ptc_apply": [_P, _OPP, ctypes.POINTER(lqcd_ptc_net), _P, _P, _P],
@@ -287,6 +293,17 @@ def lqcd_multishift_cg_solve(ctx, op_hi, op_sloppy, params, xs, b, stream=None):
     st = lib().lqcd_multishift_cg_solve(ctx, ctypes.byref(op_hi),
                                         ctypes.byref(op_sloppy) if op_sloppy is not None else None,
                                         ctypes.byref(params), ptrs, _ptr(b), ctypes.byref(info), _stream(stream))
+    if st not in (LQCD_OK, LQCD_ERR_NOT_CONVERGED):
+        _check(st, ctx)
+    return st, info
+
+
+def lqcd_bicgstab_solve(ctx, op_hi, op_sloppy, params, x_full, b_full, stream=None):
+    info = lqcd_solve_info()
+    st = lib().lqcd_bicgstab_solve(ctx, ctypes.byref(op_hi),
+                                   ctypes.byref(op_sloppy) if op_sloppy is not None else None,
+                                   ctypes.byref(params), _ptr(x_full), _ptr(b_full), ctypes.byref(info),
+                                   _stream(stream))
     if st not in (LQCD_OK, LQCD_ERR_NOT_CONVERGED):
         _check(st, ctx)
     return st, info

@@ -135,6 +135,12 @@ def multishift_params(shifts, tol=1e-10, tol_sloppy=1e-8, max_iter=20000, delta_
     return p
 
 
+def bicgstab_params(tol=1e-10, max_iter=20000, delta_reliable=0.1):
+    p = L.lqcd_bicgstab_params()
+    p.tol, p.max_iter, p.delta_reliable = tol, max_iter, delta_reliable
+    return p
+
+
 def schwarz_params(block, mr_steps=8):
     p = L.lqcd_schwarz_params()
     p.block[:] = [int(b) for b in block]

@@ -30,6 +30,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.lqcd_gcr_params) == 8 + 4 + 4 + 8 + 4 + 4 + 20 + 4 + 8
     assert ctypes.sizeof(L.lqcd_ptc_net) == 40 + 8
     assert ctypes.sizeof(L.lqcd_cg_params) == 8 + 4 + 4 + 8 + 4 + 4 + 3 * 8 + 4 + 4 + 8
+    assert ctypes.sizeof(L.lqcd_bicgstab_params) == 8 + 8 + 8
     # int + padding, 16 doubles, 2 doubles, int + padding, double
     assert ctypes.sizeof(L.lqcd_multishift_params) == 8 + 16 * 8 + 2 * 8 + 8 + 8
     # 2 ints, double, 16 solve infos, double

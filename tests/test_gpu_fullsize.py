@@ -93,6 +93,26 @@ def test_gcr_dd_full_32x64(ctx):
     assert res <= 1.05e-10
 
 
+@pytest.mark.parametrize("sprec", [1, 2])
+def test_bicgstab_full_32x64(ctx, sprec):
+    """Mixed-precision BiCGstab on the same system: FP32 or FP16 sloppy
+    iterations (recon 12, the stencil tiling), FP64 reliable updates; the
+    oracle recomputes ||b - M x|| / ||b|| in FP64."""
+    dims, U, b, Ud = wilson_fields()
+    o = {p: ops.wilson_clover(ctx, U, dims, 0.124, 1.0, p, r, tile=STENCIL_TILE, U_device=Ud)
+         for p, r in ((0, 18), (sprec, 12))}
+    x = o[0].spinor(full=True)
+    st, info = L.lqcd_bicgstab_solve(ctx, o[0].op, o[sprec].op, ops.bicgstab_params(1e-10, 5000, 0.1), x,
+                                     o[0].import_spinor(b, -1))
+    assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+    say("BiCGstab sloppy %d: %d steps %d updates %.3fs" % (sprec, info.iters, info.restarts, info.seconds))
+    xs = np_of(o[0].export_spinor(x, -1))
+    M = oracle.WilsonClover(dims, U, 0.124, 1.0, bc_t=-1)
+    res = np.linalg.norm(b - M.M(xs)) / np.linalg.norm(b)
+    say("oracle residual %.3e" % res)
+    assert res <= 1.05e-10
+
+
 def test_staggered_cg_full_48x96(ctx):
     """Reliable-update CG on N_e = m^2 - D_eo D_oe/4, FP32 sloppy, FP64 updates,
     to 1e-10; the oracle recomputes the residual over all even sites."""
