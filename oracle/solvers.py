@@ -3,8 +3,10 @@
 Written from the paper (Babich et al., SC11): CG and CG on the normal
 equations (Section III-A), BiCGstab (Section III-A cites it; the paper's
 baseline for GCR-DD, Section IX), the multi-shift CG for eq. (4) (Section
-III-A; the method is cited there, not printed), minimal residual for the Schwarz blocks
-and the additive Schwarz preconditioner (Section III-B, Section VIII-A), and
+III-A; the method is cited there, not printed), minimal residual for the Schwarz blocks,
+the additive Schwarz preconditioner (Section III-B, Section VIII-A) and its
+multiplicative form over two block colours (Section III-B; Section X names
+multiplicative and overlapping Schwarz as the next step), and
 the GCR-DD solver of Algorithm 1 (Section VIII-A), all in FP64 with numpy
 inner products <a,b> = sum conj(a) b. Every function takes the operator as a
 callable.
@@ -206,6 +208,39 @@ def schwarz(op, r, block, nsteps):
     from . import block_labels
     labels = block_labels(op.dims, block)
     return mr_blocks(lambda v: op.schur(v, block=block), r, nsteps, labels)
+
+
+def block_colour(dims, block):
+    """Colour of every site's Dirichlet block: the sum of the block's
+    coordinates modulo 2 (a checkerboard of blocks, so that two blocks of one
+    colour never share a face)."""
+    lx, ly, lz, lt = (int(d) for d in dims)
+    bx, by, bz, bt = (int(b) for b in block)
+    t, z, y, x = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly), np.arange(lx),
+                             indexing="ij")
+    return (x // bx + y // by + z // bz + t // bt) % 2
+
+
+def sap(op, r, block, nsteps, ncycles):
+    """Multiplicative Schwarz (the Schwarz alternating procedure) on the
+    Dirichlet blocks of `block`, coloured as a checkerboard (block_colour).
+    Starting from x = 0, each cycle visits colour 0 then colour 1; a visit
+    takes the current residual r - Mhat x of the whole even-odd system,
+    keeps it on the blocks of that colour, runs nsteps of block MR on the
+    Dirichlet-cut Mhat_B there (as the additive preconditioner does on every
+    block) and adds the result to x. Blocks of the other colour see the
+    update through the next residual. op is an oracle.WilsonClover; r lives
+    on even sites."""
+    from . import block_labels
+    labels = block_labels(op.dims, block)
+    colour = block_colour(op.dims, block)
+    x = np.zeros_like(r)
+    for _ in range(ncycles):
+        for c in (0, 1):
+            res = r - op.schur(x)
+            res = np.where(((colour == c) & op.even)[..., None, None], res, 0)
+            x = x + mr_blocks(lambda v: op.schur(v, block=block), res, nsteps, labels)
+    return x
 
 
 def gcr(apply_M, precond, b, tol=1e-10, kmax=16, delta=1e-3, maxiter=10000, x0=None, record=None):

@@ -198,3 +198,80 @@ def test_bicgstab_nonhermitian_dense_and_recursive_residual():
     assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-10
     true = np.linalg.norm(b - A @ x)
     assert abs(true - hist[-1]) <= 1e-9 * np.linalg.norm(b)
+
+
+def _dense_sap(M, even, labels, colour, r, ncycles):
+    """Multiplicative Schwarz with exact block solves, from the dense full
+    matrix M alone: the even-odd Schur complement of M, and of M restricted
+    to each block's sites (Dirichlet blocks), inverted densely."""
+    dof = lambda sites: (sites[:, None] * 12 + np.arange(12)[None, :]).reshape(-1)
+    E, O = dof(np.flatnonzero(even)), dof(np.flatnonzero(~even))
+    schur = lambda e, o: M[np.ix_(e, e)] - M[np.ix_(e, o)] @ np.linalg.solve(M[np.ix_(o, o)], M[np.ix_(o, e)])
+    Mhat = schur(E, O)
+    pos = {int(d): i for i, d in enumerate(E)}
+    blocks = []
+    for b in np.unique(labels):
+        sel = labels == b
+        eb, ob = dof(np.flatnonzero(sel & even)), dof(np.flatnonzero(sel & ~even))
+        blocks.append((int(colour[sel][0]), np.array([pos[int(d)] for d in eb]), schur(eb, ob)))
+    rv = r.reshape(-1)[E]
+    x = np.zeros_like(rv)
+    for _ in range(ncycles):
+        for c in (0, 1):
+            res = rv - Mhat @ x
+            for cb, ix, Mb in blocks:
+                if cb == c:
+                    x[ix] += np.linalg.solve(Mb, res[ix])
+    return x, E, Mhat
+
+
+def test_sap_exact_blocks_is_dense_block_gauss_seidel(small_op):
+    """SAP with MR run to convergence on each block equals block Gauss-Seidel
+    over the two colours built from the dense full matrix (Schur complements
+    of its block restrictions), for one and two cycles."""
+    op, shape, _, idx = small_op
+    block = (2, 2, 2, 2)
+    M, _ = dense_matrix(op.M, shape)
+    even = op.even.reshape(-1)
+    labels = oracle.block_labels(DIMS, block).reshape(-1)
+    colour = solvers.block_colour(DIMS, block).reshape(-1)
+    assert set(colour.tolist()) == {0, 1}
+    r = np.where(op.even[..., None, None], synth.gaussian_spinor(DIMS, 171), 0)
+    for ncyc in (1, 2):
+        x = solvers.sap(op, r, block, nsteps=80, ncycles=ncyc)
+        ref, E, Mhat = _dense_sap(M, even, labels, colour, r, ncyc)
+        assert np.abs(x.reshape(-1)[E] - ref).max() < 1e-10 * np.abs(ref).max()
+        assert np.abs(x[~op.even]).max() == 0
+    # multiplicative, not additive: the second colour sees the first one's update
+    xa = solvers.schwarz(op, r, block, 80)
+    assert np.abs(xa.reshape(-1)[E] - _dense_sap(M, even, labels, colour, r, 1)[0]).max() > 1e-3 * np.abs(ref).max()
+
+
+def test_sap_converges_to_the_inverse_and_is_homogeneous(small_op):
+    """Many cycles converge to Mhat^-1 r (Gauss-Seidel on this system
+    converges); K(c r) = c K(r); one block covering the lattice is plain MR."""
+    op, shape, Mhat, idx = small_op
+    block = (2, 2, 2, 2)
+    r = np.where(op.even[..., None, None], synth.gaussian_spinor(DIMS, 181), 0)
+    x = solvers.sap(op, r, block, nsteps=40, ncycles=40)
+    ref = np.linalg.solve(Mhat, r.reshape(-1)[idx])
+    assert np.abs(x.reshape(-1)[idx] - ref).max() < 1e-10 * np.abs(ref).max()
+    c = -0.4 + 2.1j
+    K1 = solvers.sap(op, r, block, 6, 2)
+    assert np.abs(solvers.sap(op, c * r, block, 6, 2) - c * K1).max() < 1e-13 * np.abs(K1).max()
+    assert np.abs(solvers.sap(op, r, DIMS, 8, 1) - solvers.mr_blocks(op.schur, r, 8)).max() < 1e-13 * np.abs(K1).max()
+
+
+def test_sap_beats_additive_in_gcr(small_op):
+    """As a GCR preconditioner, one SAP cycle (MR on each colour in turn)
+    needs fewer outer steps than the additive form with the same MR steps."""
+    op, shape, Mhat, idx = small_op
+    b = np.where(op.even[..., None, None], synth.gaussian_spinor(DIMS, 191), 0)
+    block = (2, 2, 2, 2)
+    xs, steps_s, _, _ = solvers.gcr(op.schur, lambda r: solvers.sap(op, r, block, 4, 1), b, tol=1e-10, kmax=8,
+                                    delta=1e-2)
+    xa, steps_a, _, _ = solvers.gcr(op.schur, lambda r: solvers.schwarz(op, r, block, 4), b, tol=1e-10, kmax=8,
+                                    delta=1e-2)
+    ref = np.linalg.solve(Mhat, b.reshape(-1)[idx])
+    assert np.abs(xs.reshape(-1)[idx] - ref).max() < 1e-8 * np.abs(ref).max()
+    assert steps_s < steps_a
