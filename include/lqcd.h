@@ -150,7 +150,8 @@ typedef struct {
 
 typedef struct {
   int32_t block[4]; /* Dirichlet block; must equal the tile of op_precond */
-  int32_t mr_steps; /* MR steps per block (the paper uses 10) */
+  int32_t mr_steps; /* MR steps per block and visit (the paper uses 10) */
+  int32_t cycles;   /* 0: additive (the paper's); n >= 1: multiplicative, n sweeps over the two block colours */
 } lqcd_schwarz_params;
 
 typedef struct {
@@ -314,11 +315,22 @@ lqcd_status lqcd_dslash_batch(lqcd_context *ctx, const lqcd_dslash_job *jobs, in
                               lqcd_stream stream);
 
 /*
- * Additive Schwarz preconditioner (Section III-B; Section VIII-A): on every
- * Dirichlet block B, mr_steps minimal-residual steps on the cut operator
- * Mhat_B, started from zero, with inner products over B only; the blocks are
- * independent (block Jacobi). out_even = K in_even, packed even spinors in
- * op_precond's precision. K is positively homogeneous, K(c r) = c K(r).
+ * Schwarz preconditioner on the Dirichlet blocks of params->block (Section
+ * III-B; Section VIII-A). out_even = K in_even, packed even spinors in
+ * op_precond's precision (out_even is overwritten, in_even is not).
+ * cycles = 0, additive (the paper's): on every block B, mr_steps
+ *   minimal-residual steps on the cut operator Mhat_B, started from zero, with
+ *   inner products over B only; the blocks are independent (block Jacobi).
+ * cycles = n >= 1, multiplicative (the alternating procedure; Section X names
+ *   it as the next step): blocks are coloured by the parity of the sum of
+ *   their coordinates, so blocks of one colour never touch. Starting from
+ *   out = 0, each of n cycles visits colour 0 then colour 1; a visit runs the
+ *   same block MR on that colour's blocks only, on the current residual
+ *   in - Mhat out of the whole system, and adds the result to out. One
+ *   uncut application of Mhat per visit but the last. Needs an even number of
+ *   blocks along x (else LQCD_ERR_UNSUPPORTED).
+ * Either K is positively homogeneous, K(c r) = c K(r), and depends on
+ * in_even nonlinearly (MR), so the outer solver must be flexible (GCR).
  */
 lqcd_status lqcd_schwarz_precond(lqcd_context *ctx, const lqcd_operator *op_precond,
                                  const lqcd_schwarz_params *params, void *out_even,

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <utility>
 #include <string>
 
 #include "lqcd_internal.h"
@@ -46,6 +47,7 @@ Geom make_geom(const int32_t dims[4], const int32_t tile[4], int bc_t) {
   g.Vt2 = tile[0] * tile[1] * tile[2] * tile[3] / 2;
   g.bc_t = bc_t;
   g.has_cut = 0;
+  g.colour = -1;
   g.dVt2 = make_fastdiv(g.Vt2);
   g.dBxh = make_fastdiv(tile[0] / 2);
   g.dBy = make_fastdiv(tile[1]);
@@ -53,6 +55,7 @@ Geom make_geom(const int32_t dims[4], const int32_t tile[4], int bc_t) {
   g.dNTx = make_fastdiv(g.NT[0]);
   g.dNTy = make_fastdiv(g.NT[1]);
   g.dNTz = make_fastdiv(g.NT[2]);
+  g.dNTxh = make_fastdiv(g.NT[0] >= 2 ? g.NT[0] / 2 : 1);
   for (int m = 0; m < 4; ++m) g.dcut[m] = make_fastdiv(dims[m]);
   return g;
 }
@@ -269,11 +272,41 @@ lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schw
   s = hip_check(ctx, hipMemcpyAsync(r, in, sb, hipMemcpyDeviceToDevice, st), "schwarz copy");
   if (s) return s;
   const int nps = info.g.Vt2 > 64 ? info.g.Vt2 / 64 : 1;  // reduction segments per block
-  for (int it = 0; it < prm->mr_steps; ++it) {
-    if ((s = schur_apply(ctx, info, g, q, r, t, 0, (double *)part, st))) return s;
-    if ((s = hip_check(ctx, launch_mr_update(info.g, info.prec, out, r, q, (const double *)part, nps, it == 0, st),
-                       "schwarz MR update")))
-      return s;
+  if (prm->cycles == 0) {
+    // additive: MR on every block at once
+    for (int it = 0; it < prm->mr_steps; ++it) {
+      if ((s = schur_apply(ctx, info, g, q, r, t, 0, (double *)part, st))) return s;
+      if ((s = hip_check(ctx, launch_mr_update(info.g, info.prec, out, r, q, (const double *)part, nps, it == 0, st),
+                         "schwarz MR update")))
+        return s;
+    }
+    return LQCD_OK;
+  }
+  // multiplicative: the blocks of colour 0, then those of colour 1, `cycles`
+  // times; each visit runs MR in the current residual r of the whole system on
+  // its blocks only, and r = in - Mhat out is recomputed (uncut) for the next.
+  // out starts at zero, since the residual reads it on every block.
+  if ((s = hip_check(ctx, hipMemsetAsync(out, 0, sb, st), "schwarz clear"))) return s;
+  Geom gc[2] = {g, g};
+  gc[0].colour = 0;
+  gc[1].colour = 1;
+  const size_t n = info.vh * info.nsp / 2;
+  for (int cyc = 0; cyc < prm->cycles; ++cyc) {
+    for (int c = 0; c < 2; ++c) {
+      for (int it = 0; it < prm->mr_steps; ++it) {
+        if ((s = schur_apply(ctx, info, gc[c], q, r, t, 0, (double *)part, st))) return s;
+        if ((s = hip_check(ctx, launch_mr_update(gc[c], info.prec, out, r, q, (const double *)part, nps,
+                                                 cyc == 0 && it == 0, st),
+                           "schwarz MR update")))
+          return s;
+      }
+      if (cyc == prm->cycles - 1 && c == 1) break;
+      if ((s = schur_apply(ctx, info, info.g, q, out, t, 0, nullptr, st))) return s;
+      if ((s = hip_check(ctx, blas_axpby(info.prec, in, info.prec, q, n, 1.0, 0.0, -1.0, 0.0, nullptr, st),
+                         "schwarz residual")))
+        return s;
+      std::swap(r, q);
+    }
   }
   return LQCD_OK;
 }
@@ -285,6 +318,10 @@ lqcd_status check_schwarz(lqcd_context *ctx, const OpInfo &info, const lqcd_schw
   lqcd_status s = check_fields_internal(ctx, info.op);
   if (s) return s;
   if (prm->mr_steps < 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "mr_steps must be >= 1");
+  if (prm->cycles < 0 || prm->cycles > 64) return set_error(ctx, LQCD_ERR_INVALID_ARG, "cycles must be in 0 .. 64");
+  if (prm->cycles > 0 && (info.g.NT[0] & 1))
+    return set_error(ctx, LQCD_ERR_UNSUPPORTED,
+                     "multiplicative Schwarz needs an even number of blocks along x (the colours alternate there)");
   for (int m = 0; m < 4; ++m)
     if (prm->block[m] != info.op->tile[m])
       return set_error(ctx, LQCD_ERR_INVALID_ARG, "Schwarz blocks must equal the operator's layout tile");

@@ -313,9 +313,32 @@ struct Geom {
   int bc_t;     // +1 / -1
   int cut[4];   // Dirichlet block extents (== L[mu]: no cut along mu)
   int has_cut;  // any cut active
-  FastDiv dVt2, dBxh, dBy, dBz, dNTx, dNTy, dNTz;
+  int colour;   // -1: every tile; 0 / 1: only the tiles whose coordinates sum to
+                // that parity (NT[0] even; the cut Schur pieces and the MR update)
+  FastDiv dVt2, dBxh, dBy, dBz, dNTx, dNTy, dNTz, dNTxh;
   FastDiv dcut[4];
 };
+
+// Sites one launch covers: all of one parity, or those of one tile colour.
+__host__ __device__ __forceinline__ int launch_sites(const Geom &g) { return g.colour < 0 ? g.Vh : g.Vh / 2; }
+
+// Site of a colour-restricted launch. Launch index s < Vh/2 runs over the
+// tiles of colour g.colour in order, Vt2 sites each. Along x the tiles
+// alternate in colour (NT[0] even), so the j-th tile of the colour lies in
+// x-row j / (NT[0]/2), at tile x coordinate 2 (j mod NT[0]/2) plus the parity
+// that completes the row's coordinate sum to the colour.
+__device__ __forceinline__ int colour_site(const Geom &g, int s) {
+  const uint32_t j = fdiv((uint32_t)s, g.dVt2);
+  const uint32_t k = (uint32_t)s - j * (uint32_t)g.Vt2;
+  const uint32_t row = fdiv(j, g.dNTxh);
+  const uint32_t jx = j - row * (uint32_t)(g.NT[0] >> 1);
+  const uint32_t u = fdiv(row, g.dNTy);
+  const uint32_t ty = row - u * (uint32_t)g.NT[1];
+  const uint32_t tt = fdiv(u, g.dNTz);
+  const uint32_t tz = u - tt * (uint32_t)g.NT[2];
+  const uint32_t tx = 2 * jx + ((ty + tz + tt + (uint32_t)g.colour) & 1u);
+  return (int)((tx + (uint32_t)g.NT[0] * row) * (uint32_t)g.Vt2 + k);
+}
 
 struct Site {
   int t[4];  // tile coordinate

@@ -27,7 +27,7 @@ namespace lqcd {
 std::string geom_key(const Geom &g) {
   std::ostringstream o;
   o << g.L[0] << "x" << g.L[1] << "x" << g.L[2] << "x" << g.L[3] << "/" << g.B[0] << "x" << g.B[1] << "x" << g.B[2]
-    << "x" << g.B[3] << (g.has_cut ? "c" : "");
+    << "x" << g.B[3] << (g.has_cut ? "c" : "") << (g.colour >= 0 ? "h" : "");
   return o.str();
 }
 

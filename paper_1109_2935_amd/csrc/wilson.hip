@@ -363,9 +363,14 @@ template <typename S, typename R, int RECON, int MODE, bool REDUCE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) wilson_kernel(WArgs<S> a) {
   const RhsBlock rb = rhs_block(a.nrhs, a.rg);
   double red[3] = {0, 0, 0};
-  if (rb.s < a.g.Vh) wilson_point<S, R, RECON, MODE, REDUCE>(a, rb.s, rb.rhs, red);
+  int s = rb.s;
+  if constexpr (MODE == W_HOP_CLOV || MODE == W_XPAY_CLOV) {
+    // one colour of tiles (single right-hand side; the host checks)
+    if (a.g.colour >= 0) s = rb.s < (a.g.Vh >> 1) ? colour_site(a.g, rb.s) : a.g.Vh;
+  }
+  if (s < a.g.Vh) wilson_point<S, R, RECON, MODE, REDUCE>(a, s, rb.rhs, red);
   if constexpr (REDUCE) {  // single right-hand side only
-    segment_reduce_store(red, a.g.Vt2 < 64 ? a.g.Vt2 : 64, rb.s, a.g.Vh, a.partials);
+    segment_reduce_store(red, a.g.Vt2 < 64 ? a.g.Vt2 : 64, s, a.g.Vh, a.partials);
   }
 }
 
@@ -466,8 +471,9 @@ __global__ void __launch_bounds__(256) clover_apply_kernel(Geom g, S *out, const
 template <typename S, typename R>
 __global__ void __launch_bounds__(256) mr_update_kernel(Geom g, S *x, S *r, const S *q, const double *part, int nps,
                                                         int first) {
-  const int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (s >= g.Vh) return;
+  int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (s >= launch_sites(g)) return;
+  if (g.colour >= 0) s = colour_site(g, s);
   const int b = (int)fdiv((uint32_t)s, g.dVt2);
   double qr = 0, qi = 0, qq = 0;
   for (int j = 0; j < nps; ++j) {
@@ -500,7 +506,7 @@ __global__ void __launch_bounds__(256) mr_update_kernel(Geom g, S *x, S *r, cons
 
 hipError_t launch_mr_update(const Geom &g, int prec, void *x, void *r, const void *q, const double *partials, int nps,
                             bool first, hipStream_t st) {
-  const int bt = 256, nwg = (g.Vh + bt - 1) / bt;
+  const int bt = 256, nwg = (launch_sites(g) + bt - 1) / bt;
   if (g.Vh == 0) return hipSuccess;
   switch (prec) {
 #define CASE(P)                                                                                              \
@@ -535,7 +541,9 @@ static hipError_t launch_w3(const WilsonLaunch &w, hipStream_t st) {
   a.dagger = w.dagger;
   a.nrhs = w.nrhs;
   a.rg = rhs_group(w.nrhs);
-  const int nwg = rhs_grid(w.g.Vh, w.nrhs, w.block_threads);
+  if (w.g.colour >= 0 && ((MODE != W_HOP_CLOV && MODE != W_XPAY_CLOV) || w.nrhs != 1 || w.mfma || (w.g.NT[0] & 1)))
+    return hipErrorInvalidValue;
+  const int nwg = rhs_grid(launch_sites(w.g), w.nrhs, w.block_threads);
   if constexpr ((P == LQCD_F16 || P == LQCD_BF16) && !RED) {
     if (w.mfma) {
       if (w.nrhs % 4 || w.block_threads % 64) return hipErrorInvalidValue;

@@ -57,7 +57,7 @@ class lqcd_solve_info(ctypes.Structure):
 
 
 class lqcd_schwarz_params(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32 * 4), ("mr_steps", ctypes.c_int32)]
+    _fields_ = [("block", ctypes.c_int32 * 4), ("mr_steps", ctypes.c_int32), ("cycles", ctypes.c_int32)]
 
 
 class lqcd_ptc_shape(ctypes.Structure):

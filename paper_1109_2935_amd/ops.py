@@ -111,11 +111,12 @@ def staggered(ctx, fat, U, dims, mass, prec, recon=18, tile=None, bc_t=-1, c_lon
 
 
 def gcr_params(tol=1e-10, k_max=16, delta=1e-3, max_iter=10000, precond=L.LQCD_PRECOND_NONE, block=(8, 8, 8, 8),
-               mr_steps=8):
+               mr_steps=8, cycles=0):
     p = L.lqcd_gcr_params()
     p.tol, p.k_max, p.delta, p.max_iter, p.precond = tol, k_max, delta, max_iter, precond
     p.schwarz.block[:] = [int(b) for b in block]
     p.schwarz.mr_steps = mr_steps
+    p.schwarz.cycles = cycles
     p.learned = None
     return p
 
@@ -141,8 +142,10 @@ def bicgstab_params(tol=1e-10, max_iter=20000, delta_reliable=0.1):
     return p
 
 
-def schwarz_params(block, mr_steps=8):
+def schwarz_params(block, mr_steps=8, cycles=0):
+    """cycles = 0: additive Schwarz; n >= 1: multiplicative, n sweeps over the two block colours."""
     p = L.lqcd_schwarz_params()
     p.block[:] = [int(b) for b in block]
     p.mr_steps = mr_steps
+    p.cycles = cycles
     return p

@@ -27,7 +27,8 @@ def test_struct_layouts_match_header():
     # 4 + 16 + 16 + 4*3 ints, padding to 8, 4 doubles, 4 pointers
     assert ctypes.sizeof(L.lqcd_operator) == 48 + 32 + 32
     assert ctypes.sizeof(L.lqcd_solve_info) == 40
-    assert ctypes.sizeof(L.lqcd_gcr_params) == 8 + 4 + 4 + 8 + 4 + 4 + 20 + 4 + 8
+    assert ctypes.sizeof(L.lqcd_schwarz_params) == 24
+    assert ctypes.sizeof(L.lqcd_gcr_params) == 8 + 4 + 4 + 8 + 4 + 4 + 24 + 8
     assert ctypes.sizeof(L.lqcd_ptc_net) == 40 + 8
     assert ctypes.sizeof(L.lqcd_cg_params) == 8 + 4 + 4 + 8 + 4 + 4 + 3 * 8 + 4 + 4 + 8
     assert ctypes.sizeof(L.lqcd_bicgstab_params) == 8 + 8 + 8

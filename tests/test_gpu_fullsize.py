@@ -93,6 +93,26 @@ def test_gcr_dd_full_32x64(ctx):
     assert res <= 1.05e-10
 
 
+def test_gcr_dd_sap_full_32x64(ctx):
+    """GCR-DD with the multiplicative Schwarz K (FP16, 8^4 blocks, one cycle
+    over the two colours, 4 MR steps per visit); the oracle recomputes the
+    residual."""
+    dims, U, b, Ud = wilson_fields()
+    o = {p: ops.wilson_clover(ctx, U, dims, 0.124, 1.0, p, r, tile=STENCIL_TILE if p < 2 else BLOCK, U_device=Ud)
+         for p, r in ((0, 18), (1, 12), (2, 12))}
+    x = o[0].spinor(full=True)
+    prm = ops.gcr_params(1e-10, 16, 1e-3, max_iter=2000, precond=L.LQCD_PRECOND_SCHWARZ, block=BLOCK, mr_steps=4,
+                         cycles=1)
+    st, info = L.lqcd_gcr_solve(ctx, o[0].op, o[1].op, o[2].op, prm, x, o[0].import_spinor(b, -1))
+    assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+    say("GCR-DD (SAP) %d steps %.3fs" % (info.iters, info.seconds))
+    xs = np_of(o[0].export_spinor(x, -1))
+    M = oracle.WilsonClover(dims, U, 0.124, 1.0, bc_t=-1)
+    res = np.linalg.norm(b - M.M(xs)) / np.linalg.norm(b)
+    say("oracle residual %.3e" % res)
+    assert res <= 1.05e-10
+
+
 @pytest.mark.parametrize("sprec", [1, 2])
 def test_bicgstab_full_32x64(ctx, sprec):
     """Mixed-precision BiCGstab on the same system: FP32 or FP16 sloppy
