@@ -105,6 +105,23 @@ __device__ __forceinline__ void load_chunks(const S *__restrict__ base, int64_t 
   }
 }
 
+// The same loads without conversion: out holds the stored values.
+template <typename S, int N, int CH, bool NT = false>
+__device__ __forceinline__ void load_chunks_raw(const S *__restrict__ base, int64_t stride, int64_t s, S *out) {
+  constexpr int W = (CH * (int)sizeof(S) > 16) ? 16 / (int)sizeof(S) : CH;
+#pragma unroll
+  for (int c = 0; c < N / CH; ++c) {
+    const S *p = base + (c * stride + s) * CH;
+#pragma unroll
+    for (int w = 0; w < CH / W; ++w) {
+      const Chunk<S, W> *q = reinterpret_cast<const Chunk<S, W> *>(p + w * W);
+      Chunk<S, W> v = NT ? nt_load(q) : *q;
+#pragma unroll
+      for (int k = 0; k < W; ++k) out[c * CH + w * W + k] = v.v[k];
+    }
+  }
+}
+
 template <typename S, int N, int CH, typename R, bool NT = false>
 __device__ __forceinline__ void store_chunks(S *__restrict__ base, int64_t stride, int64_t s, const R *in) {
   constexpr int W = (CH * (int)sizeof(S) > 16) ? 16 / (int)sizeof(S) : CH;
@@ -394,6 +411,33 @@ __device__ __forceinline__ int hop(const Geom &g, const Site &x, int step, int *
     if (--t[MU] < 0) { t[MU] = g.NT[MU] - 1; ++w; }
   }
   *wraps = w;
+  return encode_site(g, t, l);
+}
+
+// Neighbour one hop along MU (STEP = +1 or -1) without loops or branches: the
+// hop crosses at most one tile face (tile extents are at least 2).
+template <int MU, int STEP>
+__device__ __forceinline__ int hop1(const Geom &g, const Site &x, int *wraps) {
+  int t[4] = {x.t[0], x.t[1], x.t[2], x.t[3]};
+  int l[4] = {x.l[0], x.l[1], x.l[2], x.l[3]};
+  int lm = l[MU] + STEP, tm = t[MU];
+  bool wrap;
+  if constexpr (STEP > 0) {
+    const bool cross = lm >= g.B[MU];
+    lm = cross ? 0 : lm;
+    tm = cross ? tm + 1 : tm;
+    wrap = tm == g.NT[MU];
+    tm = wrap ? 0 : tm;
+  } else {
+    const bool cross = lm < 0;
+    lm = cross ? g.B[MU] - 1 : lm;
+    tm = cross ? tm - 1 : tm;
+    wrap = tm < 0;
+    tm = wrap ? g.NT[MU] - 1 : tm;
+  }
+  l[MU] = lm;
+  t[MU] = tm;
+  *wraps = wrap ? 1 : 0;
   return encode_site(g, t, l);
 }
 

@@ -7,6 +7,8 @@
 // to 4 spins; the boundary phase and the Dirichlet cut are applied in-kernel.
 // Epilogues fuse the clover term (A or A^-1), an xpay and, for the Schwarz
 // block solver, per-workgroup partial inner products.
+#include <type_traits>
+
 #include "lqcd_internal.h"
 
 namespace lqcd {
@@ -150,40 +152,133 @@ __device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int
   // forward: (1 - sgn gamma_mu) U_mu(x) psi(x+mu)
   if (hop_kept<MU>(a.g, x, +1)) {
     int w;
-    const int n = hop<MU>(a.g, x, +1, &w);
+    const int n = hop1<MU, +1>(a.g, x, &w);
     cpx<R> psi[4][3], h[2][3], u[2][3];
     load_spinor<S, R>(a.in, vs, rhs_index(rhs, n, vh, a.rg), psi);
     project<MU, R>(psi, -sgn, h);
     const Link<R> U = load_link<S, R, RECON>(a.gauge, vh, MU, x.p, s, a.nrhs == 1);
     su3_mv(U, h[0], u[0]);
     su3_mv(U, h[1], u[1]);
-    if (MU == 3 && (w & 1) && a.g.bc_t < 0) {
+    if constexpr (MU == 3) {
+      const R ph = ((w & 1) && a.g.bc_t < 0) ? R(-1) : R(1);
 #pragma unroll
       for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) u[k][c] = R(-1) * u[k][c];
+        for (int c = 0; c < 3; ++c) u[k][c] = ph * u[k][c];
     }
     expand_acc<MU, R>(acc, u, -sgn);
   }
   // backward: (1 + sgn gamma_mu) U_mu(x-mu)^+ psi(x-mu)
   if (hop_kept<MU>(a.g, x, -1)) {
     int w;
-    const int n = hop<MU>(a.g, x, -1, &w);
+    const int n = hop1<MU, -1>(a.g, x, &w);
     cpx<R> psi[4][3], h[2][3], u[2][3];
     load_spinor<S, R>(a.in, vs, rhs_index(rhs, n, vh, a.rg), psi);
     project<MU, R>(psi, sgn, h);
     const Link<R> U = load_link<S, R, RECON>(a.gauge, vh, MU, 1 - x.p, n, a.nrhs == 1);
     su3_adj_mv(U, h[0], u[0]);
     su3_adj_mv(U, h[1], u[1]);
-    if (MU == 3 && (w & 1) && a.g.bc_t < 0) {
+    if constexpr (MU == 3) {
+      const R ph = ((w & 1) && a.g.bc_t < 0) ? R(-1) : R(1);
 #pragma unroll
       for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) u[k][c] = R(-1) * u[k][c];
+        for (int c = 0; c < 3; ++c) u[k][c] = ph * u[k][c];
     }
     expand_acc<MU, R>(acc, u, sgn);
   }
 }
+
+// Software-pipelined hops for FP32 storage without a cut: the raw inputs of a
+// hop (neighbour spinor, link as stored, wrap count) go to one of two
+// buffers, refilled alternately, so each wave keeps the loads of the next hop
+// in flight while it multiplies the current one. Scheduling barriers hold that order
+// (without them the compiler issues the loads of all eight hops first and
+// spills).
+// The raw values stay in the storage type until they are used, so that no
+// conversion forces an early wait for the loads.
+template <typename S, int RECON> struct HopIn {
+  S psi[24];
+  S link[RECON];
+  int w;
+};
+
+template <int MU, int DIR, bool STREAM, typename S, int RECON>
+__device__ __forceinline__ void hop_fetch(const WArgs<S> &a, const Site &x, int s, int rhs, HopIn<S, RECON> &h) {
+  const int64_t vh = a.g.Vh, vs = vh * a.nrhs;
+  const int n = hop1<MU, DIR>(a.g, x, &h.w);
+  load_chunks_raw<S, 24, spinor_chunk<24>()>(a.in, vs, rhs_index(rhs, n, vh, a.rg), h.psi);
+  // forward hop: U_mu(x) of x's parity; backward: U_mu(x - mu) of the other
+  const int lp = DIR > 0 ? x.p : 1 - x.p, ls = DIR > 0 ? s : n;
+  load_chunks_raw<S, RECON, chunk_reals<S, RECON>(), STREAM>(a.gauge + (int64_t)(2 * MU + lp) * vh * RECON, vh, ls,
+                                                           h.link);
+}
+
+template <int MU, int DIR, typename S, typename R, int RECON>
+__device__ __forceinline__ void hop_apply(const HopIn<S, RECON> &h, R sgn, int bc_t, cpx<R> (&acc)[4][3]) {
+  cpx<R> psi[4][3], hh[2][3], u[2][3];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      psi[sp][c] = mk<R>(to_real<R>(h.psi[6 * sp + 2 * c]), to_real<R>(h.psi[6 * sp + 2 * c + 1]));
+  const R ps = DIR > 0 ? -sgn : sgn;
+  project<MU, R>(psi, ps, hh);
+  R lv[RECON];
+#pragma unroll
+  for (int k = 0; k < RECON; ++k) lv[k] = to_real<R>(h.link[k]);
+  const Link<R> U = unpack_link<RECON, R>(lv);
+  if constexpr (DIR > 0) {
+    su3_mv(U, hh[0], u[0]);
+    su3_mv(U, hh[1], u[1]);
+  } else {
+    su3_adj_mv(U, hh[0], u[0]);
+    su3_adj_mv(U, hh[1], u[1]);
+  }
+  if constexpr (MU == 3) {
+    const R ph = ((h.w & 1) && bc_t < 0) ? R(-1) : R(1);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u[k][c] = ph * u[k][c];
+  }
+  expand_acc<MU, R>(acc, u, ps);
+}
+
+// Where the pipelined hops pay (measured at 32^3x64): FP32 storage with 12 or
+// 18 link reals. FP64 Schur kernels spill with them, 16-bit dslash kernels
+// slow down, and recon 8's reconstruction makes the pipelined form slower.
+template <typename S, int RECON> constexpr bool pipelined_hops() {
+  return std::is_same<S, float>::value && RECON != 8;
+}
+
+// Apply the hop held in HA, then refill HA with the hop two ahead; the other
+// buffer's loads stay in flight meanwhile.
+#define HOP_STEP(MUa, DIRa, HA, MUn, DIRn)                      \
+  __builtin_amdgcn_sched_barrier(0);                           \
+  hop_apply<MUa, DIRa, S, R, RECON>(HA, sgn, a.g.bc_t, acc);   \
+  __builtin_amdgcn_sched_barrier(0);                           \
+  hop_fetch<MUn, DIRn, STREAM, S, RECON>(a, x, s, rhs, HA);
+
+template <bool STREAM, typename S, typename R, int RECON>
+__device__ __forceinline__ void wilson_hops_pipelined(const WArgs<S> &a, const Site &x, int s, int rhs, R sgn,
+                                                      cpx<R> (&acc)[4][3]) {
+  HopIn<S, RECON> A, B;
+  hop_fetch<0, +1, STREAM, S, RECON>(a, x, s, rhs, A);
+  hop_fetch<0, -1, STREAM, S, RECON>(a, x, s, rhs, B);
+  HOP_STEP(0, +1, A, 1, +1)
+  HOP_STEP(0, -1, B, 1, -1)
+  HOP_STEP(1, +1, A, 2, +1)
+  HOP_STEP(1, -1, B, 2, -1)
+  HOP_STEP(2, +1, A, 3, +1)
+  HOP_STEP(2, -1, B, 3, -1)
+  __builtin_amdgcn_sched_barrier(0);
+  hop_apply<3, +1, S, R, RECON>(A, sgn, a.g.bc_t, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_apply<3, -1, S, R, RECON>(B, sgn, a.g.bc_t, acc);
+  __builtin_amdgcn_sched_barrier(0);
+}
+#undef HOP_STEP
 
 // ---------------------------------------------------------------------------
 // Link products of several right-hand sides on the matrix cores (16-bit
@@ -289,7 +384,9 @@ __device__ __forceinline__ void segment_reduce_store(double (&v)[3], int seg, in
 // One output (site s, right-hand side rhs) of the hopping term and its epilogue.
 // MF: link products on the matrix cores (16-bit storage, sources in groups of
 // 4 lanes); then every lane of the wave calls this, `valid` marks real work.
-template <typename S, typename R, int RECON, int MODE, bool REDUCE, bool MF = false>
+// CUT = false: the launch has no Dirichlet cut (every hop is taken) and takes
+// the pipelined hops.
+template <typename S, typename R, int RECON, int MODE, bool REDUCE, bool MF = false, bool CUT = true>
 __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, double (&red)[3], bool valid = true) {
   const Site x = decode_site(a.g, s, a.parity);
   const R sgn = a.dagger ? R(-1) : R(1);
@@ -305,10 +402,22 @@ __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, 
     wilson_dir_mf<3, S, RECON>(a, x, s, rhs, valid, sgn, acc);
     if (!valid) return;
   } else {
-    wilson_dir<0, S, R, RECON>(a, x, s, rhs, sgn, acc);
-    wilson_dir<1, S, R, RECON>(a, x, s, rhs, sgn, acc);
-    wilson_dir<2, S, R, RECON>(a, x, s, rhs, sgn, acc);
-    wilson_dir<3, S, R, RECON>(a, x, s, rhs, sgn, acc);
+    if constexpr (!CUT) {
+      // One instantiation for every source count (streamed link loads), so a
+      // site's arithmetic, and its rounding, does not depend on nrhs. The
+      // branch between two calls of it is deliberate: as one basic block with
+      // the epilogue, the clover kernels spill (measured: 700-900 bytes per
+      // lane); split like this they need 137-158 VGPRs and no scratch.
+      if (a.nrhs == 1)
+        wilson_hops_pipelined<true, S, R, RECON>(a, x, s, rhs, sgn, acc);
+      else
+        wilson_hops_pipelined<true, S, R, RECON>(a, x, s, rhs, sgn, acc);
+    } else {
+      wilson_dir<0, S, R, RECON>(a, x, s, rhs, sgn, acc);
+      wilson_dir<1, S, R, RECON>(a, x, s, rhs, sgn, acc);
+      wilson_dir<2, S, R, RECON>(a, x, s, rhs, sgn, acc);
+      wilson_dir<3, S, R, RECON>(a, x, s, rhs, sgn, acc);
+    }
   }
   const R coef = (R)a.coef;
   const int64_t vh = a.g.Vh, vs = vh * a.nrhs, v = rhs_index(rhs, s, vh, a.rg);
@@ -359,7 +468,7 @@ __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, 
 // One thread per (site, rhs): the lanes of a site block's source group are
 // adjacent in the workgroup and the workgroups of its groups are adjacent in
 // the launch (rhs_block), so link and clover loads are shared.
-template <typename S, typename R, int RECON, int MODE, bool REDUCE>
+template <typename S, typename R, int RECON, int MODE, bool REDUCE, bool CUT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) wilson_kernel(WArgs<S> a) {
   const RhsBlock rb = rhs_block(a.nrhs, a.rg);
   double red[3] = {0, 0, 0};
@@ -368,7 +477,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     // one colour of tiles (single right-hand side; the host checks)
     if (a.g.colour >= 0) s = rb.s < (a.g.Vh >> 1) ? colour_site(a.g, rb.s) : a.g.Vh;
   }
-  if (s < a.g.Vh) wilson_point<S, R, RECON, MODE, REDUCE>(a, s, rb.rhs, red);
+  if (s < a.g.Vh) wilson_point<S, R, RECON, MODE, REDUCE, false, CUT>(a, s, rb.rhs, red);
   if constexpr (REDUCE) {  // single right-hand side only
     segment_reduce_store(red, a.g.Vt2 < 64 ? a.g.Vt2 : 64, s, a.g.Vh, a.partials);
   }
@@ -420,7 +529,8 @@ __device__ __forceinline__ void batch_item(const BatchArgs<S> &b, int it) {
       return;
     }
   }
-  if (valid) wilson_point<S, R, RECON, W_HOP, false>(a, rb.s, rb.rhs, red);
+  // jobs carry no cut: the same hop code as the per-operator launch
+  if (valid) wilson_point<S, R, RECON, W_HOP, false, false, !pipelined_hops<S, RECON>()>(a, rb.s, rb.rhs, red);
 }
 
 // Single launch with one workgroup per item (items remapped per XCD like the
@@ -552,7 +662,15 @@ static hipError_t launch_w3(const WilsonLaunch &w, hipStream_t st) {
     }
   }
   if (w.mfma) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED>), dim3(nwg), dim3(w.block_threads), 0, st, a);
+  // launches without a cut take the pipelined hops where they pay (measured);
+  // the others keep the runtime-checked hops
+  if constexpr (pipelined_hops<S, RECON>()) {
+    if (!w.g.has_cut) {
+      hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED, false>), dim3(nwg), dim3(w.block_threads), 0, st, a);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED, true>), dim3(nwg), dim3(w.block_threads), 0, st, a);
   return hipGetLastError();
 }
 
