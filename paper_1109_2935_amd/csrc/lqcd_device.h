@@ -441,6 +441,35 @@ __device__ __forceinline__ int hop1(const Geom &g, const Site &x, int *wraps) {
   return encode_site(g, t, l);
 }
 
+// Neighbour STEP hops along MU (|STEP| <= 3) without loops or branches: with
+// tile extents of at least 2 a hop crosses at most two tile faces, and it
+// wraps the lattice at most twice (on a lattice of extent 2).
+template <int MU, int STEP>
+__device__ __forceinline__ int hopk(const Geom &g, const Site &x, int *wraps) {
+  static_assert(STEP != 0 && STEP >= -3 && STEP <= 3, "hops of 1 to 3 sites");
+  int t[4] = {x.t[0], x.t[1], x.t[2], x.t[3]};
+  int l[4] = {x.l[0], x.l[1], x.l[2], x.l[3]};
+  const int B = g.B[MU], NT = g.NT[MU];
+  int lm = l[MU] + STEP, tm = t[MU], w;
+  if constexpr (STEP > 0) {
+    const int c = (lm >= B) + (lm >= 2 * B);  // tile faces crossed
+    lm -= c * B;
+    tm += c;
+    w = (tm >= NT) + (tm >= 2 * NT);
+    tm -= w * NT;
+  } else {
+    const int c = (lm < 0) + (lm < -B);
+    lm += c * B;
+    tm -= c;
+    w = (tm < 0) + (tm < -NT);
+    tm += w * NT;
+  }
+  l[MU] = lm;
+  t[MU] = tm;
+  *wraps = w;
+  return encode_site(g, t, l);
+}
+
 // Dirichlet cut: is the hop of `step` (+1 or -1) along MU inside one block?
 template <int MU>
 __device__ __forceinline__ bool hop_kept(const Geom &g, const Site &x, int step) {
