@@ -651,7 +651,11 @@ static hipError_t launch_w3(const WilsonLaunch &w, hipStream_t st) {
   a.dagger = w.dagger;
   a.nrhs = w.nrhs;
   a.rg = rhs_group(w.nrhs);
-  if (w.g.colour >= 0 && ((MODE != W_HOP_CLOV && MODE != W_XPAY_CLOV) || w.nrhs != 1 || w.mfma || (w.g.NT[0] & 1)))
+  // colour-restricted launches: the cut Schur pieces, one source, tiles
+  // alternating in colour along x, and a cut (blocks of one colour are
+  // independent only through it)
+  if (w.g.colour >= 0 && ((MODE != W_HOP_CLOV && MODE != W_XPAY_CLOV) || w.nrhs != 1 || w.mfma || (w.g.NT[0] & 1) ||
+                          !w.g.has_cut))
     return hipErrorInvalidValue;
   const int nwg = rhs_grid(launch_sites(w.g), w.nrhs, w.block_threads);
   if constexpr ((P == LQCD_F16 || P == LQCD_BF16) && !RED) {
