@@ -351,6 +351,11 @@ lqcd_status lqcd_schwarz_precond(lqcd_context *ctx, const lqcd_operator *op_prec
  * x_full (in: initial guess, out: solution) and b_full are packed
  * LQCD_FIELD_SPINOR_FULL fields of op_hi. Returns LQCD_ERR_NOT_CONVERGED
  * (best iterate in x_full, info filled) when max_iter is reached.
+ * precond = LQCD_PRECOND_LEARNED with params->schwarz.mr_steps > 0: a step
+ * whose residual drops by less than 5%, or whose network output is zero or
+ * not finite, hands the next step (or, for an unusable output, the same step)
+ * to the Schwarz preconditioner; info->fallback_applies counts those steps.
+ * Without the fallback an unusable direction returns LQCD_ERR_BREAKDOWN.
  */
 lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op_hi,
                            const lqcd_operator *op_krylov, const lqcd_operator *op_precond,

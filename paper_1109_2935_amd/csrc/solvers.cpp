@@ -249,6 +249,12 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
     TRY(S.result(3, zd));
     const double g = std::sqrt(zd[0]);
     if (!(g > 0) || !std::isfinite(g)) {
+      if (pk == LQCD_PRECOND_LEARNED && !schwarz_now && prm->schwarz.mr_steps > 0) {
+        // the network's direction is unusable (zero, or not finite): take
+        // this step again with the Schwarz preconditioner (rhat is unchanged)
+        use_fallback = true;
+        continue;
+      }
       status = set_error(ctx, LQCD_ERR_BREAKDOWN, "GCR breakdown: orthogonalised direction has zero norm");
       break;
     }

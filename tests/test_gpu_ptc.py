@@ -197,3 +197,37 @@ def test_ptc_training_and_fgcr_gain(ctx):
 def ctypes_pointer(s):
     import ctypes
     return ctypes.pointer(s)
+
+
+@pytest.mark.parametrize("cycles", [0, 1])
+@pytest.mark.parametrize("bad", ["zero", "nan"])
+def test_learned_fgcr_falls_back_to_schwarz(ctx, bad, cycles):
+    """A network whose output is unusable (all zero, or not finite) hands every
+    step to the Schwarz fallback (additive, or multiplicative with cycles = 1):
+    the solve still reaches an FP64 residual of 1e-10, recomputed by the
+    oracle. Without a fallback the same network is a breakdown."""
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    U, o = system(ctx, dims, 95, tile=block, precs=(0, 1))
+    net = ptc.Network(ctx, (1, 16, 16, 16, 1), seed=96)
+    Ws = net.get_weights()
+    fill = 0.0 if bad == "zero" else np.nan
+    net.set_weights([np.full_like(W, fill) for W in Ws])
+    b = synth.gaussian_spinor(dims, 9801)
+    bp = o[0].import_spinor(b, -1)
+    x = o[0].spinor(full=True)
+    prm = ops.gcr_params(1e-10, 16, 1e-3, precond=L.LQCD_PRECOND_LEARNED, block=block, mr_steps=4, cycles=cycles)
+    prm.learned = ctypes_pointer(net.net)
+    st, info = L.lqcd_gcr_solve(ctx, o[0].op, o[1].op, o[1].op, prm, x, bp)
+    assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+    assert info.true_residual <= 1e-10
+    assert info.fallback_applies == info.iters
+    M = oracle.WilsonClover(dims, U, 0.124, 1.0)
+    xs = np_of(o[0].export_spinor(x, -1))
+    assert np.linalg.norm(b - M.M(xs)) / np.linalg.norm(b) < 1.05e-10
+    # no fallback: the unusable direction is a breakdown
+    prm0 = ops.gcr_params(1e-10, 16, 1e-3, precond=L.LQCD_PRECOND_LEARNED, mr_steps=0)
+    prm0.learned = ctypes_pointer(net.net)
+    x0 = o[0].spinor(full=True)
+    with pytest.raises(L.LqcdError) as ei:
+        L.lqcd_gcr_solve(ctx, o[0].op, o[1].op, o[1].op, prm0, x0, bp)
+    assert ei.value.status == L.LQCD_ERR_BREAKDOWN
