@@ -482,7 +482,7 @@ def main():
                     "fp64_cg_true_residual": cg.true_residual,
                     "speedup_vs_fp64_cg": round(cg.seconds / tts["gcr_dd_seconds"], 2)})
     # GCR-DD with the multiplicative Schwarz K (two block colours), FP16, same blocks
-    sap_mr, sap_cycles = 4, 2
+    sap_mr, sap_cycles = 4, 3
     sprm = ops.gcr_params(1e-10, k_max=16, delta=1e-3, max_iter=2000, precond=L.LQCD_PRECOND_SCHWARZ,
                           block=block, mr_steps=sap_mr, cycles=sap_cycles)
     best = None
