@@ -16,6 +16,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <fstream>
 #include <sstream>
 
@@ -73,22 +74,31 @@ int tune_pick(lqcd_context *ctx, const std::string &key, const std::vector<int> 
     hipEventDestroy(e0);
     return fallback;
   }
+  // two interleaved rounds over the candidates, each candidate scored by its
+  // faster round, so that clock ramp-up or a cold cache in the first
+  // measurements does not decide the choice
   int best = fallback;
   float best_ms = 1e30f;
-  for (int c : cands) {
-    if (launch(c) != hipSuccess) continue;
-    hipEventRecord(e0, st);
-    bool ok = true;
-    for (int r = 0; r < 3 && ok; ++r) ok = launch(c) == hipSuccess;
-    hipEventRecord(e1, st);
-    if (!ok || hipEventSynchronize(e1) != hipSuccess) continue;
-    float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = c;
+  std::vector<float> score(cands.size(), 1e30f);
+  for (int round = 0; round < 2; ++round) {
+    for (size_t i = 0; i < cands.size(); ++i) {
+      const int c = cands[i];
+      if (launch(c) != hipSuccess) continue;
+      hipEventRecord(e0, st);
+      bool ok = true;
+      for (int r = 0; r < 3 && ok; ++r) ok = launch(c) == hipSuccess;
+      hipEventRecord(e1, st);
+      if (!ok || hipEventSynchronize(e1) != hipSuccess) continue;
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      score[i] = std::min(score[i], ms);
     }
   }
+  for (size_t i = 0; i < cands.size(); ++i)
+    if (score[i] < best_ms) {
+      best_ms = score[i];
+      best = cands[i];
+    }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   (void)hipGetLastError();
