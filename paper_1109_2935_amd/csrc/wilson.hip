@@ -189,10 +189,11 @@ __device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int
   }
 }
 
-// Software-pipelined hops for FP32 storage without a cut: the raw inputs of a
-// hop (neighbour spinor, link as stored, wrap count) go to one of two
-// buffers, refilled alternately, so each wave keeps the loads of the next hop
-// in flight while it multiplies the current one. Scheduling barriers hold that order
+// Software-pipelined hops for launches without a cut (FP32 and 16-bit
+// storage): the raw inputs of a hop (neighbour spinor, link as stored, wrap
+// count) go to one of two buffers, refilled alternately, so each wave keeps
+// the loads of the next hop in flight while it multiplies the current one.
+// Scheduling barriers hold that order
 // (without them the compiler issues the loads of all eight hops first and
 // spills).
 // The raw values stay in the storage type until they are used, so that no
@@ -220,13 +221,25 @@ __device__ __forceinline__ void hop_apply(const HopIn<S, RECON> &h, R sgn, int b
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      psi[sp][c] = mk<R>(to_real<R>(h.psi[6 * sp + 2 * c]), to_real<R>(h.psi[6 * sp + 2 * c + 1]));
+    for (int c = 0; c < 3; ++c) {
+      R re = to_real<R>(h.psi[6 * sp + 2 * c]), im = to_real<R>(h.psi[6 * sp + 2 * c + 1]);
+      if constexpr (sizeof(S) == 2) {
+        // convert here: the empty asm keeps the compiler from folding the
+        // stored halves into mixed-precision FMAs, which keeps them live
+        // across the hop (170-230 VGPRs instead of about 110)
+        __asm__ volatile("" : "+v"(re));
+        __asm__ volatile("" : "+v"(im));
+      }
+      psi[sp][c] = mk<R>(re, im);
+    }
   const R ps = DIR > 0 ? -sgn : sgn;
   project<MU, R>(psi, ps, hh);
   R lv[RECON];
 #pragma unroll
-  for (int k = 0; k < RECON; ++k) lv[k] = to_real<R>(h.link[k]);
+  for (int k = 0; k < RECON; ++k) {
+    lv[k] = to_real<R>(h.link[k]);
+    if constexpr (sizeof(S) == 2) __asm__ volatile("" : "+v"(lv[k]));
+  }
   const Link<R> U = unpack_link<RECON, R>(lv);
   if constexpr (DIR > 0) {
     su3_mv(U, hh[0], u[0]);
@@ -245,11 +258,12 @@ __device__ __forceinline__ void hop_apply(const HopIn<S, RECON> &h, R sgn, int b
   expand_acc<MU, R>(acc, u, ps);
 }
 
-// Where the pipelined hops pay (measured at 32^3x64): FP32 storage with 12 or
-// 18 link reals. FP64 Schur kernels spill with them, 16-bit dslash kernels
-// slow down, and recon 8's reconstruction makes the pipelined form slower.
-template <typename S, int RECON> constexpr bool pipelined_hops() {
-  return std::is_same<S, float>::value && RECON != 8;
+// Where the pipelined hops pay (measured at 32^3x64): FP32 and 16-bit
+// storage with 12 or 18 link reals. FP64 Schur kernels spill with them, recon
+// 8's reconstruction makes the pipelined form slower, and the 16-bit xpay-only
+// kernel (W_XPAY) spills.
+template <typename S, int RECON, int MODE> constexpr bool pipelined_hops() {
+  return !std::is_same<S, double>::value && RECON != 8 && (sizeof(S) == 4 || MODE != W_XPAY);
 }
 
 // Apply the hop held in HA, then refill HA with the hop two ahead; the other
@@ -530,7 +544,7 @@ __device__ __forceinline__ void batch_item(const BatchArgs<S> &b, int it) {
     }
   }
   // jobs carry no cut: the same hop code as the per-operator launch
-  if (valid) wilson_point<S, R, RECON, W_HOP, false, false, !pipelined_hops<S, RECON>()>(a, rb.s, rb.rhs, red);
+  if (valid) wilson_point<S, R, RECON, W_HOP, false, false, !pipelined_hops<S, RECON, W_HOP>()>(a, rb.s, rb.rhs, red);
 }
 
 // Single launch with one workgroup per item (items remapped per XCD like the
@@ -668,7 +682,7 @@ static hipError_t launch_w3(const WilsonLaunch &w, hipStream_t st) {
   if (w.mfma) return hipErrorInvalidValue;
   // launches without a cut take the pipelined hops where they pay (measured);
   // the others keep the runtime-checked hops
-  if constexpr (pipelined_hops<S, RECON>()) {
+  if constexpr (pipelined_hops<S, RECON, MODE>()) {
     if (!w.g.has_cut) {
       hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED, false>), dim3(nwg), dim3(w.block_threads), 0, st, a);
       return hipGetLastError();
