@@ -34,9 +34,6 @@ WILSON_REALS = {18: 192, 12: 144, 8: 112}  # in 24 + out 24 + 8 links per output
 # WRITE_SIZE scaled by the same counters on a 2 GiB device copy (summary under
 # profiles/). Valid only for the kernel sources it was measured on: their hash
 # is checked at run time and the traffic is reported as null when they differ.
-# (Moved forward over a host-side check added to the launcher and over the
-# pipelined 16-bit hops; the headline kernel's compiled code compared
-# identical both times.)
 PROFILED_TRAFFIC = {"sources_sha1": "0f2f0bd7bcee879b4c2f280db917f4799ecd013a", "bytes_per_launch": 662.7e6}
 
 
