@@ -13,7 +13,10 @@ pytestmark = pytest.mark.gpu
 L = pytest.importorskip("paper_1109_2935_amd.lqcd")
 from paper_1109_2935_amd import ops  # noqa: E402
 
-LAYOUTS = [((4, 4, 6, 8), None), ((8, 8, 8, 12), (4, 4, 4, 4)), ((2, 4, 2, 4), None)]
+# (4, 4, 4, 2): the 3-site hops along t wrap the lattice twice (an even number
+# of boundary signs); with 2^4 tiles they also cross two tile faces
+LAYOUTS = [((4, 4, 6, 8), None), ((8, 8, 8, 12), (4, 4, 4, 4)), ((2, 4, 2, 4), None), ((4, 4, 4, 2), None),
+           ((4, 4, 4, 2), (2, 2, 2, 2))]
 _cache = {}
 
 
@@ -32,7 +35,7 @@ def make(ctx, dims, prec, recon, tile=None, mass=0.05, bc_t=-1):
     return ops.staggered(ctx, fat, U, dims, mass, prec, recon, tile=tile, bc_t=bc_t, U_device=Ud, fat_device=Fd)
 
 
-@pytest.mark.parametrize("layout", LAYOUTS, ids=lambda l: "x".join(map(str, l[0])))
+@pytest.mark.parametrize("layout", LAYOUTS, ids=lambda l: "x".join(map(str, l[0])) + ("t" if l[1] else ""))
 @pytest.mark.parametrize("prec,recon", [(0, 18), (0, 12), (0, 8), (1, 18), (1, 12), (1, 8), (2, 18), (2, 12),
                                         (3, 12)], ids=str)
 def test_staggered_dslash_parity(ctx, layout, prec, recon):
