@@ -259,11 +259,13 @@ __device__ __forceinline__ void hop_apply(const HopIn<S, RECON> &h, R sgn, int b
 }
 
 // Where the pipelined hops pay (measured at 32^3x64): FP32 and 16-bit
-// storage with 12 or 18 link reals. FP64 Schur kernels spill with them, recon
+// storage with 12 or 18 link reals, and the FP64 hopping term with 12 (257 ->
+// 222 us). FP64 Schur kernels and the FP64 recon-18 hop spill with them, recon
 // 8's reconstruction makes the pipelined form slower, and the 16-bit xpay-only
 // kernel (W_XPAY) spills.
 template <typename S, int RECON, int MODE> constexpr bool pipelined_hops() {
-  return !std::is_same<S, double>::value && RECON != 8 && (sizeof(S) == 4 || MODE != W_XPAY);
+  if constexpr (std::is_same<S, double>::value) return MODE == W_HOP && RECON == 12;
+  return RECON != 8 && (sizeof(S) == 4 || MODE != W_XPAY);
 }
 
 // Apply the hop held in HA, then refill HA with the hop two ahead; the other
