@@ -56,7 +56,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dslash-launches", type=int, default=50)
+    ap.add_argument("--dslash-launches", type=int, default=120,
+                    help="launches per kernel timing (rotating over 3 buffer sets; median over groups)")
+    ap.add_argument("--solves", type=int, default=5, help="timed solves per solver (after one warm-up): median")
     ap.add_argument("--dims", type=str, default="32,32,32,64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
@@ -65,8 +67,10 @@ def parse():
                     help="trained network weights; FGCR with it is timed when the file exists")
     ap.add_argument("--no-staggered", action="store_true", help="skip the 48^3x96 staggered workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-RHS workload")
-    ap.add_argument("--only", choices=("staggered", "batched", "learned"), default=None,
-                    help="run one secondary workload alone and print its JSON (for profiling runs)")
+    ap.add_argument("--only", choices=("staggered", "batched", "learned", "solve"), default=None,
+                    help="run one secondary workload alone and print its JSON (for profiling runs); solve: one "
+                         "warm-up and one timed GCR-DD solve of the default workload")
+    ap.add_argument("--oracle-solve", choices=("8x4", "32x64"), default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -101,21 +105,99 @@ def time_kernel(torch, fn, launches):
     return s.elapsed_time(e) / 1e3 / launches
 
 
-def device_copy(torch, nbytes=2 << 30, launches=20):
-    """Bandwidth of a plain device-to-device copy kernel (read + write bytes /
-    time), the practical ceiling next to the 8 TB/s specification. The same
-    kernel, with known bytes, calibrates the HBM traffic counters."""
-    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+def time_rotating(torch, fns, launches):
+    """Median launch duration of a kernel over at least `launches` launches
+    that rotate over len(fns) buffer sets (one callable per set, each set with
+    its own inputs, outputs, links and clover fields, so that the 256 MB MALL
+    cannot serve a launch from the previous one). Each group of len(fns)
+    launches is bracketed by HIP events on the current stream; the result is the
+    median over the groups of the group time divided by its launch count."""
+    for f in fns:
+        f()
+    torch.cuda.synchronize()
+    groups = max(1, -(-launches // len(fns)))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(groups + 1)]
+    ev[0].record()
+    for g in range(groups):
+        for f in fns:
+            f()
+        ev[g + 1].record()
+    ev[-1].synchronize()
+    per = sorted(ev[g].elapsed_time(ev[g + 1]) / 1e3 / len(fns) for g in range(groups))
+    return per[len(per) // 2]
+
+
+def median_of(vals):
+    v = sorted(vals)
+    return v[len(v) // 2]
+
+
+def device_copy(torch, L, ctx, nbytes=2 << 30, launches=20):
+    """Bandwidth of the library's streaming copy kernel (read + write bytes /
+    time), the practical ceiling of a read-once/write-once kernel next to the
+    8 TB/s specification. The same kernel, with known bytes, calibrates the
+    HBM traffic counters."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
     c = torch.empty_like(a)
-    dt = time_kernel(torch, lambda: c.copy_(a), launches)
+    dt = time_kernel(torch, lambda: L.lqcd_stream_copy(ctx, c, a, nbytes), launches)
     del a, c
-    return {"bytes_per_launch": 2 * nbytes, "us": round(dt * 1e6, 1), "GB/s": round(2 * nbytes / dt / 1e9, 1)}
+    return {"kernel": "stream_copy_kernel", "bytes_per_launch": 2 * nbytes, "us": round(dt * 1e6, 1),
+            "GB/s": round(2 * nbytes / dt / 1e9, 1)}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_solve_timing(which):
+    """The oracle's FP64 even-odd CGNE (bench.py --oracle-solve), run in a
+    child process so that its thread count is set by the environment: the
+    full 8^4 solve of the smallest workload to 1e-10 ("8x4"), or a bounded
+    sample of the 32^3x64 solve: 2 CGNE iterations ("32x64")."""
+    import numpy as np
+    import oracle
+    import synth
+    from oracle import solvers
+    oracle.lib()
+    if which == "8x4":
+        dims, kappa, su, sb, tol, maxit = (8, 8, 8, 8), 0.12, 1001, 1002, 1e-10, 100000
+    else:
+        dims, kappa, su, sb, tol, maxit = (32, 32, 32, 64), 0.124, 2001, 2002, 1e-10, 2
+    U = synth.gauge_field(dims, 0.25, su)
+    b = synth.gaussian_spinor(dims, sb)
+    t0 = time.perf_counter()
+    op = oracle.WilsonClover(dims, U, kappa, 1.0, bc_t=-1)
+    bhat = op.schur_source(b)
+    t1 = time.perf_counter()
+    xe, it, _ = solvers.cgne(op.schur, lambda v: op.schur(v, dagger=True), bhat, tol=tol, maxiter=maxit)
+    t2 = time.perf_counter()
+    return {"setup_s": round(t1 - t0, 3), "solve_s": round(t2 - t1, 3), "iters": it}
+
+
+def run_oracle_solve(which, threads):
+    import subprocess
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = str(threads)
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-solve", which], env=env,
+                         capture_output=True, text=True, timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    return json.loads(out.stdout.strip().splitlines()[-1])
 
 
 def cpu_baseline(dims, U, b, kappa, csw):
     """The oracle's FP64 Wilson dslash (one parity) on the same fields, timed
     on the host cores; reported in the same unit (algorithmic GB/s, FP64
-    18-real links: 1536 bytes per output site)."""
+    18-real links: 1536 bytes per output site). Beside it, the oracle's FP64
+    even-odd CGNE: the whole 8^4 solve on one core and on all cores, and a
+    2-iteration sample of the 32^3x64 solve on all cores."""
     import numpy as np
     import oracle
     oracle.lib()
@@ -132,35 +214,64 @@ def cpu_baseline(dims, U, b, kappa, csw):
     dt = (time.perf_counter() - t0) / reps
     gbs = (V // 2) * 1536 / dt / 1e9
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    solves = {}
+    try:
+        solves["cgne_8x4_1core"] = run_oracle_solve("8x4", 1)
+        solves["cgne_8x4_all_cores"] = run_oracle_solve("8x4", cores)
+        s = run_oracle_solve("32x64", cores)
+        s["seconds_per_iteration"] = round(s["solve_s"] / max(1, s["iters"]), 3)
+        solves["cgne_32x64_sample_all_cores"] = s
+    except Exception as e:  # the dslash figure stands without them
+        log("oracle solve timing failed: %s" % e)
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
             "sample": "%d applications of the FP64 Wilson hopping term (one parity) on the full %s lattice, "
-                      "%.2f s each" % (reps, "x".join(map(str, dims)), dt)}
+                      "%.2f s each" % (reps, "x".join(map(str, dims)), dt),
+            "cpu_model": cpu_model(), "solves": solves}
+
+
+def timed_solves(n, fn):
+    """One warm-up solve, then n timed ones: (median seconds, all seconds, the
+    info of the median run). fn() returns (status, info)."""
+    fn()
+    runs = []
+    for _ in range(n):
+        st, info = fn()
+        runs.append((info.seconds, info))
+    runs.sort(key=lambda r: r[0])
+    return runs[len(runs) // 2][0], [round(r[0], 4) for r in runs], runs[len(runs) // 2][1]
+
+
+def solve_record(med, allt, info):
+    return {"seconds": round(med, 4), "seconds_runs": allt, "steps": info.iters, "restarts": info.restarts,
+            "matvecs": info.matvecs, "true_residual": info.true_residual}
 
 
 def learned_solves(args, L, ops, ctx, o64, o32, o32b, bp, net, prm):
-    """Two FGCR solves with the network (the faster one reported) and GCR
-    without a preconditioner."""
+    """FGCR with the network and GCR without a preconditioner (median of
+    args.solves each, after a warm-up)."""
     import ctypes
     prm.learned = ctypes.pointer(net.net)
-    best = None
-    for _ in range(2):
+
+    def fgcr():
         x = o64.spinor(full=True)
         st, info = L.lqcd_gcr_solve(ctx, o64.op, o32.op, o32b.op, prm, x, bp)
         assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
-        if best is None or info.seconds < best.seconds:
-            best = info
-    # the same outer solver without a preconditioner, for the network's gain
-    x = o64.spinor(full=True)
-    st, plain = L.lqcd_gcr_solve(ctx, o64.op, o32.op, None, ops.gcr_params(1e-10, 16, 1e-3, max_iter=5000), x, bp)
-    assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
-    log("GCR without preconditioner: %d steps, %.3f s, true residual %.2e" % (plain.iters, plain.seconds,
-                                                                           plain.true_residual))
+        return st, info
+
+    def plain():
+        x = o64.spinor(full=True)
+        st, info = L.lqcd_gcr_solve(ctx, o64.op, o32.op, None, ops.gcr_params(1e-10, 16, 1e-3, max_iter=5000), x, bp)
+        assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+        return st, info
+
+    med, allt, best = timed_solves(args.solves, fgcr)
+    pmed, pall, pinfo = timed_solves(args.solves, plain)
+    log("GCR without preconditioner: %d steps, %.3f s, true residual %.2e" % (pinfo.iters, pmed, pinfo.true_residual))
     log("FGCR(PTC): %d steps (%d Schwarz fallback), %.3f s, true residual %.2e" % (
-        best.iters, best.fallback_applies, best.seconds, best.true_residual))
-    return {"gcr_unpreconditioned_seconds": round(plain.seconds, 4), "gcr_unpreconditioned_steps": plain.iters,
-            "fgcr_learned_seconds": round(best.seconds, 4), "fgcr_learned_steps": best.iters,
-            "fgcr_learned_true_residual": best.true_residual,
-            "fgcr_learned_fallback_applies": best.fallback_applies}
+        best.iters, best.fallback_applies, med, best.true_residual))
+    r1, r2 = solve_record(pmed, pall, pinfo), solve_record(med, allt, best)
+    r2["fallback_applies"] = best.fallback_applies
+    return {"gcr_unpreconditioned": r1, "fgcr_learned": r2}
 
 
 def learned_solve(args, torch, L, ops, ctx, o64, o32, o32b, bp, block, mr, dims):
@@ -180,7 +291,7 @@ def learned_solve(args, torch, L, ops, ctx, o64, o32, o32b, bp, block, mr, dims)
     r = o32b.spinor()
     out = o32b.spinor()
     L.lqcd_spinor_convert(ctx, o32b.op, r, o64.op, bp, 0)
-    dt = time_kernel(torch, lambda: net.apply(o32b, out, r), 3)
+    dt = median_of([time_kernel(torch, lambda: net.apply(o32b, out, r), 1) for _ in range(7)])
     V = int(np.prod(dims))
     ch = net.channels
     # complex multiply-adds per site: cout*4 x cin*9*4 for each of 3 colours; both parities except the last layer
@@ -207,12 +318,14 @@ def staggered_workload(args, torch, L, ops, ctx):
     vh = int(np.prod(dims)) // 2
     out = {"dims": list(dims), "kernels": {}}
     inst = {}
+    odd_src = np.where(synth.parity_of_sites(dims)[..., None] == 1, chi, 0)
     for prec, recon in [(0, 18), (1, 18), (1, 12), (1, 8), (2, 12)]:
         o = ops.staggered(ctx, fat, U, dims, mass, prec, recon, U_device=Ud, fat_device=Fd)
         inst[(prec, recon)] = o
-        inp = o.import_spinor(np.where(synth.parity_of_sites(dims)[..., None] == 1, chi, 0), 1)
-        res = o.spinor()
-        dt = time_kernel(torch, lambda: L.lqcd_dslash(ctx, o.op, res, inp, 0), 20)
+        sets = [(r, r.import_spinor(odd_src, 1), r.spinor()) for r in (o, o.replica(), o.replica())]
+        dt = time_rotating(torch, [lambda r=r, i=i, q=q: L.lqcd_dslash(ctx, r.op, q, i, 0) for r, i, q in sets],
+                           args.dslash_launches // 2)
+        del sets
         byts = vh * (12 + 8 * 18 + 8 * recon) * PREC_BYTES[prec]
         out["kernels"]["stag_dslash_%s_r%d" % (PREC_NAME[prec], recon)] = {
             "us": round(dt * 1e6, 1), "GB/s": round(byts / dt / 1e9, 1), "frac": round(byts / dt / 1e9 / HBM_PEAK_GBS, 4)}
@@ -223,13 +336,17 @@ def staggered_workload(args, torch, L, ops, ctx):
     hi = inst[(0, 18)]
     b = hi.import_spinor(np.where(synth.parity_of_sites(dims)[..., None] == 0, chi, 0), 0)
     for name, lo in (("fp64", None), ("fp32_sloppy", inst[(1, 12)]), ("fp16_sloppy", inst[(2, 12)])):
-        x = hi.spinor()
-        st, info = L.lqcd_cg_solve(ctx, hi.op, lo.op if lo else None,
-                                   ops.cg_params(1e-10, 20000, 0.1, L.LQCD_CG_STAG_NORMAL), x, b)
-        out["cg_" + name] = {"status": st, "iters": info.iters, "updates": info.restarts,
-                             "seconds": round(info.seconds, 4), "true_residual": info.true_residual}
-        log("staggered CG %s: %d it, %.3f s, res %.2e" % (name, info.iters, info.seconds, info.true_residual))
+        def solve(lo=lo):
+            x = hi.spinor()
+            st, info = L.lqcd_cg_solve(ctx, hi.op, lo.op if lo else None,
+                                       ops.cg_params(1e-10, 20000, 0.1, L.LQCD_CG_STAG_NORMAL), x, b)
+            assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+            return st, info
+        med, allt, info = timed_solves(args.solves, solve)
+        out["cg_" + name] = solve_record(med, allt, info)
+        log("staggered CG %s: %d it, %.3f s, res %.2e" % (name, info.iters, med, info.true_residual))
     out["multishift"] = multishift_workload(L, ops, ctx, hi, inst[(1, 12)], b, mass)
+    out["speedup_fp32_sloppy_vs_fp64"] = round(out["cg_fp64"]["seconds"] / out["cg_fp32_sloppy"]["seconds"], 2)
     return out
 
 
@@ -240,9 +357,13 @@ def multishift_workload(L, ops, ctx, hi, lo, b, mass):
     import math
     shifts = [0.0] + [1e-4 * 4 ** k for k in range(7)]
     xs = [hi.spinor() for _ in shifts]
-    st, info = L.lqcd_multishift_cg_solve(ctx, hi.op, lo.op, ops.multishift_params(shifts, tol=1e-10, tol_sloppy=1e-8),
-                                          xs, b)
-    assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+    runs = []
+    for _ in range(4):  # a warm-up, then the median of 3
+        st, info = L.lqcd_multishift_cg_solve(ctx, hi.op, lo.op,
+                                              ops.multishift_params(shifts, tol=1e-10, tol_sloppy=1e-8), xs, b)
+        assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+        runs.append(info)
+    info = sorted(runs[1:], key=lambda i: i.seconds)[1]
     ref_iters = [info.shift[i].iters for i in range(len(shifts))]
     worst = max(info.shift[i].true_residual for i in range(len(shifts)))
     # the same systems one at a time: mixed-precision CG at mass sqrt(m^2 + sigma)
@@ -295,21 +416,24 @@ def batched_workload(args, torch, L, ops, ctx):
         U = synth.gauge_field(dims, 0.25, 4001)
         o = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon, tile=full_x_tile(dims))
         srcs = np.stack([synth.point_source(dims, sc // 3, sc % 3) for sc in range(12)])
-        inp = o.import_spinor(srcs, 0, nrhs=12)
-        res_ = o.spinor(nrhs=12)
+        reps = [o, o.replica(), o.replica()]
+        sets = [(r, r.import_spinor(srcs, 0, nrhs=12), r.spinor(nrhs=12)) for r in reps]
         vh = int(np.prod(dims)) // 2
         byts = vh * (12 * 48 + 8 * recon) * pb
-        single_in = o.import_spinor(srcs[0], 0)
-        single_out = o.spinor()
-        dt1 = time_kernel(torch, lambda: L.lqcd_dslash(ctx, o.op, single_out, single_in, 1), 20)
+        singles = [(r, r.import_spinor(srcs[0], 0), r.spinor()) for r in reps]
+        dt1 = time_rotating(torch, [lambda r=r, i=i, q=q: L.lqcd_dslash(ctx, r.op, q, i, 1) for r, i, q in singles],
+                            args.dslash_launches // 2)
         for mf in variants:
-            dt = with_mfma(mf, lambda: time_kernel(torch, lambda: L.lqcd_dslash(ctx, o.op, res_, inp, 1, nrhs=12), 20))
+            dt = with_mfma(mf, lambda: time_rotating(
+                torch, [lambda r=r, i=i, q=q: L.lqcd_dslash(ctx, r.op, q, i, 1, nrhs=12) for r, i, q in sets],
+                args.dslash_launches // 2))
             key = "point12_24x48_%s%s" % (PREC_NAME[prec], "_mfma" if mf else "")
             out[key] = {"us": round(dt * 1e6, 1), "GB/s": round(byts / dt / 1e9, 1), "bytes": byts,
                         "us_per_rhs": round(dt * 1e6 / 12, 2), "single_rhs_us": round(dt1 * 1e6, 1),
                         "speedup_vs_sequential": round(12 * dt1 / dt, 2)}
             log("batched %s%s: 12 point sources %.1f us (%.1f GB/s, x%.2f vs 12 single-source launches)" % (
                 PREC_NAME[prec], " mfma" if mf else "", dt * 1e6, byts / dt / 1e9, 12 * dt1 / dt))
+        del sets, singles, reps
         # mixed batch, one persistent launch
         jobs, keep, tot_bytes = [], [], 0
         for k, dims in enumerate(((16, 16, 16, 32), (20, 20, 20, 40), (24, 24, 24, 48))):
@@ -322,22 +446,85 @@ def batched_workload(args, torch, L, ops, ctx):
             jobs.append((ok.op, o_, i_, 0, 4))
             keep.append((ok, i_, o_))
             tot_bytes += int(np.prod(dims)) // 2 * (4 * 48 + 8 * recon) * pb
+        # three buffer sets of the whole batch (links, inputs, outputs)
+        jsets = [jobs]
+        for _ in range(2):
+            js = []
+            for ok, i_, o_ in keep[:3]:
+                rk = ok.replica()
+                i2, o2 = i_.clone(), torch.empty_like(o_)
+                js.append((rk.op, o2, i2, 0, 4))
+                keep.append((rk, i2, o2))
+            jsets.append(js)
         for mf in variants:
-            def separate():  # the three launches in turn, as a caller without batching would run them
-                for j in jobs:
+            def separate(js):  # the three launches in turn, as a caller without batching would run them
+                for j in js:
                     L.lqcd_dslash(ctx, j[0], j[1], j[2], 0, nrhs=4)
-            seq = with_mfma(mf, lambda: time_kernel(torch, separate, 10))
-            dtb = with_mfma(mf, lambda: time_kernel(torch, lambda: L.lqcd_dslash_batch(ctx, jobs), 20))
+            seq = with_mfma(mf, lambda: time_rotating(torch, [lambda js=js: separate(js) for js in jsets], 30))
+            dtb = with_mfma(mf, lambda: time_rotating(
+                torch, [lambda js=js: L.lqcd_dslash_batch(ctx, js) for js in jsets], args.dslash_launches // 2))
             key = "mixed3x4_%s%s" % (PREC_NAME[prec], "_mfma" if mf else "")
             out[key] = {"us": round(dtb * 1e6, 1), "GB/s": round(tot_bytes / dtb / 1e9, 1), "bytes": tot_bytes,
                         "separate_launches_us": round(seq * 1e6, 1)}
             log("batched %s%s: mixed batch %.1f us (%.1f GB/s; separate launches %.1f us)" % (
                 PREC_NAME[prec], " mfma" if mf else "", dtb * 1e6, tot_bytes / dtb / 1e9, seq * 1e6))
+        del jsets, jobs, keep
+    out["solve_point12_24x48"] = batched_solve(args, torch, L, ops, ctx)
     return out
+
+
+def batched_solve(args, torch, L, ops, ctx):
+    """The batched workload's solve: even-odd CGNE for the 12 point sources on
+    24^3x48 (kappa 0.122) with FP32 sloppy iterations and FP64 reliable
+    updates, all sources in one multi-source solve (each operator application
+    one launch over the 12 sources) against 12 single-source solves in
+    sequence; a warm-up, then the median of 3 of each."""
+    import numpy as np
+    import synth
+    dims = (24, 24, 24, 48)
+    U = synth.gauge_field(dims, 0.25, 4001)
+    Ud = torch.from_numpy(U).cuda()
+    t = full_x_tile(dims)
+    hi = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, 0, 18, tile=t, U_device=Ud)
+    lo = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, 1, 12, tile=t, U_device=Ud)
+    srcs = np.stack([synth.point_source(dims, sc // 3, sc % 3) for sc in range(12)])
+    bp = hi.import_spinor(srcs, -1, nrhs=12)
+    singles = [hi.import_spinor(srcs[j], -1) for j in range(12)]
+
+    def batch():
+        x = hi.spinor(full=True, nrhs=12)
+        prm = ops.cg_params(1e-10, 20000, 0.1, nrhs=12)
+        st, info = L.lqcd_cg_solve(ctx, hi.op, lo.op, prm, x, bp)
+        assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+        return st, info
+
+    def sequential():
+        tot, its, worst = 0.0, [], 0.0
+        for bj in singles:
+            x = hi.spinor(full=True)
+            st, info = L.lqcd_cg_solve(ctx, hi.op, lo.op, ops.cg_params(1e-10, 20000, 0.1), x, bj)
+            assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+            tot += info.seconds
+            its.append(info.iters)
+            worst = max(worst, info.true_residual)
+        return tot, its, worst
+
+    med, allt, info = timed_solves(3, batch)
+    sequential()
+    seq = sorted(sequential() for _ in range(3))[1]
+    log("12 point sources on 24^3x48, CGNE FP32/FP64: one multi-source solve %.3f s (%d iterations, worst residual "
+        "%.2e); 12 single-source solves %.3f s" % (med, info.iters, info.true_residual, seq[0]))
+    return {"batched_seconds": round(med, 4), "batched_seconds_runs": allt, "batched_iters": info.iters,
+            "batched_updates": info.restarts, "batched_worst_true_residual": info.true_residual,
+            "sequential_seconds": round(seq[0], 4), "sequential_iters": seq[1],
+            "sequential_worst_true_residual": seq[2], "speedup_vs_sequential": round(seq[0] / med, 2)}
 
 
 def main():
     args = parse()
+    if args.oracle_solve:
+        print(json.dumps(oracle_solve_timing(args.oracle_solve)))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X (--gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -355,7 +542,7 @@ def main():
         fn = staggered_workload if args.only == "staggered" else batched_workload
         res = {args.only: fn(args, torch, L, ops, ctx)}
         if args.kernels_only:
-            res["device_copy"] = device_copy(torch)  # calibrates the profiler's byte counters
+            res["device_copy"] = device_copy(torch, L, ctx)  # calibrates the profiler's byte counters
         print(json.dumps(res))
         L.lqcd_context_destroy(ctx)
         return
@@ -375,8 +562,27 @@ def main():
         res = {"learned": learned_solve(args, torch, L, ops, ctx, o64, o32, o32b, o64.import_spinor(b, -1), block, mr,
                                         dims)}
         if args.kernels_only:
-            res["device_copy"] = device_copy(torch)  # calibrates the profiler's byte counters
+            res["device_copy"] = device_copy(torch, L, ctx)  # calibrates the profiler's byte counters
         print(json.dumps(res))
+        L.lqcd_context_destroy(ctx)
+        return
+    if args.only == "solve":
+        # the solve alone, for a kernel trace: one warm-up and one timed GCR-DD
+        # solve (FP64 restarts, FP32 Krylov, FP16 Schwarz K on 8^4 blocks)
+        tile = stencil_tile(dims, block)
+        o64 = ops.wilson_clover(ctx, U, dims, kappa, csw, 0, 18, tile=tile, U_device=Ud)
+        o32 = ops.wilson_clover(ctx, U, dims, kappa, csw, 1, 12, tile=tile, U_device=Ud)
+        o16 = ops.wilson_clover(ctx, U, dims, kappa, csw, 2, 12, tile=block, U_device=Ud)
+        bp = o64.import_spinor(b, -1)
+        prm = ops.gcr_params(1e-10, k_max=16, delta=1e-3, max_iter=2000, precond=L.LQCD_PRECOND_SCHWARZ,
+                             block=block, mr_steps=mr)
+        out = []
+        for _ in range(2):
+            x = o64.spinor(full=True)
+            st, info = L.lqcd_gcr_solve(ctx, o64.op, o32.op, o16.op, prm, x, bp)
+            assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+            out.append(solve_record(info.seconds, [round(info.seconds, 4)], info))
+        print(json.dumps({"solve": out[-1], "warmup": out[0], "device_copy": device_copy(torch, L, ctx)}))
         L.lqcd_context_destroy(ctx)
         return
     # Stencil operators use tiles spanning the full x extent (the site order
@@ -392,129 +598,153 @@ def main():
     torch.cuda.synchronize()
     log("operators ready (stencil tile %s, Schwarz tile %s)" % (tile, block))
 
-    # ---- kernel table: Wilson dslash and Schur matvec, every precision/recon
+    # ---- kernel table: Wilson dslash and Schur matvec, every precision/recon,
+    # each the median over >= args.dslash_launches launches rotating over three
+    # buffer sets (links, clover, input and output of their own)
     kernels = {}
-    head = None
+    odd_b = np.where(synth.parity_of_sites(dims)[..., None, None] == 1, b, 0)
     for (prec, recon), o in inst.items():
-        inp = o.import_spinor(np.where(synth.parity_of_sites(dims)[..., None, None] == 1, b, 0), 1)
-        out = o.spinor()
-        dt = time_kernel(torch, lambda: L.lqcd_dslash(ctx, o.op, out, inp, 0, 0), args.dslash_launches)
+        reps = [o, o.replica(), o.replica()]
+        sets = [(r, r.import_spinor(odd_b, 1), r.spinor()) for r in reps]
+        dt = time_rotating(torch, [lambda r=r, i=i, q=q: L.lqcd_dslash(ctx, r.op, q, i, 0, 0) for r, i, q in sets],
+                           args.dslash_launches)
         byts = vh * WILSON_REALS[recon] * PREC_BYTES[prec]
         kernels["dslash_%s_r%d" % (PREC_NAME[prec], recon)] = {
             "us": round(dt * 1e6, 2), "GB/s": round(byts / dt / 1e9, 1),
             "frac": round(byts / dt / 1e9 / HBM_PEAK_GBS, 4), "bytes": byts}
-        if (prec, recon) == (1, 12):
-            head = (dt, byts)
-        ein = o.import_spinor(b, 0)
-        eout = o.spinor()
-        dts = time_kernel(torch, lambda: L.lqcd_schur_apply(ctx, o.op, eout, ein), max(5, args.dslash_launches // 4))
+        esets = [(r, r.import_spinor(b, 0), r.spinor()) for r in reps]
+        dts = time_rotating(torch, [lambda r=r, i=i, q=q: L.lqcd_schur_apply(ctx, r.op, q, i) for r, i, q in esets],
+                            max(30, args.dslash_launches // 4))
         sb = vh * SCHUR_REALS[recon] * PREC_BYTES[prec]
         kernels["schur_%s_r%d" % (PREC_NAME[prec], recon)] = {
             "us": round(dts * 1e6, 2), "GB/s": round(sb / dts / 1e9, 1),
             "frac": round(sb / dts / 1e9 / HBM_PEAK_GBS, 4), "bytes": sb}
         log("%-18s %8.1f us %7.1f GB/s | schur %8.1f us %7.1f GB/s" % (
             "%s r%d" % (PREC_NAME[prec], recon), dt * 1e6, byts / dt / 1e9, dts * 1e6, sb / dts / 1e9))
-    # the same kernel in the Schwarz block tiling, for comparison (skipped with
-    # --kernels-only, whose profiles group dispatches by kernel name and grid)
+        del reps, sets, esets
     if args.kernels_only:
-        print(json.dumps({"kernels": kernels, "device_copy": device_copy(torch)}))
+        print(json.dumps({"kernels": kernels, "device_copy": device_copy(torch, L, ctx),
+                          "tuned": L.lqcd_tuned_choices(ctx)}))
         return
-    inp = o32b.import_spinor(np.where(synth.parity_of_sites(dims)[..., None, None] == 1, b, 0), 1)
-    out = o32b.spinor()
-    dt = time_kernel(torch, lambda: L.lqcd_dslash(ctx, o32b.op, out, inp, 0, 0), args.dslash_launches)
+    # the same kernel in the Schwarz block tiling, for comparison
+    reps = [o32b, o32b.replica(), o32b.replica()]
+    sets = [(r, r.import_spinor(odd_b, 1), r.spinor()) for r in reps]
+    dt = time_rotating(torch, [lambda r=r, i=i, q=q: L.lqcd_dslash(ctx, r.op, q, i, 0, 0) for r, i, q in sets],
+                       args.dslash_launches)
     byts = vh * WILSON_REALS[12] * PREC_BYTES[1]
     kernels["dslash_f32_r12_block_tile"] = {"us": round(dt * 1e6, 2), "GB/s": round(byts / dt / 1e9, 1),
                                             "frac": round(byts / dt / 1e9 / HBM_PEAK_GBS, 4), "bytes": byts}
     log("f32 r12 in %s tiles %8.1f us %7.1f GB/s" % (block, dt * 1e6, byts / dt / 1e9))
-    copy = device_copy(torch)
-    log("device copy %.1f GB/s" % copy["GB/s"])
-    if args.kernels_only:
-        print(json.dumps({"kernels": kernels, "device_copy": copy}))
-        return
+    del reps, sets
+    copy = device_copy(torch, L, ctx)
+    log("streaming copy %.1f GB/s" % copy["GB/s"])
 
     o64, o32, o16 = inst[(0, 18)], inst[(1, 12)], o16b
     bp = o64.import_spinor(b, -1)
     prm = ops.gcr_params(1e-10, k_max=16, delta=1e-3, max_iter=2000, precond=L.LQCD_PRECOND_SCHWARZ,
                          block=block, mr_steps=mr)
-    inp = o32.import_spinor(np.where(synth.parity_of_sites(dims)[..., None, None] == 1, b, 0), 1)
-    out = o32.spinor()
-    ein, eout = o32.import_spinor(b, 0), o32.spinor()
+    hsets = [(r, r.import_spinor(odd_b, 1), r.spinor()) for r in (o32, o32.replica(), o32.replica())]
+    esets = [(r, r.import_spinor(b, 0), r.spinor()) for r, _, _ in hsets]
+    groups = max(1, -(-args.dslash_launches // 3))
 
     def step():
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s.record()
-        for _ in range(args.dslash_launches):
-            L.lqcd_dslash(ctx, o32.op, out, inp, 0, 0)
-        e.record()
-        for _ in range(5):
-            L.lqcd_schur_apply(ctx, o32.op, eout, ein)
+        """One pass over the path: the headline dslash (rotating over three
+        buffer sets, each group of three launches timed with HIP events), a
+        group of Schur matvecs, and one complete GCR-DD solve."""
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(groups + 1)]
+        ev[0].record()
+        for g in range(groups):
+            for r, i, q in hsets:
+                L.lqcd_dslash(ctx, r.op, q, i, 0, 0)
+            ev[g + 1].record()
+        for r, i, q in esets:
+            L.lqcd_schur_apply(ctx, r.op, q, i)
         x = o64.spinor(full=True)
         st, info = L.lqcd_gcr_solve(ctx, o64.op, o32.op, o16.op, prm, x, bp)
         assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
-        e.synchronize()
-        return s.elapsed_time(e) / 1e3 / args.dslash_launches, info
+        ev[-1].synchronize()
+        return [ev[g].elapsed_time(ev[g + 1]) / 1e3 / 3 for g in range(groups)], info
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    dts, infos = [], []
+    per, infos = [], []
     for _ in range(args.steps):
-        dt, info = step()
-        dts.append(dt)
+        p, info = step()
+        per += p
         infos.append(info)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    dt_avg = sum(dts) / len(dts)
-    byts = head[1]
-    gbs = byts / dt_avg / 1e9
-    gcr = infos[-1]
-    log("GCR-DD: %d steps, %d restarts, %.3f s, true residual %.2e" % (gcr.iters, gcr.restarts, gcr.seconds,
-                                                                      gcr.true_residual))
-    tts = {"gcr_dd_seconds": round(min(i.seconds for i in infos), 4), "gcr_dd_steps": gcr.iters,
-           "gcr_dd_restarts": gcr.restarts, "gcr_dd_true_residual": gcr.true_residual,
-           "precond_applies": gcr.precond_applies}
+    dt_head = median_of(per)
+    byts = vh * WILSON_REALS[12] * PREC_BYTES[1]
+    gbs = byts / dt_head / 1e9
+    log("headline dslash in the timed steps: median %.2f us over %d launches, %.1f GB/s" % (
+        dt_head * 1e6, 3 * len(per), gbs))
+    del hsets, esets
+
+    # ---- time to solution: one warm-up, then the median of args.solves, per solver
+    tts = {}
+
+    def gcr(precond_op, p):
+        def run():
+            x = o64.spinor(full=True)
+            st, info = L.lqcd_gcr_solve(ctx, o64.op, o32.op, precond_op, p, x, bp)
+            assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+            run.x = x
+            return st, info
+        return run
+
+    gold = load_oracle_solution()
+    run = gcr(o16.op, prm)
+    med, allt, info = timed_solves(args.solves, run)
+    tts["gcr_dd"] = solve_record(med, allt, info)
+    tts["gcr_dd"]["precond_applies"] = info.precond_applies
+    if gold is not None:
+        tts["gcr_dd"]["rel_error_vs_oracle"] = rel_error_sampled(o64, run.x, gold)
+    log("GCR-DD: %d steps, %.3f s (median of %d), true residual %.2e, vs oracle %s" % (
+        info.iters, med, args.solves, info.true_residual, tts["gcr_dd"].get("rel_error_vs_oracle")))
     if not args.no_cg:
-        x = o64.spinor(full=True)
-        st, cg = L.lqcd_cg_solve(ctx, o64.op, None, ops.cg_params(1e-10, max_iter=20000), x, bp)
-        log("FP64 CGNE: %d iterations, %.3f s, true residual %.2e" % (cg.iters, cg.seconds, cg.true_residual))
-        tts.update({"fp64_cg_seconds": round(cg.seconds, 4), "fp64_cg_iters": cg.iters,
-                    "fp64_cg_true_residual": cg.true_residual,
-                    "speedup_vs_fp64_cg": round(cg.seconds / tts["gcr_dd_seconds"], 2)})
+        def cg():
+            x = o64.spinor(full=True)
+            st, info = L.lqcd_cg_solve(ctx, o64.op, None, ops.cg_params(1e-10, max_iter=20000), x, bp)
+            assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+            cg.x = x
+            return st, info
+        med, allt, info = timed_solves(args.solves, cg)
+        tts["fp64_cg"] = solve_record(med, allt, info)
+        if gold is not None:
+            tts["fp64_cg"]["rel_error_vs_oracle"] = rel_error_sampled(o64, cg.x, gold)
+        log("FP64 CGNE: %d iterations, %.3f s, true residual %.2e" % (info.iters, med, info.true_residual))
     # GCR-DD with the multiplicative Schwarz K (two block colours), FP16, same blocks
     sap_mr, sap_cycles = 4, 3
     sprm = ops.gcr_params(1e-10, k_max=16, delta=1e-3, max_iter=2000, precond=L.LQCD_PRECOND_SCHWARZ,
                           block=block, mr_steps=sap_mr, cycles=sap_cycles)
-    best = None
-    for _ in range(3):
-        x = o64.spinor(full=True)
-        st, si = L.lqcd_gcr_solve(ctx, o64.op, o32.op, o16.op, sprm, x, bp)
-        assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
-        best = si if best is None or si.seconds < best.seconds else best
+    med, allt, info = timed_solves(args.solves, gcr(o16.op, sprm))
+    tts["gcr_dd_sap"] = solve_record(med, allt, info)
+    tts["gcr_dd_sap"].update({"mr_steps": sap_mr, "cycles": sap_cycles})
     log("GCR-DD with multiplicative Schwarz (%d MR steps, %d cycles): %d steps, %.3f s, true residual %.2e" % (
-        sap_mr, sap_cycles, best.iters, best.seconds, best.true_residual))
-    tts.update({"gcr_dd_sap_seconds": round(best.seconds, 4), "gcr_dd_sap_steps": best.iters,
-                "gcr_dd_sap_true_residual": best.true_residual, "gcr_dd_sap_mr_steps": sap_mr,
-                "gcr_dd_sap_cycles": sap_cycles})
+        sap_mr, sap_cycles, info.iters, med, info.true_residual))
     # mixed-precision BiCGstab (FP64 reliable updates), the paper's baseline for GCR-DD
     for sp in (1, 2):
-        x = o64.spinor(full=True)
-        bprm = ops.bicgstab_params(1e-10, 5000, 0.1)
-        L.lqcd_bicgstab_solve(ctx, o64.op, inst[(sp, 12)].op, bprm, x, bp)  # warm-up
-        best = None
-        for _ in range(3):
+        def bicg(sp=sp):
             x = o64.spinor(full=True)
-            st, bi = L.lqcd_bicgstab_solve(ctx, o64.op, inst[(sp, 12)].op, bprm, x, bp)
+            st, info = L.lqcd_bicgstab_solve(ctx, o64.op, inst[(sp, 12)].op, ops.bicgstab_params(1e-10, 5000, 0.1),
+                                             x, bp)
             assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
-            best = bi if best is None or bi.seconds < best.seconds else best
+            return st, info
+        med, allt, info = timed_solves(args.solves, bicg)
         name = "bicgstab_%s" % PREC_NAME[sp]
+        tts[name] = solve_record(med, allt, info)
         log("BiCGstab FP64/%s: %d steps, %d reliable updates, %.3f s, true residual %.2e" % (
-            PREC_NAME[sp].upper(), best.iters, best.restarts, best.seconds, best.true_residual))
-        tts.update({name + "_seconds": round(best.seconds, 4), name + "_steps": best.iters,
-                    name + "_true_residual": best.true_residual,
-                    "gcr_dd_speedup_vs_" + name: round(best.seconds / tts["gcr_dd_seconds"], 2)})
+            PREC_NAME[sp].upper(), info.iters, info.restarts, med, info.true_residual))
     if os.path.exists(args.learned):
         tts.update(learned_solve(args, torch, L, ops, ctx, o64, o32, o32b, bp, block, mr, dims))
+    if "fp64_cg" in tts:
+        ref = tts["fp64_cg"]["seconds"]
+        tts["speedup_vs_fp64_cg"] = {k: round(ref / v["seconds"], 2) for k, v in tts.items()
+                                     if isinstance(v, dict) and "seconds" in v and k != "fp64_cg"}
+    tts["smallest_8x4_fp64_cgne"] = smallest_workload(args, torch, L, ops, ctx)
     res = {
         "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 2), "higher_is_better": True,
@@ -524,12 +754,15 @@ def main():
                                    "x".join(map(str, dims)), kappa, csw, eps, mr),
                    "dims": list(dims), "tile": list(tile), "schwarz_tile": list(block),
                    "kernel": "wilson dslash f32 recon12, one parity",
-                   "dslash_launches_per_step": args.dslash_launches},
+                   "dslash_launches_per_step": 3 * groups, "buffer_sets": 3,
+                   "timing": "median over groups of 3 launches (one per buffer set)"},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": (PROFILED_TRAFFIC["bytes_per_launch"]
                                  if kernel_sources_sha1() == PROFILED_TRAFFIC["sources_sha1"] else None),
-                     "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": byts},
+                     "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": byts,
+                     "median_launch_us": round(dt_head * 1e6, 2),
+                     "frac_of_streaming_copy": round(gbs / copy["GB/s"], 4)},
         "time_to_solution": tts,
         "device_copy": copy,
         "kernels": kernels,
@@ -538,12 +771,49 @@ def main():
         res["staggered"] = staggered_workload(args, torch, L, ops, ctx)
     if not args.no_batched:
         res["batched"] = batched_workload(args, torch, L, ops, ctx)
+    res["tuned"] = L.lqcd_tuned_choices(ctx)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline(dims, U, b, kappa, csw)
     torch.cuda.synchronize()
     L.lqcd_context_destroy(ctx)
     print(json.dumps(res))
+
+
+def load_oracle_solution():
+    """The oracle's FP64 solution of the default workload at 2048 sampled sites
+    (written by tests/golden/make_wilson_solution_32x64.py), or None."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "wilson_solution_32x64_sites.npz")
+    return np.load(path) if os.path.exists(path) else None
+
+
+def rel_error_sampled(o64, x, gold):
+    """||x - x_ora|| / ||x_ora|| over the sampled sites of the stored oracle solution."""
+    import numpy as np
+    xs = o64.export_spinor(x, -1).cpu().numpy().reshape(-1, 4, 3)[gold["sites"]]
+    return float(np.linalg.norm(xs - gold["x"]) / np.linalg.norm(gold["x"]))
+
+
+def smallest_workload(args, torch, L, ops, ctx):
+    """8^4 Wilson-clover (kappa 0.12, c_sw 1, eps 0.25, seeds 1001/1002): FP64
+    even-odd CGNE to 1e-10 on the GPU (a warm-up, then the median of
+    args.solves). Latency-bound (2048 even sites), not a bandwidth datum."""
+    import synth
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_field(dims, 0.25, 1001)
+    b = synth.gaussian_spinor(dims, 1002)
+    o = ops.wilson_clover(ctx, U, dims, 0.12, 1.0, 0, 18)
+    bp = o.import_spinor(b, -1)
+
+    def run():
+        x = o.spinor(full=True)
+        st, info = L.lqcd_cg_solve(ctx, o.op, None, ops.cg_params(1e-10, 20000), x, bp)
+        assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+        return st, info
+    med, allt, info = timed_solves(args.solves, run)
+    log("8^4 FP64 CGNE: %d iterations, %.4f s" % (info.iters, med))
+    return solve_record(med, allt, info)
 
 
 if __name__ == "__main__":

@@ -121,7 +121,7 @@ typedef struct {
   int32_t matvecs;           /* operator applications in the Krylov precision */
   int32_t precond_applies;   /* applications of K */
   int32_t fallback_applies;  /* of those, Schwarz steps taken in place of the learned K */
-  int32_t reserved;          /* zero */
+  int32_t history_len;       /* entries written to the params' res_history (0 without one) */
   double true_residual;      /* ||b - M x|| / ||b||, recomputed in FP64 at the end */
   double seconds;            /* wall time of the call */
 } lqcd_solve_info;
@@ -152,6 +152,8 @@ typedef struct {
   int32_t block[4]; /* Dirichlet block; must equal the tile of op_precond */
   int32_t mr_steps; /* MR steps per block and visit (the paper uses 10) */
   int32_t cycles;   /* 0: additive (the paper's); n >= 1: multiplicative, n sweeps over the two block colours */
+  double omega;     /* MR over-relaxation, 0 < omega < 2: x += omega a r, r -= omega a q; 0 is read as 1,
+                       the plain MR of Section VIII-A (the paper gives no relaxation factor) */
 } lqcd_schwarz_params;
 
 typedef struct {
@@ -162,6 +164,12 @@ typedef struct {
   int32_t precond;   /* lqcd_precond_kind */
   lqcd_schwarz_params schwarz; /* SCHWARZ; with LEARNED, the fallback (mr_steps 0: none) */
   const lqcd_ptc_net *learned; /* LEARNED: the network (op_precond: FP32 instance for its transports) */
+  /* Optional residual history (host memory, may be NULL): entry k receives
+   * ||rhat|| after Krylov step k+1 (the iterated residual of Algorithm 1, in
+   * the Krylov precision, not divided by ||b||), while k < res_history_max;
+   * info->history_len is the number written. */
+  double *res_history;
+  int32_t res_history_max;
 } lqcd_gcr_params;
 
 typedef enum { LQCD_CG_CGNE_SCHUR = 0, LQCD_CG_STAG_NORMAL = 1 } lqcd_cg_kind;
@@ -183,7 +191,24 @@ typedef struct {
   int32_t record_every;
   int32_t record_max;
   int32_t *record_count;
+  /* Right-hand sides solved together (0 is read as 1), at most LQCD_MAX_CG_RHS.
+   * x and b then hold nrhs fields in the multi-source layout of
+   * lqcd_spinor_import; every system runs its own CG recurrences and stops on
+   * its own ||b_j - A x_j|| <= tol ||b_j||, while the operator is applied to
+   * all sources in one launch (each link is read once for all of them). */
+  int32_t nrhs;
+  /* Optional (host, may be NULL): nrhs entries, the final FP64 true residual
+   * ||b_j - M x_j|| / ||b_j|| of each system (info->true_residual is their
+   * maximum). */
+  double *rhs_residuals;
+  /* Optional residual history (host, may be NULL; nrhs = 1): entry k receives
+   * ||r|| after iteration k+1 (the iterated residual, in absolute units:
+   * ||bhat - Mhat x|| for CGNE_SCHUR), while k < res_history_max. */
+  double *res_history;
+  int32_t res_history_max;
 } lqcd_cg_params;
+
+#define LQCD_MAX_CG_RHS 32
 
 /* ---------------------------------------------------------------------- */
 /* context and sizes                                                       */
@@ -196,6 +221,26 @@ const char *lqcd_last_error(const lqcd_context *ctx);
 
 /* Bytes of one packed field of `kind` for operator `op` with nrhs right-hand sides. */
 lqcd_status lqcd_field_bytes(const lqcd_operator *op, int32_t kind, int32_t nrhs, size_t *bytes);
+
+/*
+ * dst = src on the device, `bytes` a multiple of 16 (both pointers 16-byte
+ * aligned, not overlapping): one streaming pass of 16-byte loads and stores.
+ * Not part of the paper's method: it measures the bandwidth a
+ * read-once/write-once kernel reaches on this GPU (the practical ceiling next
+ * to the stencil kernels) and calibrates hardware byte counters with a kernel
+ * of known traffic.
+ */
+lqcd_status lqcd_stream_copy(lqcd_context *ctx, void *dst, const void *src, size_t bytes, lqcd_stream stream);
+
+/*
+ * The autotuner's choices so far in this context, as text: one
+ * "key<TAB>value" line per tuned kernel shape (kernel, precision, link format,
+ * lattice/tile and source count in the key; workgroup size, batch form or
+ * network form as the value). Writes at most cap bytes including the
+ * terminating NUL (buf may be NULL to query); *len receives the full size
+ * needed, NUL included.
+ */
+lqcd_status lqcd_tuned_choices(lqcd_context *ctx, char *buf, size_t cap, size_t *len);
 
 /* ---------------------------------------------------------------------- */
 /* setup: packing and derived fields                                       */
@@ -365,6 +410,8 @@ lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op_hi,
 /*
  * CG (Section III-A) with reliable updates when op_sloppy is less precise
  * than op_hi (x and the true residual kept in op_hi's precision).
+ * params->nrhs > 1 solves that many systems with the same operator at once
+ * (x and b in the multi-source layout; see lqcd_cg_params).
  * kind = LQCD_CG_CGNE_SCHUR: solves M x = b for the full Wilson-clover
  *   lattice through CG on the normal equations of Mhat (x, b packed FULL);
  * kind = LQCD_CG_STAG_NORMAL: solves N_e x_e = b_e on even sites (eq. (4)

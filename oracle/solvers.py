@@ -164,12 +164,13 @@ def cgne(apply_A, apply_Adag, b, tol=1e-10, maxiter=10000, x0=None):
     return x, it, hist
 
 
-def mr_blocks(apply_A, b, nsteps, labels=None, site_axes=4):
+def mr_blocks(apply_A, b, nsteps, labels=None, site_axes=4, omega=1.0):
     """Minimal-residual iteration started from x = 0, r = b, run independently on
     every Dirichlet block: inner products are summed over one block only
     (domain-restricted reductions, Section VIII-A). labels: integer block id per
     site (natural grid) or None for one block. Each step:
-        q = A r ; alpha = <q,r>/<q,q> ; x += alpha r ; r -= alpha q.
+        q = A r ; alpha = omega <q,r>/<q,q> ; x += alpha r ; r -= alpha q,
+    omega the over-relaxation factor (1: plain MR; the paper gives none).
     """
     x = np.zeros_like(b)
     r = b.copy()
@@ -179,7 +180,7 @@ def mr_blocks(apply_A, b, nsteps, labels=None, site_axes=4):
             qq = dot(q, q).real
             if qq == 0.0:
                 break
-            alpha = dot(q, r) / qq
+            alpha = omega * dot(q, r) / qq
             x += alpha * r
             r -= alpha * q
         return x
@@ -193,21 +194,21 @@ def mr_blocks(apply_A, b, nsteps, labels=None, site_axes=4):
         qr = np.bincount(lab, weights=np.sum(np.conj(qf) * rf, axis=1).real, minlength=nb) \
             + 1j * np.bincount(lab, weights=np.sum(np.conj(qf) * rf, axis=1).imag, minlength=nb)
         qq = np.bincount(lab, weights=np.sum(np.abs(qf) ** 2, axis=1), minlength=nb)
-        alpha = np.where(qq > 0, qr / np.where(qq > 0, qq, 1.0), 0.0)
+        alpha = omega * np.where(qq > 0, qr / np.where(qq > 0, qq, 1.0), 0.0)
         a_site = alpha[labels].reshape(labels.shape + (1,) * (b.ndim - site_axes))
         x += a_site * r
         r -= a_site * q
     return x
 
 
-def schwarz(op, r, block, nsteps):
+def schwarz(op, r, block, nsteps, omega=1.0):
     """Non-overlapping additive Schwarz preconditioner (block Jacobi,
     Section III-B): on every block B of size `block`, nsteps of MR on the
     Dirichlet-cut even-odd operator Mhat_B with block-restricted inner products.
     op is an oracle.WilsonClover; r lives on even sites."""
     from . import block_labels
     labels = block_labels(op.dims, block)
-    return mr_blocks(lambda v: op.schur(v, block=block), r, nsteps, labels)
+    return mr_blocks(lambda v: op.schur(v, block=block), r, nsteps, labels, omega=omega)
 
 
 def block_colour(dims, block):
@@ -221,7 +222,7 @@ def block_colour(dims, block):
     return (x // bx + y // by + z // bz + t // bt) % 2
 
 
-def sap(op, r, block, nsteps, ncycles):
+def sap(op, r, block, nsteps, ncycles, omega=1.0):
     """Multiplicative Schwarz (the Schwarz alternating procedure) on the
     Dirichlet blocks of `block`, coloured as a checkerboard (block_colour).
     Starting from x = 0, each cycle visits colour 0 then colour 1; a visit
@@ -239,7 +240,7 @@ def sap(op, r, block, nsteps, ncycles):
         for c in (0, 1):
             res = r - op.schur(x)
             res = np.where(((colour == c) & op.even)[..., None, None], res, 0)
-            x = x + mr_blocks(lambda v: op.schur(v, block=block), res, nsteps, labels)
+            x = x + mr_blocks(lambda v: op.schur(v, block=block), res, nsteps, labels, omega=omega)
     return x
 
 

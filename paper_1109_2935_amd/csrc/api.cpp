@@ -118,9 +118,11 @@ lqcd_status scratch(lqcd_context *ctx, int slot, size_t bytes, void **ptr) {
     ctx->scratch_bytes.resize(slot + 1, 0);
   }
   if (ctx->scratch_bytes[slot] < bytes) {
+    // A slot that must grow keeps its old buffer until the context is
+    // destroyed: work already enqueued may still use it, and freeing it here
+    // would stall every stream of the device in the middle of a call.
     if (ctx->scratch[slot]) {
-      hipDeviceSynchronize();
-      hipFree(ctx->scratch[slot]);
+      ctx->retired.push_back(ctx->scratch[slot]);
       ctx->scratch[slot] = nullptr;
       ctx->scratch_bytes[slot] = 0;
     }
@@ -272,11 +274,12 @@ lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schw
   s = hip_check(ctx, hipMemcpyAsync(r, in, sb, hipMemcpyDeviceToDevice, st), "schwarz copy");
   if (s) return s;
   const int nps = info.g.Vt2 > 64 ? info.g.Vt2 / 64 : 1;  // reduction segments per block
+  const double omega = prm->omega == 0 ? 1.0 : prm->omega;
   if (prm->cycles == 0) {
     // additive: MR on every block at once
     for (int it = 0; it < prm->mr_steps; ++it) {
       if ((s = schur_apply(ctx, info, g, q, r, t, 0, (double *)part, st))) return s;
-      if ((s = hip_check(ctx, launch_mr_update(info.g, info.prec, out, r, q, (const double *)part, nps, it == 0, st),
+      if ((s = hip_check(ctx, launch_mr_update(info.g, info.prec, out, r, q, (const double *)part, nps, it == 0, omega, st),
                          "schwarz MR update")))
         return s;
     }
@@ -296,7 +299,7 @@ lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schw
       for (int it = 0; it < prm->mr_steps; ++it) {
         if ((s = schur_apply(ctx, info, gc[c], q, r, t, 0, (double *)part, st))) return s;
         if ((s = hip_check(ctx, launch_mr_update(gc[c], info.prec, out, r, q, (const double *)part, nps,
-                                                 cyc == 0 && it == 0, st),
+                                                 cyc == 0 && it == 0, omega, st),
                            "schwarz MR update")))
           return s;
       }
@@ -319,6 +322,8 @@ lqcd_status check_schwarz(lqcd_context *ctx, const OpInfo &info, const lqcd_schw
   if (s) return s;
   if (prm->mr_steps < 1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "mr_steps must be >= 1");
   if (prm->cycles < 0 || prm->cycles > 64) return set_error(ctx, LQCD_ERR_INVALID_ARG, "cycles must be in 0 .. 64");
+  if (!(prm->omega >= 0 && prm->omega < 2))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "omega must be in (0, 2) (0 selects 1)");
   if (prm->cycles > 0 && (info.g.NT[0] & 1))
     return set_error(ctx, LQCD_ERR_UNSUPPORTED,
                      "multiplicative Schwarz needs an even number of blocks along x (the colours alternate there)");
@@ -349,6 +354,8 @@ lqcd_status check_fields_internal(lqcd_context *ctx, const lqcd_operator *op) {
 
 extern "C" {
 
+static bool aligned16(const void *p);
+
 lqcd_status lqcd_context_create(lqcd_context **out) {
   if (!out) return set_error(nullptr, LQCD_ERR_INVALID_ARG, "ctx pointer is NULL");
   lqcd_context *ctx = new lqcd_context();
@@ -375,12 +382,21 @@ lqcd_status lqcd_context_destroy(lqcd_context *ctx) {
   hipDeviceSynchronize();
   for (void *p : ctx->scratch)
     if (p) hipFree(p);
+  for (void *p : ctx->retired) hipFree(p);
   if (ctx->red_partials) hipFree(ctx->red_partials);
   if (ctx->red_counter) hipFree(ctx->red_counter);
   if (ctx->red_result) hipFree(ctx->red_result);
   if (ctx->red_host) hipHostFree(ctx->red_host);
   delete ctx;
   return LQCD_OK;
+}
+
+lqcd_status lqcd_stream_copy(lqcd_context *ctx, void *dst, const void *src, size_t bytes, lqcd_stream stream) {
+  if (!aligned16(dst) || !aligned16(src) || bytes % 16)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+  const char *d = (const char *)dst, *s = (const char *)src;
+  if (d < s + bytes && s < d + bytes) return set_error(ctx, LQCD_ERR_INVALID_ARG, "copy source and destination overlap");
+  return hip_check(ctx, blas_stream_copy(dst, src, bytes, (hipStream_t)stream), "stream copy");
 }
 
 const char *lqcd_last_error(const lqcd_context *ctx) { return ctx ? ctx->last_error.c_str() : g_last_error.c_str(); }

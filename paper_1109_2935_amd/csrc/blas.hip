@@ -16,6 +16,7 @@ namespace lqcd {
 constexpr int kBT = 256;
 constexpr int kMaxVec = 32;
 constexpr int kMaxShiftVec = 17;  // 16 shifted systems and the base direction
+constexpr int kMaxRhs = LQCD_MAX_CG_RHS;  // sources of one multi-source kernel
 
 // 4 consecutive reals (2 complex numbers) of storage type S.
 template <typename S> struct Quad;
@@ -504,6 +505,249 @@ hipError_t blas_cg_update(int px, void *x, const void *p, int pr, void *r, const
     hipLaunchKernelGGL((cg_update_kernel<T1, T2>), dim3(g), dim3(kBT), 0, st, (T1 *)x, (const T1 *)p, (T2 *)r,
                        (const T2 *)q, nq, a, red);
     return hipGetLastError();});
+}
+
+
+// ---------------------------------------------------------------------------
+// Several right-hand sides, in the multi-source layout (blocks of R sources,
+// lqcd_device.h): workgroup row blockIdx.y serves source blockIdx.y, each
+// thread one site of it with all its reals, so every source has its own
+// coefficients and its own reductions. The reductions keep the fixed order
+// of grid_reduce: per-thread sums, the wave butterfly, the waves through
+// LDS, then the last workgroup of the launch sums each row's partials in
+// workgroup order.
+
+template <int NR>
+__device__ void grid_reduce_rows(double (&v)[NR], RedScratch r) {
+  __shared__ double lds[kBT / 64][NR];
+  __shared__ int last;
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) lds[wave][k] = v[k];
+  __syncthreads();
+  const size_t gx = gridDim.x, row = blockIdx.y;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NR; ++k) {
+      double t = 0;
+      for (int w = 0; w < kBT / 64; ++w) t += lds[w][k];
+      __hip_atomic_store(r.partials + (row * gx + blockIdx.x) * NR + k, t, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __threadfence();
+    const unsigned ticket = atomicAdd(r.counter, 1u);
+    last = (ticket == gridDim.x * gridDim.y - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (unsigned rw = 0; rw < gridDim.y; ++rw) {
+    double acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = 0;
+    for (size_t w = threadIdx.x; w < gx; w += kBT)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] += atomic_load_relaxed(r.partials + (rw * gx + w) * NR + k);
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) lds[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int k = 0; k < NR; ++k) {
+        double t = 0;
+        for (int w = 0; w < kBT / 64; ++w) t += lds[w][k];
+        r.result[rw * NR + k] = t;
+      }
+  }
+  if (threadIdx.x == 0) atomicExch(r.counter, 0u);
+}
+
+struct RhsCoef {
+  double a[kMaxRhs], b[kMaxRhs];
+};
+
+// y_j = a_j x_j + b_j y_j (y not read where b_j = 0); RED: ||y_j||^2 of the stored y.
+template <typename SX, typename SY, int NSP, bool RED>
+__global__ void __launch_bounds__(kBT) mrhs_axpby_kernel(const SX *x, SY *y, int64_t vh, int nrhs, RhsCoef c,
+                                                        RedScratch r) {
+  const int j = blockIdx.y, R = rhs_group(nrhs);
+  const int64_t stride = vh * nrhs;
+  const double a = c.a[j], b = c.b[j];
+  double acc[1] = {0};
+  for (int64_t s = (int64_t)blockIdx.x * kBT + threadIdx.x; s < vh; s += (int64_t)gridDim.x * kBT) {
+    const int64_t i = rhs_index(j, s, vh, R);
+    double xv[NSP], yv[NSP];
+    load_spinor_reals<SX, NSP, double>(x, stride, i, xv);
+    if (b != 0) {
+      load_spinor_reals<SY, NSP, double>(y, stride, i, yv);
+#pragma unroll
+      for (int k = 0; k < NSP; ++k) yv[k] = a * xv[k] + b * yv[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < NSP; ++k) yv[k] = a * xv[k];
+    }
+    store_spinor_reals<SY, NSP, double>(y, stride, i, yv);
+    if (RED) {
+      load_spinor_reals<SY, NSP, double>(y, stride, i, yv);
+#pragma unroll
+      for (int k = 0; k < NSP; ++k) acc[0] += yv[k] * yv[k];
+    }
+  }
+  if (RED) grid_reduce_rows<1>(acc, r);
+}
+
+// <x_j, y_j> (re, im) per source
+template <typename S, int NSP>
+__global__ void __launch_bounds__(kBT) mrhs_cdot_kernel(const S *x, const S *y, int64_t vh, int nrhs, RedScratch r) {
+  const int j = blockIdx.y, R = rhs_group(nrhs);
+  const int64_t stride = vh * nrhs;
+  double acc[2] = {0, 0};
+  for (int64_t s = (int64_t)blockIdx.x * kBT + threadIdx.x; s < vh; s += (int64_t)gridDim.x * kBT) {
+    const int64_t i = rhs_index(j, s, vh, R);
+    double xv[NSP], yv[NSP];
+    load_spinor_reals<S, NSP, double>(x, stride, i, xv);
+    load_spinor_reals<S, NSP, double>(y, stride, i, yv);
+#pragma unroll
+    for (int k = 0; k < NSP / 2; ++k) {
+      acc[0] += xv[2 * k] * yv[2 * k] + xv[2 * k + 1] * yv[2 * k + 1];
+      acc[1] += xv[2 * k] * yv[2 * k + 1] - xv[2 * k + 1] * yv[2 * k];
+    }
+  }
+  grid_reduce_rows<2>(acc, r);
+}
+
+// x_j += a_j p_j ; r_j -= a_j q_j ; ||r_j||^2 of the stored r
+template <typename SX, typename SR, int NSP>
+__global__ void __launch_bounds__(kBT) mrhs_cg_update_kernel(SX *x, const SX *p, SR *rv, const SR *q, int64_t vh,
+                                                            int nrhs, RhsCoef c, RedScratch r) {
+  const int j = blockIdx.y, R = rhs_group(nrhs);
+  const int64_t stride = vh * nrhs;
+  const double a = c.a[j];
+  double acc[1] = {0};
+  for (int64_t s = (int64_t)blockIdx.x * kBT + threadIdx.x; s < vh; s += (int64_t)gridDim.x * kBT) {
+    const int64_t i = rhs_index(j, s, vh, R);
+    double u[NSP], w[NSP];
+    if (a != 0) {
+      load_spinor_reals<SX, NSP, double>(x, stride, i, u);
+      load_spinor_reals<SX, NSP, double>(p, stride, i, w);
+#pragma unroll
+      for (int k = 0; k < NSP; ++k) u[k] += a * w[k];
+      store_spinor_reals<SX, NSP, double>(x, stride, i, u);
+      load_spinor_reals<SR, NSP, double>(rv, stride, i, u);
+      load_spinor_reals<SR, NSP, double>(q, stride, i, w);
+#pragma unroll
+      for (int k = 0; k < NSP; ++k) u[k] -= a * w[k];
+      store_spinor_reals<SR, NSP, double>(rv, stride, i, u);
+    }
+    load_spinor_reals<SR, NSP, double>(rv, stride, i, u);
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) acc[0] += u[k] * u[k];
+  }
+  grid_reduce_rows<1>(acc, r);
+}
+
+static int mrhs_grid(int64_t vh, int nrhs, int nr, const RedScratch *red) {
+  int64_t g = (vh + kBT - 1) / kBT;
+  const int64_t cap = red ? (int64_t)red->max_wg * kMaxRed / ((int64_t)nrhs * nr) : 4096;
+  if (g > cap) g = cap;
+  if (g > 4096) g = 4096;
+  return g < 1 ? 1 : (int)g;
+}
+
+template <typename F> static hipError_t dispatch_nsp(int nsp, F &&f) {
+  if (nsp == 24) return f(std::integral_constant<int, 24>());
+  if (nsp == 6) return f(std::integral_constant<int, 6>());
+  return hipErrorInvalidValue;
+}
+
+hipError_t blas_mrhs_axpby(int px, const void *x, int py, void *y, int64_t vh, int nsp, int nrhs, const double *a,
+                           const double *b, const RedScratch *red, hipStream_t st) {
+  if (nrhs < 1 || nrhs > kMaxRhs || (red && nrhs > kMaxRed)) return hipErrorInvalidValue;
+  RhsCoef c;
+  for (int j = 0; j < nrhs; ++j) {
+    c.a[j] = a[j];
+    c.b[j] = b[j];
+  }
+  const dim3 grid(mrhs_grid(vh, nrhs, 1, red), nrhs);
+  const RedScratch r = red ? *red : kNoRed;
+  return dispatch2(px, py, [&](auto t1, auto t2) -> hipError_t {
+    return dispatch_nsp(nsp, [&](auto ns) -> hipError_t {
+      constexpr int NS = decltype(ns)::value;
+      if (red)
+        hipLaunchKernelGGL((mrhs_axpby_kernel<T1, T2, NS, true>), grid, dim3(kBT), 0, st, (const T1 *)x, (T2 *)y, vh,
+                           nrhs, c, r);
+      else
+        hipLaunchKernelGGL((mrhs_axpby_kernel<T1, T2, NS, false>), grid, dim3(kBT), 0, st, (const T1 *)x, (T2 *)y, vh,
+                           nrhs, c, r);
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t blas_mrhs_cdot(int p, const void *x, const void *y, int64_t vh, int nsp, int nrhs, const RedScratch &red,
+                          hipStream_t st) {
+  if (nrhs < 1 || 2 * nrhs > kMaxRed) return hipErrorInvalidValue;
+  const dim3 grid(mrhs_grid(vh, nrhs, 2, &red), nrhs);
+  return dispatch1(p, [&](auto t1) -> hipError_t {
+    return dispatch_nsp(nsp, [&](auto ns) -> hipError_t {
+      constexpr int NS = decltype(ns)::value;
+      hipLaunchKernelGGL((mrhs_cdot_kernel<T1, NS>), grid, dim3(kBT), 0, st, (const T1 *)x, (const T1 *)y, vh, nrhs,
+                         red);
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t blas_mrhs_cg_update(int px, void *x, const void *p, int pr, void *r, const void *q, int64_t vh, int nsp,
+                               int nrhs, const double *a, const RedScratch &red, hipStream_t st) {
+  if (nrhs < 1 || nrhs > kMaxRhs || nrhs > kMaxRed) return hipErrorInvalidValue;
+  RhsCoef c;
+  for (int j = 0; j < nrhs; ++j) {
+    c.a[j] = a[j];
+    c.b[j] = 0;
+  }
+  const dim3 grid(mrhs_grid(vh, nrhs, 1, &red), nrhs);
+  return dispatch2(px, pr, [&](auto t1, auto t2) -> hipError_t {
+    return dispatch_nsp(nsp, [&](auto ns) -> hipError_t {
+      constexpr int NS = decltype(ns)::value;
+      hipLaunchKernelGGL((mrhs_cg_update_kernel<T1, T2, NS>), grid, dim3(kBT), 0, st, (T1 *)x, (const T1 *)p, (T2 *)r,
+                         (const T2 *)q, vh, nrhs, c, red);
+      return hipGetLastError();
+    });
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Streaming copy: 16-byte non-temporal loads and stores, grid-stride, the
+// workgroups of each XCD on one contiguous range. The measured HBM ceiling
+// of a read-once/write-once kernel, and the known-size kernel that calibrates
+// the profiler's byte counters.
+typedef RawVec<16>::T u32x4;
+__global__ void __launch_bounds__(kBT) stream_copy_kernel(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
+                                                         size_t n16) {
+  const size_t per = (n16 + gridDim.x - 1) / gridDim.x;
+  const size_t wg = (size_t)xcd_remap(blockIdx.x, gridDim.x);
+  const size_t lo = wg * per, hi = lo + per < n16 ? lo + per : n16;
+  for (size_t i = lo + threadIdx.x; i < hi; i += kBT) nt_store(dst + i, nt_load(src + i));
+}
+
+hipError_t blas_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t st) {
+  if (bytes % 16) return hipErrorInvalidValue;
+  const size_t n16 = bytes / 16;
+  if (!n16) return hipSuccess;
+  size_t g = (n16 + 4 * kBT - 1) / (4 * kBT);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)g), dim3(kBT), 0, st, (const u32x4 *)src, (u32x4 *)dst, n16);
+  return hipGetLastError();
 }
 
 }  // namespace lqcd

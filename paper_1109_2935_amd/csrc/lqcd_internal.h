@@ -23,6 +23,7 @@ struct lqcd_context {
   // general scratch vectors, grown on demand and reused between calls
   std::vector<void *> scratch;
   std::vector<size_t> scratch_bytes;
+  std::vector<void *> retired;  // outgrown scratch buffers, freed with the context
   // autotuner results: launch parameter per kernel/shape key
   std::map<std::string, int> tuned;
   std::string tune_file;
@@ -31,7 +32,7 @@ struct lqcd_context {
 
 namespace lqcd {
 
-constexpr int kMaxRed = 40;  // max values one reduction kernel returns
+constexpr int kMaxRed = 64;  // max values one reduction kernel returns
 
 // Spin-colour reals per site of the action's spinor.
 inline int spinor_reals(int action) { return action == LQCD_WILSON_CLOVER ? 24 : 6; }
@@ -182,5 +183,20 @@ hipError_t blas_bicgstab_dir(int prec, const void *r, void *p, const void *v, si
 // CG: x += a p; r -= a q; result ||r||^2 (x, p in px; r, q in pr)
 hipError_t blas_cg_update(int px, void *x, const void *p, int pr, void *r, const void *q, size_t n, double a,
                           const RedScratch &red, hipStream_t st);
+
+// Several right-hand sides (nrhs <= LQCD_MAX_CG_RHS) of vh sites and nsp
+// reals per site each, in the multi-source layout; per-source coefficients
+// a[j], b[j] and per-source results (result[j], or result[2j..2j+1]).
+// y_j = a_j x_j + b_j y_j (y_j not read where b_j = 0); red: ||y_j||^2.
+hipError_t blas_mrhs_axpby(int px, const void *x, int py, void *y, int64_t vh, int nsp, int nrhs, const double *a,
+                           const double *b, const RedScratch *red, hipStream_t st);
+// <x_j, y_j>
+hipError_t blas_mrhs_cdot(int p, const void *x, const void *y, int64_t vh, int nsp, int nrhs, const RedScratch &red,
+                          hipStream_t st);
+// x_j += a_j p_j; r_j -= a_j q_j; ||r_j||^2 (sources with a_j = 0 are left as they are)
+hipError_t blas_mrhs_cg_update(int px, void *x, const void *p, int pr, void *r, const void *q, int64_t vh, int nsp,
+                               int nrhs, const double *a, const RedScratch &red, hipStream_t st);
+// dst = src (bytes a multiple of 16), streaming
+hipError_t blas_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 
 }  // namespace lqcd

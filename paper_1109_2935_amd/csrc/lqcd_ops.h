@@ -50,7 +50,9 @@ lqcd_status check_schwarz(lqcd_context *ctx, const OpInfo &info, const lqcd_schw
 // operator fields present and aligned (clover for Wilson, long links for staggered)
 lqcd_status check_fields_internal(lqcd_context *ctx, const lqcd_operator *op);
 
+// x += omega a_B r; r -= omega a_B q per Dirichlet block B, a_B = <q,r>_B / <q,q>_B
+// from the per-segment partials (x read as zero when first)
 hipError_t launch_mr_update(const Geom &g, int prec, void *x, void *r, const void *q, const double *partials, int nps,
-                            bool first, hipStream_t st);
+                            bool first, double omega, hipStream_t st);
 
 }  // namespace lqcd

@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <vector>
 
 #include "lqcd_internal.h"
@@ -44,7 +45,11 @@ struct Solver {
   lqcd_context *ctx;
   hipStream_t st;
   int slot;  // next free scratch slot
-  lqcd_status vec(size_t bytes, void **p) { return scratch(ctx, slot++, bytes, p); }
+  // Every work vector is given at least this many bytes (the size of the
+  // system's FP64 vectors), so that solves of other precisions that follow
+  // find their slots large enough and never reallocate.
+  size_t min_bytes = 0;
+  lqcd_status vec(size_t bytes, void **p) { return scratch(ctx, slot++, std::max(bytes, min_bytes), p); }
   lqcd_status result(int n, double *out) { return read_result(ctx, st, n, out); }
   RedScratch red() { return red_scratch(ctx); }
   lqcd_status hip(hipError_t e, const char *what) { return hip_check(ctx, e, what); }
@@ -61,10 +66,12 @@ lqcd_status residual_from(Solver &S, int p, const void *b, void *y, size_t n, do
 }
 
 // Wilson even-odd source bhat = b_e + kappa D_eo A_oo^-1 b_o.
-lqcd_status wilson_schur_source(Solver &S, const OpInfo &hi, void *bhat, const void *b_full, void *tmp) {
-  const char *be = (const char *)b_full, *bo = be + hi.spinor_bytes;
-  TRY(S.hip(launch_clover_apply(hi.g, hi.prec, tmp, bo, clover_block(hi, hi.op->clover_inv, 1), 1, S.st), "clover"));
-  return wilson_hop(S.ctx, hi, hi.g, W_XPAY, bhat, tmp, be, nullptr, 0, hi.op->kappa, 0, nullptr, S.st);
+// nrhs sources: b_full holds the even blocks of all sources, then the odd ones.
+lqcd_status wilson_schur_source(Solver &S, const OpInfo &hi, void *bhat, const void *b_full, void *tmp, int nrhs = 1) {
+  const char *be = (const char *)b_full, *bo = be + hi.spinor_bytes * nrhs;
+  TRY(S.hip(launch_clover_apply(hi.g, hi.prec, tmp, bo, clover_block(hi, hi.op->clover_inv, 1), nrhs, S.st),
+            "clover"));
+  return wilson_hop(S.ctx, hi, hi.g, W_XPAY, bhat, tmp, be, nullptr, 0, hi.op->kappa, 0, nullptr, S.st, nrhs);
 }
 
 // x_o = A_oo^-1 (b_o + kappa D_oe x_e), then the true full residual ||b - M x|| / ||b||.
@@ -86,6 +93,32 @@ lqcd_status wilson_finish(Solver &S, const OpInfo &hi, void *x_full, const void 
   TRY(residual_from(S, hi.prec, bo, y, ncomplex(hi), &rr));
   tot += rr;
   *true_res = bnorm > 0 ? std::sqrt(tot) / bnorm : 0.0;
+  return LQCD_OK;
+}
+
+// x_o = A_oo^-1 (b_o + kappa D_oe x_e) for nrhs sources, then each source's
+// true full residual ||b_j - M x_j|| / ||b_j|| (res[j]; 0 for a zero source).
+lqcd_status wilson_finish_mrhs(Solver &S, const OpInfo &hi, void *x_full, const void *b_full, void *tmp, void *y,
+                               const double *bn2, int nrhs, double *res) {
+  const size_t blk = hi.spinor_bytes * nrhs;
+  char *xe = (char *)x_full, *xo = xe + blk;
+  const char *be = (const char *)b_full, *bo = be + blk;
+  const lqcd_operator *op = hi.op;
+  TRY(wilson_hop(S.ctx, hi, hi.g, W_XPAY, tmp, xe, bo, nullptr, 1, op->kappa, 0, nullptr, S.st, nrhs));
+  TRY(S.hip(launch_clover_apply(hi.g, hi.prec, xo, tmp, clover_block(hi, op->clover_inv, 1), nrhs, S.st), "clover"));
+  std::vector<double> one(nrhs, 1.0), mone(nrhs, -1.0), rr(nrhs), tot(nrhs, 0.0);
+  RedScratch red = S.red();
+  for (int par = 0; par < 2; ++par) {
+    // y = A_pp x_p - kappa D_p,1-p x_1-p, then y = b_p - y
+    TRY(wilson_hop(S.ctx, hi, hi.g, W_XPAY_CLOV, y, par ? xe : xo, par ? xo : xe, clover_block(hi, op->clover, par),
+                   par, -op->kappa, 0, nullptr, S.st, nrhs));
+    TRY(S.hip(blas_mrhs_axpby(hi.prec, par ? bo : be, hi.prec, y, (int64_t)hi.vh, hi.nsp, nrhs, one.data(),
+                              mone.data(), &red, S.st),
+              "residual"));
+    TRY(S.result(nrhs, rr.data()));
+    for (int j = 0; j < nrhs; ++j) tot[j] += rr[j];
+  }
+  for (int j = 0; j < nrhs; ++j) res[j] = bn2[j] > 0 ? std::sqrt(tot[j] / bn2[j]) : 0.0;
   return LQCD_OK;
 }
 
@@ -122,6 +155,8 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
   if (!prm) return set_error(ctx, LQCD_ERR_INVALID_ARG, "params are NULL");
   if (!(prm->tol > 0) || prm->k_max < 1 || prm->k_max > 32 || !(prm->delta > 0) || prm->max_iter < 1)
     return set_error(ctx, LQCD_ERR_INVALID_ARG, "need tol > 0, 1 <= k_max <= 32, delta > 0, max_iter >= 1");
+  if (prm->res_history_max < 0 || (prm->res_history_max > 0 && !prm->res_history))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "res_history_max > 0 needs a res_history array");
   const int pk = prm->precond;
   if (pk == LQCD_PRECOND_SCHWARZ) {
     TRY(check_op(ctx, op_precond, &pc));
@@ -144,6 +179,7 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
     return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
 
   Solver S{ctx, (hipStream_t)stream, kSlotSolver};
+  S.min_bytes = hi.spinor_bytes;
   const size_t n = ncomplex(hi);
   const int kmax = prm->k_max;
   void *bhat, *r, *y, *tmp, *rhat, *ktmp, *pin = nullptr, *pout = nullptr;
@@ -265,6 +301,7 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
     TRY(S.result(1, &rr));
     rhn_prev = rhn;
     rhn = std::sqrt(rr);
+    if (prm->res_history && inf.history_len < prm->res_history_max) prm->res_history[inf.history_len++] = rhn;
     if (pk == LQCD_PRECOND_LEARNED && prm->schwarz.mr_steps > 0 && !schwarz_now &&
         (!(rhn < 0.95 * rhn_prev) || !std::isfinite(rhn)))
       use_fallback = true;
@@ -328,10 +365,189 @@ struct CgOps {
   int kind;
   void *tmp_hi, *tmp_lo;
   // A applied in the given precision. For CGNE: A = Mhat (dag = 0) or Mhat^+ (dag = 1).
-  lqcd_status apply(const OpInfo &o, void *out, const void *in, int dag, void *tmp) {
-    return schur_apply(S->ctx, o, o.g, out, in, tmp, dag, nullptr, S->st);
+  lqcd_status apply(const OpInfo &o, void *out, const void *in, int dag, void *tmp, int nrhs = 1) {
+    return schur_apply(S->ctx, o, o.g, out, in, tmp, dag, nullptr, S->st, nrhs);
   }
 };
+
+// CG or CGNE (the same recurrences as lqcd_cg_solve) on nrhs systems at once:
+// every operator application is one launch over all sources, while each
+// system keeps its own scalars, its own reliable-update scale and its own stop
+// test. A system that has converged takes no further steps (its coefficients
+// are zero); a reliable update, triggered by any system, refreshes all of them.
+lqcd_status cg_solve_mrhs(Solver &S, const OpInfo &hi, const OpInfo &lo, const lqcd_cg_params *prm, int nrhs, void *x,
+                          const void *b, lqcd_solve_info *inf) {
+  lqcd_context *ctx = S.ctx;
+  const bool cgne = prm->kind == LQCD_CG_CGNE_SCHUR;
+  const bool mixed = lo.prec != hi.prec;
+  const bool half = lo.prec == LQCD_F16 || lo.prec == LQCD_BF16;
+  const double delta = prm->delta_reliable;
+  const int64_t vh = (int64_t)hi.vh;
+  const int nsp = hi.nsp;
+  const size_t nreal = (size_t)vh * nsp;  // reals of one source on one parity
+  void *bhat, *r, *y, *tmp_hi, *rs, *xs, *p, *q, *t, *tmp_lo;
+  TRY(S.vec(hi.spinor_bytes * nrhs, &bhat));
+  TRY(S.vec(hi.spinor_bytes * nrhs, &r));
+  TRY(S.vec(hi.spinor_bytes * nrhs, &y));
+  TRY(S.vec(hi.spinor_bytes * nrhs, &tmp_hi));
+  TRY(S.vec(lo.spinor_bytes * nrhs, &rs));
+  TRY(S.vec(lo.spinor_bytes * nrhs, &xs));
+  TRY(S.vec(lo.spinor_bytes * nrhs, &p));
+  TRY(S.vec(lo.spinor_bytes * nrhs, &q));
+  TRY(S.vec(lo.spinor_bytes * nrhs, &t));
+  TRY(S.vec(lo.spinor_bytes * nrhs, &tmp_lo));
+  RedScratch red = S.red();
+  CgOps A{&S, &hi, &lo, prm->kind, tmp_hi, tmp_lo};
+  std::vector<double> bn2(nrhs), part(2 * nrhs), coef(nrhs), coef2(nrhs), one(nrhs, 1.0), mone(nrhs, -1.0),
+      zero(nrhs, 0.0);
+  // source norms: both parities (CGNE_SCHUR) or the even sites
+  for (int j = 0; j < nrhs; ++j) bn2[j] = 0;
+  for (int par = 0; par < (cgne ? 2 : 1); ++par) {
+    const char *bp = (const char *)b + par * hi.spinor_bytes * nrhs;
+    TRY(S.hip(blas_mrhs_cdot(hi.prec, bp, bp, vh, nsp, nrhs, red, S.st), "norms"));
+    TRY(S.result(2 * nrhs, part.data()));
+    for (int j = 0; j < nrhs; ++j) bn2[j] += part[2 * j];
+  }
+  for (int j = 0; j < nrhs; ++j)
+    if (!std::isfinite(bn2[j])) return set_error(ctx, LQCD_ERR_INVALID_ARG, "source contains non-finite values");
+  // a zero source has the solution zero
+  for (int j = 0; j < nrhs; ++j) coef[j] = bn2[j] > 0 ? 1.0 : 0.0;
+  for (int par = 0; par < (cgne ? 2 : 1); ++par) {
+    char *xp = (char *)x + par * hi.spinor_bytes * nrhs;
+    TRY(S.hip(blas_mrhs_axpby(hi.prec, xp, hi.prec, xp, vh, nsp, nrhs, coef.data(), zero.data(), nullptr, S.st),
+              "zero sources"));
+  }
+  if (cgne)
+    TRY(wilson_schur_source(S, hi, bhat, b, tmp_hi, nrhs));
+  else
+    TRY(S.hip(hipMemcpyAsync(bhat, b, hi.spinor_bytes * nrhs, hipMemcpyDeviceToDevice, S.st), "copy"));
+  void *xe = x;
+  std::vector<double> rr_true(nrhs);
+  auto true_residual = [&]() -> lqcd_status {
+    TRY(A.apply(hi, y, xe, 0, tmp_hi, nrhs));
+    TRY(S.hip(hipMemcpyAsync(r, bhat, hi.spinor_bytes * nrhs, hipMemcpyDeviceToDevice, S.st), "copy"));
+    TRY(S.hip(blas_mrhs_axpby(hi.prec, y, hi.prec, r, vh, nsp, nrhs, mone.data(), one.data(), &red, S.st), "axpby"));
+    return S.result(nrhs, rr_true.data());
+  };
+  TRY(true_residual());
+  std::vector<double> sc(nrhs), rr(nrhs), rr_new(nrhs), pp(nrhs, 0.0), maxrr(nrhs), stop(nrhs), a(nrhs), bta(nrhs);
+  std::vector<char> conv(nrhs);
+  for (int j = 0; j < nrhs; ++j) {
+    sc[j] = half ? unit_rms_scale(std::sqrt(rr_true[j]), nreal) : 1.0;
+    rr[j] = rr_true[j] * sc[j] * sc[j];
+    maxrr[j] = rr_true[j];
+    stop[j] = prm->tol * prm->tol * bn2[j];
+    conv[j] = rr_true[j] <= stop[j];
+  }
+  TRY(S.hip(blas_mrhs_axpby(hi.prec, r, lo.prec, rs, vh, nsp, nrhs, sc.data(), zero.data(), nullptr, S.st),
+            "convert"));
+  TRY(S.hip(hipMemsetAsync(xs, 0, lo.spinor_bytes * nrhs, S.st), "memset"));
+  if (cgne) {
+    TRY(A.apply(lo, p, rs, 1, tmp_lo, nrhs));
+    TRY(S.hip(blas_mrhs_cdot(lo.prec, p, p, vh, nsp, nrhs, red, S.st), "norms"));
+    TRY(S.result(2 * nrhs, part.data()));
+    for (int j = 0; j < nrhs; ++j) pp[j] = part[2 * j];
+    inf->matvecs += nrhs;
+  } else {
+    TRY(S.hip(hipMemcpyAsync(p, rs, lo.spinor_bytes * nrhs, hipMemcpyDeviceToDevice, S.st), "copy"));
+  }
+  auto all_converged = [&]() {
+    for (int j = 0; j < nrhs; ++j)
+      if (!conv[j]) return false;
+    return true;
+  };
+  lqcd_status status = LQCD_OK;
+  int it = 0;
+  while (!all_converged() && it < prm->max_iter) {
+    TRY(A.apply(lo, q, p, 0, tmp_lo, nrhs));
+    inf->matvecs += nrhs;
+    if (!cgne) {
+      TRY(S.hip(blas_mrhs_cdot(lo.prec, p, q, vh, nsp, nrhs, red, S.st), "dots"));
+      TRY(S.result(2 * nrhs, part.data()));
+    }
+    bool broke = false;
+    for (int j = 0; j < nrhs; ++j) {
+      a[j] = 0;
+      if (conv[j]) continue;
+      const double den = cgne ? pp[j] : part[2 * j];
+      if (!(den > 0)) broke = true;
+      else a[j] = rr[j] / den;
+    }
+    if (broke) {
+      status = set_error(ctx, LQCD_ERR_BREAKDOWN, cgne ? "CGNE breakdown: |p| = 0" : "CG breakdown: <p, A p> <= 0");
+      break;
+    }
+    TRY(S.hip(blas_mrhs_cg_update(lo.prec, xs, p, lo.prec, rs, q, vh, nsp, nrhs, a.data(), red, S.st), "cg update"));
+    TRY(S.result(nrhs, rr_new.data()));
+    ++it;
+    bool trigger = false;
+    for (int j = 0; j < nrhs; ++j) {
+      if (conv[j]) continue;
+      const double rt = rr_new[j] / (sc[j] * sc[j]);
+      if (rt <= stop[j] || (mixed && rt < delta * delta * maxrr[j])) trigger = true;
+    }
+    if (trigger) {
+      // x += xs / sc ; r = bhat - A x ; every sloppy residual restarts from it
+      for (int j = 0; j < nrhs; ++j) coef[j] = 1.0 / sc[j];
+      TRY(S.hip(blas_mrhs_axpby(lo.prec, xs, hi.prec, xe, vh, nsp, nrhs, coef.data(), one.data(), nullptr, S.st),
+                "x update"));
+      TRY(true_residual());
+      inf->restarts++;
+      for (int j = 0; j < nrhs; ++j) {
+        const double sn = half ? unit_rms_scale(std::sqrt(rr_true[j]), nreal) : 1.0;
+        coef[j] = sn;
+        coef2[j] = sn / sc[j];
+        rr[j] *= coef2[j] * coef2[j];
+        sc[j] = sn;
+        rr_new[j] = rr_true[j] * sn * sn;
+        maxrr[j] = rr_true[j];
+        if (rr_true[j] <= stop[j]) conv[j] = 1;
+      }
+      TRY(S.hip(blas_mrhs_axpby(hi.prec, r, lo.prec, rs, vh, nsp, nrhs, coef.data(), zero.data(), nullptr, S.st),
+                "convert"));
+      TRY(S.hip(hipMemsetAsync(xs, 0, lo.spinor_bytes * nrhs, S.st), "memset"));
+      if (half)
+        TRY(S.hip(blas_mrhs_axpby(lo.prec, p, lo.prec, p, vh, nsp, nrhs, coef2.data(), zero.data(), nullptr, S.st),
+                  "rescale"));
+      if (all_converged()) break;
+    }
+    for (int j = 0; j < nrhs; ++j) bta[j] = conv[j] ? 0.0 : rr_new[j] / rr[j];
+    if (cgne) {
+      TRY(A.apply(lo, t, rs, 1, tmp_lo, nrhs));
+      inf->matvecs += nrhs;
+      TRY(S.hip(blas_mrhs_axpby(lo.prec, t, lo.prec, p, vh, nsp, nrhs, one.data(), bta.data(), &red, S.st), "xpay"));
+      TRY(S.result(nrhs, pp.data()));
+    } else {
+      TRY(S.hip(blas_mrhs_axpby(lo.prec, rs, lo.prec, p, vh, nsp, nrhs, one.data(), bta.data(), nullptr, S.st),
+                "xpay"));
+    }
+    for (int j = 0; j < nrhs; ++j) {
+      rr[j] = rr_new[j];
+      maxrr[j] = std::max(maxrr[j], rr_new[j] / (sc[j] * sc[j]));
+    }
+  }
+  if (!all_converged()) {
+    for (int j = 0; j < nrhs; ++j) coef[j] = 1.0 / sc[j];
+    TRY(S.hip(blas_mrhs_axpby(lo.prec, xs, hi.prec, xe, vh, nsp, nrhs, coef.data(), one.data(), nullptr, S.st),
+              "x update"));
+  }
+  std::vector<double> res(nrhs);
+  if (cgne) {
+    TRY(wilson_finish_mrhs(S, hi, x, b, tmp_hi, y, bn2.data(), nrhs, res.data()));
+  } else {
+    TRY(true_residual());
+    for (int j = 0; j < nrhs; ++j) res[j] = bn2[j] > 0 ? std::sqrt(rr_true[j] / bn2[j]) : 0.0;
+  }
+  inf->iters = it;
+  inf->true_residual = 0;
+  for (int j = 0; j < nrhs; ++j) {
+    inf->true_residual = std::max(inf->true_residual, res[j]);
+    if (prm->rhs_residuals) prm->rhs_residuals[j] = res[j];
+  }
+  if (status != LQCD_OK) return status;
+  if (!all_converged()) return set_error(ctx, LQCD_ERR_NOT_CONVERGED, "CG reached max_iter");
+  return LQCD_OK;
+}
 
 }  // namespace
 
@@ -363,8 +579,23 @@ extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
   if (!x || !b || ((uintptr_t)x & 15) || ((uintptr_t)b & 15))
     return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
   if (hi.prec != LQCD_F64) return set_error(ctx, LQCD_ERR_UNSUPPORTED, "op_hi must be FP64");
+  const int nrhs = prm->nrhs <= 0 ? 1 : prm->nrhs;
+  if (nrhs > LQCD_MAX_CG_RHS) return set_error(ctx, LQCD_ERR_INVALID_ARG, "nrhs exceeds LQCD_MAX_CG_RHS");
+  TRY(check_nrhs(ctx, hi, nrhs));
+  if (prm->res_history_max < 0 || (prm->res_history_max > 0 && !prm->res_history))
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "res_history_max > 0 needs a res_history array");
 
   Solver S{ctx, (hipStream_t)stream, kSlotSolver};
+  S.min_bytes = hi.spinor_bytes * nrhs;
+  if (nrhs > 1) {
+    if (prm->record_max > 0 || prm->res_history_max > 0)
+      return set_error(ctx, LQCD_ERR_INVALID_ARG, "recording and residual histories need nrhs = 1");
+    lqcd_solve_info inf{};
+    const lqcd_status st = cg_solve_mrhs(S, hi, lo, prm, nrhs, x, b, &inf);
+    inf.seconds = elapsed(t0);
+    if (info) *info = inf;
+    return st;
+  }
   const bool cgne = kind == LQCD_CG_CGNE_SCHUR;
   const size_t n = ncomplex(hi);
   const bool mixed = lo.prec != hi.prec;
@@ -459,6 +690,7 @@ extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
     TRY(S.result(1, &rr_new));
     ++it;
     double rr_new_true = rr_new / (sc * sc);
+    if (inf.history_len < prm->res_history_max) prm->res_history[inf.history_len++] = std::sqrt(rr_new_true);
     if (verbose()) fprintf(stderr, "cg it %d |r|/|b| %.3e alpha %.3e\n", it, std::sqrt(rr_new_true) / bn, a);
     if (recording && it % prm->record_every == 0 && *prm->record_count < prm->record_max) {
       // pure precision: x_k = x_e + xs, r_k = rs; e_k = x* - x_k
@@ -567,6 +799,7 @@ extern "C" lqcd_status lqcd_multishift_cg_solve(lqcd_context *ctx, const lqcd_op
   }
 
   Solver S{ctx, (hipStream_t)stream, kSlotSolver};
+  S.min_bytes = hi.spinor_bytes;
   const size_t n = ncomplex(hi);  // complex entries of one even field
   RedScratch red = S.red();
   lqcd_multishift_info inf{};
@@ -731,6 +964,7 @@ extern "C" lqcd_status lqcd_bicgstab_solve(lqcd_context *ctx, const lqcd_operato
     return set_error(ctx, LQCD_ERR_INVALID_ARG, "bad field pointers");
 
   Solver S{ctx, (hipStream_t)stream, kSlotSolver};
+  S.min_bytes = hi.spinor_bytes;
   const size_t n = ncomplex(hi);
   const bool mixed = lo.prec != hi.prec;
   const bool half = lo.prec == LQCD_F16 || lo.prec == LQCD_BF16;

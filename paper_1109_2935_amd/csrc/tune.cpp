@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstring>
 #include <cstdlib>
 #include <algorithm>
 #include <fstream>
@@ -111,3 +112,16 @@ int tune_pick(lqcd_context *ctx, const std::string &key, const std::vector<int> 
 }
 
 }  // namespace lqcd
+
+extern "C" lqcd_status lqcd_tuned_choices(lqcd_context *ctx, char *buf, size_t cap, size_t *len) {
+  if (!ctx || !len) return lqcd::set_error(ctx, LQCD_ERR_INVALID_ARG, "context and len must not be NULL");
+  std::string text;
+  for (const auto &kv : ctx->tuned) text += kv.first + "\t" + std::to_string(kv.second) + "\n";
+  *len = text.size() + 1;
+  if (buf && cap > 0) {
+    const size_t n = std::min(cap - 1, text.size());
+    memcpy(buf, text.data(), n);
+    buf[n] = 0;
+  }
+  return LQCD_OK;
+}

@@ -596,7 +596,7 @@ __global__ void __launch_bounds__(256) clover_apply_kernel(Geom g, S *out, const
 // x += alpha_B r (x = alpha_B r on the first step), r -= alpha_B q.
 template <typename S, typename R>
 __global__ void __launch_bounds__(256) mr_update_kernel(Geom g, S *x, S *r, const S *q, const double *part, int nps,
-                                                        int first) {
+                                                        int first, double omega) {
   int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (s >= launch_sites(g)) return;
   if (g.colour >= 0) s = colour_site(g, s);
@@ -608,7 +608,7 @@ __global__ void __launch_bounds__(256) mr_update_kernel(Geom g, S *x, S *r, cons
     qi += p[1];
     qq += p[2];
   }
-  const R ar = qq > 0 ? (R)(qr / qq) : R(0), ai = qq > 0 ? (R)(qi / qq) : R(0);
+  const R ar = qq > 0 ? (R)(omega * qr / qq) : R(0), ai = qq > 0 ? (R)(omega * qi / qq) : R(0);
   R rv[24], qv[24], xv[24];
   load_spinor_reals<S, 24, R>(r, g.Vh, s, rv);
   load_spinor_reals<S, 24, R>(q, g.Vh, s, qv);
@@ -631,14 +631,14 @@ __global__ void __launch_bounds__(256) mr_update_kernel(Geom g, S *x, S *r, cons
 }
 
 hipError_t launch_mr_update(const Geom &g, int prec, void *x, void *r, const void *q, const double *partials, int nps,
-                            bool first, hipStream_t st) {
+                            bool first, double omega, hipStream_t st) {
   const int bt = 256, nwg = (launch_sites(g) + bt - 1) / bt;
   if (g.Vh == 0) return hipSuccess;
   switch (prec) {
 #define CASE(P)                                                                                              \
   case P:                                                                                                    \
     hipLaunchKernelGGL((mr_update_kernel<Prec<P>::S, Prec<P>::R>), dim3(nwg), dim3(bt), 0, st, g,            \
-                       (Prec<P>::S *)x, (Prec<P>::S *)r, (const Prec<P>::S *)q, partials, nps, (int)first);  \
+                       (Prec<P>::S *)x, (Prec<P>::S *)r, (const Prec<P>::S *)q, partials, nps, (int)first, omega);  \
     return hipGetLastError();
     CASE(LQCD_F64)
     CASE(LQCD_F32)

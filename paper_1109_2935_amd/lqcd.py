@@ -49,7 +49,7 @@ class lqcd_operator(ctypes.Structure):
 class lqcd_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("matvecs", ctypes.c_int32),
                 ("precond_applies", ctypes.c_int32), ("fallback_applies", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("true_residual", ctypes.c_double),
+                ("history_len", ctypes.c_int32), ("true_residual", ctypes.c_double),
                 ("seconds", ctypes.c_double)]
 
     def as_dict(self):
@@ -57,7 +57,8 @@ class lqcd_solve_info(ctypes.Structure):
 
 
 class lqcd_schwarz_params(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32 * 4), ("mr_steps", ctypes.c_int32), ("cycles", ctypes.c_int32)]
+    _fields_ = [("block", ctypes.c_int32 * 4), ("mr_steps", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("omega", ctypes.c_double)]
 
 
 class lqcd_ptc_shape(ctypes.Structure):
@@ -71,7 +72,8 @@ class lqcd_ptc_net(ctypes.Structure):
 class lqcd_gcr_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("k_max", ctypes.c_int32), ("delta", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("schwarz", lqcd_schwarz_params), ("learned", ctypes.POINTER(lqcd_ptc_net))]
+                ("schwarz", lqcd_schwarz_params), ("learned", ctypes.POINTER(lqcd_ptc_net)),
+                ("res_history", ctypes.POINTER(ctypes.c_double)), ("res_history_max", ctypes.c_int32)]
 
 
 class lqcd_dslash_job(ctypes.Structure):
@@ -83,10 +85,13 @@ class lqcd_cg_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("delta_reliable", ctypes.c_double),
                 ("kind", ctypes.c_int32), ("record_r", ctypes.c_void_p), ("record_e", ctypes.c_void_p),
                 ("record_xstar", ctypes.c_void_p), ("record_every", ctypes.c_int32), ("record_max", ctypes.c_int32),
-                ("record_count", ctypes.POINTER(ctypes.c_int32))]
+                ("record_count", ctypes.POINTER(ctypes.c_int32)), ("nrhs", ctypes.c_int32),
+                ("rhs_residuals", ctypes.POINTER(ctypes.c_double)), ("res_history", ctypes.POINTER(ctypes.c_double)),
+                ("res_history_max", ctypes.c_int32)]
 
 
 LQCD_MAX_SHIFTS = 16
+LQCD_MAX_CG_RHS = 32
 
 
 class lqcd_multishift_params(ctypes.Structure):
@@ -113,6 +118,8 @@ _SIGNATURES = {
     "lqcd_context_destroy": [_P],
     "lqcd_last_error": [_P],
     "lqcd_field_bytes": [_OPP, _I, _I, ctypes.POINTER(ctypes.c_size_t)],
+    "lqcd_stream_copy": [_P, _P, _P, ctypes.c_size_t, _P],
+    "lqcd_tuned_choices": [_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
     "lqcd_gauge_import": [_P, _OPP, _P, _P, _I, _P],
     "lqcd_long_link_build": [_P, _OPP, _P, _P, _P],
     "lqcd_clover_build": [_P, _OPP, _P, _P, _P, _P],
@@ -202,6 +209,23 @@ def lqcd_field_bytes(op, kind, nrhs=1):
     n = ctypes.c_size_t()
     _check(lib().lqcd_field_bytes(ctypes.byref(op), kind, nrhs, ctypes.byref(n)), None)
     return n.value
+
+
+def lqcd_stream_copy(ctx, dst, src, nbytes, stream=None):
+    _check(lib().lqcd_stream_copy(ctx, _ptr(dst), _ptr(src), int(nbytes), _stream(stream)), ctx)
+
+
+def lqcd_tuned_choices(ctx):
+    """The autotuner's choices as a dict {key: value}."""
+    n = ctypes.c_size_t()
+    _check(lib().lqcd_tuned_choices(ctx, None, 0, ctypes.byref(n)), ctx)
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().lqcd_tuned_choices(ctx, buf, n.value, ctypes.byref(n)), ctx)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        k, _, v = line.rpartition("\t")
+        out[k] = int(v)
+    return out
 
 
 def lqcd_gauge_import(ctx, op, packed, natural, which=LQCD_FIELD_GAUGE, stream=None):

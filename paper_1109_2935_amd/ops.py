@@ -5,6 +5,7 @@ fields as torch uint8 device tensors, imports natural FP64 links (device or
 host arrays) and builds the derived fields (clover and its inverse, long
 links) with the library's own kernels. All arithmetic stays in liblqcd.so.
 """
+import ctypes
 import numpy as np
 import torch
 
@@ -51,6 +52,21 @@ class Operator:
         if zero:
             t.zero_()
         return t
+
+    def replica(self):
+        """The same operator with its own copies of the packed links and clover
+        fields (equal values at other addresses)."""
+        r = Operator.__new__(Operator)
+        r.ctx, r.device, r.dims = self.ctx, self.device, self.dims
+        r.op = L.lqcd_operator.from_buffer_copy(self.op)
+        r._keep = {}
+        for name, field in (("gauge", "gauge"), ("long", "long_links"), ("clover", "clover"),
+                            ("clover_inv", "clover_inv")):
+            if name in self._keep:
+                t = self._keep[name].clone()
+                r._keep[name] = t
+                setattr(r.op, field, t.data_ptr())
+        return r
 
     @property
     def spinor_bytes(self):
@@ -110,21 +126,50 @@ def staggered(ctx, fat, U, dims, mass, prec, recon=18, tile=None, bc_t=-1, c_lon
     return o
 
 
+def _history(p, history):
+    """Point the params' residual history at a host array of `history` doubles
+    (kept alive on the params object; read it back with residual_history)."""
+    if history:
+        buf = (ctypes.c_double * int(history))()
+        p._history_buf = buf
+        p.res_history = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+        p.res_history_max = int(history)
+
+
+def residual_history(p, info):
+    """The residual history a solve wrote (a list of info.history_len floats)."""
+    buf = getattr(p, "_history_buf", None)
+    return [] if buf is None else [buf[i] for i in range(info.history_len)]
+
+
 def gcr_params(tol=1e-10, k_max=16, delta=1e-3, max_iter=10000, precond=L.LQCD_PRECOND_NONE, block=(8, 8, 8, 8),
-               mr_steps=8, cycles=0):
+               mr_steps=8, cycles=0, omega=1.0, history=0):
     p = L.lqcd_gcr_params()
     p.tol, p.k_max, p.delta, p.max_iter, p.precond = tol, k_max, delta, max_iter, precond
     p.schwarz.block[:] = [int(b) for b in block]
     p.schwarz.mr_steps = mr_steps
     p.schwarz.cycles = cycles
+    p.schwarz.omega = omega
     p.learned = None
+    _history(p, history)
     return p
 
 
-def cg_params(tol=1e-10, max_iter=10000, delta_reliable=0.1, kind=L.LQCD_CG_CGNE_SCHUR):
+def cg_params(tol=1e-10, max_iter=10000, delta_reliable=0.1, kind=L.LQCD_CG_CGNE_SCHUR, nrhs=1, history=0):
     p = L.lqcd_cg_params()
-    p.tol, p.max_iter, p.delta_reliable, p.kind = tol, max_iter, delta_reliable, kind
+    p.tol, p.max_iter, p.delta_reliable, p.kind, p.nrhs = tol, max_iter, delta_reliable, kind, nrhs
+    if nrhs > 1:
+        buf = (ctypes.c_double * nrhs)()
+        p._rhs_buf = buf
+        p.rhs_residuals = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+    _history(p, history)
     return p
+
+
+def rhs_residuals(p):
+    """Per-source FP64 true residuals of a multi-source CG solve."""
+    buf = getattr(p, "_rhs_buf", None)
+    return [] if buf is None else list(buf)
 
 
 def multishift_params(shifts, tol=1e-10, tol_sloppy=1e-8, max_iter=20000, delta_reliable=0.1):
@@ -142,10 +187,12 @@ def bicgstab_params(tol=1e-10, max_iter=20000, delta_reliable=0.1):
     return p
 
 
-def schwarz_params(block, mr_steps=8, cycles=0):
-    """cycles = 0: additive Schwarz; n >= 1: multiplicative, n sweeps over the two block colours."""
+def schwarz_params(block, mr_steps=8, cycles=0, omega=1.0):
+    """cycles = 0: additive Schwarz; n >= 1: multiplicative, n sweeps over the two block colours.
+    omega: MR over-relaxation (1: plain MR)."""
     p = L.lqcd_schwarz_params()
     p.block[:] = [int(b) for b in block]
     p.mr_steps = mr_steps
     p.cycles = cycles
+    p.omega = omega
     return p

@@ -22,20 +22,35 @@ def test_every_declared_symbol_is_exported_and_bound():
     assert set(syms) == set(L.EXPORTED)
 
 
-def test_struct_layouts_match_header():
+STRUCTS = ("lqcd_operator", "lqcd_solve_info", "lqcd_schwarz_params", "lqcd_ptc_shape", "lqcd_ptc_net",
+           "lqcd_gcr_params", "lqcd_cg_params", "lqcd_multishift_params", "lqcd_multishift_info",
+           "lqcd_bicgstab_params", "lqcd_dslash_job")
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes struct of the binding has the size and field offsets the C
+    compiler gives the header's struct (a small C program prints them)."""
     import ctypes
-    # 4 + 16 + 16 + 4*3 ints, padding to 8, 4 doubles, 4 pointers
-    assert ctypes.sizeof(L.lqcd_operator) == 48 + 32 + 32
-    assert ctypes.sizeof(L.lqcd_solve_info) == 40
-    assert ctypes.sizeof(L.lqcd_schwarz_params) == 24
-    assert ctypes.sizeof(L.lqcd_gcr_params) == 8 + 4 + 4 + 8 + 4 + 4 + 24 + 8
-    assert ctypes.sizeof(L.lqcd_ptc_net) == 40 + 8
-    assert ctypes.sizeof(L.lqcd_cg_params) == 8 + 4 + 4 + 8 + 4 + 4 + 3 * 8 + 4 + 4 + 8
-    assert ctypes.sizeof(L.lqcd_bicgstab_params) == 8 + 8 + 8
-    # int + padding, 16 doubles, 2 doubles, int + padding, double
-    assert ctypes.sizeof(L.lqcd_multishift_params) == 8 + 16 * 8 + 2 * 8 + 8 + 8
-    # 2 ints, double, 16 solve infos, double
-    assert ctypes.sizeof(L.lqcd_multishift_info) == 8 + 8 + 16 * 40 + 8
+    import subprocess
+    # the binding names the job's `in` field in_ (a Python keyword)
+    cname = {("lqcd_dslash_job", "in_"): "in"}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lqcd.h"', "int main(void) {"]
+    for st in STRUCTS:
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (st, st))
+        for f, _ in getattr(L, st)._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (st, f, st, cname.get((st, f), f)))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for st in STRUCTS:
+        cls = getattr(L, st)
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for f, _ in cls._fields_:
+            assert int(got["%s.%s" % (st, f)]) == getattr(cls, f).offset, (st, f)
 
 
 def test_validation_without_gpu():

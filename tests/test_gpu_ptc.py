@@ -6,7 +6,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import ctx, np_of, on_parity, rel  # noqa: F401
+from gpu_util import check, check_entries, ctx, np_of, on_parity, rel  # noqa: F401
 from oracle import ptc as optc
 
 pytestmark = pytest.mark.gpu
@@ -30,6 +30,13 @@ def weights_c64(Ws):
     return [np.asarray(W, dtype=np.complex64).astype(np.complex128) for W in Ws]
 
 
+# Weight gradients: sums over sites of products of a forward activation and a
+# back-propagated cotangent, both carrying the BF16 roundings of up to four
+# layers (the forward bound below for the deepest network, and as much again
+# for the backward pass), added in quadrature: about 1.5x the 16-channel
+# forward bound.
+GRAD_TOL = 6e-2
+
 # BF16 matrix-core inputs (weights and transported activations, unit roundoff
 # u = 2^-9 each) with FP32 accumulation: a layer's relative error is about 2u
 # times a growth factor of order one for these weights; over the layers of the
@@ -46,7 +53,7 @@ def test_ptc_forward_matches_oracle(ctx, channels, tol):
     net.apply(op32, out, op32.import_spinor(r, 0))
     got = np_of(op32.export_spinor(out, 0))
     ref, _ = optc.forward(DIMS, U, r, Ws, oracle.parity_mask(DIMS, 0))
-    assert rel(got, ref) < tol
+    check(got, ref, tol)
 
 
 # every form of the 16-input-channel layers (256 or 512 threads, waves per
@@ -73,7 +80,7 @@ def test_ptc_forward_every_form(ctx, form, dims, recon, monkeypatch):
     net.apply(op32, out, op32.import_spinor(r, 0))
     got = np_of(op32.export_spinor(out, 0))
     ref, _ = optc.forward(dims, U, r, Ws, oracle.parity_mask(dims, 0))
-    assert rel(got, ref) < 4e-2
+    check(got, ref, 4e-2)
 
 
 def test_ptc_gauge_equivariance_on_gpu(ctx):
@@ -112,7 +119,7 @@ def test_ptc_gradient_matches_oracle(ctx, channels):
     for k, G in enumerate(gref):
         gk = flat[off:off + G.size].reshape(G.shape)
         off += G.size
-        assert rel(gk, G) < 6e-2, k
+        check_entries(gk, G, GRAD_TOL, "layer %d" % k)
 
 
 def _flat_grads(net, gref):
@@ -140,7 +147,7 @@ def test_ptc_residual_gradient_matches_oracle(ctx, channels):
     Lref, gref = optc.residual_loss_and_grads(DIMS, U, r, Ws, even, M.schur)
     assert abs(loss - Lref) < 2e-2 * Lref
     for k, (g, G) in enumerate(zip(_flat_grads(net, gref), gref)):
-        assert rel(g, G) < 6e-2, k
+        check_entries(g, G, GRAD_TOL, "layer %d" % k)
 
 
 def test_ptc_vjp_matches_oracle(ctx):
@@ -156,7 +163,7 @@ def test_ptc_vjp_matches_oracle(ctx):
     net.vjp(op32, op32.import_spinor(r, 0), op32.import_spinor(dy, 0))
     gref = optc.vjp(DIMS, U, r, dy, Ws, even)
     for k, (g, G) in enumerate(zip(_flat_grads(net, gref), gref)):
-        assert rel(g, G) < 6e-2, k
+        check_entries(g, G, GRAD_TOL, "layer %d" % k)
 
 
 def test_ptc_residual_training_reduces_loss(ctx):

@@ -8,7 +8,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import ctx, np_of, on_parity, rel  # noqa: F401
+from gpu_util import check, ctx, np_of, on_parity, rel  # noqa: F401
 from oracle import solvers
 
 pytestmark = pytest.mark.gpu
@@ -46,9 +46,12 @@ def test_sap_parity(ctx, dims, block, prec, cycles):
     out = o.spinor()
     out.fill_(7)  # overwritten, not accumulated
     L.lqcd_schwarz_precond(ctx, o.op, ops.schwarz_params(block, 6, cycles), out, o.import_spinor(src, 0))
-    e = rel(np_of(o.export_spinor(out, 0)), ref)
-    tol = {0: 1e-12, 1: 1e-5, 2: 2e-2, 3: 1e-1}[prec]
-    assert e < tol, e
+    # the additive K's model (tests/test_gpu_wilson.py, SCHWARZ_TOL) with the
+    # roundings of 6 MR steps per visit, `cycles` visits per block and the
+    # residual recomputed between visits: at most 2 x 28 + 8 roundings per block
+    # instead of 32, sqrt(64 / 32) = 1.4 times the additive bound
+    tol = {0: 1e-12, 1: 1e-5, 2: 1.4e-2, 3: 1.1e-1}[prec]
+    check(np_of(o.export_spinor(out, 0)), ref, tol)
 
 
 def test_sap_differs_from_additive_and_keeps_input(ctx):

@@ -37,9 +37,12 @@ def test_cgne_fp64_8x4(ctx):
     hi = o[0]
     bp = hi.import_spinor(b, -1)
     x = hi.spinor(full=True)
-    st, info = L.lqcd_cg_solve(ctx, hi.op, None, ops.cg_params(1e-10), x, bp)
+    prm = ops.cg_params(1e-10, history=400)
+    st, info = L.lqcd_cg_solve(ctx, hi.op, None, prm, x, bp)
     assert st == L.LQCD_OK
     assert info.true_residual <= 1e-10
+    hist = ops.residual_history(prm, info)
+    assert len(hist) == info.iters
     xs = np_of(hi.export_spinor(x, -1))
     res, op = oracle_residual(dims, U, kappa, csw, xs, b)
     assert res <= 1.05e-10
@@ -48,8 +51,11 @@ def test_cgne_fp64_8x4(ctx):
     xe, it, _ = solvers.cgne(op.schur, lambda v: op.schur(v, dagger=True), bhat, tol=1e-12)
     xo = op.reconstruct(xe, b)
     assert rel(xs, xo) < 1e-8
-    _, it10, _ = solvers.cgne(op.schur, lambda v: op.schur(v, dagger=True), bhat, tol=1e-10)
+    _, it10, h10 = solvers.cgne(op.schur, lambda v: op.schur(v, dagger=True), bhat, tol=1e-10)
     assert abs(info.iters - it10) <= max(2, 0.02 * it10)
+    # the first 10 iterated residuals ||bhat - Mhat x_k|| match the oracle's
+    for k in range(10):
+        assert abs(hist[k] - h10[k + 1]) <= 1e-10 * h10[k + 1], (k, hist[k], h10[k + 1])
 
 
 @pytest.mark.parametrize("precond", ["none", "schwarz"])
@@ -61,17 +67,24 @@ def test_gcr_fp64_matches_oracle(ctx, precond):
     bp = hi.import_spinor(b, -1)
     x = hi.spinor(full=True)
     pk = L.LQCD_PRECOND_SCHWARZ if precond == "schwarz" else L.LQCD_PRECOND_NONE
-    prm = ops.gcr_params(1e-10, k_max=8, delta=1e-2, precond=pk, block=block, mr_steps=4)
+    prm = ops.gcr_params(1e-10, k_max=8, delta=1e-2, precond=pk, block=block, mr_steps=4, history=200)
     st, info = L.lqcd_gcr_solve(ctx, hi.op, hi.op, hi.op, prm, x, bp)
     assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+    hist = ops.residual_history(prm, info)
+    assert len(hist) == info.iters
     xs = np_of(hi.export_spinor(x, -1))
     res, op = oracle_residual(dims, U, kappa, csw, xs, b)
     assert res <= 1.05e-10
     bhat = op.schur_source(b)
     K = (lambda r: solvers.schwarz(op, r, block, 4)) if precond == "schwarz" else None
-    xe, steps, restarts, _ = solvers.gcr(op.schur, K, bhat, tol=1e-10, kmax=8, delta=1e-2)
+    rec = {}
+    xe, steps, restarts, _ = solvers.gcr(op.schur, K, bhat, tol=1e-10, kmax=8, delta=1e-2, record=rec)
     assert rel(xs, op.reconstruct(xe, b)) < 1e-8
     assert abs(info.iters - steps) <= max(2, 0.05 * steps)  # classical vs modified Gram-Schmidt
+    # the first 10 iterated residuals ||rhat_k|| of Algorithm 1 match the oracle's
+    for k in range(10):
+        ref = rec["rhat"][k]
+        assert abs(hist[k] - ref) <= 1e-10 * ref, (k, hist[k], ref)
 
 
 @pytest.mark.parametrize("kprec", [2, 3])

@@ -5,7 +5,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import TOL, ctx, np_of, on_parity, rel  # noqa: F401
+from gpu_util import TOL, check, ctx, np_of, on_parity, rel  # noqa: F401
 from oracle import solvers
 
 pytestmark = pytest.mark.gpu
@@ -51,7 +51,7 @@ def test_staggered_dslash_parity(ctx, layout, prec, recon):
             ref = oracle.stag_dslash(dims, fat, lng, src, bc_t=-1, out_parity=p)
             if dagger:
                 ref = -ref
-            assert rel(np_of(o.export_spinor(out, p)), ref) < TOL[prec]
+            check(np_of(o.export_spinor(out, p)), ref, TOL[prec], "parity %d" % p)
 
 
 @pytest.mark.parametrize("bc_t", [1, -1])
@@ -75,7 +75,7 @@ def test_staggered_normal_operator(ctx, prec, recon):
     src = on_parity(chi, ref_op.even)
     out = o.spinor()
     L.lqcd_schur_apply(ctx, o.op, out, o.import_spinor(src, 0))
-    assert rel(np_of(o.export_spinor(out, 0)), ref_op.normal_even(src)) < TOL[prec]
+    check(np_of(o.export_spinor(out, 0)), ref_op.normal_even(src), TOL[prec])
 
 
 @pytest.mark.parametrize("sloppy", [None, 1, 2])

@@ -104,6 +104,31 @@ def test_mr_many_steps_is_block_inverse(small_op):
     assert np.abs(K.reshape(-1)[idx] - ref).max() < 1e-10 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("omega", [0.6, 1.0, 1.5])
+def test_mr_relaxation_closed_form(omega):
+    """On A = lambda * 1 every MR step has <q,r>/<q,q> = 1/lambda, so with
+    over-relaxation omega the residual shrinks by (1 - omega) per step and
+    x_n = (1 - (1 - omega)^n) b / lambda exactly."""
+    b = synth.gaussian_spinor(DIMS, 151)
+    lam = 1.3 - 0.4j
+    for n in (1, 2, 5):
+        x = solvers.mr_blocks(lambda v: lam * v, b, n, omega=omega)
+        ref = (1 - (1 - omega) ** n) * b / lam
+        assert np.abs(x - ref).max() < 1e-14 * np.abs(ref).max() + 1e-300
+
+
+def test_mr_over_relaxed_converges_to_block_inverse(small_op):
+    """Over-relaxed block MR (omega = 1.3) still converges to the dense inverse
+    of each Dirichlet block."""
+    op, shape, _, idx = small_op
+    block = (2, 2, 2, 2)
+    Mcut, _ = dense_matrix(lambda v: op.schur(v, block=block), shape, mask=op.even)
+    r = np.where(op.even[..., None, None], synth.gaussian_spinor(DIMS, 122), 0)
+    K = solvers.schwarz(op, r, block, nsteps=80, omega=1.3)
+    ref = np.linalg.solve(Mcut, r.reshape(-1)[idx])
+    assert np.abs(K.reshape(-1)[idx] - ref).max() < 1e-10 * np.abs(ref).max()
+
+
 def test_schwarz_homogeneous_and_single_block(small_op):
     op, shape, Mhat, idx = small_op
     r = np.where(op.even[..., None, None], synth.gaussian_spinor(DIMS, 131), 0)
