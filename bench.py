@@ -47,8 +47,12 @@ def kernel_sources_sha1():
             h.update((hashlib.sha1(fh.read()).hexdigest() + "  " + os.path.join("paper_1109_2935_amd", "csrc", f) + "\n").encode())
     return h.hexdigest()
 SCHUR_REALS = {18: 552, 12: 456, 8: 392}   # two fused kernels, per even site
-PREC_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
-PREC_NAME = {0: "f64", 1: "f32", 2: "f16", 3: "bf16"}
+PREC_BYTES = {0: 8, 1: 4, 2: 2, 3: 2, 4: 2}
+PREC_NAME = {0: "f64", 1: "f32", 2: "f16", 3: "bf16", 4: "half"}
+# 16-bit fixed point adds an FP32 norm per site to every spinor and clover
+# access: 2 spinor norms per dslash output site; 5 spinor and 2 clover norms
+# per even site of the Schur operator
+FIXED_NORM_BYTES = {"dslash": 8, "schur": 28}
 
 
 def parse():
@@ -591,9 +595,10 @@ def main():
     # and output.
     tile = stencil_tile(dims, block)
     inst = {}
-    for prec, recon in [(0, 18), (0, 12), (1, 18), (1, 12), (1, 8), (2, 18), (2, 12), (3, 12)]:
+    for prec, recon in [(0, 18), (0, 12), (1, 18), (1, 12), (1, 8), (2, 18), (2, 12), (3, 12), (4, 12)]:
         inst[(prec, recon)] = ops.wilson_clover(ctx, U, dims, kappa, csw, prec, recon, tile=tile, U_device=Ud)
     o16b = ops.wilson_clover(ctx, U, dims, kappa, csw, 2, 12, tile=block, U_device=Ud)
+    ohb = ops.wilson_clover(ctx, U, dims, kappa, csw, 4, 12, tile=block, U_device=Ud)
     o32b = ops.wilson_clover(ctx, U, dims, kappa, csw, 1, 12, tile=block, U_device=Ud)
     torch.cuda.synchronize()
     log("operators ready (stencil tile %s, Schwarz tile %s)" % (tile, block))
@@ -608,14 +613,14 @@ def main():
         sets = [(r, r.import_spinor(odd_b, 1), r.spinor()) for r in reps]
         dt = time_rotating(torch, [lambda r=r, i=i, q=q: L.lqcd_dslash(ctx, r.op, q, i, 0, 0) for r, i, q in sets],
                            args.dslash_launches)
-        byts = vh * WILSON_REALS[recon] * PREC_BYTES[prec]
+        byts = vh * (WILSON_REALS[recon] * PREC_BYTES[prec] + (FIXED_NORM_BYTES["dslash"] if prec == 4 else 0))
         kernels["dslash_%s_r%d" % (PREC_NAME[prec], recon)] = {
             "us": round(dt * 1e6, 2), "GB/s": round(byts / dt / 1e9, 1),
             "frac": round(byts / dt / 1e9 / HBM_PEAK_GBS, 4), "bytes": byts}
         esets = [(r, r.import_spinor(b, 0), r.spinor()) for r in reps]
         dts = time_rotating(torch, [lambda r=r, i=i, q=q: L.lqcd_schur_apply(ctx, r.op, q, i) for r, i, q in esets],
                             max(30, args.dslash_launches // 4))
-        sb = vh * SCHUR_REALS[recon] * PREC_BYTES[prec]
+        sb = vh * (SCHUR_REALS[recon] * PREC_BYTES[prec] + (FIXED_NORM_BYTES["schur"] if prec == 4 else 0))
         kernels["schur_%s_r%d" % (PREC_NAME[prec], recon)] = {
             "us": round(dts * 1e6, 2), "GB/s": round(sb / dts / 1e9, 1),
             "frac": round(sb / dts / 1e9 / HBM_PEAK_GBS, 4), "bytes": sb}
@@ -725,6 +730,11 @@ def main():
     tts["gcr_dd_sap"].update({"mr_steps": sap_mr, "cycles": sap_cycles})
     log("GCR-DD with multiplicative Schwarz (%d MR steps, %d cycles): %d steps, %.3f s, true residual %.2e" % (
         sap_mr, sap_cycles, info.iters, med, info.true_residual))
+    # the same two solvers with the Schwarz K in 16-bit fixed point (the paper's "half")
+    for name, p in (("gcr_dd_half", prm), ("gcr_dd_sap_half", sprm)):
+        med, allt, info = timed_solves(args.solves, gcr(ohb.op, p))
+        tts[name] = solve_record(med, allt, info)
+        log("%s: %d steps, %.3f s, true residual %.2e" % (name, info.iters, med, info.true_residual))
     # mixed-precision BiCGstab (FP64 reliable updates), the paper's baseline for GCR-DD
     for sp in (1, 2):
         def bicg(sp=sp):

@@ -75,7 +75,17 @@ typedef enum {
   LQCD_ERR_BREAKDOWN = 6
 } lqcd_status;
 
-typedef enum { LQCD_F64 = 0, LQCD_F32 = 1, LQCD_F16 = 2, LQCD_BF16 = 3 } lqcd_precision;
+/*
+ * Storage precisions. Arithmetic is FP64 for LQCD_F64 and FP32 otherwise.
+ * LQCD_HALF is 16-bit fixed point (the paper's "half" format, Section V):
+ * integer codes q in [-32767, 32767] standing for q / 32767; link entries are
+ * stored so directly (recon 18 or 12), while spinors and the clover term
+ * carry one FP32 norm per site (its largest magnitude; codes hold value /
+ * norm), stored after the codes of each parity block (lqcd_field_bytes counts
+ * them). HALF operators are Wilson-clover; they serve the Schwarz
+ * preconditioner and sloppy CG iterations.
+ */
+typedef enum { LQCD_F64 = 0, LQCD_F32 = 1, LQCD_F16 = 2, LQCD_BF16 = 3, LQCD_HALF = 4 } lqcd_precision;
 
 typedef enum { LQCD_WILSON_CLOVER = 0, LQCD_STAGGERED = 1 } lqcd_action;
 

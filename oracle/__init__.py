@@ -258,3 +258,46 @@ def transport(dims, U, psi, path, bc_t=-1, adjoint=False):
     lib().ora_transport(_p(_dims(dims)), int(bc_t), _p(U), int(path), int(bool(adjoint)), nfield,
                         _p(psi), _p(out))
     return out
+
+
+# --------------------------------------------------------------------------
+# 16-bit fixed-point storage (the "half" format of Section V): integer codes
+# q in [-32767, 32767] standing for q / 32767, scaled per site by the site's
+# largest magnitude (spinors, clover) or unscaled (link entries, |u| <= 1).
+# The format is the library's storage convention; its arithmetic is stated
+# here in FP32, the precision the codes are decided in, so that a stored code
+# is reproduced exactly: m = fp32(max |v|), w = fp32(v) * fp32(1 / m),
+# q = round-half-even(fp32(w * 32767)) clamped to +-32767, and a code reads back
+# as fp32(q * fp32(1 / 32767)) * m.
+
+FX_SCALE = np.float32(32767.0)
+
+
+def fixed16_codes(v, inner_axes):
+    """Codes and FP32 norms of a real array v whose last `inner_axes` axes are
+    the reals of one site (norms: one per site)."""
+    v = np.asarray(v, dtype=np.float64)
+    axes = tuple(range(v.ndim - inner_axes, v.ndim))
+    m = np.max(np.abs(v), axis=axes, keepdims=True).astype(np.float32)
+    with np.errstate(divide="ignore"):
+        inv = np.where(m > 0, np.float32(1.0) / np.where(m > 0, m, np.float32(1.0)), np.float32(0.0))
+    w = v.astype(np.float32) * inv.astype(np.float32)
+    q = np.clip(np.rint(w * FX_SCALE), -FX_SCALE, FX_SCALE).astype(np.int16)
+    return q, m
+
+
+def fixed16_decode(q, m):
+    """Values of codes q with per-site FP32 norms m (FP64 result)."""
+    unit = q.astype(np.float32) * np.float32(np.float32(1.0) / FX_SCALE)
+    return unit.astype(np.float64) * m.astype(np.float64)
+
+
+def fixed16_site_round(psi):
+    """A complex spinor field (natural layout, ..., spin, colour) as it reads
+    back from fixed-point storage: every site's 24 reals rounded to codes of
+    its own norm."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    r = np.stack([psi.real, psi.imag], axis=-1)  # ..., 4, 3, 2: the 24 reals of a site
+    q, m = fixed16_codes(r, 3)
+    out = fixed16_decode(q, m)
+    return out[..., 0] + 1j * out[..., 1]

@@ -74,12 +74,14 @@ lqcd_status check_op(lqcd_context *ctx, const lqcd_operator *op, OpInfo *info) {
   }
   if (V / 2 >= (int64_t)1 << 30) return set_error(ctx, LQCD_ERR_UNSUPPORTED, "lattice too large");
   if (op->bc_t != 1 && op->bc_t != -1) return set_error(ctx, LQCD_ERR_INVALID_ARG, "bc_t must be +1 or -1");
-  if (op->prec < LQCD_F64 || op->prec > LQCD_BF16) return set_error(ctx, LQCD_ERR_INVALID_ARG, "unknown precision");
+  if (op->prec < LQCD_F64 || op->prec > LQCD_HALF) return set_error(ctx, LQCD_ERR_INVALID_ARG, "unknown precision");
   if (op->recon != 18 && op->recon != 12 && op->recon != 8)
     return set_error(ctx, LQCD_ERR_INVALID_ARG, "recon must be 18, 12 or 8");
-  if (op->recon == 8 && (op->prec == LQCD_F16 || op->prec == LQCD_BF16))
+  if (op->recon == 8 && (op->prec == LQCD_F16 || op->prec == LQCD_BF16 || op->prec == LQCD_HALF))
     return set_error(ctx, LQCD_ERR_UNSUPPORTED,
                      "8-real link compression divides by |U01|^2+|U02|^2 and is not supported in 16-bit storage");
+  if (op->prec == LQCD_HALF && op->action != LQCD_WILSON_CLOVER)
+    return set_error(ctx, LQCD_ERR_UNSUPPORTED, "16-bit fixed-point storage is implemented for Wilson-clover");
   if (info) {
     info->op = op;
     info->g = make_geom(op->dims, op->tile, op->bc_t);
@@ -87,7 +89,7 @@ lqcd_status check_op(lqcd_context *ctx, const lqcd_operator *op, OpInfo *info) {
     info->recon = op->recon;
     info->nsp = spinor_reals(op->action);
     info->vh = (size_t)(V / 2);
-    info->spinor_bytes = info->vh * info->nsp * prec_bytes(op->prec);
+    info->spinor_bytes = site_block_bytes(op->prec, info->nsp, info->vh, true);
   }
   return LQCD_OK;
 }
@@ -160,7 +162,7 @@ lqcd_status read_result(lqcd_context *ctx, hipStream_t st, int n, double *out) {
 }
 
 const void *clover_block(const OpInfo &info, const void *clov, int parity) {
-  return (const char *)clov + (size_t)parity * info.vh * 72 * prec_bytes(info.prec);
+  return (const char *)clov + (size_t)parity * site_block_bytes(info.prec, 72, info.vh, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,9 +307,12 @@ lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schw
       }
       if (cyc == prm->cycles - 1 && c == 1) break;
       if ((s = schur_apply(ctx, info, info.g, q, out, t, 0, nullptr, st))) return s;
-      if ((s = hip_check(ctx, blas_axpby(info.prec, in, info.prec, q, n, 1.0, 0.0, -1.0, 0.0, nullptr, st),
-                         "schwarz residual")))
-        return s;
+      const double one = 1.0, mone = -1.0;
+      const hipError_t e = info.prec == LQCD_HALF
+                               ? blas_mrhs_axpby(info.prec, in, info.prec, q, (int64_t)info.vh, info.nsp, 1, &one,
+                                                 &mone, nullptr, st)
+                               : blas_axpby(info.prec, in, info.prec, q, n, 1.0, 0.0, -1.0, 0.0, nullptr, st);
+      if ((s = hip_check(ctx, e, "schwarz residual"))) return s;
       std::swap(r, q);
     }
   }
@@ -409,8 +414,8 @@ lqcd_status lqcd_field_bytes(const lqcd_operator *op, int32_t kind, int32_t nrhs
   const size_t pb = prec_bytes(op->prec), vh = info.vh;
   size_t n = 0;
   switch (kind) {
-    case LQCD_FIELD_SPINOR: n = vh * info.nsp * pb; break;
-    case LQCD_FIELD_SPINOR_FULL: n = 2 * vh * info.nsp * pb; break;
+    case LQCD_FIELD_SPINOR: n = site_block_bytes(op->prec, info.nsp, vh, true); break;
+    case LQCD_FIELD_SPINOR_FULL: n = 2 * site_block_bytes(op->prec, info.nsp, vh, true); break;
     case LQCD_FIELD_GAUGE: n = 8 * vh * (op->action == LQCD_STAGGERED ? 18 : op->recon) * pb; break;
     case LQCD_FIELD_LONG:
       if (op->action != LQCD_STAGGERED) return set_error(nullptr, LQCD_ERR_INVALID_ARG, "long links are staggered only");
@@ -418,7 +423,7 @@ lqcd_status lqcd_field_bytes(const lqcd_operator *op, int32_t kind, int32_t nrhs
       break;
     case LQCD_FIELD_CLOVER:
       if (op->action != LQCD_WILSON_CLOVER) return set_error(nullptr, LQCD_ERR_INVALID_ARG, "clover is Wilson only");
-      n = 2 * vh * 72 * pb;
+      n = 2 * site_block_bytes(op->prec, 72, vh, true);
       break;
     default: return set_error(nullptr, LQCD_ERR_INVALID_ARG, "unknown field kind");
   }
@@ -533,7 +538,8 @@ lqcd_status lqcd_spinor_convert(lqcd_context *ctx, const lqcd_operator *op_out, 
   if (out == in && (op_out->prec != op_in->prec || !same_tile))
     return set_error(ctx, LQCD_ERR_INVALID_ARG, "in-place conversion needs equal precisions and tiles");
   hipStream_t st = (hipStream_t)stream;
-  if (same_tile) {  // the packed spinor layout does not depend on the precision: element-wise
+  if (same_tile && op_out->prec != LQCD_HALF && op_in->prec != LQCD_HALF) {
+    // the packed spinor layout does not depend on the precision: element-wise
     const size_t n = io.vh * io.nsp / 2 * (parity < 0 ? 2 : 1) * (size_t)nrhs;
     return hip_check(ctx, blas_convert(op_in->prec, in, op_out->prec, out, n, scale, st), "convert");
   }

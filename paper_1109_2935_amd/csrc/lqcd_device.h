@@ -17,11 +17,26 @@ struct bf16 {
   uint16_t bits;
 };
 
+// 16-bit fixed point (the "half" format of Section V): a signed integer code
+// q in [-32767, 32767] standing for q / 32767. SU(3) link entries lie in
+// [-1, 1] and are stored so directly; spinors and the clover term carry one
+// FP32 norm per site (the largest magnitude among the site's reals), stored
+// after the codes of their parity block, and the codes hold value / norm.
+struct fx16 {
+  int16_t q;
+};
+constexpr float kFxScale = 32767.0f;
+
 template <int P> struct Prec;
 template <> struct Prec<LQCD_F64> { using S = double; using R = double; };
 template <> struct Prec<LQCD_F32> { using S = float; using R = float; };
 template <> struct Prec<LQCD_F16> { using S = _Float16; using R = float; };
 template <> struct Prec<LQCD_BF16> { using S = bf16; using R = float; };
+template <> struct Prec<LQCD_HALF> { using S = fx16; using R = float; };
+
+template <typename S> constexpr bool is_fixed() { return sizeof(S) == 2 && !__is_same(S, _Float16) && !__is_same(S, bf16); }
+// IEEE-style 16-bit storage (FP16, BF16): the matrix-core and mixed-precision paths
+template <typename S> constexpr bool is_float16() { return __is_same(S, _Float16) || __is_same(S, bf16); }
 
 template <typename R> __device__ __forceinline__ R to_real(double v) { return (R)v; }
 template <typename R> __device__ __forceinline__ R to_real(float v) { return (R)v; }
@@ -29,6 +44,8 @@ template <typename R> __device__ __forceinline__ R to_real(_Float16 v) { return 
 template <typename R> __device__ __forceinline__ R to_real(bf16 v) {
   return (R)__uint_as_float(((uint32_t)v.bits) << 16);
 }
+// the code's unit-scale value (times the site norm where there is one)
+template <typename R> __device__ __forceinline__ R to_real(fx16 v) { return (R)((float)v.q * (1.0f / kFxScale)); }
 
 template <typename S> struct Store;
 template <> struct Store<double> {
@@ -52,6 +69,15 @@ template <> struct Store<bf16> {
       r.bits = (uint16_t)(u >> 16);
     }
     return r;
+  }
+};
+
+template <> struct Store<fx16> {
+  // round to nearest (even) in FP32, saturating at +-1
+  template <typename R> __device__ __forceinline__ static fx16 from(R v) {
+    float f = (float)v * kFxScale;
+    f = fminf(fmaxf(f, -kFxScale), kFxScale);
+    return fx16{(int16_t)__float2int_rn(f)};
   }
 };
 
@@ -171,13 +197,52 @@ __device__ __forceinline__ void load_site_once(const S *__restrict__ base, int64
 // the level-1 kernels can convert and combine fields of different precision
 // element by element.
 template <int N> constexpr int spinor_chunk() { return N % 4 == 0 ? 4 : 2; }
+
+// Fixed-point fields with a per-site norm: the FP32 norms of a block of
+// `stride` sites follow its N * stride codes.
+template <typename S, int N>
+__device__ __forceinline__ const float *site_norms(const S *__restrict__ base, int64_t stride) {
+  return reinterpret_cast<const float *>(base + N * stride);
+}
+template <typename S, int N> __device__ __forceinline__ float *site_norms(S *__restrict__ base, int64_t stride) {
+  return reinterpret_cast<float *>(base + N * stride);
+}
+// The norm of a site and the codes' scale, in FP32: m = max_k |v_k|, then
+// each value is stored as the code of (float)v_k * (1 / m).
+template <int N, typename R> __device__ __forceinline__ float fixed_norm(const R *v) {
+  R m = 0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) m = v[k] < 0 ? (-v[k] > m ? -v[k] : m) : (v[k] > m ? v[k] : m);
+  return (float)m;
+}
+// The values a fixed-point store of v returns when read back.
+template <int N, typename R> __device__ __forceinline__ void fixed_round(R *v) {
+  const float m = fixed_norm<N, R>(v), inv = m > 0 ? 1.0f / m : 0.0f;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = (R)to_real<float>(Store<fx16>::from((float)v[k] * inv)) * (R)m;
+}
+
 template <typename S, int N, typename R>
 __device__ __forceinline__ void load_spinor_reals(const S *__restrict__ base, int64_t stride, int64_t s, R *out) {
   load_chunks<S, N, spinor_chunk<N>(), R>(base, stride, s, out);
+  if constexpr (is_fixed<S>()) {
+    const R m = (R)site_norms<S, N>(base, stride)[s];
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[k] *= m;
+  }
 }
 template <typename S, int N, typename R, bool NT = false>
 __device__ __forceinline__ void store_spinor_reals(S *__restrict__ base, int64_t stride, int64_t s, const R *in) {
-  store_chunks<S, N, spinor_chunk<N>(), R, NT>(base, stride, s, in);
+  if constexpr (is_fixed<S>()) {
+    const float m = fixed_norm<N, R>(in), inv = m > 0 ? 1.0f / m : 0.0f;
+    float w[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) w[k] = (float)in[k] * inv;
+    store_chunks<S, N, spinor_chunk<N>(), float, NT>(base, stride, s, w);
+    site_norms<S, N>(base, stride)[s] = m;
+  } else {
+    store_chunks<S, N, spinor_chunk<N>(), R, NT>(base, stride, s, in);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -416,20 +481,21 @@ __device__ __forceinline__ int hop(const Geom &g, const Site &x, int step, int *
 
 // Neighbour one hop along MU (STEP = +1 or -1) without loops or branches: the
 // hop crosses at most one tile face (tile extents are at least 2).
+// *crossed: whether the hop leaves x's tile.
 template <int MU, int STEP>
-__device__ __forceinline__ int hop1(const Geom &g, const Site &x, int *wraps) {
+__device__ __forceinline__ int hop1c(const Geom &g, const Site &x, int *wraps, bool *crossed) {
   int t[4] = {x.t[0], x.t[1], x.t[2], x.t[3]};
   int l[4] = {x.l[0], x.l[1], x.l[2], x.l[3]};
   int lm = l[MU] + STEP, tm = t[MU];
-  bool wrap;
+  bool wrap, cross;
   if constexpr (STEP > 0) {
-    const bool cross = lm >= g.B[MU];
+    cross = lm >= g.B[MU];
     lm = cross ? 0 : lm;
     tm = cross ? tm + 1 : tm;
     wrap = tm == g.NT[MU];
     tm = wrap ? 0 : tm;
   } else {
-    const bool cross = lm < 0;
+    cross = lm < 0;
     lm = cross ? g.B[MU] - 1 : lm;
     tm = cross ? tm - 1 : tm;
     wrap = tm < 0;
@@ -438,7 +504,22 @@ __device__ __forceinline__ int hop1(const Geom &g, const Site &x, int *wraps) {
   l[MU] = lm;
   t[MU] = tm;
   *wraps = wrap ? 1 : 0;
+  *crossed = cross;
   return encode_site(g, t, l);
+}
+template <int MU, int STEP>
+__device__ __forceinline__ int hop1(const Geom &g, const Site &x, int *wraps) {
+  bool cross;
+  return hop1c<MU, STEP>(g, x, wraps, &cross);
+}
+
+// A cut whose blocks are the layout tiles: along every axis the block extent
+// is the tile extent or the whole lattice, so a hop is dropped exactly when
+// it leaves its tile along an axis with more than one block.
+__host__ __device__ __forceinline__ bool cut_is_tiles(const Geom &g) {
+  for (int m = 0; m < 4; ++m)
+    if (g.cut[m] != g.B[m] && g.cut[m] != g.L[m]) return false;
+  return true;
 }
 
 // Neighbour STEP hops along MU (|STEP| <= 3) without loops or branches: with

@@ -37,6 +37,11 @@ constexpr int kMaxRed = 64;  // max values one reduction kernel returns
 // Spin-colour reals per site of the action's spinor.
 inline int spinor_reals(int action) { return action == LQCD_WILSON_CLOVER ? 24 : 6; }
 inline size_t prec_bytes(int prec) { return prec == LQCD_F64 ? 8 : (prec == LQCD_F32 ? 4 : 2); }
+// Bytes of one parity block of a per-site field of n reals (fixed-point
+// storage adds an FP32 norm per site for spinors and the clover term).
+inline size_t site_block_bytes(int prec, int n, size_t sites, bool normed) {
+  return sites * n * prec_bytes(prec) + (prec == LQCD_HALF && normed ? sites * 4 : 0);
+}
 
 struct OpInfo {
   const lqcd_operator *op;

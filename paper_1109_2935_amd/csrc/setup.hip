@@ -95,6 +95,7 @@ static hipError_t relayout_in(const Geom &go, So *out, const Geom &gi, int pin, 
     CASE(LQCD_F32)
     CASE(LQCD_F16)
     CASE(LQCD_BF16)
+    CASE(LQCD_HALF)
 #undef CASE
   }
   return hipErrorInvalidValue;
@@ -112,6 +113,7 @@ hipError_t launch_spinor_relayout(const Geom &go, int pout, void *out, const Geo
     CASE(LQCD_F32)
     CASE(LQCD_F16)
     CASE(LQCD_BF16)
+    CASE(LQCD_HALF)
 #undef CASE
   }
   return hipErrorInvalidValue;
@@ -135,6 +137,7 @@ static hipError_t spinor_io(const Geom &g, int prec, void *packed, double *natur
     CASE(LQCD_F32)
     CASE(LQCD_F16)
     CASE(LQCD_BF16)
+    CASE(LQCD_HALF)
 #undef CASE
   }
   return hipErrorInvalidValue;
@@ -253,6 +256,7 @@ static hipError_t gauge_io(const Geom &g, int prec, void *packed, const double *
     CASE(LQCD_F32)
     CASE(LQCD_F16)
     CASE(LQCD_BF16)
+    CASE(LQCD_HALF)
 #undef CASE
   }
   return hipErrorInvalidValue;
@@ -372,6 +376,25 @@ __device__ __forceinline__ void pack_herm6(const double (&ar)[6][6], const doubl
     }
 }
 
+// A parity block of the clover field: 72 reals per site, and for fixed-point
+// storage the FP32 site norms after them (two code slots per norm).
+template <typename S> __host__ __device__ constexpr int64_t clover_block_elems(int64_t vh) {
+  return vh * 72 + (is_fixed<S>() ? 2 * vh : 0);
+}
+
+template <typename S>
+__device__ __forceinline__ void store_clover_site(S *base, int64_t vh, int s, const double *v) {
+  if constexpr (is_fixed<S>()) {
+    const float m = fixed_norm<72, double>(v), inv = m > 0 ? 1.0f / m : 0.0f;
+    float w[72];
+    for (int k = 0; k < 72; ++k) w[k] = (float)v[k] * inv;
+    store_site<S, 72, float>(base, vh, s, w);
+    site_norms<S, 72>(base, vh)[s] = m;
+  } else {
+    store_site<S, 72, double>(base, vh, s, v);
+  }
+}
+
 template <typename S>
 __global__ void __launch_bounds__(64) clover_build_kernel(Geom g, double kc, S *clov, S *clov_inv, const double *nat,
                                                           int *fail) {
@@ -431,8 +454,8 @@ __global__ void __launch_bounds__(64) clover_build_kernel(Geom g, double kc, S *
     pack_herm6(br, bi, packed_i + 36 * b);
   }
   if (!ok) fail[0] = 1;
-  store_site<S, 72, double>(clov + (int64_t)parity * g.Vh * 72, g.Vh, s, packed_a);
-  store_site<S, 72, double>(clov_inv + (int64_t)parity * g.Vh * 72, g.Vh, s, packed_i);
+  store_clover_site<S>(clov + (int64_t)parity * clover_block_elems<S>(g.Vh), g.Vh, s, packed_a);
+  store_clover_site<S>(clov_inv + (int64_t)parity * clover_block_elems<S>(g.Vh), g.Vh, s, packed_i);
 }
 
 hipError_t launch_clover_build(const Geom &g, int prec, double kappa, double csw, void *clov, void *clov_inv,
@@ -450,6 +473,7 @@ hipError_t launch_clover_build(const Geom &g, int prec, double kappa, double csw
     CASE(LQCD_F32)
     CASE(LQCD_F16)
     CASE(LQCD_BF16)
+    CASE(LQCD_HALF)
 #undef CASE
   }
   return hipErrorInvalidValue;

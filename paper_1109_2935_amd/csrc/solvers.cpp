@@ -150,6 +150,8 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
   if (op_hi->action != LQCD_WILSON_CLOVER) return set_error(ctx, LQCD_ERR_INVALID_ARG, "GCR solves Wilson-clover systems");
   if (op_hi->prec != LQCD_F64) return set_error(ctx, LQCD_ERR_UNSUPPORTED, "op_hi must be FP64");
   if (!same_system(op_hi, op_krylov)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "op_krylov describes another system");
+  if (op_krylov->prec == LQCD_HALF)
+    return set_error(ctx, LQCD_ERR_UNSUPPORTED, "the Krylov space is kept in FP64, FP32, FP16 or BF16");
   TRY(check_fields_internal(ctx, op_hi));
   TRY(check_fields_internal(ctx, op_krylov));
   if (!prm) return set_error(ctx, LQCD_ERR_INVALID_ARG, "params are NULL");
@@ -200,7 +202,10 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
     TRY(S.vec(pc.spinor_bytes, &pout));
   }
   auto to_layout = [&](const OpInfo &a, const void *in, const OpInfo &b, void *out, double scale) -> lqcd_status {
-    if (same_tile(a, b)) return S.hip(blas_convert(a.prec, in, b.prec, out, ncomplex(a), scale, S.st), "convert");
+    // element-wise when only the precision changes (fixed point needs the
+    // per-site kernel, which forms each site's norm)
+    if (same_tile(a, b) && a.prec != LQCD_HALF && b.prec != LQCD_HALF)
+      return S.hip(blas_convert(a.prec, in, b.prec, out, ncomplex(a), scale, S.st), "convert");
     return S.hip(launch_spinor_relayout(b.g, b.prec, out, a.g, a.prec, in, a.nsp, 0, 1, scale, S.st), "relayout");
   };
   // LEARNED: a step whose residual reduction stalls (or whose network output
@@ -587,9 +592,12 @@ extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
 
   Solver S{ctx, (hipStream_t)stream, kSlotSolver};
   S.min_bytes = hi.spinor_bytes * nrhs;
-  if (nrhs > 1) {
+  // several sources, or 16-bit fixed-point sloppy vectors (whose kernels
+  // work site by site): the multi-source iteration
+  if (nrhs > 1 || lo.prec == LQCD_HALF) {
     if (prm->record_max > 0 || prm->res_history_max > 0)
-      return set_error(ctx, LQCD_ERR_INVALID_ARG, "recording and residual histories need nrhs = 1");
+      return set_error(ctx, LQCD_ERR_INVALID_ARG,
+                       "recording and residual histories need nrhs = 1 and op_sloppy not in fixed point");
     lqcd_solve_info inf{};
     const lqcd_status st = cg_solve_mrhs(S, hi, lo, prm, nrhs, x, b, &inf);
     inf.seconds = elapsed(t0);
@@ -954,6 +962,8 @@ extern "C" lqcd_status lqcd_bicgstab_solve(lqcd_context *ctx, const lqcd_operato
   if (op_sloppy) {
     TRY(check_op(ctx, op_sloppy, &lo));
     if (!same_system(op_hi, op_sloppy)) return set_error(ctx, LQCD_ERR_INVALID_ARG, "op_sloppy describes another system");
+    if (op_sloppy->prec == LQCD_HALF)
+      return set_error(ctx, LQCD_ERR_UNSUPPORTED, "BiCGstab's sloppy iteration runs in FP32, FP16 or BF16");
     TRY(check_fields_internal(ctx, op_sloppy));
   } else {
     lo = hi;

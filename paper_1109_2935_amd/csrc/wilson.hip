@@ -107,6 +107,16 @@ __device__ __forceinline__ void clover_mul(const S *__restrict__ clov, int64_t v
                                            cpx<R> (&out)[4][3], bool stream) {
   R a[72];
   load_site_once<S, 72, R>(clov, vh, s, a, stream);
+  if constexpr (is_fixed<S>()) {
+    const R m = (R)site_norms<S, 72>(clov, vh)[s];
+#pragma unroll
+    for (int k = 0; k < 72; ++k) a[k] *= m;
+  }
+  if constexpr (is_float16<S>()) {
+    // converted here, as in the hops: kept from folding into mixed-precision FMAs
+#pragma unroll
+    for (int k = 0; k < 72; ++k) __asm__ volatile("" : "+v"(a[k]));
+  }
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const R *A = a + 36 * b;
@@ -202,12 +212,18 @@ template <typename S, int RECON> struct HopIn {
   S psi[24];
   S link[RECON];
   int w;
+  int keep;  // TC: 0 when the hop leaves its Dirichlet block (tile)
 };
 
-template <int MU, int DIR, bool STREAM, typename S, int RECON>
+// TC: a launch whose Dirichlet blocks are the tiles (cut_is_tiles): a hop
+// that leaves the tile along a cut axis is loaded like any other and its
+// product multiplied by zero, so the hop code stays branch-free.
+template <int MU, int DIR, bool STREAM, bool TC, typename S, int RECON>
 __device__ __forceinline__ void hop_fetch(const WArgs<S> &a, const Site &x, int s, int rhs, HopIn<S, RECON> &h) {
   const int64_t vh = a.g.Vh, vs = vh * a.nrhs;
-  const int n = hop1<MU, DIR>(a.g, x, &h.w);
+  bool cross;
+  const int n = hop1c<MU, DIR>(a.g, x, &h.w, &cross);
+  h.keep = TC ? (int)!(cross && a.g.cut[MU] < a.g.L[MU]) : 1;
   load_chunks_raw<S, 24, spinor_chunk<24>()>(a.in, vs, rhs_index(rhs, n, vh, a.rg), h.psi);
   // forward hop: U_mu(x) of x's parity; backward: U_mu(x - mu) of the other
   const int lp = DIR > 0 ? x.p : 1 - x.p, ls = DIR > 0 ? s : n;
@@ -215,7 +231,7 @@ __device__ __forceinline__ void hop_fetch(const WArgs<S> &a, const Site &x, int 
                                                            h.link);
 }
 
-template <int MU, int DIR, typename S, typename R, int RECON>
+template <int MU, int DIR, bool TC, typename S, typename R, int RECON>
 __device__ __forceinline__ void hop_apply(const HopIn<S, RECON> &h, R sgn, int bc_t, cpx<R> (&acc)[4][3]) {
   cpx<R> psi[4][3], hh[2][3], u[2][3];
 #pragma unroll
@@ -223,7 +239,7 @@ __device__ __forceinline__ void hop_apply(const HopIn<S, RECON> &h, R sgn, int b
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       R re = to_real<R>(h.psi[6 * sp + 2 * c]), im = to_real<R>(h.psi[6 * sp + 2 * c + 1]);
-      if constexpr (sizeof(S) == 2) {
+      if constexpr (is_float16<S>()) {
         // convert here: the empty asm keeps the compiler from folding the
         // stored halves into mixed-precision FMAs, which keeps them live
         // across the hop (170-230 VGPRs instead of about 110)
@@ -234,11 +250,18 @@ __device__ __forceinline__ void hop_apply(const HopIn<S, RECON> &h, R sgn, int b
     }
   const R ps = DIR > 0 ? -sgn : sgn;
   project<MU, R>(psi, ps, hh);
+  if constexpr (TC) {
+    const R k = (R)h.keep;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) hh[i][c] = k * hh[i][c];
+  }
   R lv[RECON];
 #pragma unroll
   for (int k = 0; k < RECON; ++k) {
     lv[k] = to_real<R>(h.link[k]);
-    if constexpr (sizeof(S) == 2) __asm__ volatile("" : "+v"(lv[k]));
+    if constexpr (is_float16<S>()) __asm__ volatile("" : "+v"(lv[k]));
   }
   const Link<R> U = unpack_link<RECON, R>(lv);
   if constexpr (DIR > 0) {
@@ -265,23 +288,31 @@ __device__ __forceinline__ void hop_apply(const HopIn<S, RECON> &h, R sgn, int b
 // kernel (W_XPAY) spills.
 template <typename S, int RECON, int MODE> constexpr bool pipelined_hops() {
   if constexpr (std::is_same<S, double>::value) return MODE == W_HOP && RECON == 12;
+  if constexpr (is_fixed<S>()) return false;  // the neighbour's norm is read with its codes
   return RECON != 8 && (sizeof(S) == 4 || MODE != W_XPAY);
+}
+
+// Launches whose Dirichlet blocks are the tiles (the Schwarz preconditioner's
+// cut Schur kernels) take the pipelined hops with the cut as a mask where the
+// uncut launches take them.
+template <typename S, int RECON, int MODE> constexpr bool tile_cut_pipelined() {
+  return pipelined_hops<S, RECON, MODE>();
 }
 
 // Apply the hop held in HA, then refill HA with the hop two ahead; the other
 // buffer's loads stay in flight meanwhile.
-#define HOP_STEP(MUa, DIRa, HA, MUn, DIRn)                      \
-  __builtin_amdgcn_sched_barrier(0);                           \
-  hop_apply<MUa, DIRa, S, R, RECON>(HA, sgn, a.g.bc_t, acc);   \
-  __builtin_amdgcn_sched_barrier(0);                           \
-  hop_fetch<MUn, DIRn, STREAM, S, RECON>(a, x, s, rhs, HA);
+#define HOP_STEP(MUa, DIRa, HA, MUn, DIRn)                          \
+  __builtin_amdgcn_sched_barrier(0);                               \
+  hop_apply<MUa, DIRa, TC, S, R, RECON>(HA, sgn, a.g.bc_t, acc);   \
+  __builtin_amdgcn_sched_barrier(0);                               \
+  hop_fetch<MUn, DIRn, STREAM, TC, S, RECON>(a, x, s, rhs, HA);
 
-template <bool STREAM, typename S, typename R, int RECON>
+template <bool STREAM, bool TC, typename S, typename R, int RECON>
 __device__ __forceinline__ void wilson_hops_pipelined(const WArgs<S> &a, const Site &x, int s, int rhs, R sgn,
                                                       cpx<R> (&acc)[4][3]) {
   HopIn<S, RECON> A, B;
-  hop_fetch<0, +1, STREAM, S, RECON>(a, x, s, rhs, A);
-  hop_fetch<0, -1, STREAM, S, RECON>(a, x, s, rhs, B);
+  hop_fetch<0, +1, STREAM, TC, S, RECON>(a, x, s, rhs, A);
+  hop_fetch<0, -1, STREAM, TC, S, RECON>(a, x, s, rhs, B);
   HOP_STEP(0, +1, A, 1, +1)
   HOP_STEP(0, -1, B, 1, -1)
   HOP_STEP(1, +1, A, 2, +1)
@@ -289,9 +320,9 @@ __device__ __forceinline__ void wilson_hops_pipelined(const WArgs<S> &a, const S
   HOP_STEP(2, +1, A, 3, +1)
   HOP_STEP(2, -1, B, 3, -1)
   __builtin_amdgcn_sched_barrier(0);
-  hop_apply<3, +1, S, R, RECON>(A, sgn, a.g.bc_t, acc);
+  hop_apply<3, +1, TC, S, R, RECON>(A, sgn, a.g.bc_t, acc);
   __builtin_amdgcn_sched_barrier(0);
-  hop_apply<3, -1, S, R, RECON>(B, sgn, a.g.bc_t, acc);
+  hop_apply<3, -1, TC, S, R, RECON>(B, sgn, a.g.bc_t, acc);
   __builtin_amdgcn_sched_barrier(0);
 }
 #undef HOP_STEP
@@ -397,12 +428,14 @@ __device__ __forceinline__ void segment_reduce_store(double (&v)[3], int seg, in
     for (int k = 0; k < 3; ++k) dst[3 * (site / seg) + k] = v[k];
 }
 
+// How a launch takes its hops: checked one by one at run time (any cut),
+// pipelined (no cut), or pipelined with the tile faces cut (cut_is_tiles).
+enum HopForm { kHopsChecked = 0, kHopsPipe = 1, kHopsPipeTileCut = 2 };
+
 // One output (site s, right-hand side rhs) of the hopping term and its epilogue.
 // MF: link products on the matrix cores (16-bit storage, sources in groups of
 // 4 lanes); then every lane of the wave calls this, `valid` marks real work.
-// CUT = false: the launch has no Dirichlet cut (every hop is taken) and takes
-// the pipelined hops.
-template <typename S, typename R, int RECON, int MODE, bool REDUCE, bool MF = false, bool CUT = true>
+template <typename S, typename R, int RECON, int MODE, bool REDUCE, bool MF = false, int HOPS = kHopsChecked>
 __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, double (&red)[3], bool valid = true) {
   const Site x = decode_site(a.g, s, a.parity);
   const R sgn = a.dagger ? R(-1) : R(1);
@@ -418,16 +451,17 @@ __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, 
     wilson_dir_mf<3, S, RECON>(a, x, s, rhs, valid, sgn, acc);
     if (!valid) return;
   } else {
-    if constexpr (!CUT) {
+    if constexpr (HOPS != kHopsChecked) {
       // One instantiation for every source count (streamed link loads), so a
       // site's arithmetic, and its rounding, does not depend on nrhs. The
       // branch between two calls of it is deliberate: as one basic block with
       // the epilogue, the clover kernels spill (measured: 700-900 bytes per
       // lane); split like this they need 137-158 VGPRs and no scratch.
+      constexpr bool TC = HOPS == kHopsPipeTileCut;
       if (a.nrhs == 1)
-        wilson_hops_pipelined<true, S, R, RECON>(a, x, s, rhs, sgn, acc);
+        wilson_hops_pipelined<true, TC, S, R, RECON>(a, x, s, rhs, sgn, acc);
       else
-        wilson_hops_pipelined<true, S, R, RECON>(a, x, s, rhs, sgn, acc);
+        wilson_hops_pipelined<true, TC, S, R, RECON>(a, x, s, rhs, sgn, acc);
     } else {
       wilson_dir<0, S, R, RECON>(a, x, s, rhs, sgn, acc);
       wilson_dir<1, S, R, RECON>(a, x, s, rhs, sgn, acc);
@@ -435,6 +469,9 @@ __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, 
       wilson_dir<3, S, R, RECON>(a, x, s, rhs, sgn, acc);
     }
   }
+  // the epilogue's loads (xin, clover) are not hoisted into the hop pipeline,
+  // where they would hold registers through all eight hops
+  if constexpr (HOPS != kHopsChecked) __builtin_amdgcn_sched_barrier(0);
   const R coef = (R)a.coef;
   const int64_t vh = a.g.Vh, vs = vh * a.nrhs, v = rhs_index(rhs, s, vh, a.rg);
   cpx<R> res[4][3];
@@ -452,6 +489,15 @@ __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, 
   } else {
     cpx<R> xv[4][3];
     load_spinor<S, R>(a.xin, vs, v, xv);
+    if constexpr (is_float16<S>()) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          __asm__ volatile("" : "+v"(xv[i][c].re));
+          __asm__ volatile("" : "+v"(xv[i][c].im));
+        }
+    }
     if constexpr (MODE == W_XPAY_CLOV) {
       clover_mul<S, R>(a.clov, vh, s, xv, res, a.nrhs == 1);
 #pragma unroll
@@ -466,11 +512,29 @@ __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, 
     }
     if constexpr (REDUCE) {
       // inner products of the values as stored
+      R fx[24];
+      if constexpr (is_fixed<S>()) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            fx[6 * i + 2 * c] = res[i][c].re;
+            fx[6 * i + 2 * c + 1] = res[i][c].im;
+          }
+        fixed_round<24, R>(fx);
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const double qr = quantize<S, R>(res[i][c].re), qi = quantize<S, R>(res[i][c].im);
+          double qr, qi;
+          if constexpr (is_fixed<S>()) {
+            qr = fx[6 * i + 2 * c];
+            qi = fx[6 * i + 2 * c + 1];
+          } else {
+            qr = quantize<S, R>(res[i][c].re);
+            qi = quantize<S, R>(res[i][c].im);
+          }
           const double rr = xv[i][c].re, ri = xv[i][c].im;
           red[0] += qr * rr + qi * ri;
           red[1] += qr * ri - qi * rr;
@@ -484,7 +548,7 @@ __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, 
 // One thread per (site, rhs): the lanes of a site block's source group are
 // adjacent in the workgroup and the workgroups of its groups are adjacent in
 // the launch (rhs_block), so link and clover loads are shared.
-template <typename S, typename R, int RECON, int MODE, bool REDUCE, bool CUT>
+template <typename S, typename R, int RECON, int MODE, bool REDUCE, int HOPS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) wilson_kernel(WArgs<S> a) {
   const RhsBlock rb = rhs_block(a.nrhs, a.rg);
   double red[3] = {0, 0, 0};
@@ -493,7 +557,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     // one colour of tiles (single right-hand side; the host checks)
     if (a.g.colour >= 0) s = rb.s < (a.g.Vh >> 1) ? colour_site(a.g, rb.s) : a.g.Vh;
   }
-  if (s < a.g.Vh) wilson_point<S, R, RECON, MODE, REDUCE, false, CUT>(a, s, rb.rhs, red);
+  if (s < a.g.Vh) wilson_point<S, R, RECON, MODE, REDUCE, false, HOPS>(a, s, rb.rhs, red);
   if constexpr (REDUCE) {  // single right-hand side only
     segment_reduce_store(red, a.g.Vt2 < 64 ? a.g.Vt2 : 64, s, a.g.Vh, a.partials);
   }
@@ -539,14 +603,16 @@ __device__ __forceinline__ void batch_item(const BatchArgs<S> &b, int it) {
   const RhsBlock rb = rhs_block_at(it - b.begin[j], a.nrhs, a.rg);
   const bool valid = rb.s < a.g.Vh;
   double red[3];
-  if constexpr (sizeof(S) == 2) {
+  if constexpr (is_float16<S>()) {
     if (b.mfma && a.nrhs % 4 == 0) {  // uniform over the workgroup
       wilson_point<S, R, RECON, W_HOP, false, true>(a, valid ? rb.s : 0, rb.rhs, red, valid);
       return;
     }
   }
   // jobs carry no cut: the same hop code as the per-operator launch
-  if (valid) wilson_point<S, R, RECON, W_HOP, false, false, !pipelined_hops<S, RECON, W_HOP>()>(a, rb.s, rb.rhs, red);
+  if (valid)
+    wilson_point<S, R, RECON, W_HOP, false, false, pipelined_hops<S, RECON, W_HOP>() ? kHopsPipe : kHopsChecked>(
+        a, rb.s, rb.rhs, red);
 }
 
 // Single launch with one workgroup per item (items remapped per XCD like the
@@ -644,6 +710,7 @@ hipError_t launch_mr_update(const Geom &g, int prec, void *x, void *r, const voi
     CASE(LQCD_F32)
     CASE(LQCD_F16)
     CASE(LQCD_BF16)
+    CASE(LQCD_HALF)
 #undef CASE
   }
   return hipErrorInvalidValue;
@@ -686,11 +753,18 @@ static hipError_t launch_w3(const WilsonLaunch &w, hipStream_t st) {
   // the others keep the runtime-checked hops
   if constexpr (pipelined_hops<S, RECON, MODE>()) {
     if (!w.g.has_cut) {
-      hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED, false>), dim3(nwg), dim3(w.block_threads), 0, st, a);
+      hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED, kHopsPipe>), dim3(nwg), dim3(w.block_threads), 0, st,
+                         a);
+      return hipGetLastError();
+    }
+    if (tile_cut_pipelined<S, RECON, MODE>() && cut_is_tiles(w.g)) {
+      hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED, kHopsPipeTileCut>), dim3(nwg), dim3(w.block_threads), 0,
+                         st, a);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED, true>), dim3(nwg), dim3(w.block_threads), 0, st, a);
+  hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED, kHopsChecked>), dim3(nwg), dim3(w.block_threads), 0, st,
+                     a);
   return hipGetLastError();
 }
 
@@ -726,6 +800,7 @@ hipError_t launch_wilson(const WilsonLaunch &w, hipStream_t st) {
     case LQCD_F32: return launch_w1<LQCD_F32>(w, st);
     case LQCD_F16: return launch_w1<LQCD_F16>(w, st);
     case LQCD_BF16: return launch_w1<LQCD_BF16>(w, st);
+    case LQCD_HALF: return launch_w1<LQCD_HALF>(w, st);
   }
   return hipErrorInvalidValue;
 }
@@ -744,6 +819,7 @@ hipError_t launch_clover_apply(const Geom &g, int prec, void *out, const void *i
     CASE(LQCD_F32)
     CASE(LQCD_F16)
     CASE(LQCD_BF16)
+    CASE(LQCD_HALF)
 #undef CASE
   }
   return hipErrorInvalidValue;
@@ -810,6 +886,7 @@ hipError_t launch_wilson_batch(int prec, int recon, const BatchJob *jobs, int nj
     case LQCD_F32: return launch_b1<LQCD_F32>(recon, jobs, njobs, dagger, t, mfma, counter, st);
     case LQCD_F16: return launch_b1<LQCD_F16>(recon, jobs, njobs, dagger, t, mfma, counter, st);
     case LQCD_BF16: return launch_b1<LQCD_BF16>(recon, jobs, njobs, dagger, t, mfma, counter, st);
+    case LQCD_HALF: return launch_b1<LQCD_HALF>(recon, jobs, njobs, dagger, t, mfma, counter, st);
   }
   return hipErrorInvalidValue;
 }

@@ -23,13 +23,13 @@ LQCD_ERR_DEVICE = 4
 LQCD_ERR_NOT_CONVERGED = 5
 LQCD_ERR_BREAKDOWN = 6
 
-LQCD_F64, LQCD_F32, LQCD_F16, LQCD_BF16 = 0, 1, 2, 3
+LQCD_F64, LQCD_F32, LQCD_F16, LQCD_BF16, LQCD_HALF = 0, 1, 2, 3, 4
 LQCD_WILSON_CLOVER, LQCD_STAGGERED = 0, 1
 LQCD_FIELD_SPINOR, LQCD_FIELD_SPINOR_FULL, LQCD_FIELD_GAUGE, LQCD_FIELD_LONG, LQCD_FIELD_CLOVER = 0, 1, 2, 3, 4
 LQCD_PRECOND_NONE, LQCD_PRECOND_SCHWARZ, LQCD_PRECOND_LEARNED = 0, 1, 2
 LQCD_CG_CGNE_SCHUR, LQCD_CG_STAG_NORMAL = 0, 1
 
-PREC_BYTES = {LQCD_F64: 8, LQCD_F32: 4, LQCD_F16: 2, LQCD_BF16: 2}
+PREC_BYTES = {LQCD_F64: 8, LQCD_F32: 4, LQCD_F16: 2, LQCD_BF16: 2, LQCD_HALF: 2}
 
 
 class LqcdError(RuntimeError):

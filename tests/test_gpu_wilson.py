@@ -19,14 +19,15 @@ PREC_RECON = [(0, 18), (0, 12), (0, 8), (1, 18), (1, 12), (1, 8), (2, 18), (2, 1
 
 
 # Schwarz K with 8 MR steps, by storage precision. Each MR step stores r, the
-# intermediate odd spinor, q and x in the storage format (independent
-# round-to-nearest errors of relative RMS u / sqrt(3), u the unit roundoff);
-# an error in r_k reaches x through the remaining steps, which approximate
-# Mhat_B^-1 (norm below 2 on these blocks). Adding the 32 roundings in
-# quadrature and allowing a factor 3 for the spread gives
-# 3 * 2 * sqrt(32) / sqrt(3) u ~ 20 u: 1e-2 for FP16 (u = 2^-11) and 8e-2 for
-# BF16 (u = 2^-8).
-SCHWARZ_TOL = {0: 1e-12, 1: 1e-5, 2: 1e-2, 3: 8e-2}
+# intermediate odd spinor, q and x in the storage format: independent
+# round-to-nearest errors of relative RMS u / sqrt(3), u the unit roundoff
+# (2^-11 for FP16, 2^-8 for BF16). An error in r_k reaches x through the
+# remaining steps, which approximate Mhat_B^-1; Mhat_B = A - kappa^2 (...) with
+# kappa^2 = 0.015 is close to the identity, so that factor is taken as 1. The
+# 32 roundings added in quadrature give sqrt(32 / 3) u = 3.3 u; a factor 3 for
+# the spread of a statistical bound gives 10 u: 5e-3 for FP16 and 4e-2 for
+# BF16.
+SCHWARZ_TOL = {0: 1e-12, 1: 1e-5, 2: 5e-3, 3: 4e-2}
 
 
 class Fields:
@@ -175,7 +176,7 @@ def test_schwarz_over_relaxed(ctx, omega, cycles):
     else:
         ref = solvers.sap(ref_op, src, block, steps, cycles, omega=omega)
         plain = solvers.sap(ref_op, src, block, steps, cycles)
-    assert rel(ref, plain) > 1e-3
+    assert rel(ref, plain) > 1e-5
     out = o.spinor()
     L.lqcd_schwarz_precond(ctx, o.op, ops.schwarz_params(block, steps, cycles, omega=omega), out,
                            o.import_spinor(src, 0))
