@@ -481,21 +481,20 @@ __device__ __forceinline__ int hop(const Geom &g, const Site &x, int step, int *
 
 // Neighbour one hop along MU (STEP = +1 or -1) without loops or branches: the
 // hop crosses at most one tile face (tile extents are at least 2).
-// *crossed: whether the hop leaves x's tile.
 template <int MU, int STEP>
-__device__ __forceinline__ int hop1c(const Geom &g, const Site &x, int *wraps, bool *crossed) {
+__device__ __forceinline__ int hop1(const Geom &g, const Site &x, int *wraps) {
   int t[4] = {x.t[0], x.t[1], x.t[2], x.t[3]};
   int l[4] = {x.l[0], x.l[1], x.l[2], x.l[3]};
   int lm = l[MU] + STEP, tm = t[MU];
-  bool wrap, cross;
+  bool wrap;
   if constexpr (STEP > 0) {
-    cross = lm >= g.B[MU];
+    const bool cross = lm >= g.B[MU];
     lm = cross ? 0 : lm;
     tm = cross ? tm + 1 : tm;
     wrap = tm == g.NT[MU];
     tm = wrap ? 0 : tm;
   } else {
-    cross = lm < 0;
+    const bool cross = lm < 0;
     lm = cross ? g.B[MU] - 1 : lm;
     tm = cross ? tm - 1 : tm;
     wrap = tm < 0;
@@ -504,22 +503,7 @@ __device__ __forceinline__ int hop1c(const Geom &g, const Site &x, int *wraps, b
   l[MU] = lm;
   t[MU] = tm;
   *wraps = wrap ? 1 : 0;
-  *crossed = cross;
   return encode_site(g, t, l);
-}
-template <int MU, int STEP>
-__device__ __forceinline__ int hop1(const Geom &g, const Site &x, int *wraps) {
-  bool cross;
-  return hop1c<MU, STEP>(g, x, wraps, &cross);
-}
-
-// A cut whose blocks are the layout tiles: along every axis the block extent
-// is the tile extent or the whole lattice, so a hop is dropped exactly when
-// it leaves its tile along an axis with more than one block.
-__host__ __device__ __forceinline__ bool cut_is_tiles(const Geom &g) {
-  for (int m = 0; m < 4; ++m)
-    if (g.cut[m] != g.B[m] && g.cut[m] != g.L[m]) return false;
-  return true;
 }
 
 // Neighbour STEP hops along MU (|STEP| <= 3) without loops or branches: with

@@ -212,18 +212,12 @@ template <typename S, int RECON> struct HopIn {
   S psi[24];
   S link[RECON];
   int w;
-  int keep;  // TC: 0 when the hop leaves its Dirichlet block (tile)
 };
 
-// TC: a launch whose Dirichlet blocks are the tiles (cut_is_tiles): a hop
-// that leaves the tile along a cut axis is loaded like any other and its
-// product multiplied by zero, so the hop code stays branch-free.
-template <int MU, int DIR, bool STREAM, bool TC, typename S, int RECON>
+template <int MU, int DIR, bool STREAM, typename S, int RECON>
 __device__ __forceinline__ void hop_fetch(const WArgs<S> &a, const Site &x, int s, int rhs, HopIn<S, RECON> &h) {
   const int64_t vh = a.g.Vh, vs = vh * a.nrhs;
-  bool cross;
-  const int n = hop1c<MU, DIR>(a.g, x, &h.w, &cross);
-  h.keep = TC ? (int)!(cross && a.g.cut[MU] < a.g.L[MU]) : 1;
+  const int n = hop1<MU, DIR>(a.g, x, &h.w);
   load_chunks_raw<S, 24, spinor_chunk<24>()>(a.in, vs, rhs_index(rhs, n, vh, a.rg), h.psi);
   // forward hop: U_mu(x) of x's parity; backward: U_mu(x - mu) of the other
   const int lp = DIR > 0 ? x.p : 1 - x.p, ls = DIR > 0 ? s : n;
@@ -231,7 +225,7 @@ __device__ __forceinline__ void hop_fetch(const WArgs<S> &a, const Site &x, int 
                                                            h.link);
 }
 
-template <int MU, int DIR, bool TC, typename S, typename R, int RECON>
+template <int MU, int DIR, typename S, typename R, int RECON>
 __device__ __forceinline__ void hop_apply(const HopIn<S, RECON> &h, R sgn, int bc_t, cpx<R> (&acc)[4][3]) {
   cpx<R> psi[4][3], hh[2][3], u[2][3];
 #pragma unroll
@@ -250,13 +244,6 @@ __device__ __forceinline__ void hop_apply(const HopIn<S, RECON> &h, R sgn, int b
     }
   const R ps = DIR > 0 ? -sgn : sgn;
   project<MU, R>(psi, ps, hh);
-  if constexpr (TC) {
-    const R k = (R)h.keep;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) hh[i][c] = k * hh[i][c];
-  }
   R lv[RECON];
 #pragma unroll
   for (int k = 0; k < RECON; ++k) {
@@ -292,27 +279,20 @@ template <typename S, int RECON, int MODE> constexpr bool pipelined_hops() {
   return RECON != 8 && (sizeof(S) == 4 || MODE != W_XPAY);
 }
 
-// Launches whose Dirichlet blocks are the tiles (the Schwarz preconditioner's
-// cut Schur kernels) take the pipelined hops with the cut as a mask where the
-// uncut launches take them.
-template <typename S, int RECON, int MODE> constexpr bool tile_cut_pipelined() {
-  return pipelined_hops<S, RECON, MODE>();
-}
-
 // Apply the hop held in HA, then refill HA with the hop two ahead; the other
 // buffer's loads stay in flight meanwhile.
-#define HOP_STEP(MUa, DIRa, HA, MUn, DIRn)                          \
-  __builtin_amdgcn_sched_barrier(0);                               \
-  hop_apply<MUa, DIRa, TC, S, R, RECON>(HA, sgn, a.g.bc_t, acc);   \
-  __builtin_amdgcn_sched_barrier(0);                               \
-  hop_fetch<MUn, DIRn, STREAM, TC, S, RECON>(a, x, s, rhs, HA);
+#define HOP_STEP(MUa, DIRa, HA, MUn, DIRn)                      \
+  __builtin_amdgcn_sched_barrier(0);                           \
+  hop_apply<MUa, DIRa, S, R, RECON>(HA, sgn, a.g.bc_t, acc);   \
+  __builtin_amdgcn_sched_barrier(0);                           \
+  hop_fetch<MUn, DIRn, STREAM, S, RECON>(a, x, s, rhs, HA);
 
-template <bool STREAM, bool TC, typename S, typename R, int RECON>
+template <bool STREAM, typename S, typename R, int RECON>
 __device__ __forceinline__ void wilson_hops_pipelined(const WArgs<S> &a, const Site &x, int s, int rhs, R sgn,
                                                       cpx<R> (&acc)[4][3]) {
   HopIn<S, RECON> A, B;
-  hop_fetch<0, +1, STREAM, TC, S, RECON>(a, x, s, rhs, A);
-  hop_fetch<0, -1, STREAM, TC, S, RECON>(a, x, s, rhs, B);
+  hop_fetch<0, +1, STREAM, S, RECON>(a, x, s, rhs, A);
+  hop_fetch<0, -1, STREAM, S, RECON>(a, x, s, rhs, B);
   HOP_STEP(0, +1, A, 1, +1)
   HOP_STEP(0, -1, B, 1, -1)
   HOP_STEP(1, +1, A, 2, +1)
@@ -320,9 +300,9 @@ __device__ __forceinline__ void wilson_hops_pipelined(const WArgs<S> &a, const S
   HOP_STEP(2, +1, A, 3, +1)
   HOP_STEP(2, -1, B, 3, -1)
   __builtin_amdgcn_sched_barrier(0);
-  hop_apply<3, +1, TC, S, R, RECON>(A, sgn, a.g.bc_t, acc);
+  hop_apply<3, +1, S, R, RECON>(A, sgn, a.g.bc_t, acc);
   __builtin_amdgcn_sched_barrier(0);
-  hop_apply<3, -1, TC, S, R, RECON>(B, sgn, a.g.bc_t, acc);
+  hop_apply<3, -1, S, R, RECON>(B, sgn, a.g.bc_t, acc);
   __builtin_amdgcn_sched_barrier(0);
 }
 #undef HOP_STEP
@@ -428,9 +408,12 @@ __device__ __forceinline__ void segment_reduce_store(double (&v)[3], int seg, in
     for (int k = 0; k < 3; ++k) dst[3 * (site / seg) + k] = v[k];
 }
 
-// How a launch takes its hops: checked one by one at run time (any cut),
-// pipelined (no cut), or pipelined with the tile faces cut (cut_is_tiles).
-enum HopForm { kHopsChecked = 0, kHopsPipe = 1, kHopsPipeTileCut = 2 };
+// How a launch takes its hops: checked one by one at run time (any cut), or
+// pipelined (no cut). A pipelined form for cuts at the tile faces (the dropped
+// hop loaded like any other and zeroed by a select) measured 2.5% slower in
+// the Schwarz preconditioner than the checked form, which skips the dropped
+// hops' loads, and is not kept.
+enum HopForm { kHopsChecked = 0, kHopsPipe = 1 };
 
 // One output (site s, right-hand side rhs) of the hopping term and its epilogue.
 // MF: link products on the matrix cores (16-bit storage, sources in groups of
@@ -457,11 +440,10 @@ __device__ __forceinline__ void wilson_point(const WArgs<S> &a, int s, int rhs, 
       // branch between two calls of it is deliberate: as one basic block with
       // the epilogue, the clover kernels spill (measured: 700-900 bytes per
       // lane); split like this they need 137-158 VGPRs and no scratch.
-      constexpr bool TC = HOPS == kHopsPipeTileCut;
       if (a.nrhs == 1)
-        wilson_hops_pipelined<true, TC, S, R, RECON>(a, x, s, rhs, sgn, acc);
+        wilson_hops_pipelined<true, S, R, RECON>(a, x, s, rhs, sgn, acc);
       else
-        wilson_hops_pipelined<true, TC, S, R, RECON>(a, x, s, rhs, sgn, acc);
+        wilson_hops_pipelined<true, S, R, RECON>(a, x, s, rhs, sgn, acc);
     } else {
       wilson_dir<0, S, R, RECON>(a, x, s, rhs, sgn, acc);
       wilson_dir<1, S, R, RECON>(a, x, s, rhs, sgn, acc);
@@ -755,11 +737,6 @@ static hipError_t launch_w3(const WilsonLaunch &w, hipStream_t st) {
     if (!w.g.has_cut) {
       hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED, kHopsPipe>), dim3(nwg), dim3(w.block_threads), 0, st,
                          a);
-      return hipGetLastError();
-    }
-    if (tile_cut_pipelined<S, RECON, MODE>() && cut_is_tiles(w.g)) {
-      hipLaunchKernelGGL((wilson_kernel<S, R, RECON, MODE, RED, kHopsPipeTileCut>), dim3(nwg), dim3(w.block_threads), 0,
-                         st, a);
       return hipGetLastError();
     }
   }

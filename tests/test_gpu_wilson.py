@@ -83,6 +83,28 @@ def test_dslash_dirichlet_cut(ctx, prec, recon, block):
             check(got, ref, TOL[prec], "dagger %d parity %d" % (dagger, p))
 
 
+@pytest.mark.parametrize("prec,recon", [(0, 18), (1, 12), (2, 12), (3, 12), (4, 12)])
+def test_dslash_cut_never_reads_other_blocks(ctx, prec, recon):
+    """With a cut at the tile faces, values in another block must not reach an
+    output, not even as 0 * NaN: one block's input is NaN, and every output
+    outside that block is finite and equals the oracle's cut operator applied
+    to the input with that block zeroed."""
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    U, psi, _ = Fields.get(dims)
+    o = make_op(ctx, dims, prec, recon, tile=block)
+    lab = oracle.block_labels(dims, block)
+    for p in (0, 1):
+        src = on_parity(psi, oracle.parity_mask(dims, 1 - p))
+        bad = np.where((lab == 5)[..., None, None], np.nan + 0j, src)
+        out = o.spinor()
+        L.lqcd_dslash(ctx, o.op, out, o.import_spinor(bad, 1 - p), p, 0, block=block)
+        got = np_of(o.export_spinor(out, p))
+        ref = oracle.wilson_dslash(dims, U, np.where((lab == 5)[..., None, None], 0, src), out_parity=p, block=block)
+        keep = (lab != 5)[..., None, None] & np.ones(got.shape, bool)
+        assert np.isfinite(got[keep]).all()
+        check(np.where(keep, got, 0), np.where(keep, ref, 0), TOL[prec] if prec < 4 else 6e-4, "parity %d" % p)
+
+
 @pytest.mark.parametrize("bc_t", [1, -1])
 def test_dslash_periodic_and_antiperiodic(ctx, bc_t):
     dims = (4, 4, 6, 8)
