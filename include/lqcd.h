@@ -348,6 +348,27 @@ lqcd_status lqcd_schur_apply(lqcd_context *ctx, const lqcd_operator *op, void *o
                              int32_t dagger, const int32_t *block, int32_t nrhs, lqcd_stream stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): exactly
+ * lqcd_schur_apply (the same kernels and result, bit for bit), but its
+ * intermediate odd-parity spinor lives in a fixed 64 MiB device array of the
+ * library (one per GPU, held from library load until the process ends)
+ * instead of context scratch, and the autotuner does not run timing launches
+ * (tuned launch parameters if the shape was tuned in this context, else
+ * defaults). Nothing is allocated: no hipMalloc, hipFree or event creation.
+ * The caller passes the inputs and outputs as for lqcd_schur_apply.
+ * Errors: LQCD_ERR_UNSUPPORTED when one parity of nrhs spinors of op
+ * (lqcd_field_bytes(op, LQCD_FIELD_SPINOR, nrhs)) exceeds 64 MiB, with
+ * nothing launched; otherwise the checks of lqcd_schur_apply.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (other streams, other host threads, other contexts) race and must be
+ * ordered by the caller. The array needs no clearing (each call writes the
+ * part it reads first).
+ */
+lqcd_status lqcd_schur_apply_noalloc(lqcd_context *ctx, const lqcd_operator *op, void *out, const void *in,
+                                     int32_t dagger, const int32_t *block, int32_t nrhs, lqcd_stream stream);
+
+/*
  * Batched Wilson hopping term over several operators in one persistent
  * launch (the lattices may differ in size): for every job,
  * out = D_{p,1-p} in (dagger: D^+) with nrhs right-hand sides (source-major).

@@ -365,6 +365,7 @@ lqcd_status lqcd_context_create(lqcd_context **out) {
   if (!out) return set_error(nullptr, LQCD_ERR_INVALID_ARG, "ctx pointer is NULL");
   lqcd_context *ctx = new lqcd_context();
   hipGetDevice(&ctx->device);
+  noalloc_init_device(ctx->device);
   lqcd_status s = LQCD_OK;
   if (hipMalloc(&ctx->red_partials, 1024 * kMaxRed * sizeof(double)) != hipSuccess ||
       hipMalloc(&ctx->red_counter, 64) != hipSuccess ||

@@ -28,6 +28,7 @@ struct lqcd_context {
   std::map<std::string, int> tuned;
   std::string tune_file;
   bool tune_enabled = true;
+  bool tune_frozen = false;  // no timing runs: tuned or default launch parameters only
 };
 
 namespace lqcd {

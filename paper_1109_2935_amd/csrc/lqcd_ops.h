@@ -55,4 +55,8 @@ lqcd_status check_fields_internal(lqcd_context *ctx, const lqcd_operator *op);
 hipError_t launch_mr_update(const Geom &g, int prec, void *x, void *r, const void *q, const double *partials, int nps,
                             bool first, double omega, hipStream_t st);
 
+// Looks up this device's copy of the no-allocation entry point's device array
+// (called at context creation, with the device current).
+void noalloc_init_device(int dev);
+
 }  // namespace lqcd

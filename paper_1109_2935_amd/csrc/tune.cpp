@@ -68,7 +68,7 @@ int tune_pick(lqcd_context *ctx, const std::string &key, const std::vector<int> 
   load_file(ctx);
   auto it = ctx->tuned.find(key);
   if (it != ctx->tuned.end()) return it->second;
-  if (!may_time || !ctx->tune_enabled) return fallback;
+  if (!may_time || !ctx->tune_enabled || ctx->tune_frozen) return fallback;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fallback;
   if (hipEventCreate(&e1) != hipSuccess) {

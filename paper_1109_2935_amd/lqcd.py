@@ -130,6 +130,7 @@ _SIGNATURES = {
     "lqcd_dslash": [_P, _OPP, _P, _P, _I, _I, ctypes.POINTER(ctypes.c_int32), _I, _P],
     "lqcd_clover_apply": [_P, _OPP, _P, _P, _I, _I, _I, _P],
     "lqcd_schur_apply": [_P, _OPP, _P, _P, _I, ctypes.POINTER(ctypes.c_int32), _I, _P],
+    "lqcd_schur_apply_noalloc": [_P, _OPP, _P, _P, _I, ctypes.POINTER(ctypes.c_int32), _I, _P],
     "lqcd_schwarz_precond": [_P, _OPP, ctypes.POINTER(lqcd_schwarz_params), _P, _P, _P],
     "lqcd_gcr_solve": [_P, _OPP, _OPP, _OPP, ctypes.POINTER(lqcd_gcr_params), _P, _P,
                        ctypes.POINTER(lqcd_solve_info), _P],
@@ -284,6 +285,11 @@ def lqcd_clover_apply(ctx, op, out, inp, parity, inverse=0, nrhs=1, stream=None)
 def lqcd_schur_apply(ctx, op, out, inp, dagger=0, block=None, nrhs=1, stream=None):
     _check(lib().lqcd_schur_apply(ctx, ctypes.byref(op), _ptr(out), _ptr(inp), int(dagger), _block(block), nrhs,
                                   _stream(stream)), ctx)
+
+
+def lqcd_schur_apply_noalloc(ctx, op, out, inp, dagger=0, block=None, nrhs=1, stream=None):
+    _check(lib().lqcd_schur_apply_noalloc(ctx, ctypes.byref(op), _ptr(out), _ptr(inp), int(dagger), _block(block), nrhs,
+                                          _stream(stream)), ctx)
 
 
 def lqcd_schwarz_precond(ctx, op_precond, params, out_even, in_even, stream=None):
