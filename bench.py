@@ -586,7 +586,8 @@ def main():
             st, info = L.lqcd_gcr_solve(ctx, o64.op, o32.op, o16.op, prm, x, bp)
             assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
             out.append(solve_record(info.seconds, [round(info.seconds, 4)], info))
-        print(json.dumps({"solve": out[-1], "warmup": out[0], "device_copy": device_copy(torch, L, ctx)}))
+        print(json.dumps({"solve": out[-1], "warmup": out[0], "device_copy": device_copy(torch, L, ctx),
+                          "tuned": L.lqcd_tuned_choices(ctx)}))
         L.lqcd_context_destroy(ctx)
         return
     # Stencil operators use tiles spanning the full x extent (the site order
@@ -629,7 +630,7 @@ def main():
         del reps, sets, esets
     if args.kernels_only:
         print(json.dumps({"kernels": kernels, "device_copy": device_copy(torch, L, ctx),
-                          "tuned": L.lqcd_tuned_choices(ctx)}))
+                          "tuned": L.lqcd_tuned_choices(ctx), "kernel_sources_sha1": kernel_sources_sha1()}))
         return
     # the same kernel in the Schwarz block tiling, for comparison
     reps = [o32b, o32b.replica(), o32b.replica()]
