@@ -640,6 +640,27 @@ def main():
                                             "frac": round(byts / dt / 1e9 / HBM_PEAK_GBS, 4), "bytes": byts}
     log("f32 r12 in %s tiles %8.1f us %7.1f GB/s" % (block, dt * 1e6, byts / dt / 1e9))
     del reps, sets
+    # the FP16 Schwarz preconditioner (8 MR steps on the 8^4 blocks) in each of
+    # its forms: 0 separate launches per MR step, 1 and 2 one workgroup per
+    # block with the block in LDS (x in memory / in registers). Bytes: the
+    # block form's algorithmic traffic per even site, r read once, then per MR
+    # step the links of both half steps and both clover blocks, x written once
+    # (x read and written each step in form 1 adds 96 bytes per step).
+    reps = [o16b, o16b.replica(), o16b.replica()]
+    ksets = [(r, r.import_spinor(b, 0), r.spinor()) for r in reps]
+    kprm = ops.schwarz_params(block, mr)
+    k_bytes = vh * (48 + mr * (2 * 8 * 24 + 2 * 144) + 48)
+    for form in (0, 1, 2):
+        os.environ["LQCD_SCHWARZ_FORM"] = str(form)
+        dk = time_rotating(torch, [lambda r=r, i=i, q=q: L.lqcd_schwarz_precond(ctx, r.op, kprm, q, i)
+                                   for r, i, q in ksets], 30)
+        kernels["schwarz_f16_r12_form%d" % form] = {
+            "us": round(dk * 1e6, 2), "GB/s": round(k_bytes / dk / 1e9, 1),
+            "frac": round(k_bytes / dk / 1e9 / HBM_PEAK_GBS, 4), "bytes": k_bytes}
+        log("Schwarz K (FP16, %d MR steps) form %d: %8.1f us, %7.1f GB/s of the block form's bytes" % (
+            mr, form, dk * 1e6, k_bytes / dk / 1e9))
+    del os.environ["LQCD_SCHWARZ_FORM"]
+    del reps, ksets
     copy = device_copy(torch, L, ctx)
     log("streaming copy %.1f GB/s" % copy["GB/s"])
 

@@ -258,27 +258,51 @@ lqcd_status schur_apply(lqcd_context *ctx, const OpInfo &info, const Geom &g, vo
   return stag_hop(ctx, info, out, tmp, in, 0, -0.25, op->mass * op->mass, st, nrhs);
 }
 
-// Additive Schwarz on the tile blocks: out = K in, both packed even spinors of
-// op_precond. Work vectors come from scratch slots [slot0, slot0+4).
-lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schwarz_params *prm, void *out,
-                          const void *in, int slot0, hipStream_t st) {
-  Geom g;
-  lqcd_status s = apply_cut(ctx, info, prm->block, &g);
-  if (s) return s;
+// The Schwarz preconditioner on the blocks (additive: every block at once;
+// multiplicative: the blocks of one colour after the other): out = K in, both
+// packed even spinors of op_precond. Form 0 runs each MR step as two cut Schur
+// launches and an update, with work vectors from scratch slots
+// [slot0, slot0+4); forms 1 and 2 run every MR step of a block in one
+// workgroup with the block in LDS (blocks equal to the tiles, 16-bit
+// storage), x in memory (1) or in registers (2).
+static lqcd_status schwarz_form(lqcd_context *ctx, const OpInfo &info, const Geom &g, const lqcd_schwarz_params *prm,
+                                void *out, const void *in, int slot0, hipStream_t st, int form) {
+  const lqcd_operator *op = info.op;
   const size_t sb = info.spinor_bytes;
-  void *r, *q, *t, *part;
-  if ((s = scratch(ctx, slot0, sb, &r)) || (s = scratch(ctx, slot0 + 1, sb, &q)) || (s = scratch(ctx, slot0 + 2, sb, &t)))
-    return s;
+  const double omega = prm->omega == 0 ? 1.0 : prm->omega;
+  lqcd_status s;
+  SapLaunch bl;
+  bl.prec = info.prec;
+  bl.recon = info.recon;
+  bl.gauge = op->gauge;
+  bl.clov_inv_odd = clover_block(info, op->clover_inv, 1);
+  bl.clov_even = clover_block(info, op->clover, 0);
+  bl.coef = -op->kappa * op->kappa;
+  bl.omega = omega;
+  bl.steps = prm->mr_steps;
+  bl.x = out;
+  bl.xreg = form == 2;
+  void *r = nullptr, *q = nullptr, *t = nullptr, *part = nullptr;
+  if (form == 0 || prm->cycles > 0) {
+    if ((s = scratch(ctx, slot0, sb, &r)) || (s = scratch(ctx, slot0 + 1, sb, &q)) ||
+        (s = scratch(ctx, slot0 + 2, sb, &t)))
+      return s;
+  }
   // one (<q,r>, <q,q>) triple per reduction segment of min(tile sites, 64) sites
   const int seg = info.g.Vt2 < 64 ? info.g.Vt2 : 64;
   const size_t nseg = (info.vh + seg - 1) / seg;
-  if ((s = scratch(ctx, slot0 + 3, nseg * 3 * sizeof(double), &part))) return s;
-  s = hip_check(ctx, hipMemcpyAsync(r, in, sb, hipMemcpyDeviceToDevice, st), "schwarz copy");
-  if (s) return s;
+  if (form == 0 && (s = scratch(ctx, slot0 + 3, nseg * 3 * sizeof(double), &part))) return s;
   const int nps = info.g.Vt2 > 64 ? info.g.Vt2 / 64 : 1;  // reduction segments per block
-  const double omega = prm->omega == 0 ? 1.0 : prm->omega;
   if (prm->cycles == 0) {
     // additive: MR on every block at once
+    if (form != 0) {
+      bl.g = g;
+      bl.r0 = in;
+      bl.first = 1;
+      return hip_check(ctx, launch_sap_block(bl, st), "schwarz block launch");
+    }
+    s = hip_check(ctx, hipMemcpyAsync(r, in, sb, hipMemcpyDeviceToDevice, st), "schwarz copy");
+    if (s) return s;
     for (int it = 0; it < prm->mr_steps; ++it) {
       if ((s = schur_apply(ctx, info, g, q, r, t, 0, (double *)part, st))) return s;
       if ((s = hip_check(ctx, launch_mr_update(info.g, info.prec, out, r, q, (const double *)part, nps, it == 0, omega, st),
@@ -292,18 +316,28 @@ lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schw
   // its blocks only, and r = in - Mhat out is recomputed (uncut) for the next.
   // out starts at zero, since the residual reads it on every block.
   if ((s = hip_check(ctx, hipMemsetAsync(out, 0, sb, st), "schwarz clear"))) return s;
+  const void *rc = in;  // the current residual
   Geom gc[2] = {g, g};
   gc[0].colour = 0;
   gc[1].colour = 1;
   const size_t n = info.vh * info.nsp / 2;
   for (int cyc = 0; cyc < prm->cycles; ++cyc) {
     for (int c = 0; c < 2; ++c) {
-      for (int it = 0; it < prm->mr_steps; ++it) {
-        if ((s = schur_apply(ctx, info, gc[c], q, r, t, 0, (double *)part, st))) return s;
-        if ((s = hip_check(ctx, launch_mr_update(gc[c], info.prec, out, r, q, (const double *)part, nps,
-                                                 cyc == 0 && it == 0, omega, st),
-                           "schwarz MR update")))
+      if (form != 0) {
+        bl.g = gc[c];
+        bl.r0 = rc;
+        bl.first = 0;
+        if ((s = hip_check(ctx, launch_sap_block(bl, st), "schwarz block launch"))) return s;
+      } else {
+        if (rc != r && (s = hip_check(ctx, hipMemcpyAsync(r, rc, sb, hipMemcpyDeviceToDevice, st), "schwarz copy")))
           return s;
+        for (int it = 0; it < prm->mr_steps; ++it) {
+          if ((s = schur_apply(ctx, info, gc[c], q, r, t, 0, (double *)part, st))) return s;
+          if ((s = hip_check(ctx, launch_mr_update(gc[c], info.prec, out, r, q, (const double *)part, nps,
+                                                   cyc == 0 && it == 0, omega, st),
+                             "schwarz MR update")))
+            return s;
+        }
       }
       if (cyc == prm->cycles - 1 && c == 1) break;
       if ((s = schur_apply(ctx, info, info.g, q, out, t, 0, nullptr, st))) return s;
@@ -314,9 +348,42 @@ lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schw
                                : blas_axpby(info.prec, in, info.prec, q, n, 1.0, 0.0, -1.0, 0.0, nullptr, st);
       if ((s = hip_check(ctx, e, "schwarz residual"))) return s;
       std::swap(r, q);
+      rc = r;
     }
   }
   return LQCD_OK;
+}
+
+// Does the block-resident form apply (blocks equal to the tiles, 16-bit
+// floating-point storage, 12 or 18 link reals, a block in LDS)?
+static bool schwarz_block_form_fits(const OpInfo &info, const Geom &g) {
+  if ((info.prec != LQCD_F16 && info.prec != LQCD_BF16) || info.recon == 8) return false;
+  for (int m = 0; m < 4; ++m)
+    if (g.cut[m] != info.g.B[m] || info.g.B[m] > 256) return false;
+  return sap_block_spt(info.g.Vt2) != 0;
+}
+
+lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schwarz_params *prm, void *out,
+                          const void *in, int slot0, hipStream_t st) {
+  Geom g;
+  lqcd_status s = apply_cut(ctx, info, prm->block, &g);
+  if (s) return s;
+  int form = 0;
+  if (schwarz_block_form_fits(info, g)) {
+    // the forms give the same result; the autotuner keeps the fastest, and
+    // LQCD_SCHWARZ_FORM=0, 1 or 2 fixes the choice
+    const char *f = std::getenv("LQCD_SCHWARZ_FORM");
+    if (f && f[0] >= '0' && f[0] <= '2' && f[1] == 0) {
+      form = f[0] - '0';
+    } else {
+      const std::string key = "schwarz p" + std::to_string(info.prec) + " r" + std::to_string(info.recon) + " " +
+                              geom_key(g) + " m" + std::to_string(prm->mr_steps) + " c" + std::to_string(prm->cycles);
+      form = tune_pick(ctx, key, {2, 1, 0}, 2, out != in, st, [&](int c) {
+        return schwarz_form(ctx, info, g, prm, out, in, slot0, st, c) == LQCD_OK ? hipSuccess : hipErrorUnknown;
+      });
+    }
+  }
+  return schwarz_form(ctx, info, g, prm, out, in, slot0, st, form);
 }
 
 lqcd_status check_schwarz(lqcd_context *ctx, const OpInfo &info, const lqcd_schwarz_params *prm) {

@@ -111,6 +111,27 @@ struct BatchTune {
 hipError_t launch_wilson_batch(int prec, int recon, const BatchJob *jobs, int njobs, int dagger, const BatchTune &t,
                                int mfma, unsigned *counter, hipStream_t st);
 
+// Schwarz MR with each block resident in LDS: `steps` MR steps of the cut
+// Schur operator on every block, or on the blocks of one colour (blocks equal
+// to the tiles; 16-bit storage; 12 or 18 link reals) in one launch: x += K r0
+// (x starts at zero, unread, if first).
+struct SapLaunch {
+  Geom g;  // cut equal to the tiles; colour -1 or 0 / 1
+  int prec, recon;
+  void *x;
+  const void *r0;
+  const void *gauge;
+  const void *clov_inv_odd;
+  const void *clov_even;
+  double coef;  // -kappa^2
+  double omega;
+  int steps;
+  int first;
+  int xreg;  // x kept in registers (else read and written in memory each step)
+};
+hipError_t launch_sap_block(const SapLaunch &l, hipStream_t st);
+int sap_block_spt(int vt2);  // sites per thread of that launch; 0: blocks of vt2 sites do not fit
+
 hipError_t launch_clover_apply(const Geom &g, int prec, void *out, const void *in, const void *clov, int nrhs,
                                hipStream_t st);
 

@@ -639,6 +639,453 @@ __global__ void __launch_bounds__(256) clover_apply_kernel(Geom g, S *out, const
   store_spinor<S, R, true>(out, vs, pidx, y);
 }
 
+// ---------------------------------------------------------------------------
+// Additive Schwarz with each block resident in LDS (Section 4's block solver,
+// with blocks equal to the tiles and 16-bit storage): one workgroup runs every
+// MR step of one block. The block's spinor of the current half step (r on the
+// even sites, then t on the odd sites) lives in LDS, so neighbours are read
+// from there; links and clover stream from memory in each half step; the
+// workgroup keeps its sites' r and q (and x, where registers allow) as stored
+// 16-bit values. Per step and even site this moves the links twice and both
+// clover blocks (672 bytes at 12 link reals, 768 with x in memory) instead of
+// the 1152 bytes of two cut Schur launches and an update. The arithmetic is
+// the launches' (same operations, same roundings to the storage format, the
+// same order of the FP64 sums of <q,r> and <q,q>: per 64-site segment by the
+// wave butterfly, then the block's segments in order), so both forms give the
+// same result.
+constexpr int kSapMaxSites = 2048;  // sites per parity of one block (96 KiB of 16-bit spinor)
+
+template <typename S> struct SapArgs {
+  S *x;           // out: x (even sites)
+  const S *r0;    // in: residual (even sites)
+  const S *gauge;
+  const S *clov_inv_odd;  // A_oo^-1
+  const S *clov_even;     // A_ee
+  Geom g;                 // for the tile of a colour-restricted launch
+  int64_t vh;
+  int vt2;
+  int b[4];   // block (tile) extents
+  int wrap;   // bit mu: the block spans the lattice along mu, its hops wrap inside it
+  int bc_t;
+  float coef;  // -kappa^2
+  double omega;
+  int steps;
+  int first;  // x starts at zero (not read)
+};
+
+// two stored 16-bit values in one register
+template <typename S> __device__ __forceinline__ uint32_t pack16(S lo, S hi) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+}
+template <typename S> __device__ __forceinline__ float lo16(uint32_t u) {
+  return to_real<float>(__builtin_bit_cast(S, (uint16_t)(u & 0xffffu)));
+}
+template <typename S> __device__ __forceinline__ float hi16(uint32_t u) {
+  return to_real<float>(__builtin_bit_cast(S, (uint16_t)(u >> 16)));
+}
+
+// A site's 24 stored values as 12 registers; in LDS and in memory the spinor
+// is chunk-major (chunk c = reals 4c .. 4c+3 = registers 2c, 2c+1).
+template <typename S> __device__ __forceinline__ void sap_pack(const cpx<float> (&v)[4][3], uint32_t (&p)[12]) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      p[3 * sp + c] = pack16<S>(Store<S>::from(v[sp][c].re), Store<S>::from(v[sp][c].im));
+}
+template <typename S> __device__ __forceinline__ void sap_unpack(const uint32_t (&p)[12], cpx<float> (&v)[4][3]) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[sp][c] = mk<float>(lo16<S>(p[3 * sp + c]), hi16<S>(p[3 * sp + c]));
+}
+// The packed registers become opaque to the compiler here: values derived
+// from them (unpacked FP32 copies) are not kept alive across the point.
+__device__ __forceinline__ void sap_opaque(uint32_t (&p)[12]) {
+#pragma unroll
+  for (int j = 0; j < 12; ++j) __asm__ volatile("" : "+v"(p[j]));
+}
+__device__ __forceinline__ void sap_lds_put(uint2 *lds, int vt2, int k, const uint32_t (&p)[12]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) lds[c * vt2 + k] = make_uint2(p[2 * c], p[2 * c + 1]);
+}
+__device__ __forceinline__ void sap_lds_get(const uint2 *lds, int vt2, int k, uint32_t (&p)[12]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const uint2 v = lds[c * vt2 + k];
+    p[2 * c] = v.x;
+    p[2 * c + 1] = v.y;
+  }
+}
+template <typename S> __device__ __forceinline__ void sap_mem_get(const S *f, int64_t vh, int64_t s, uint32_t (&p)[12]) {
+  const uint2 *q = reinterpret_cast<const uint2 *>(f);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const uint2 v = q[c * vh + s];
+    p[2 * c] = v.x;
+    p[2 * c + 1] = v.y;
+  }
+}
+template <typename S> __device__ __forceinline__ void sap_mem_put(S *f, int64_t vh, int64_t s, const uint32_t (&p)[12]) {
+  uint2 *q = reinterpret_cast<uint2 *>(f);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) nt_store(q + c * vh + s, make_uint2(p[2 * c], p[2 * c + 1]));
+}
+
+// Hop of STEP along MU from block coordinates l: false if the cut drops it;
+// else the neighbour's block-local index and whether the hop wrapped the
+// lattice along t with antiperiodic boundary (a sign flip).
+template <int MU, int STEP, typename S>
+__device__ __forceinline__ bool sap_hop(const SapArgs<S> &a, const int (&l)[4], int *kn, bool *flip) {
+  int c[4] = {l[0], l[1], l[2], l[3]};
+  c[MU] += STEP;
+  const bool out = STEP > 0 ? c[MU] >= a.b[MU] : c[MU] < 0;
+  if (out && !((a.wrap >> MU) & 1)) return false;
+  c[MU] = out ? (STEP > 0 ? 0 : a.b[MU] - 1) : c[MU];
+  *flip = MU == 3 && out && a.bc_t < 0;
+  *kn = (c[0] >> 1) + (a.b[0] >> 1) * (c[1] + a.b[1] * (c[2] + a.b[2] * c[3]));
+  return true;
+}
+
+template <int MU, int STEP, typename S, int RECON>
+__device__ __forceinline__ void sap_hop_acc(const SapArgs<S> &a, const uint2 *lds, int base, const int (&l)[4], int k,
+                                            int par, cpx<float> (&acc)[4][3]) {
+  int kn;
+  bool flip;
+  if (!sap_hop<MU, STEP>(a, l, &kn, &flip)) return;
+  uint32_t raw[12];
+  cpx<float> psi[4][3], h[2][3], u[2][3];
+  sap_lds_get(lds, a.vt2, kn, raw);
+  sap_unpack<S>(raw, psi);
+  // forward: (1 - gamma_mu) U_mu(x) psi(x+mu); backward: (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu)
+  const float g = STEP > 0 ? -1.f : 1.f;
+  project<MU, float>(psi, g, h);
+  const Link<float> U = STEP > 0 ? load_link<S, float, RECON>(a.gauge, a.vh, MU, par, base + k, true)
+                                 : load_link<S, float, RECON>(a.gauge, a.vh, MU, 1 - par, base + kn, true);
+  if constexpr (STEP > 0) {
+    su3_mv(U, h[0], u[0]);
+    su3_mv(U, h[1], u[1]);
+  } else {
+    su3_adj_mv(U, h[0], u[0]);
+    su3_adj_mv(U, h[1], u[1]);
+  }
+  if constexpr (MU == 3) {
+    const float ph = flip ? -1.f : 1.f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u[i][c] = ph * u[i][c];
+  }
+  expand_acc<MU, float>(acc, u, g);
+}
+
+// D restricted to the block at block-local site k of parity par (coordinates
+// packed 8 bits each: x/2, y, z, t), neighbours from LDS
+template <typename S, int RECON>
+__device__ __forceinline__ void sap_hops(const SapArgs<S> &a, const uint2 *lds, int base, int k, uint32_t coords,
+                                         int par, cpx<float> (&acc)[4][3]) {
+  int l[4];
+  l[1] = (coords >> 8) & 255;
+  l[2] = (coords >> 16) & 255;
+  l[3] = coords >> 24;
+  l[0] = 2 * (int)(coords & 255) + ((l[1] + l[2] + l[3] + par) & 1);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[i][c] = mk<float>(0, 0);
+  sap_hop_acc<0, +1, S, RECON>(a, lds, base, l, k, par, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  sap_hop_acc<0, -1, S, RECON>(a, lds, base, l, k, par, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  sap_hop_acc<1, +1, S, RECON>(a, lds, base, l, k, par, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  sap_hop_acc<1, -1, S, RECON>(a, lds, base, l, k, par, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  sap_hop_acc<2, +1, S, RECON>(a, lds, base, l, k, par, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  sap_hop_acc<2, -1, S, RECON>(a, lds, base, l, k, par, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  sap_hop_acc<3, +1, S, RECON>(a, lds, base, l, k, par, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  sap_hop_acc<3, -1, S, RECON>(a, lds, base, l, k, par, acc);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Clover product for the block kernel: the same operations as clover_mul, one
+// chirality block at a time (36 values in registers instead of 72).
+template <typename S>
+__device__ __forceinline__ void sap_clover(const S *__restrict__ clov, int64_t vh, int s, const cpx<float> (&in)[4][3],
+                                           cpx<float> (&out)[4][3]) {
+  constexpr int CH = chunk_reals<S, 72>();  // reals per chunk (8 for 16-bit storage)
+  static_assert(CH == 8, "16-bit clover chunks of 8 reals");
+  float a[72];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    // chunks 0..4 hold block 0 (reals 0..35), chunks 4..8 block 1 (36..71)
+#pragma unroll
+    for (int c = 5 * b - b; c < 5 * b - b + 5; ++c) {
+      if (b == 1 && c == 4) continue;  // loaded with block 0
+      const Chunk<S, 8> v = nt_load(reinterpret_cast<const Chunk<S, 8> *>(clov + (c * vh + s) * 8));
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[8 * c + j] = to_real<float>(v.v[j]);
+    }
+#pragma unroll
+    for (int k = 36 * b; k < 36 * b + 36; ++k) __asm__ volatile("" : "+v"(a[k]));
+    const float *A = a + 36 * b;
+    cpx<float> x[6], y[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) x[i] = in[2 * b + i / 3][i % 3];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) y[i] = A[i] * x[i];
+    int off = 6;
+#pragma unroll
+    for (int i = 1; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < i; ++j) {
+        const cpx<float> aij = mk<float>(A[off], A[off + 1]);
+        off += 2;
+        cmac(y[i], aij, x[j]);
+        cmac_conj(y[j], aij, x[i]);
+      }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) out[2 * b + i / 3][i % 3] = y[i];
+  }
+}
+
+// One workgroup per block (blockIdx.x: the block's tile, or the j-th tile of
+// one colour); SPT sites per thread and parity, site k = p * blockDim.x + tid.
+// XREG: x stays in registers (else it is read and written in memory each step).
+template <typename S, int RECON, int SPT, bool XREG>
+__global__ void __launch_bounds__(512) sap_block_kernel(SapArgs<S> a) {
+  extern __shared__ uint2 sap_lds[];  // 6 chunks x Vt2 sites, then the segment sums
+  const int vt2 = a.vt2, nt = blockDim.x, tid = threadIdx.x;
+  double *seg = reinterpret_cast<double *>(sap_lds + 6 * vt2);  // [Vt2 / 64][3]
+  const int tile = a.g.colour >= 0 ? colour_site(a.g, blockIdx.x * vt2) / vt2 : (int)blockIdx.x;
+  const int base = tile * vt2;
+  uint32_t r[SPT][12], w[SPT][12];  // w: t (odd sites) or q (even sites)
+  uint32_t x[XREG ? SPT : 1][12];
+  uint32_t coords[SPT];
+#pragma unroll
+  for (int p = 0; p < SPT; ++p) {
+    const int k = p * nt + tid;
+    const int bxh = a.b[0] >> 1;
+    const int q1 = k / bxh, q2 = q1 / a.b[1];
+    coords[p] = (uint32_t)(k - q1 * bxh) | ((uint32_t)(q1 - q2 * a.b[1]) << 8) |
+                ((uint32_t)(q2 % a.b[2]) << 16) | ((uint32_t)(q2 / a.b[2]) << 24);
+    sap_mem_get<S>(a.r0, a.vh, base + k, r[p]);
+    sap_lds_put(sap_lds, vt2, k, r[p]);
+    if constexpr (XREG)
+      if (!a.first) sap_mem_get<S>(a.x, a.vh, base + k, x[p]);
+  }
+  __syncthreads();
+  for (int step = 0; step < a.steps; ++step) {
+    // the thread's index and coordinates pass through an empty asm each step,
+    // so that the addresses derived from them are not held in registers
+    // across the loop
+    // t_o = A_oo^-1 D_oe r on the block's odd sites
+#pragma unroll
+    for (int p = 0; p < SPT; ++p) {
+      int k = p * nt + tid;
+      __asm__ volatile("" : "+v"(k));
+      cpx<float> acc[4][3], res[4][3];
+      uint32_t cp = coords[p];
+      __asm__ volatile("" : "+v"(cp));
+      sap_hops<S, RECON>(a, sap_lds, base, k, cp, 1, acc);
+      sap_clover<S>(a.clov_inv_odd, a.vh, base + k, acc, res);
+      sap_pack<S>(res, w[p]);
+      sap_opaque(w[p]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();  // every read of r is done
+#pragma unroll
+    for (int p = 0; p < SPT; ++p) {
+      int k = p * nt + tid;
+      __asm__ volatile("" : "+v"(k));
+      sap_lds_put(sap_lds, vt2, k, w[p]);
+    }
+    __syncthreads();
+    // q_e = A_ee r + coef D_eo t, and the segment sums of <q,r>, <q,q>
+#pragma unroll
+    for (int p = 0; p < SPT; ++p) {
+      int k = p * nt + tid;
+      __asm__ volatile("" : "+v"(k));
+      cpx<float> acc[4][3], res[4][3], xv[4][3];
+      uint32_t cp = coords[p];
+      __asm__ volatile("" : "+v"(cp));
+      sap_hops<S, RECON>(a, sap_lds, base, k, cp, 0, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      sap_unpack<S>(r[p], xv);
+      sap_clover<S>(a.clov_even, a.vh, base + k, xv, res);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) res[i][c] = res[i][c] + a.coef * acc[i][c];
+      double red[3] = {0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double qr = quantize<S, float>(res[i][c].re), qi = quantize<S, float>(res[i][c].im);
+          const double rr = xv[i][c].re, ri = xv[i][c].im;
+          red[0] += qr * rr + qi * ri;
+          red[1] += qr * ri - qi * rr;
+          red[2] += qr * qr + qi * qi;
+        }
+      sap_pack<S>(res, w[p]);
+      sap_opaque(w[p]);
+      sap_opaque(r[p]);
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        for (int off = 32; off > 0; off >>= 1) red[j] += __shfl_xor(red[j], off, 64);
+      if ((k & 63) == 0)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) seg[3 * (k >> 6) + j] = red[j];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();  // every read of t and every segment sum is done
+    double qr = 0, qi = 0, qq = 0;
+    for (int j = 0; j < (vt2 >> 6); ++j) {
+      qr += seg[3 * j];
+      qi += seg[3 * j + 1];
+      qq += seg[3 * j + 2];
+    }
+    const float ar = qq > 0 ? (float)(a.omega * qr / qq) : 0.f, ai = qq > 0 ? (float)(a.omega * qi / qq) : 0.f;
+    const bool last = step == a.steps - 1, zero_x = a.first && step == 0;
+    // x += alpha r, r -= alpha q (the last step needs no new r)
+#pragma unroll
+    for (int p = 0; p < SPT; ++p) {
+      int k = p * nt + tid;
+      __asm__ volatile("" : "+v"(k));
+      uint32_t xo[12];
+      if constexpr (XREG) {
+#pragma unroll
+        for (int j = 0; j < 12; ++j) xo[j] = x[p][j];
+      } else {
+        if (!zero_x) sap_mem_get<S>(a.x, a.vh, base + k, xo);
+      }
+      float rv[24], qv[24], xv[24];
+#pragma unroll
+      for (int j = 0; j < 12; ++j) {
+        rv[2 * j] = lo16<S>(r[p][j]);
+        rv[2 * j + 1] = hi16<S>(r[p][j]);
+        qv[2 * j] = lo16<S>(w[p][j]);
+        qv[2 * j + 1] = hi16<S>(w[p][j]);
+        xv[2 * j] = zero_x ? 0.f : lo16<S>(xo[j]);
+        xv[2 * j + 1] = zero_x ? 0.f : hi16<S>(xo[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 12; ++j) {
+        const float re = rv[2 * j], im = rv[2 * j + 1];
+        xv[2 * j] += ar * re - ai * im;
+        xv[2 * j + 1] += ar * im + ai * re;
+        rv[2 * j] = re - (ar * qv[2 * j] - ai * qv[2 * j + 1]);
+        rv[2 * j + 1] = im - (ar * qv[2 * j + 1] + ai * qv[2 * j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 12; ++j) {
+        xo[j] = pack16<S>(Store<S>::from(xv[2 * j]), Store<S>::from(xv[2 * j + 1]));
+        if (!last) r[p][j] = pack16<S>(Store<S>::from(rv[2 * j]), Store<S>::from(rv[2 * j + 1]));
+      }
+      sap_opaque(r[p]);
+      if constexpr (XREG) {
+#pragma unroll
+        for (int j = 0; j < 12; ++j) x[p][j] = xo[j];
+      } else {
+        sap_mem_put<S>(a.x, a.vh, base + k, xo);
+      }
+      if (!last) sap_lds_put(sap_lds, vt2, k, r[p]);
+    }
+    __syncthreads();  // the new r is in LDS; the segment sums are read
+  }
+  if constexpr (XREG) {
+#pragma unroll
+    for (int p = 0; p < SPT; ++p) sap_mem_put<S>(a.x, a.vh, base + p * nt + tid, x[p]);
+  }
+}
+
+// Sites per thread of the block-resident form for blocks of vt2 sites per
+// parity (0: the form does not apply).
+int sap_block_spt(int vt2) {
+  if (vt2 % 64 || vt2 > kSapMaxSites) return 0;
+  for (int spt : {1, 2, 4})
+    if (vt2 / spt <= 512 && vt2 % (64 * spt) == 0) return spt;
+  return 0;
+}
+
+size_t sap_block_lds_bytes(int vt2) { return (size_t)vt2 * 48 + (size_t)(vt2 / 64) * 3 * sizeof(double); }
+
+template <typename S, int RECON, int SPT, bool XREG>
+static hipError_t launch_sap4(const SapLaunch &l, hipStream_t st) {
+  SapArgs<S> a;
+  a.x = (S *)l.x;
+  a.r0 = (const S *)l.r0;
+  a.gauge = (const S *)l.gauge;
+  a.clov_inv_odd = (const S *)l.clov_inv_odd;
+  a.clov_even = (const S *)l.clov_even;
+  a.g = l.g;
+  a.vh = l.g.Vh;
+  a.vt2 = l.g.Vt2;
+  a.wrap = 0;
+  for (int m = 0; m < 4; ++m) {
+    a.b[m] = l.g.B[m];
+    if (l.g.B[m] == l.g.L[m]) a.wrap |= 1 << m;
+  }
+  a.bc_t = l.g.bc_t;
+  a.coef = (float)l.coef;
+  a.omega = l.omega;
+  a.steps = l.steps;
+  a.first = l.first;
+  const size_t lds = sap_block_lds_bytes(l.g.Vt2);
+  static bool attr_set = false;  // per instantiation
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sap_block_kernel<S, RECON, SPT, XREG>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)sap_block_lds_bytes(kSapMaxSites));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int nblocks = launch_sites(l.g) / l.g.Vt2;
+  hipLaunchKernelGGL((sap_block_kernel<S, RECON, SPT, XREG>), dim3(nblocks), dim3(l.g.Vt2 / SPT), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename S, int RECON, int SPT>
+static hipError_t launch_sap3(const SapLaunch &l, hipStream_t st) {
+  return l.xreg ? launch_sap4<S, RECON, SPT, true>(l, st) : launch_sap4<S, RECON, SPT, false>(l, st);
+}
+
+template <typename S, int RECON>
+static hipError_t launch_sap2(const SapLaunch &l, hipStream_t st) {
+  switch (sap_block_spt(l.g.Vt2)) {
+    case 1: return launch_sap3<S, RECON, 1>(l, st);
+    case 2: return launch_sap3<S, RECON, 2>(l, st);
+    case 4: return launch_sap3<S, RECON, 4>(l, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename S>
+static hipError_t launch_sap1(const SapLaunch &l, hipStream_t st) {
+  switch (l.recon) {
+    case 18: return launch_sap2<S, 18>(l, st);
+    case 12: return launch_sap2<S, 12>(l, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sap_block(const SapLaunch &l, hipStream_t st) {
+  for (int m = 0; m < 4; ++m)  // blocks are the tiles; coordinates fit 8 bits
+    if (l.g.cut[m] != l.g.B[m] || l.g.B[m] > 256) return hipErrorInvalidValue;
+  if (l.steps < 1 || !sap_block_spt(l.g.Vt2)) return hipErrorInvalidValue;
+  if (l.g.colour >= 0 && (l.g.NT[0] & 1)) return hipErrorInvalidValue;
+  if (l.g.Vh == 0) return hipSuccess;
+  switch (l.prec) {
+    case LQCD_F16: return launch_sap1<_Float16>(l, st);
+    case LQCD_BF16: return launch_sap1<bf16>(l, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 // Schwarz MR step on every block at once, after q = Mhat_B r and the
 // per-segment partials of <q,r> and <q,q>: alpha_B = <q,r>_B / <q,q>_B,
 // x += alpha_B r (x = alpha_B r on the first step), r -= alpha_B q.
