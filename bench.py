@@ -69,7 +69,7 @@ def parse():
                     help="trained network weights; FGCR with it is timed when the file exists")
     ap.add_argument("--no-staggered", action="store_true", help="skip the 48^3x96 staggered workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-RHS workload")
-    ap.add_argument("--only", choices=("staggered", "batched", "learned", "solve"), default=None,
+    ap.add_argument("--only", choices=("staggered", "batched", "learned", "solve", "blocks"), default=None,
                     help="run one secondary workload alone and print its JSON (for profiling runs); solve: one "
                          "warm-up and one timed GCR-DD solve of the default workload")
     ap.add_argument("--oracle-solve", choices=("8x4", "32x64"), default=None, help=argparse.SUPPRESS)
@@ -416,7 +416,11 @@ def batched_workload(args, torch, L, ops, ctx):
         # 12 point sources on 24^3x48 (the origin is even: D_oe acts on them)
         dims = (24, 24, 24, 48)
         U = synth.gauge_field(dims, 0.25, 4001)
-        o = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon, tile=full_x_tile(dims))
+        # the layout tile: the fastest candidate for 12 sources (ops.tune_tile)
+        tile, tile_us = ops.tune_tile(ctx, U, dims, 0.122, 1.0, prec, recon, nrhs=12)
+        log("batched %s: layout tile %s (%s)" % (PREC_NAME[prec], tile, ", ".join(
+            "%s %.1f us" % ("x".join(map(str, t)), u) for t, u in tile_us.items())))
+        o = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon, tile=tile)
         srcs = np.stack([synth.point_source(dims, sc // 3, sc % 3) for sc in range(12)])
         reps = [o, o.replica(), o.replica()]
         sets = [(r, r.import_spinor(srcs, 0, nrhs=12), r.spinor(nrhs=12)) for r in reps]
@@ -432,15 +436,18 @@ def batched_workload(args, torch, L, ops, ctx):
             key = "point12_24x48_%s%s" % (PREC_NAME[prec], "_mfma" if mf else "")
             out[key] = {"us": round(dt * 1e6, 1), "GB/s": round(byts / dt / 1e9, 1), "bytes": byts,
                         "us_per_rhs": round(dt * 1e6 / 12, 2), "single_rhs_us": round(dt1 * 1e6, 1),
-                        "speedup_vs_sequential": round(12 * dt1 / dt, 2)}
+                        "speedup_vs_sequential": round(12 * dt1 / dt, 2), "tile": list(tile),
+                        "tile_candidates_us": {"x".join(map(str, t)): round(u, 1) for t, u in tile_us.items()}}
             log("batched %s%s: 12 point sources %.1f us (%.1f GB/s, x%.2f vs 12 single-source launches)" % (
                 PREC_NAME[prec], " mfma" if mf else "", dt * 1e6, byts / dt / 1e9, 12 * dt1 / dt))
         del sets, singles, reps
         # mixed batch, one persistent launch
-        jobs, keep, tot_bytes = [], [], 0
+        jobs, keep, tot_bytes, mixed_tiles = [], [], 0, []
         for k, dims in enumerate(((16, 16, 16, 32), (20, 20, 20, 40), (24, 24, 24, 48))):
             U = synth.gauge_field(dims, 0.25, 4011 + 10 * k)
-            ok = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon, tile=full_x_tile(dims))
+            t_k, _ = ops.tune_tile(ctx, U, dims, 0.122, 1.0, prec, recon, nrhs=4)
+            mixed_tiles.append(list(t_k))
+            ok = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, prec, recon, tile=t_k)
             srcs = np.stack([np.where(synth.parity_of_sites(dims)[..., None, None] == 1,
                                       synth.gaussian_spinor(dims, 4012 + 10 * k + r), 0) for r in range(4)])
             i_ = ok.import_spinor(srcs, 1, nrhs=4)
@@ -467,15 +474,15 @@ def batched_workload(args, torch, L, ops, ctx):
                 torch, [lambda js=js: L.lqcd_dslash_batch(ctx, js) for js in jsets], args.dslash_launches // 2))
             key = "mixed3x4_%s%s" % (PREC_NAME[prec], "_mfma" if mf else "")
             out[key] = {"us": round(dtb * 1e6, 1), "GB/s": round(tot_bytes / dtb / 1e9, 1), "bytes": tot_bytes,
-                        "separate_launches_us": round(seq * 1e6, 1)}
+                        "separate_launches_us": round(seq * 1e6, 1), "tiles": mixed_tiles}
             log("batched %s%s: mixed batch %.1f us (%.1f GB/s; separate launches %.1f us)" % (
                 PREC_NAME[prec], " mfma" if mf else "", dtb * 1e6, tot_bytes / dtb / 1e9, seq * 1e6))
         del jsets, jobs, keep
-    out["solve_point12_24x48"] = batched_solve(args, torch, L, ops, ctx)
+    out["solve_point12_24x48"] = batched_solve(args, torch, L, ops, ctx, tuple(out["point12_24x48_f32"]["tile"]))
     return out
 
 
-def batched_solve(args, torch, L, ops, ctx):
+def batched_solve(args, torch, L, ops, ctx, tile):
     """The batched workload's solve: even-odd CGNE for the 12 point sources on
     24^3x48 (kappa 0.122) with FP32 sloppy iterations and FP64 reliable
     updates, all sources in one multi-source solve (each operator application
@@ -486,7 +493,7 @@ def batched_solve(args, torch, L, ops, ctx):
     dims = (24, 24, 24, 48)
     U = synth.gauge_field(dims, 0.25, 4001)
     Ud = torch.from_numpy(U).cuda()
-    t = full_x_tile(dims)
+    t = tile  # the layout tile tuned for the FP32 hop with 12 sources
     hi = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, 0, 18, tile=t, U_device=Ud)
     lo = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, 1, 12, tile=t, U_device=Ud)
     srcs = np.stack([synth.point_source(dims, sc // 3, sc % 3) for sc in range(12)])
@@ -566,6 +573,10 @@ def main():
         if args.kernels_only:
             res["device_copy"] = device_copy(torch, L, ctx)  # calibrates the profiler's byte counters
         print(json.dumps(res))
+        L.lqcd_context_destroy(ctx)
+        return
+    if args.only == "blocks":
+        print(json.dumps({"blocks": block_sweep(args, torch, L, ops, ctx, U, Ud, b, dims, kappa, csw, mr)}))
         L.lqcd_context_destroy(ctx)
         return
     if args.only == "solve":
@@ -808,6 +819,44 @@ def main():
     torch.cuda.synchronize()
     L.lqcd_context_destroy(ctx)
     print(json.dumps(res))
+
+
+def block_sweep(args, torch, L, ops, ctx, U, Ud, b, dims, kappa, csw, mr):
+    """GCR-DD with the additive FP16 Schwarz K on blocks from 4^4 (128 sites
+    per parity) to 32x16^3 (65,536), 8 MR steps: one K application (median
+    over rotated launches of one buffer set), GCR steps and time to solution
+    (the median of 3 solves after the tuning ones), and the form of K the
+    autotuner chose (2, 1: block in LDS; 0: separate launches)."""
+    import numpy as np
+    tile = stencil_tile(dims, (8, 8, 8, 8))
+    o64 = ops.wilson_clover(ctx, U, dims, kappa, csw, 0, 18, tile=tile, U_device=Ud)
+    o32 = ops.wilson_clover(ctx, U, dims, kappa, csw, 1, 12, tile=tile, U_device=Ud)
+    bp = o64.import_spinor(b, -1)
+    rows = []
+    for block in [(4, 4, 4, 4), (8, 4, 4, 4), (8, 8, 4, 4), (8, 8, 8, 4), (8, 8, 8, 8), (16, 8, 8, 8),
+                  (16, 16, 8, 8), (16, 16, 16, 16), (32, 16, 16, 16)]:
+        if any(d % e for d, e in zip(dims, block)):
+            continue
+        ok = ops.wilson_clover(ctx, U, dims, kappa, csw, 2, 12, tile=block, U_device=Ud)
+        inp, out = ok.import_spinor(b, 0), ok.spinor()
+        kp = ops.schwarz_params(block, mr)
+        dk = time_rotating(torch, [lambda: L.lqcd_schwarz_precond(ctx, ok.op, kp, out, inp)], 20)
+        prm = ops.gcr_params(1e-10, k_max=16, delta=1e-3, max_iter=3000, precond=L.LQCD_PRECOND_SCHWARZ,
+                             block=block, mr_steps=mr)
+
+        def run():
+            x = o64.spinor(full=True)
+            st, info = L.lqcd_gcr_solve(ctx, o64.op, o32.op, ok.op, prm, x, bp)
+            assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+            return st, info
+        med, allt, info = timed_solves(3, run)
+        form = [v for k, v in L.lqcd_tuned_choices(ctx).items()
+                if k.startswith("schwarz") and "/%dx%dx%dx%d" % block in k]
+        rows.append({"block": list(block), "sites_per_parity": int(np.prod(block)) // 2, "K_us": round(dk * 1e6, 1),
+                     "steps": info.iters, "seconds": round(med, 4), "K_form": form[0] if form else 0})
+        log("blocks %s: K %.1f us, %d steps, %.4f s" % (block, dk * 1e6, info.iters, med))
+        del ok, inp, out
+    return rows
 
 
 def load_oracle_solution():

@@ -109,6 +109,50 @@ def wilson_clover(ctx, U, dims, kappa, csw, prec, recon=18, tile=None, bc_t=-1, 
     return o
 
 
+def tile_candidates(dims):
+    """Layout tiles to try for a lattice: the full x extent with 8, 6, 4 or 2
+    sites along y, z and t (each dividing its extent, the same along the
+    three), and the hypercubes 8^4 and 4^4 where they divide."""
+    out = []
+    for e in (8, 6, 4, 2):
+        t = (dims[0], e, e, e)
+        if all(d % b == 0 for d, b in zip(dims[1:], t[1:])):
+            out.append(t)
+    for e in (8, 4):
+        t = (e, e, e, e)
+        if all(d % e == 0 for d in dims) and t not in out:
+            out.append(t)
+    return out
+
+
+def tune_tile(ctx, U, dims, kappa, csw, prec, recon, nrhs=1, candidates=None, launches=12, U_device=None):
+    """The layout tile under which the hopping term with `nrhs` sources runs
+    fastest on this GPU: each candidate operator is built and timed (HIP
+    events, after one warm-up launch; the median of `launches` launches).
+    Returns (best tile, {tile: microseconds}). The fields of a chosen layout
+    are then imported with it; the kernels' own launch parameters are tuned
+    separately by the library."""
+    cands = [tuple(t) for t in (candidates or tile_candidates(dims))]
+    Ud = U_device if U_device is not None else _device_complex(U)
+    times = {}
+    for t in cands:
+        o = wilson_clover(ctx, U, dims, kappa, csw, prec, recon, tile=t, U_device=Ud)
+        inp, out = o.spinor(nrhs=nrhs), o.spinor(nrhs=nrhs)
+        inp.zero_()
+        L.lqcd_dslash(ctx, o.op, out, inp, 0, nrhs=nrhs)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(launches + 1)]
+        ev[0].record()
+        for k in range(launches):
+            L.lqcd_dslash(ctx, o.op, out, inp, 0, nrhs=nrhs)
+            ev[k + 1].record()
+        ev[-1].synchronize()
+        times[t] = float(np.median([ev[k].elapsed_time(ev[k + 1]) * 1e3 for k in range(launches)]))
+        del o, inp, out
+    best = min(times, key=times.get)
+    return best, times
+
+
 def staggered(ctx, fat, U, dims, mass, prec, recon=18, tile=None, bc_t=-1, c_long=1.0, device="cuda",
               fat_device=None, U_device=None):
     """Improved-staggered instance: packs the fat links and forms the long

@@ -55,13 +55,16 @@ def run_form(ctx, monkeypatch, o, prm, inp, form):
     return out
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[0])) + "_b" + "x".join(map(str, c[1])))
+# the multiplicative form (cycles > 0) needs an even number of blocks along x
+FORM_CASES = [(case, cycles) for case in CASES for cycles in (0, 2) if cycles == 0 or (case[0][0] // case[1][0]) % 2 == 0]
+
+
+@pytest.mark.parametrize("case,cycles", FORM_CASES,
+                         ids=lambda v: "x".join(map(str, v[0])) + "_b" + "x".join(map(str, v[1])) if isinstance(v, tuple)
+                         else "c%d" % v)
 @pytest.mark.parametrize("prec,recon", [(2, 12), (3, 12), (2, 18)])
-@pytest.mark.parametrize("cycles", [0, 2])
-def test_block_form_matches_launches(ctx, monkeypatch, case, prec, recon, cycles):
+def test_block_form_matches_launches(ctx, monkeypatch, case, cycles, prec, recon):
     dims, block = case
-    if cycles and (dims[0] // block[0]) % 2:
-        pytest.skip("the multiplicative form needs an even number of blocks along x")
     U, psi, Ud = Fields.get(dims)
     o = ops.wilson_clover(ctx, U, dims, 0.124, 1.0, prec, recon, tile=block, bc_t=-1, U_device=Ud)
     ref_op = oracle.WilsonClover(dims, U, 0.124, 1.0, bc_t=-1)
