@@ -34,7 +34,7 @@ WILSON_REALS = {18: 192, 12: 144, 8: 112}  # in 24 + out 24 + 8 links per output
 # WRITE_SIZE scaled by the same counters on a 2 GiB device copy (summary under
 # profiles/). Valid only for the kernel sources it was measured on: their hash
 # is checked at run time and the traffic is reported as null when they differ.
-PROFILED_TRAFFIC = {"sources_sha1": "815fdb2a92116e9b86a4a6a46b59052c421cc4a5", "bytes_per_launch": 662.1e6}
+PROFILED_TRAFFIC = {"sources_sha1": "b2bcd5382620ba71d1a8fd0dc9e99e3efe40a2cd", "bytes_per_launch": 662.0e6}
 
 
 def kernel_sources_sha1():
