@@ -114,6 +114,35 @@ def schur_oracle():
     return _W["M"]
 
 
+def schwarz_oracle_32x64():
+    """The oracle's FP64 additive Schwarz K (8^4 blocks, 8 MR steps) of the
+    benchmark's even source over the whole lattice."""
+    if "K" not in _W:
+        from oracle import solvers
+        dims, U, b, _ = wilson_fields()
+        src = np.where(oracle.parity_mask(dims, 0)[..., None, None], b, 0)
+        t = time.time()
+        _W["K"] = (src, solvers.schwarz(schur_oracle(), src, BLOCK, 8))
+        say("oracle Schwarz K at 32^3x64 %.1fs" % (time.time() - t))
+    return _W["K"]
+
+
+@pytest.mark.parametrize("form", [0, 1, 2])
+def test_schwarz_k_full_32x64(ctx, monkeypatch, form):
+    """The FP16 Schwarz preconditioner of the benchmark's GCR-DD (8^4 blocks
+    as the tiles, 8 MR steps) over the whole 32^3x64 even field, in each form
+    (0 separate launches; 1, 2 one workgroup per block with the block in LDS),
+    against the oracle's FP64 K, to the derived bound of the 16-bit K (5e-3,
+    whole field and worst site)."""
+    dims, U, b, Ud = wilson_fields()
+    src, ref = schwarz_oracle_32x64()
+    monkeypatch.setenv("LQCD_SCHWARZ_FORM", str(form))
+    o = ops.wilson_clover(ctx, U, dims, 0.124, 1.0, 2, 12, tile=BLOCK, U_device=Ud)
+    out = o.spinor()
+    L.lqcd_schwarz_precond(ctx, o.op, ops.schwarz_params(BLOCK, 8), out, o.import_spinor(src, 0))
+    check(np_of(o.export_spinor(out, 0)), ref, 5e-3, "form %d" % form)
+
+
 def test_gcr_dd_exact_solution_32x64(ctx):
     """A system with a known solution: x* Gaussian (seed 2003), b = M x*
     formed by the oracle. The benchmark's GCR-DD (FP64 restarts, FP32 Krylov,
