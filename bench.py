@@ -740,6 +740,12 @@ def main():
         tts["gcr_dd"]["rel_error_vs_oracle"] = rel_error_sampled(o64, run.x, gold)
     log("GCR-DD: %d steps, %.3f s (median of %d), true residual %.2e, vs oracle %s" % (
         info.iters, med, args.solves, info.true_residual, tts["gcr_dd"].get("rel_error_vs_oracle")))
+    # the same with re-orthogonalised classical Gram-Schmidt (CGS2)
+    prm2 = ops.gcr_params(1e-10, k_max=16, delta=1e-3, max_iter=2000, precond=L.LQCD_PRECOND_SCHWARZ,
+                          block=block, mr_steps=mr, orth_passes=2)
+    med, allt, info = timed_solves(args.solves, gcr(o16.op, prm2))
+    tts["gcr_dd_cgs2"] = solve_record(med, allt, info)
+    log("GCR-DD with CGS2: %d steps, %.3f s" % (info.iters, med))
     if not args.no_cg:
         def cg():
             x = o64.spinor(full=True)

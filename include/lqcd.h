@@ -180,6 +180,12 @@ typedef struct {
    * info->history_len is the number written. */
   double *res_history;
   int32_t res_history_max;
+  /* Gram-Schmidt passes of the orthogonalisation (Algorithm 1's MGS loop
+   * over z_0..z_{k-1}): 0 or 1 one classical pass (all coefficients from one
+   * set of dot products, then one multi-axpy), 2 classical Gram-Schmidt with
+   * re-orthogonalisation (CGS2: a second pass whose coefficients add to the
+   * first's). Both equal MGS in exact arithmetic; other values are refused. */
+  int32_t orth_passes;
 } lqcd_gcr_params;
 
 typedef enum { LQCD_CG_CGNE_SCHUR = 0, LQCD_CG_STAG_NORMAL = 1 } lqcd_cg_kind;

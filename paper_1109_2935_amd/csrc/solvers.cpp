@@ -157,6 +157,8 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
   if (!prm) return set_error(ctx, LQCD_ERR_INVALID_ARG, "params are NULL");
   if (!(prm->tol > 0) || prm->k_max < 1 || prm->k_max > 32 || !(prm->delta > 0) || prm->max_iter < 1)
     return set_error(ctx, LQCD_ERR_INVALID_ARG, "need tol > 0, 1 <= k_max <= 32, delta > 0, max_iter >= 1");
+  if (prm->orth_passes < 0 || prm->orth_passes > 2)
+    return set_error(ctx, LQCD_ERR_INVALID_ARG, "orth_passes must be 0, 1 or 2");
   if (prm->res_history_max < 0 || (prm->res_history_max > 0 && !prm->res_history))
     return set_error(ctx, LQCD_ERR_INVALID_ARG, "res_history_max > 0 needs a res_history array");
   const int pk = prm->precond;
@@ -270,24 +272,30 @@ extern "C" lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op
     // z_k = Mhat p_k
     TRY(schur_apply(ctx, kr, kr.g, Z[k], P[k], ktmp, 0, nullptr, S.st));
     inf.matvecs++;
-    // orthogonalise against z_0..z_{k-1} (classical Gram-Schmidt: all
-    // beta_{i,k} from one pass, then one multi-axpy)
-    for (int i0 = 0; i0 < k; i0 += 8) {
-      const int m = std::min(8, k - i0);
-      double d[16];
-      TRY(S.hip(blas_multi_cdot(kr.prec, (const void *const *)&Z[i0], m, Z[k], n, red, S.st), "multi dot"));
-      TRY(S.result(2 * m, d));
-      for (int j = 0; j < m; ++j) beta[(size_t)(i0 + j) * kmax + k] = cd(d[2 * j], d[2 * j + 1]);
-    }
+    // orthogonalise against z_0..z_{k-1}: classical Gram-Schmidt (all
+    // beta_{i,k} from one pass, then one multi-axpy), once, or twice (CGS2:
+    // the second pass removes what rounding left of the first, and its
+    // coefficients add to beta_{i,k})
+    const int passes = prm->orth_passes == 2 ? 2 : 1;
+    double zd[3] = {0, 0, 0};
     std::vector<double> bc(2 * std::max(k, 1));
-    for (int i = 0; i < k; ++i) {
-      bc[2 * i] = beta[(size_t)i * kmax + k].real();
-      bc[2 * i + 1] = beta[(size_t)i * kmax + k].imag();
+    for (int pass = 0; pass < passes && (k > 0 || pass == 0); ++pass) {
+      for (int i0 = 0; i0 < k; i0 += 8) {
+        const int m = std::min(8, k - i0);
+        double d[16];
+        TRY(S.hip(blas_multi_cdot(kr.prec, (const void *const *)&Z[i0], m, Z[k], n, red, S.st), "multi dot"));
+        TRY(S.result(2 * m, d));
+        for (int j = 0; j < m; ++j) {
+          bc[2 * (i0 + j)] = d[2 * j];
+          bc[2 * (i0 + j) + 1] = d[2 * j + 1];
+          cd &b = beta[(size_t)(i0 + j) * kmax + k];
+          b = pass == 0 ? cd(d[2 * j], d[2 * j + 1]) : b + cd(d[2 * j], d[2 * j + 1]);
+        }
+      }
+      TRY(S.hip(blas_multi_caxpy_dots(kr.prec, (const void *const *)Z.data(), bc.data(), k, Z[k], rhat, n, red, S.st),
+                "multi caxpy"));
+      TRY(S.result(3, zd));
     }
-    double zd[3];
-    TRY(S.hip(blas_multi_caxpy_dots(kr.prec, (const void *const *)Z.data(), bc.data(), k, Z[k], rhat, n, red, S.st),
-              "multi caxpy"));
-    TRY(S.result(3, zd));
     const double g = std::sqrt(zd[0]);
     if (!(g > 0) || !std::isfinite(g)) {
       if (pk == LQCD_PRECOND_LEARNED && !schwarz_now && prm->schwarz.mr_steps > 0) {

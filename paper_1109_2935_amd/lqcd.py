@@ -73,7 +73,8 @@ class lqcd_gcr_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("k_max", ctypes.c_int32), ("delta", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("schwarz", lqcd_schwarz_params), ("learned", ctypes.POINTER(lqcd_ptc_net)),
-                ("res_history", ctypes.POINTER(ctypes.c_double)), ("res_history_max", ctypes.c_int32)]
+                ("res_history", ctypes.POINTER(ctypes.c_double)), ("res_history_max", ctypes.c_int32),
+                ("orth_passes", ctypes.c_int32)]
 
 
 class lqcd_dslash_job(ctypes.Structure):

@@ -187,9 +187,10 @@ def residual_history(p, info):
 
 
 def gcr_params(tol=1e-10, k_max=16, delta=1e-3, max_iter=10000, precond=L.LQCD_PRECOND_NONE, block=(8, 8, 8, 8),
-               mr_steps=8, cycles=0, omega=1.0, history=0):
+               mr_steps=8, cycles=0, omega=1.0, history=0, orth_passes=1):
     p = L.lqcd_gcr_params()
     p.tol, p.k_max, p.delta, p.max_iter, p.precond = tol, k_max, delta, max_iter, precond
+    p.orth_passes = orth_passes
     p.schwarz.block[:] = [int(b) for b in block]
     p.schwarz.mr_steps = mr_steps
     p.schwarz.cycles = cycles

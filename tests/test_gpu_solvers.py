@@ -58,16 +58,20 @@ def test_cgne_fp64_8x4(ctx):
         assert abs(hist[k] - h10[k + 1]) <= 1e-10 * h10[k + 1], (k, hist[k], h10[k + 1])
 
 
+@pytest.mark.parametrize("orth", [1, 2])
 @pytest.mark.parametrize("precond", ["none", "schwarz"])
-def test_gcr_fp64_matches_oracle(ctx, precond):
-    """All-FP64 GCR (FP64 Krylov and K): same solution as the oracle's Algorithm 1."""
+def test_gcr_fp64_matches_oracle(ctx, precond, orth):
+    """All-FP64 GCR (FP64 Krylov and K), with one classical Gram-Schmidt pass
+    or with CGS2: same solution as the oracle's Algorithm 1 (modified
+    Gram-Schmidt), and its first 10 iterated residuals."""
     dims, kappa, csw, block = (8, 8, 8, 8), 0.124, 1.0, (4, 4, 4, 4)
     U, b, o = wilson_system(ctx, dims, kappa, csw, 0.25, 201, 202, [0], tile=block)
     hi = o[0]
     bp = hi.import_spinor(b, -1)
     x = hi.spinor(full=True)
     pk = L.LQCD_PRECOND_SCHWARZ if precond == "schwarz" else L.LQCD_PRECOND_NONE
-    prm = ops.gcr_params(1e-10, k_max=8, delta=1e-2, precond=pk, block=block, mr_steps=4, history=200)
+    prm = ops.gcr_params(1e-10, k_max=8, delta=1e-2, precond=pk, block=block, mr_steps=4, history=200,
+                         orth_passes=orth)
     st, info = L.lqcd_gcr_solve(ctx, hi.op, hi.op, hi.op, prm, x, bp)
     assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
     hist = ops.residual_history(prm, info)
@@ -148,6 +152,11 @@ def test_solver_zero_and_bad_sources(ctx):
     with pytest.raises(L.LqcdError) as ei:
         L.lqcd_cg_solve(ctx, hi.op, None, ops.cg_params(), x, nanb)
     assert ei.value.status == L.LQCD_ERR_INVALID_ARG
+    bp = hi.import_spinor(b, -1)
+    for bad in (-1, 3):
+        with pytest.raises(L.LqcdError) as ei:
+            L.lqcd_gcr_solve(ctx, hi.op, hi.op, hi.op, ops.gcr_params(orth_passes=bad), x, bp)
+        assert ei.value.status == L.LQCD_ERR_INVALID_ARG
 
 
 def test_cgne_mixed_precision_reliable_updates(ctx):
