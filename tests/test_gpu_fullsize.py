@@ -52,9 +52,10 @@ def sample_sites(dims, parity, n, seed):
     return np.sort(keep[:n])
 
 
-# the benchmark's tilings: stencil operators span the full x extent, the FP16
-# Schwarz operator is tiled by its 8^4 Dirichlet blocks
-STENCIL_TILE, BLOCK = (32, 8, 8, 8), (8, 8, 8, 8)
+# the benchmark's tilings: stencil operators span the full x and y extents
+# (4 sites along z and t), the FP16 Schwarz operator is tiled by its 8^4
+# Dirichlet blocks
+STENCIL_TILE, BLOCK = (32, 32, 4, 4), (8, 8, 8, 8)
 
 
 @pytest.mark.parametrize("prec,recon,tile", [(1, 12, STENCIL_TILE), (2, 12, STENCIL_TILE), (3, 12, STENCIL_TILE),
