@@ -355,9 +355,9 @@ static lqcd_status schwarz_form(lqcd_context *ctx, const OpInfo &info, const Geo
 }
 
 // Does the block-resident form apply (blocks equal to the tiles, 16-bit
-// floating-point storage, 12 or 18 link reals, a block in LDS)?
+// storage, 12 or 18 link reals, a block in LDS)?
 static bool schwarz_block_form_fits(const OpInfo &info, const Geom &g) {
-  if ((info.prec != LQCD_F16 && info.prec != LQCD_BF16) || info.recon == 8) return false;
+  if ((info.prec != LQCD_F16 && info.prec != LQCD_BF16 && info.prec != LQCD_HALF) || info.recon == 8) return false;
   for (int m = 0; m < 4; ++m)
     if (g.cut[m] != info.g.B[m] || info.g.B[m] > 256) return false;
   return sap_block_spt(info.g.Vt2) != 0;

@@ -641,7 +641,8 @@ __global__ void __launch_bounds__(256) clover_apply_kernel(Geom g, S *out, const
 
 // ---------------------------------------------------------------------------
 // Additive Schwarz with each block resident in LDS (Section 4's block solver,
-// with blocks equal to the tiles and 16-bit storage): one workgroup runs every
+// with blocks equal to the tiles and 16-bit storage: FP16, BF16, or fixed
+// point with a per-site norm): one workgroup runs every
 // MR step of one block. The block's spinor of the current half step (r on the
 // even sites, then t on the odd sites) lives in LDS, so neighbours are read
 // from there; links and clover stream from memory in each half step; the
@@ -684,52 +685,101 @@ template <typename S> __device__ __forceinline__ float hi16(uint32_t u) {
   return to_real<float>(__builtin_bit_cast(S, (uint16_t)(u >> 16)));
 }
 
-// A site's 24 stored values as 12 registers; in LDS and in memory the spinor
-// is chunk-major (chunk c = reals 4c .. 4c+3 = registers 2c, 2c+1).
-template <typename S> __device__ __forceinline__ void sap_pack(const cpx<float> (&v)[4][3], uint32_t (&p)[12]) {
+// A site's stored spinor: its 24 16-bit values as 12 registers (register j =
+// reals 2j, 2j+1; in LDS and in memory the spinor is chunk-major, chunk c =
+// registers 2c, 2c+1) and, with fixed-point storage, the site norm.
+template <typename S, bool FIXED = is_fixed<S>()> struct SapSite {
+  uint32_t p[12];
+};
+template <typename S> struct SapSite<S, true> {
+  uint32_t p[12];
+  float m;
+};
+
+// stored -> FP32, as the other kernels load (fixed point: the code's value,
+// then times the site norm)
+template <typename S> __device__ __forceinline__ void sap_reals(const SapSite<S> &s, float (&v)[24]) {
+#pragma unroll
+  for (int j = 0; j < 12; ++j) {
+    v[2 * j] = lo16<S>(s.p[j]);
+    v[2 * j + 1] = hi16<S>(s.p[j]);
+  }
+  if constexpr (is_fixed<S>()) {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] *= s.m;
+  }
+}
+// FP32 -> stored, as the other kernels store (fixed point: the norm is the
+// largest |v_k|, the codes those of v_k times its reciprocal)
+template <typename S> __device__ __forceinline__ void sap_store(const float (&v)[24], SapSite<S> &s) {
+  if constexpr (is_fixed<S>()) {
+    const float m = fixed_norm<24, float>(v), inv = m > 0 ? 1.0f / m : 0.0f;
+    s.m = m;
+#pragma unroll
+    for (int j = 0; j < 12; ++j)
+      s.p[j] = pack16<S>(Store<S>::from((float)v[2 * j] * inv), Store<S>::from((float)v[2 * j + 1] * inv));
+  } else {
+#pragma unroll
+    for (int j = 0; j < 12; ++j) s.p[j] = pack16<S>(Store<S>::from(v[2 * j]), Store<S>::from(v[2 * j + 1]));
+  }
+}
+__device__ __forceinline__ void sap_flat(const cpx<float> (&v)[4][3], float (&f)[24]) {
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      p[3 * sp + c] = pack16<S>(Store<S>::from(v[sp][c].re), Store<S>::from(v[sp][c].im));
+    for (int c = 0; c < 3; ++c) {
+      f[6 * sp + 2 * c] = v[sp][c].re;
+      f[6 * sp + 2 * c + 1] = v[sp][c].im;
+    }
 }
-template <typename S> __device__ __forceinline__ void sap_unpack(const uint32_t (&p)[12], cpx<float> (&v)[4][3]) {
+__device__ __forceinline__ void sap_cpx(const float (&f)[24], cpx<float> (&v)[4][3]) {
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[sp][c] = mk<float>(lo16<S>(p[3 * sp + c]), hi16<S>(p[3 * sp + c]));
+    for (int c = 0; c < 3; ++c) v[sp][c] = mk<float>(f[6 * sp + 2 * c], f[6 * sp + 2 * c + 1]);
 }
-// The packed registers become opaque to the compiler here: values derived
+// The site's registers become opaque to the compiler here: values derived
 // from them (unpacked FP32 copies) are not kept alive across the point.
-__device__ __forceinline__ void sap_opaque(uint32_t (&p)[12]) {
+template <typename S> __device__ __forceinline__ void sap_opaque(SapSite<S> &s) {
 #pragma unroll
-  for (int j = 0; j < 12; ++j) __asm__ volatile("" : "+v"(p[j]));
+  for (int j = 0; j < 12; ++j) __asm__ volatile("" : "+v"(s.p[j]));
+  if constexpr (is_fixed<S>()) __asm__ volatile("" : "+v"(s.m));
 }
-__device__ __forceinline__ void sap_lds_put(uint2 *lds, int vt2, int k, const uint32_t (&p)[12]) {
+// LDS: 6 chunk arrays of vt2 sites (8 bytes each), then (fixed point) the
+// vt2 site norms
+template <typename S> __device__ __forceinline__ void sap_lds_put(uint2 *lds, int vt2, int k, const SapSite<S> &s) {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) lds[c * vt2 + k] = make_uint2(p[2 * c], p[2 * c + 1]);
+  for (int c = 0; c < 6; ++c) lds[c * vt2 + k] = make_uint2(s.p[2 * c], s.p[2 * c + 1]);
+  if constexpr (is_fixed<S>()) reinterpret_cast<float *>(lds + 6 * vt2)[k] = s.m;
 }
-__device__ __forceinline__ void sap_lds_get(const uint2 *lds, int vt2, int k, uint32_t (&p)[12]) {
+template <typename S> __device__ __forceinline__ void sap_lds_get(const uint2 *lds, int vt2, int k, SapSite<S> &s) {
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     const uint2 v = lds[c * vt2 + k];
-    p[2 * c] = v.x;
-    p[2 * c + 1] = v.y;
+    s.p[2 * c] = v.x;
+    s.p[2 * c + 1] = v.y;
   }
+  if constexpr (is_fixed<S>()) s.m = reinterpret_cast<const float *>(lds + 6 * vt2)[k];
 }
-template <typename S> __device__ __forceinline__ void sap_mem_get(const S *f, int64_t vh, int64_t s, uint32_t (&p)[12]) {
+template <typename S> __device__ __forceinline__ void sap_mem_get(const S *f, int64_t vh, int64_t s, SapSite<S> &o) {
   const uint2 *q = reinterpret_cast<const uint2 *>(f);
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     const uint2 v = q[c * vh + s];
-    p[2 * c] = v.x;
-    p[2 * c + 1] = v.y;
+    o.p[2 * c] = v.x;
+    o.p[2 * c + 1] = v.y;
   }
+  if constexpr (is_fixed<S>()) o.m = site_norms<S, 24>(f, vh)[s];
 }
-template <typename S> __device__ __forceinline__ void sap_mem_put(S *f, int64_t vh, int64_t s, const uint32_t (&p)[12]) {
+template <typename S> __device__ __forceinline__ void sap_mem_put(S *f, int64_t vh, int64_t s, const SapSite<S> &o) {
   uint2 *q = reinterpret_cast<uint2 *>(f);
 #pragma unroll
-  for (int c = 0; c < 6; ++c) nt_store(q + c * vh + s, make_uint2(p[2 * c], p[2 * c + 1]));
+  for (int c = 0; c < 6; ++c) nt_store(q + c * vh + s, make_uint2(o.p[2 * c], o.p[2 * c + 1]));
+  if constexpr (is_fixed<S>()) site_norms<S, 24>(f, vh)[s] = o.m;
+}
+// bytes of dynamic LDS: the spinor (and norms) of a block, then the segment sums
+__host__ __device__ constexpr size_t sap_lds_bytes(int vt2, bool fixed) {
+  return (size_t)vt2 * (48 + (fixed ? 4 : 0)) + (size_t)(vt2 / 64) * 3 * sizeof(double);
 }
 
 // Hop of STEP along MU from block coordinates l: false if the cut drops it;
@@ -753,10 +803,12 @@ __device__ __forceinline__ void sap_hop_acc(const SapArgs<S> &a, const uint2 *ld
   int kn;
   bool flip;
   if (!sap_hop<MU, STEP>(a, l, &kn, &flip)) return;
-  uint32_t raw[12];
+  SapSite<S> nb;
+  float pf[24];
   cpx<float> psi[4][3], h[2][3], u[2][3];
-  sap_lds_get(lds, a.vt2, kn, raw);
-  sap_unpack<S>(raw, psi);
+  sap_lds_get<S>(lds, a.vt2, kn, nb);
+  sap_reals<S>(nb, pf);
+  sap_cpx(pf, psi);
   // forward: (1 - gamma_mu) U_mu(x) psi(x+mu); backward: (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu)
   const float g = STEP > 0 ? -1.f : 1.f;
   project<MU, float>(psi, g, h);
@@ -819,6 +871,8 @@ __device__ __forceinline__ void sap_clover(const S *__restrict__ clov, int64_t v
   constexpr int CH = chunk_reals<S, 72>();  // reals per chunk (8 for 16-bit storage)
   static_assert(CH == 8, "16-bit clover chunks of 8 reals");
   float a[72];
+  float m = 1.f;  // fixed point: the site norm of the clover term
+  if constexpr (is_fixed<S>()) m = site_norms<S, 72>(clov, vh)[s];
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     // chunks 0..4 hold block 0 (reals 0..35), chunks 4..8 block 1 (36..71)
@@ -830,7 +884,12 @@ __device__ __forceinline__ void sap_clover(const S *__restrict__ clov, int64_t v
       for (int j = 0; j < 8; ++j) a[8 * c + j] = to_real<float>(v.v[j]);
     }
 #pragma unroll
-    for (int k = 36 * b; k < 36 * b + 36; ++k) __asm__ volatile("" : "+v"(a[k]));
+    for (int k = 36 * b; k < 36 * b + 36; ++k) {
+      if constexpr (is_fixed<S>())
+        a[k] *= m;
+      else
+        __asm__ volatile("" : "+v"(a[k]));
+    }
     const float *A = a + 36 * b;
     cpx<float> x[6], y[6];
 #pragma unroll
@@ -856,14 +915,15 @@ __device__ __forceinline__ void sap_clover(const S *__restrict__ clov, int64_t v
 // one colour); SPT sites per thread and parity, site k = p * blockDim.x + tid.
 // XREG: x stays in registers (else it is read and written in memory each step).
 template <typename S, int RECON, int SPT, bool XREG>
-__global__ void __launch_bounds__(512) sap_block_kernel(SapArgs<S> a) {
-  extern __shared__ uint2 sap_lds[];  // 6 chunks x Vt2 sites, then the segment sums
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) sap_block_kernel(SapArgs<S> a) {
+  extern __shared__ uint2 sap_lds[];  // the block's spinor (and norms), then the segment sums
   const int vt2 = a.vt2, nt = blockDim.x, tid = threadIdx.x;
-  double *seg = reinterpret_cast<double *>(sap_lds + 6 * vt2);  // [Vt2 / 64][3]
+  double *seg = reinterpret_cast<double *>(reinterpret_cast<char *>(sap_lds) + sap_lds_bytes(vt2, is_fixed<S>()) -
+                                           (size_t)(vt2 / 64) * 3 * sizeof(double));  // [Vt2 / 64][3]
   const int tile = a.g.colour >= 0 ? colour_site(a.g, blockIdx.x * vt2) / vt2 : (int)blockIdx.x;
   const int base = tile * vt2;
-  uint32_t r[SPT][12], w[SPT][12];  // w: t (odd sites) or q (even sites)
-  uint32_t x[XREG ? SPT : 1][12];
+  SapSite<S> r[SPT], w[SPT];  // w: t (odd sites) or q (even sites)
+  SapSite<S> x[XREG ? SPT : 1];
   uint32_t coords[SPT];
 #pragma unroll
   for (int p = 0; p < SPT; ++p) {
@@ -873,27 +933,32 @@ __global__ void __launch_bounds__(512) sap_block_kernel(SapArgs<S> a) {
     coords[p] = (uint32_t)(k - q1 * bxh) | ((uint32_t)(q1 - q2 * a.b[1]) << 8) |
                 ((uint32_t)(q2 % a.b[2]) << 16) | ((uint32_t)(q2 / a.b[2]) << 24);
     sap_mem_get<S>(a.r0, a.vh, base + k, r[p]);
-    sap_lds_put(sap_lds, vt2, k, r[p]);
+    sap_lds_put<S>(sap_lds, vt2, k, r[p]);
     if constexpr (XREG)
-      if (!a.first) sap_mem_get<S>(a.x, a.vh, base + k, x[p]);
+      if (a.first)
+        x[p] = SapSite<S>{};
+      else
+        sap_mem_get<S>(a.x, a.vh, base + k, x[p]);
   }
   __syncthreads();
+  // In each phase the thread's site index and coordinates pass through an
+  // empty asm, so that the addresses derived from them are recomputed there
+  // rather than held in registers across the step loop.
   for (int step = 0; step < a.steps; ++step) {
-    // the thread's index and coordinates pass through an empty asm each step,
-    // so that the addresses derived from them are not held in registers
-    // across the loop
     // t_o = A_oo^-1 D_oe r on the block's odd sites
 #pragma unroll
     for (int p = 0; p < SPT; ++p) {
       int k = p * nt + tid;
       __asm__ volatile("" : "+v"(k));
       cpx<float> acc[4][3], res[4][3];
+      float f[24];
       uint32_t cp = coords[p];
       __asm__ volatile("" : "+v"(cp));
       sap_hops<S, RECON>(a, sap_lds, base, k, cp, 1, acc);
       sap_clover<S>(a.clov_inv_odd, a.vh, base + k, acc, res);
-      sap_pack<S>(res, w[p]);
-      sap_opaque(w[p]);
+      sap_flat(res, f);
+      sap_store<S>(f, w[p]);
+      sap_opaque<S>(w[p]);
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();  // every read of r is done
@@ -901,39 +966,46 @@ __global__ void __launch_bounds__(512) sap_block_kernel(SapArgs<S> a) {
     for (int p = 0; p < SPT; ++p) {
       int k = p * nt + tid;
       __asm__ volatile("" : "+v"(k));
-      sap_lds_put(sap_lds, vt2, k, w[p]);
+      sap_lds_put<S>(sap_lds, vt2, k, w[p]);
     }
     __syncthreads();
-    // q_e = A_ee r + coef D_eo t, and the segment sums of <q,r>, <q,q>
+    // q_e = A_ee r + coef D_eo t, and the segment sums of <q,r>, <q,q> over
+    // the values as stored
 #pragma unroll
     for (int p = 0; p < SPT; ++p) {
       int k = p * nt + tid;
       __asm__ volatile("" : "+v"(k));
       cpx<float> acc[4][3], res[4][3], xv[4][3];
+      float rf[24], qf[24];
       uint32_t cp = coords[p];
       __asm__ volatile("" : "+v"(cp));
       sap_hops<S, RECON>(a, sap_lds, base, k, cp, 0, acc);
       __builtin_amdgcn_sched_barrier(0);
-      sap_unpack<S>(r[p], xv);
+      sap_reals<S>(r[p], rf);
+      sap_cpx(rf, xv);
       sap_clover<S>(a.clov_even, a.vh, base + k, xv, res);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int c = 0; c < 3; ++c) res[i][c] = res[i][c] + a.coef * acc[i][c];
+      sap_flat(res, qf);
+      sap_store<S>(qf, w[p]);
+      if constexpr (is_fixed<S>()) {
+        sap_reals<S>(w[p], qf);  // the values as stored
+      } else {
+#pragma unroll
+        for (int j = 0; j < 24; ++j) qf[j] = quantize<S, float>(qf[j]);
+      }
       double red[3] = {0, 0, 0};
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double qr = quantize<S, float>(res[i][c].re), qi = quantize<S, float>(res[i][c].im);
-          const double rr = xv[i][c].re, ri = xv[i][c].im;
-          red[0] += qr * rr + qi * ri;
-          red[1] += qr * ri - qi * rr;
-          red[2] += qr * qr + qi * qi;
-        }
-      sap_pack<S>(res, w[p]);
-      sap_opaque(w[p]);
-      sap_opaque(r[p]);
+      for (int j = 0; j < 12; ++j) {
+        const double qr = qf[2 * j], qi = qf[2 * j + 1], rr = rf[2 * j], ri = rf[2 * j + 1];
+        red[0] += qr * rr + qi * ri;
+        red[1] += qr * ri - qi * rr;
+        red[2] += qr * qr + qi * qi;
+      }
+      sap_opaque<S>(w[p]);
+      sap_opaque<S>(r[p]);
 #pragma unroll
       for (int j = 0; j < 3; ++j)
         for (int off = 32; off > 0; off >>= 1) red[j] += __shfl_xor(red[j], off, 64);
@@ -956,23 +1028,18 @@ __global__ void __launch_bounds__(512) sap_block_kernel(SapArgs<S> a) {
     for (int p = 0; p < SPT; ++p) {
       int k = p * nt + tid;
       __asm__ volatile("" : "+v"(k));
-      uint32_t xo[12];
+      SapSite<S> xo{};
       if constexpr (XREG) {
-#pragma unroll
-        for (int j = 0; j < 12; ++j) xo[j] = x[p][j];
+        xo = x[p];
       } else {
         if (!zero_x) sap_mem_get<S>(a.x, a.vh, base + k, xo);
       }
       float rv[24], qv[24], xv[24];
+      sap_reals<S>(r[p], rv);
+      sap_reals<S>(w[p], qv);
+      sap_reals<S>(xo, xv);
 #pragma unroll
-      for (int j = 0; j < 12; ++j) {
-        rv[2 * j] = lo16<S>(r[p][j]);
-        rv[2 * j + 1] = hi16<S>(r[p][j]);
-        qv[2 * j] = lo16<S>(w[p][j]);
-        qv[2 * j + 1] = hi16<S>(w[p][j]);
-        xv[2 * j] = zero_x ? 0.f : lo16<S>(xo[j]);
-        xv[2 * j + 1] = zero_x ? 0.f : hi16<S>(xo[j]);
-      }
+      for (int j = 0; j < 24; ++j) xv[j] = zero_x ? 0.f : xv[j];
 #pragma unroll
       for (int j = 0; j < 12; ++j) {
         const float re = rv[2 * j], im = rv[2 * j + 1];
@@ -981,19 +1048,15 @@ __global__ void __launch_bounds__(512) sap_block_kernel(SapArgs<S> a) {
         rv[2 * j] = re - (ar * qv[2 * j] - ai * qv[2 * j + 1]);
         rv[2 * j + 1] = im - (ar * qv[2 * j + 1] + ai * qv[2 * j]);
       }
-#pragma unroll
-      for (int j = 0; j < 12; ++j) {
-        xo[j] = pack16<S>(Store<S>::from(xv[2 * j]), Store<S>::from(xv[2 * j + 1]));
-        if (!last) r[p][j] = pack16<S>(Store<S>::from(rv[2 * j]), Store<S>::from(rv[2 * j + 1]));
-      }
-      sap_opaque(r[p]);
+      sap_store<S>(xv, xo);
+      if (!last) sap_store<S>(rv, r[p]);
+      sap_opaque<S>(r[p]);
       if constexpr (XREG) {
-#pragma unroll
-        for (int j = 0; j < 12; ++j) x[p][j] = xo[j];
+        x[p] = xo;
       } else {
         sap_mem_put<S>(a.x, a.vh, base + k, xo);
       }
-      if (!last) sap_lds_put(sap_lds, vt2, k, r[p]);
+      if (!last) sap_lds_put<S>(sap_lds, vt2, k, r[p]);
     }
     __syncthreads();  // the new r is in LDS; the segment sums are read
   }
@@ -1011,8 +1074,6 @@ int sap_block_spt(int vt2) {
     if (vt2 / spt <= 512 && vt2 % (64 * spt) == 0) return spt;
   return 0;
 }
-
-size_t sap_block_lds_bytes(int vt2) { return (size_t)vt2 * 48 + (size_t)(vt2 / 64) * 3 * sizeof(double); }
 
 template <typename S, int RECON, int SPT, bool XREG>
 static hipError_t launch_sap4(const SapLaunch &l, hipStream_t st) {
@@ -1035,12 +1096,12 @@ static hipError_t launch_sap4(const SapLaunch &l, hipStream_t st) {
   a.omega = l.omega;
   a.steps = l.steps;
   a.first = l.first;
-  const size_t lds = sap_block_lds_bytes(l.g.Vt2);
+  const size_t lds = sap_lds_bytes(l.g.Vt2, is_fixed<S>());
   static bool attr_set = false;  // per instantiation
   if (!attr_set) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sap_block_kernel<S, RECON, SPT, XREG>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)sap_block_lds_bytes(kSapMaxSites));
+                                             (int)sap_lds_bytes(kSapMaxSites, is_fixed<S>()));
     if (e != hipSuccess) return e;
     attr_set = true;
   }
@@ -1082,6 +1143,7 @@ hipError_t launch_sap_block(const SapLaunch &l, hipStream_t st) {
   switch (l.prec) {
     case LQCD_F16: return launch_sap1<_Float16>(l, st);
     case LQCD_BF16: return launch_sap1<bf16>(l, st);
+    case LQCD_HALF: return launch_sap1<fx16>(l, st);
   }
   return hipErrorInvalidValue;
 }

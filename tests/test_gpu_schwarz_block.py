@@ -9,7 +9,9 @@ outputs are bit-identical, and the test requires that. FP16 conversions are
 folded by the compiler into its mixed-precision instructions, differently in
 the two kernels, and a few percent of the FP16 outputs differ by rounding
 steps: there the forms are compared within a tenth of the bound each meets
-against the oracle (the derived bound of the 16-bit preconditioner)."""
+against the oracle (the derived bound of the 16-bit preconditioner). The same
+comparison holds for 16-bit fixed point (codes and a per-site norm), whose
+bound is derived beside its own operator tests."""
 import numpy as np
 import pytest
 import torch
@@ -23,7 +25,9 @@ pytestmark = pytest.mark.gpu
 L = pytest.importorskip("paper_1109_2935_amd.lqcd")
 from paper_1109_2935_amd import ops  # noqa: E402
 
-SCHWARZ_TOL = {2: 5e-3, 3: 4e-2}  # derivation beside the Schwarz parity test of the Wilson kernels
+# derivations beside the Schwarz parity tests of the Wilson kernels (FP16, BF16)
+# and of the fixed-point storage (HALF)
+SCHWARZ_TOL = {2: 5e-3, 3: 4e-2, 4: 8e-4}
 
 # (dims, block = tile): blocks cut along every axis (128 sites per parity, one
 # site per thread); 8^4 blocks spanning y, z and t of the lattice (2048 sites,
@@ -49,7 +53,7 @@ class Fields:
 def run_form(ctx, monkeypatch, o, prm, inp, form):
     monkeypatch.setenv("LQCD_SCHWARZ_FORM", str(form))
     out = o.spinor()
-    out.fill_(255)  # all-ones 16-bit values (a NaN): every output element must be written
+    out.fill_(255)  # all-ones 16-bit values (a NaN; for fixed point a NaN norm): every element must be written
     L.lqcd_schwarz_precond(ctx, o.op, prm, out, inp)
     torch.cuda.synchronize()
     return out
@@ -62,7 +66,7 @@ FORM_CASES = [(case, cycles) for case in CASES for cycles in (0, 2) if cycles ==
 @pytest.mark.parametrize("case,cycles", FORM_CASES,
                          ids=lambda v: "x".join(map(str, v[0])) + "_b" + "x".join(map(str, v[1])) if isinstance(v, tuple)
                          else "c%d" % v)
-@pytest.mark.parametrize("prec,recon", [(2, 12), (3, 12), (2, 18)])
+@pytest.mark.parametrize("prec,recon", [(2, 12), (3, 12), (2, 18), (4, 12), (4, 18)])
 def test_block_form_matches_launches(ctx, monkeypatch, case, cycles, prec, recon):
     dims, block = case
     U, psi, Ud = Fields.get(dims)
@@ -77,7 +81,8 @@ def test_block_form_matches_launches(ctx, monkeypatch, case, cycles, prec, recon
     assert torch.equal(inp, keep)  # the input is left as it was
     for f in (1, 2):
         a, b = outs[0], outs[f]
-        assert int((b.view(torch.int16) == -1).sum()) == 0, f
+        if prec != 4:  # (a fixed-point code of -1 is a value; an unwritten norm shows as NaN below)
+            assert int((b.view(torch.int16) == -1).sum()) == 0, f
         diff = int((a.view(torch.int16) != b.view(torch.int16)).sum())
         n = a.numel() // 2
         va, vb = np_of(o.export_spinor(a, 0)), np_of(o.export_spinor(b, 0))
