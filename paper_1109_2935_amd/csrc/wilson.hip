@@ -64,6 +64,119 @@ __device__ __forceinline__ void expand_acc(cpx<R> (&acc)[4][3], const cpx<R> (&u
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP16 storage: a hop in packed half arithmetic. The spin projection runs on
+// packed FP16 pairs (each component of h rounded once to FP16; the sign flips
+// and factors i are exact) and the colour products U h on v_dot2_f32_f16
+// (products of two FP16 values are exact in FP32, sums in FP32). With 12
+// stored link reals the third row is rebuilt in FP32 from the same dot2 sums
+// and multiplied in FP32. Against the FP32-arithmetic hop this removes the 36
+// half-to-float conversions of a hop and halves its colour-product
+// instructions; the one new rounding (of h) is a quarter of the storage
+// rounding already in the input.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h2v h2_times_i(h2v a) { return h2v{-a.y, a.x}; }
+__device__ __forceinline__ float dot2(h2v a, h2v b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+
+template <int MU>
+__device__ __forceinline__ void project_h2(const h2v (&s)[4][3], h2v g, h2v (&h)[2][3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if constexpr (MU == 0) {
+      h[0][c] = s[0][c] - g * h2_times_i(s[3][c]);
+      h[1][c] = s[1][c] - g * h2_times_i(s[2][c]);
+    } else if constexpr (MU == 1) {
+      h[0][c] = s[0][c] - g * s[3][c];
+      h[1][c] = s[1][c] + g * s[2][c];
+    } else if constexpr (MU == 2) {
+      h[0][c] = s[0][c] - g * h2_times_i(s[2][c]);
+      h[1][c] = s[1][c] + g * h2_times_i(s[3][c]);
+    } else {
+      h[0][c] = s[0][c] + g * s[2][c];
+      h[1][c] = s[1][c] + g * s[3][c];
+    }
+  }
+}
+
+// u_k = U h_k (FWD) or U^+ h_k for both half-spinor rows k; U as stored: rows
+// 0 and 1 (and 2 with 18 reals) as packed (re, im) pairs, row-major.
+template <int RECON, bool FWD>
+__device__ __forceinline__ void su3_h2(const h2v (&U)[RECON / 2], const h2v (&h)[2][3], cpx<float> (&u)[2][3]) {
+  static_assert(RECON == 12 || RECON == 18, "16-bit links hold 12 or 18 reals");
+  // conj-swapped forms of h: Re(a b) = dot2(a, hc), Im(a b) = dot2(a, hs);
+  // Re(conj(a) b) = dot2(a, b), Im(conj(a) b) = dot2(a, ha)
+  h2v hx[2][3], hy[2][3];
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      hx[k][c] = FWD ? h2v{h[k][c].x, -h[k][c].y} : h[k][c];
+      hy[k][c] = FWD ? h2v{h[k][c].y, h[k][c].x} : h2v{h[k][c].y, -h[k][c].x};
+    }
+  constexpr int NR = RECON == 18 ? 3 : 2;  // rows taken from storage
+  // forward: output rows i < NR over all columns j; adjoint: all outputs i
+  // over the stored rows j < NR
+  constexpr int NI = FWD ? NR : 3, NJ = FWD ? 3 : NR;
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        // forward: row i of U, column j of h; adjoint: column i of U (row j)
+        const h2v a = FWD ? U[3 * i + j] : U[3 * j + i];
+        re = dot2(a, hx[k][j], re);
+        im = dot2(a, hy[k][j], im);
+      }
+      u[k][i] = mk<float>(re, im);
+    }
+  if constexpr (RECON == 12) {
+    // third row conj(row0 x row1) in FP32: U2j = conj(U0k U1l - U0l U1k)
+    cpx<float> r2[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int k = (j + 1) % 3, l = (j + 2) % 3;
+      const h2v a = U[k], b = U[3 + l], c = U[l], d = U[3 + k];
+      const float re = dot2(a, h2v{b.x, -b.y}, dot2(-c, h2v{d.x, -d.y}, 0.f));
+      const float im = dot2(c, h2v{d.y, d.x}, dot2(-a, h2v{b.y, b.x}, 0.f));
+      r2[j] = mk<float>(re, im);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      cpx<float> hf[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) hf[j] = mk<float>((float)h[k][j].x, (float)h[k][j].y);
+      if constexpr (FWD) {
+        cpx<float> a = r2[0] * hf[0];
+        cmac(a, r2[1], hf[1]);
+        cmac(a, r2[2], hf[2]);
+        u[k][2] = a;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) cmac_conj(u[k][i], r2[i], hf[2]);
+      }
+    }
+  }
+}
+
+// One FP16 hop from stored values: psi the neighbour's 24 halves, link its
+// RECON halves, ps the projection sign (+-1); u as su3_h2.
+template <int MU, int DIR, int RECON>
+__device__ __forceinline__ void hop_h2(const uint32_t (&psi)[12], const uint32_t (&link)[RECON / 2], float ps,
+                                       cpx<float> (&u)[2][3]) {
+  h2v s[4][3], hh[2][3], U[RECON / 2];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[sp][c] = __builtin_bit_cast(h2v, psi[3 * sp + c]);
+#pragma unroll
+  for (int k = 0; k < RECON / 2; ++k) U[k] = __builtin_bit_cast(h2v, link[k]);
+  const _Float16 g16 = (_Float16)ps;
+  project_h2<MU>(s, h2v{g16, g16}, hh);
+  su3_h2<RECON, (DIR > 0)>(U, hh, u);
+}
+
 template <typename S, typename R>
 __device__ __forceinline__ void load_spinor(const S *__restrict__ f, int64_t vh, int s, cpx<R> (&v)[4][3]) {
   R r[24];
@@ -155,9 +268,113 @@ template <typename S> struct WArgs {
   int rg;    // sources per block of the multi-source layout (rhs_group(nrhs))
 };
 
+// Software-pipelined hops for launches without a cut (FP32 and 16-bit
+// storage): the raw inputs of a hop (neighbour spinor, link as stored, wrap
+// count) go to one of two buffers, refilled alternately, so each wave keeps
+// the loads of the next hop in flight while it multiplies the current one.
+// Scheduling barriers hold that order
+// (without them the compiler issues the loads of all eight hops first and
+// spills).
+// The raw values stay in the storage type until they are used, so that no
+// conversion forces an early wait for the loads.
+template <typename S, int RECON> struct HopIn {
+  S psi[24];
+  S link[RECON];
+  int w;
+};
+
+template <int MU, int DIR, bool STREAM, typename S, int RECON>
+__device__ __forceinline__ void hop_fetch(const WArgs<S> &a, const Site &x, int s, int rhs, HopIn<S, RECON> &h) {
+  const int64_t vh = a.g.Vh, vs = vh * a.nrhs;
+  const int n = hop1<MU, DIR>(a.g, x, &h.w);
+  load_chunks_raw<S, 24, spinor_chunk<24>()>(a.in, vs, rhs_index(rhs, n, vh, a.rg), h.psi);
+  // forward hop: U_mu(x) of x's parity; backward: U_mu(x - mu) of the other
+  const int lp = DIR > 0 ? x.p : 1 - x.p, ls = DIR > 0 ? s : n;
+  load_chunks_raw<S, RECON, chunk_reals<S, RECON>(), STREAM>(a.gauge + (int64_t)(2 * MU + lp) * vh * RECON, vh, ls,
+                                                           h.link);
+}
+
+// FP16 storage takes the packed-half hop (hop_h2) with 12 or 18 link reals.
+template <typename S, int RECON> constexpr bool half_hop() {
+  return std::is_same<S, _Float16>::value && (RECON == 12 || RECON == 18);
+}
+
+template <int MU, int DIR, typename S, typename R, int RECON>
+__device__ __forceinline__ void hop_apply(const HopIn<S, RECON> &h, R sgn, int bc_t, cpx<R> (&acc)[4][3]) {
+  const R ps = DIR > 0 ? -sgn : sgn;
+  cpx<R> u[2][3];
+  if constexpr (half_hop<S, RECON>()) {
+    uint32_t pw[12], lw[RECON / 2];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) pw[j] = __builtin_bit_cast(uint32_t, h2v{h.psi[2 * j], h.psi[2 * j + 1]});
+#pragma unroll
+    for (int j = 0; j < RECON / 2; ++j) lw[j] = __builtin_bit_cast(uint32_t, h2v{h.link[2 * j], h.link[2 * j + 1]});
+    hop_h2<MU, DIR, RECON>(pw, lw, ps, u);
+  } else {
+    cpx<R> psi[4][3], hh[2][3];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        R re = to_real<R>(h.psi[6 * sp + 2 * c]), im = to_real<R>(h.psi[6 * sp + 2 * c + 1]);
+        if constexpr (is_float16<S>()) {
+          // convert here: the empty asm keeps the compiler from folding the
+          // stored halves into mixed-precision FMAs, which keeps them live
+          // across the hop (170-230 VGPRs instead of about 110)
+          __asm__ volatile("" : "+v"(re));
+          __asm__ volatile("" : "+v"(im));
+        }
+        psi[sp][c] = mk<R>(re, im);
+      }
+    project<MU, R>(psi, ps, hh);
+    R lv[RECON];
+#pragma unroll
+    for (int k = 0; k < RECON; ++k) {
+      lv[k] = to_real<R>(h.link[k]);
+      if constexpr (is_float16<S>()) __asm__ volatile("" : "+v"(lv[k]));
+    }
+    const Link<R> U = unpack_link<RECON, R>(lv);
+    if constexpr (DIR > 0) {
+      su3_mv(U, hh[0], u[0]);
+      su3_mv(U, hh[1], u[1]);
+    } else {
+      su3_adj_mv(U, hh[0], u[0]);
+      su3_adj_mv(U, hh[1], u[1]);
+    }
+  }
+  if constexpr (MU == 3) {
+    const R ph = ((h.w & 1) && bc_t < 0) ? R(-1) : R(1);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u[k][c] = ph * u[k][c];
+  }
+  expand_acc<MU, R>(acc, u, ps);
+}
+
+// One direction of the hopping term, each hop checked against the cut.
 template <int MU, typename S, typename R, int RECON>
 __device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int s, int rhs, R sgn,
                                            cpx<R> (&acc)[4][3]) {
+  if constexpr (half_hop<S, RECON>()) {
+    // raw loads and the packed-half hop, as in the pipelined form
+    HopIn<S, RECON> h;
+    if (hop_kept<MU>(a.g, x, +1)) {
+      if (a.nrhs == 1)
+        hop_fetch<MU, +1, true, S, RECON>(a, x, s, rhs, h);
+      else
+        hop_fetch<MU, +1, false, S, RECON>(a, x, s, rhs, h);
+      hop_apply<MU, +1, S, R, RECON>(h, sgn, a.g.bc_t, acc);
+    }
+    if (hop_kept<MU>(a.g, x, -1)) {
+      if (a.nrhs == 1)
+        hop_fetch<MU, -1, true, S, RECON>(a, x, s, rhs, h);
+      else
+        hop_fetch<MU, -1, false, S, RECON>(a, x, s, rhs, h);
+      hop_apply<MU, -1, S, R, RECON>(h, sgn, a.g.bc_t, acc);
+    }
+    return;
+  }
   const int64_t vh = a.g.Vh, vs = vh * a.nrhs;
   // forward: (1 - sgn gamma_mu) U_mu(x) psi(x+mu)
   if (hop_kept<MU>(a.g, x, +1)) {
@@ -197,75 +414,6 @@ __device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int
     }
     expand_acc<MU, R>(acc, u, sgn);
   }
-}
-
-// Software-pipelined hops for launches without a cut (FP32 and 16-bit
-// storage): the raw inputs of a hop (neighbour spinor, link as stored, wrap
-// count) go to one of two buffers, refilled alternately, so each wave keeps
-// the loads of the next hop in flight while it multiplies the current one.
-// Scheduling barriers hold that order
-// (without them the compiler issues the loads of all eight hops first and
-// spills).
-// The raw values stay in the storage type until they are used, so that no
-// conversion forces an early wait for the loads.
-template <typename S, int RECON> struct HopIn {
-  S psi[24];
-  S link[RECON];
-  int w;
-};
-
-template <int MU, int DIR, bool STREAM, typename S, int RECON>
-__device__ __forceinline__ void hop_fetch(const WArgs<S> &a, const Site &x, int s, int rhs, HopIn<S, RECON> &h) {
-  const int64_t vh = a.g.Vh, vs = vh * a.nrhs;
-  const int n = hop1<MU, DIR>(a.g, x, &h.w);
-  load_chunks_raw<S, 24, spinor_chunk<24>()>(a.in, vs, rhs_index(rhs, n, vh, a.rg), h.psi);
-  // forward hop: U_mu(x) of x's parity; backward: U_mu(x - mu) of the other
-  const int lp = DIR > 0 ? x.p : 1 - x.p, ls = DIR > 0 ? s : n;
-  load_chunks_raw<S, RECON, chunk_reals<S, RECON>(), STREAM>(a.gauge + (int64_t)(2 * MU + lp) * vh * RECON, vh, ls,
-                                                           h.link);
-}
-
-template <int MU, int DIR, typename S, typename R, int RECON>
-__device__ __forceinline__ void hop_apply(const HopIn<S, RECON> &h, R sgn, int bc_t, cpx<R> (&acc)[4][3]) {
-  cpx<R> psi[4][3], hh[2][3], u[2][3];
-#pragma unroll
-  for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      R re = to_real<R>(h.psi[6 * sp + 2 * c]), im = to_real<R>(h.psi[6 * sp + 2 * c + 1]);
-      if constexpr (is_float16<S>()) {
-        // convert here: the empty asm keeps the compiler from folding the
-        // stored halves into mixed-precision FMAs, which keeps them live
-        // across the hop (170-230 VGPRs instead of about 110)
-        __asm__ volatile("" : "+v"(re));
-        __asm__ volatile("" : "+v"(im));
-      }
-      psi[sp][c] = mk<R>(re, im);
-    }
-  const R ps = DIR > 0 ? -sgn : sgn;
-  project<MU, R>(psi, ps, hh);
-  R lv[RECON];
-#pragma unroll
-  for (int k = 0; k < RECON; ++k) {
-    lv[k] = to_real<R>(h.link[k]);
-    if constexpr (is_float16<S>()) __asm__ volatile("" : "+v"(lv[k]));
-  }
-  const Link<R> U = unpack_link<RECON, R>(lv);
-  if constexpr (DIR > 0) {
-    su3_mv(U, hh[0], u[0]);
-    su3_mv(U, hh[1], u[1]);
-  } else {
-    su3_adj_mv(U, hh[0], u[0]);
-    su3_adj_mv(U, hh[1], u[1]);
-  }
-  if constexpr (MU == 3) {
-    const R ph = ((h.w & 1) && bc_t < 0) ? R(-1) : R(1);
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) u[k][c] = ph * u[k][c];
-  }
-  expand_acc<MU, R>(acc, u, ps);
 }
 
 // Where the pipelined hops pay (measured at 32^3x64): FP32 and 16-bit
@@ -804,22 +952,35 @@ __device__ __forceinline__ void sap_hop_acc(const SapArgs<S> &a, const uint2 *ld
   bool flip;
   if (!sap_hop<MU, STEP>(a, l, &kn, &flip)) return;
   SapSite<S> nb;
-  float pf[24];
-  cpx<float> psi[4][3], h[2][3], u[2][3];
+  cpx<float> u[2][3];
   sap_lds_get<S>(lds, a.vt2, kn, nb);
-  sap_reals<S>(nb, pf);
-  sap_cpx(pf, psi);
   // forward: (1 - gamma_mu) U_mu(x) psi(x+mu); backward: (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu)
   const float g = STEP > 0 ? -1.f : 1.f;
-  project<MU, float>(psi, g, h);
-  const Link<float> U = STEP > 0 ? load_link<S, float, RECON>(a.gauge, a.vh, MU, par, base + k, true)
-                                 : load_link<S, float, RECON>(a.gauge, a.vh, MU, 1 - par, base + kn, true);
-  if constexpr (STEP > 0) {
-    su3_mv(U, h[0], u[0]);
-    su3_mv(U, h[1], u[1]);
+  if constexpr (half_hop<S, RECON>()) {
+    // the packed-half hop of the launch kernels, on the stored values
+    S raw[RECON];
+    uint32_t lw[RECON / 2];
+    const int lpar = STEP > 0 ? par : 1 - par, ls = base + (STEP > 0 ? k : kn);
+    load_chunks_raw<S, RECON, chunk_reals<S, RECON>(), true>(a.gauge + (int64_t)(2 * MU + lpar) * a.vh * RECON, a.vh,
+                                                             ls, raw);
+#pragma unroll
+    for (int j = 0; j < RECON / 2; ++j) lw[j] = __builtin_bit_cast(uint32_t, h2v{raw[2 * j], raw[2 * j + 1]});
+    hop_h2<MU, STEP, RECON>(nb.p, lw, g, u);
   } else {
-    su3_adj_mv(U, h[0], u[0]);
-    su3_adj_mv(U, h[1], u[1]);
+    float pf[24];
+    cpx<float> psi[4][3], h[2][3];
+    sap_reals<S>(nb, pf);
+    sap_cpx(pf, psi);
+    project<MU, float>(psi, g, h);
+    const Link<float> U = STEP > 0 ? load_link<S, float, RECON>(a.gauge, a.vh, MU, par, base + k, true)
+                                   : load_link<S, float, RECON>(a.gauge, a.vh, MU, 1 - par, base + kn, true);
+    if constexpr (STEP > 0) {
+      su3_mv(U, h[0], u[0]);
+      su3_mv(U, h[1], u[1]);
+    } else {
+      su3_adj_mv(U, h[0], u[0]);
+      su3_adj_mv(U, h[1], u[1]);
+    }
   }
   if constexpr (MU == 3) {
     const float ph = flip ? -1.f : 1.f;
