@@ -184,42 +184,56 @@ struct VecPack {
 };
 
 // <z_i, w> for i < k (k <= 8 per launch)
-template <typename S>
+// K is a template argument so that the loads of all K vectors are issued
+// together, ahead of their products (with a run-time count each vector's
+// load waited behind a branch).
+template <typename S, int K>
 __global__ void __launch_bounds__(kBT) multi_cdot_kernel(VecPack z, const S *w, size_t nq, RedScratch r) {
-  double acc[16];
+  double acc[2 * K];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) acc[k] = 0;
+  for (int k = 0; k < 2 * K; ++k) acc[k] = 0;
   for (size_t i = (size_t)blockIdx.x * kBT + threadIdx.x; i < nq; i += (size_t)gridDim.x * kBT) {
-    double wv[4];
+    double wv[4], zv[K][4];
     ld4(w, i, wv);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      if (j < z.k) {
-        double zv[4];
-        ld4((const S *)z.p[j], i, zv);
-        acc[2 * j] += zv[0] * wv[0] + zv[1] * wv[1] + zv[2] * wv[2] + zv[3] * wv[3];
-        acc[2 * j + 1] += zv[0] * wv[1] - zv[1] * wv[0] + zv[2] * wv[3] - zv[3] * wv[2];
-      }
+    for (int j = 0; j < K; ++j) ld4((const S *)z.p[j], i, zv[j]);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      acc[2 * j] += zv[j][0] * wv[0] + zv[j][1] * wv[1] + zv[j][2] * wv[2] + zv[j][3] * wv[3];
+      acc[2 * j + 1] += zv[j][0] * wv[1] - zv[j][1] * wv[0] + zv[j][2] * wv[3] - zv[j][3] * wv[2];
     }
   }
-  grid_reduce<16>(acc, r);
+  grid_reduce<2 * K>(acc, r);
 }
 
-// w -= sum_i beta_i z_i ; reduce ||w||^2, <w, rr>
-template <typename S>
+// w -= sum_i beta_i z_i ; reduce ||w||^2, <w, rr>. K >= 0: that many vectors,
+// their loads issued together (as in multi_cdot_kernel); K < 0: any count
+// z.k, one vector after another.
+template <typename S, int K>
 __global__ void __launch_bounds__(kBT) multi_caxpy_dots_kernel(VecPack z, S *w, const S *rr, size_t nq, RedScratch r) {
   double acc[3] = {0, 0, 0};
   for (size_t i = (size_t)blockIdx.x * kBT + threadIdx.x; i < nq; i += (size_t)gridDim.x * kBT) {
     double wv[4];
     ld4(w, i, wv);
-    for (int j = 0; j < z.k; ++j) {
-      double zv[4];
-      ld4((const S *)z.p[j], i, zv);
+    auto sub = [&](int j, const double (&zv)[4]) {
       const double br = z.c[2 * j], bi = z.c[2 * j + 1];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         wv[2 * c] -= br * zv[2 * c] - bi * zv[2 * c + 1];
         wv[2 * c + 1] -= br * zv[2 * c + 1] + bi * zv[2 * c];
+      }
+    };
+    if constexpr (K >= 0) {
+      double zv[K > 0 ? K : 1][4];
+#pragma unroll
+      for (int j = 0; j < K; ++j) ld4((const S *)z.p[j], i, zv[j]);
+#pragma unroll
+      for (int j = 0; j < K; ++j) sub(j, zv[j]);
+    } else {
+      for (int j = 0; j < z.k; ++j) {
+        double zv[4];
+        ld4((const S *)z.p[j], i, zv);
+        sub(j, zv);
       }
     }
     st4(w, i, wv);
@@ -370,6 +384,16 @@ template <typename F> static hipError_t dispatch2(int p1, int p2, F &&f) {
   return dispatch1(p1, [&](auto t1) { return dispatch1(p2, [&](auto t2) { return f(t1, t2); }); });
 }
 
+// f(std::integral_constant<int, k>) for LO <= k <= HI (the caller checks the range)
+template <int LO, int HI, typename F> static hipError_t with_count(int k, F &&f) {
+  if constexpr (LO > HI) {
+    return hipErrorInvalidValue;
+  } else {
+    if (k == LO) return f(std::integral_constant<int, LO>{});
+    return with_count<LO + 1, HI>(k, f);
+  }
+}
+
 #define T1 std::remove_pointer_t<decltype(t1)>
 #define T2 std::remove_pointer_t<decltype(t2)>
 
@@ -420,8 +444,11 @@ hipError_t blas_multi_cdot(int p, const void *const *z, int k, const void *w, si
   const size_t nq = n / 2;
   const int g = grid_for(nq, red.max_wg);
   return dispatch1(p, [&](auto t1) -> hipError_t {
-    hipLaunchKernelGGL((multi_cdot_kernel<T1>), dim3(g), dim3(kBT), 0, st, pk, (const T1 *)w, nq, red);
-    return hipGetLastError();});
+    return with_count<1, 8>(k, [&](auto kc) {
+      hipLaunchKernelGGL((multi_cdot_kernel<T1, decltype(kc)::value>), dim3(g), dim3(kBT), 0, st, pk, (const T1 *)w,
+                         nq, red);
+      return hipGetLastError();
+    });});
 }
 
 hipError_t blas_multi_caxpy_dots(int p, const void *const *z, const double *beta, int k, void *w, const void *r,
@@ -437,8 +464,16 @@ hipError_t blas_multi_caxpy_dots(int p, const void *const *z, const double *beta
   const size_t nq = n / 2;
   const int g = grid_for(nq, red.max_wg);
   return dispatch1(p, [&](auto t1) -> hipError_t {
-    hipLaunchKernelGGL((multi_caxpy_dots_kernel<T1>), dim3(g), dim3(kBT), 0, st, pk, (T1 *)w, (const T1 *)r, nq, red);
-    return hipGetLastError();});
+    if (k > 16) {
+      hipLaunchKernelGGL((multi_caxpy_dots_kernel<T1, -1>), dim3(g), dim3(kBT), 0, st, pk, (T1 *)w, (const T1 *)r, nq,
+                         red);
+      return hipGetLastError();
+    }
+    return with_count<0, 16>(k, [&](auto kc) {
+      hipLaunchKernelGGL((multi_caxpy_dots_kernel<T1, decltype(kc)::value>), dim3(g), dim3(kBT), 0, st, pk, (T1 *)w,
+                         (const T1 *)r, nq, red);
+      return hipGetLastError();
+    });});
 }
 
 hipError_t blas_gcr_update(int p, void *z, void *r, size_t n, double inv_gamma, double ar, double ai,
