@@ -46,6 +46,11 @@ def kernel_sources_sha1():
     return h.hexdigest()
 SCHUR_REALS = {18: 552, 12: 456, 8: 392}   # two fused kernels, per even site
 PREC_BYTES = {0: 8, 1: 4, 2: 2, 3: 2, 4: 2}
+# Link reals of the FP16 Schwarz operator: with the packed-half hops the
+# block-resident K is bound by vector issue, and rebuilding the third link row
+# costs more there than the 50% more link bytes of the full matrix (1.38 ms
+# against 1.58 ms for 8 MR steps at 32^3x64)
+K_RECON = 18
 PREC_NAME = {0: "f64", 1: "f32", 2: "f16", 3: "bf16", 4: "half"}
 # 16-bit fixed point adds an FP32 norm per site to every spinor and clover
 # access: 2 spinor norms per dslash output site; 5 spinor and 2 clover norms
@@ -591,7 +596,7 @@ def main():
         tile = stencil_tile(dims, block)
         o64 = ops.wilson_clover(ctx, U, dims, kappa, csw, 0, 18, tile=tile, U_device=Ud)
         o32 = ops.wilson_clover(ctx, U, dims, kappa, csw, 1, 12, tile=tile, U_device=Ud)
-        o16 = ops.wilson_clover(ctx, U, dims, kappa, csw, 2, 12, tile=block, U_device=Ud)
+        o16 = ops.wilson_clover(ctx, U, dims, kappa, csw, 2, K_RECON, tile=block, U_device=Ud)
         bp = o64.import_spinor(b, -1)
         prm = ops.gcr_params(1e-10, k_max=16, delta=1e-3, max_iter=2000, precond=L.LQCD_PRECOND_SCHWARZ,
                              block=block, mr_steps=mr)
@@ -613,7 +618,8 @@ def main():
     inst = {}
     for prec, recon in [(0, 18), (0, 12), (1, 18), (1, 12), (1, 8), (2, 18), (2, 12), (3, 12), (4, 12)]:
         inst[(prec, recon)] = ops.wilson_clover(ctx, U, dims, kappa, csw, prec, recon, tile=tile, U_device=Ud)
-    o16b = ops.wilson_clover(ctx, U, dims, kappa, csw, 2, 12, tile=block, U_device=Ud)
+    o16b = ops.wilson_clover(ctx, U, dims, kappa, csw, 2, K_RECON, tile=block, U_device=Ud)
+    o16b12 = ops.wilson_clover(ctx, U, dims, kappa, csw, 2, 12, tile=block, U_device=Ud)
     ohb = ops.wilson_clover(ctx, U, dims, kappa, csw, 4, 12, tile=block, U_device=Ud)
     o32b = ops.wilson_clover(ctx, U, dims, kappa, csw, 1, 12, tile=block, U_device=Ud)
     torch.cuda.synchronize()
@@ -662,22 +668,27 @@ def main():
     # block with the block in LDS (x in memory / in registers). Bytes: the
     # block form's algorithmic traffic per even site, r read once, then per MR
     # step the links of both half steps and both clover blocks, x written once
-    # (x read and written each step in form 1 adds 96 bytes per step).
-    reps = [o16b, o16b.replica(), o16b.replica()]
-    ksets = [(r, r.import_spinor(b, 0), r.spinor()) for r in reps]
+    # (x read and written each step in form 1 adds 96 bytes per step), for
+    # 12 and 18 link reals.
     kprm = ops.schwarz_params(block, mr)
-    k_bytes = vh * (48 + mr * (2 * 8 * 24 + 2 * 144) + 48)
-    for form in (0, 1, 2):
-        os.environ["LQCD_SCHWARZ_FORM"] = str(form)
-        dk = time_rotating(torch, [lambda r=r, i=i, q=q: L.lqcd_schwarz_precond(ctx, r.op, kprm, q, i)
-                                   for r, i, q in ksets], 30)
-        kernels["schwarz_f16_r12_form%d" % form] = {
-            "us": round(dk * 1e6, 2), "GB/s": round(k_bytes / dk / 1e9, 1),
-            "frac": round(k_bytes / dk / 1e9 / HBM_PEAK_GBS, 4), "bytes": k_bytes}
-        log("Schwarz K (FP16, %d MR steps) form %d: %8.1f us, %7.1f GB/s of the block form's bytes" % (
-            mr, form, dk * 1e6, k_bytes / dk / 1e9))
-    del os.environ["LQCD_SCHWARZ_FORM"]
-    del reps, ksets
+    for krec, ko in ((12, o16b12), (18, o16b if K_RECON == 18 else None)):
+        if ko is None:
+            ko = ops.wilson_clover(ctx, U, dims, kappa, csw, 2, krec, tile=block, U_device=Ud)
+        reps = [ko, ko.replica(), ko.replica()]
+        ksets = [(r, r.import_spinor(b, 0), r.spinor()) for r in reps]
+        k_bytes = vh * (48 + mr * (2 * 8 * 2 * krec + 2 * 144) + 48)
+        for form in (0, 1, 2):
+            os.environ["LQCD_SCHWARZ_FORM"] = str(form)
+            dk = time_rotating(torch, [lambda r=r, i=i, q=q: L.lqcd_schwarz_precond(ctx, r.op, kprm, q, i)
+                                       for r, i, q in ksets], 30)
+            kernels["schwarz_f16_r%d_form%d" % (krec, form)] = {
+                "us": round(dk * 1e6, 2), "GB/s": round(k_bytes / dk / 1e9, 1),
+                "frac": round(k_bytes / dk / 1e9 / HBM_PEAK_GBS, 4), "bytes": k_bytes}
+            log("Schwarz K (FP16, %d link reals, %d MR steps) form %d: %8.1f us, %7.1f GB/s of the block form's "
+                "bytes" % (krec, mr, form, dk * 1e6, k_bytes / dk / 1e9))
+        del os.environ["LQCD_SCHWARZ_FORM"]
+        del reps, ksets
+    del o16b12
     copy = device_copy(torch, L, ctx)
     log("streaming copy %.1f GB/s" % copy["GB/s"])
 
@@ -803,8 +814,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 2), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "wilson-clover %s, kappa %.3f, c_sw %.1f, eps %.2f, antiperiodic t; GCR-DD "
-                               "FP64/FP32/FP16, Schwarz 8^4 blocks, %d MR steps" % (
-                                   "x".join(map(str, dims)), kappa, csw, eps, mr),
+                               "FP64/FP32/FP16, Schwarz 8^4 blocks (FP16, %d link reals), %d MR steps" % (
+                                   "x".join(map(str, dims)), kappa, csw, eps, K_RECON, mr),
                    "dims": list(dims), "tile": list(tile), "schwarz_tile": list(block),
                    "kernel": "wilson dslash f32 recon12, one parity",
                    "dslash_launches_per_step": 3 * groups, "buffer_sets": 3,
