@@ -76,7 +76,10 @@ typedef enum {
 } lqcd_status;
 
 /*
- * Storage precisions. Arithmetic is FP64 for LQCD_F64 and FP32 otherwise.
+ * Storage precisions. Arithmetic is FP64 for LQCD_F64 and FP32 otherwise,
+ * except that the Wilson hops of LQCD_F16 operators (12 or 18 link reals)
+ * form the spin projection in packed FP16 (one rounding of each half-spinor
+ * component) and the colour products as FP16 x FP16 products with FP32 sums.
  * LQCD_HALF is 16-bit fixed point (the paper's "half" format, Section V):
  * integer codes q in [-32767, 32767] standing for q / 32767; link entries are
  * stored so directly (recon 18 or 12), while spinors and the clover term
