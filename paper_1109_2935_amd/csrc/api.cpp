@@ -144,7 +144,6 @@ lqcd_status scratch(lqcd_context *ctx, int slot, size_t bytes, void **ptr) {
 RedScratch red_scratch(lqcd_context *ctx) {
   RedScratch r;
   r.partials = ctx->red_partials;
-  r.counter = ctx->red_counter;
   r.result = ctx->red_result;
   r.max_wg = 1024;
   return r;
@@ -435,11 +434,9 @@ lqcd_status lqcd_context_create(lqcd_context **out) {
   noalloc_init_device(ctx->device);
   lqcd_status s = LQCD_OK;
   if (hipMalloc(&ctx->red_partials, 1024 * kMaxRed * sizeof(double)) != hipSuccess ||
-      hipMalloc(&ctx->red_counter, 64) != hipSuccess ||
       hipMalloc(&ctx->red_result, kMaxRed * sizeof(double)) != hipSuccess ||
       hipHostMalloc(&ctx->red_host, kMaxRed * sizeof(double), hipHostMallocDefault) != hipSuccess)
     s = LQCD_ERR_OUT_OF_MEMORY;
-  if (!s && hipMemset(ctx->red_counter, 0, 64) != hipSuccess) s = LQCD_ERR_DEVICE;
   if (s) {
     (void)hipGetLastError();
     lqcd_context_destroy(ctx);
@@ -457,7 +454,6 @@ lqcd_status lqcd_context_destroy(lqcd_context *ctx) {
     if (p) hipFree(p);
   for (void *p : ctx->retired) hipFree(p);
   if (ctx->red_partials) hipFree(ctx->red_partials);
-  if (ctx->red_counter) hipFree(ctx->red_counter);
   if (ctx->red_result) hipFree(ctx->red_result);
   if (ctx->red_host) hipHostFree(ctx->red_host);
   delete ctx;

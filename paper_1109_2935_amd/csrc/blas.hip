@@ -4,9 +4,12 @@
 // precision; the packed spinor layouts keep each (re, im) pair adjacent, so a
 // field of any layout is such a vector. Arithmetic is done in FP32 (FP64 for
 // FP64 vectors) and every reduction accumulates in FP64: per-thread sums, a
-// wave64 butterfly, the waves of a workgroup through LDS, then the last
-// workgroup to finish (ticket counter) sums the per-workgroup partials in a
-// fixed order. Results are therefore deterministic for a given n.
+// wave64 butterfly, the waves of a workgroup through LDS into one partial per
+// workgroup, then a one-workgroup launch that follows in stream order sums the
+// partials in a fixed order. Results are therefore deterministic for a given
+// n. (A last-workgroup-to-finish sum inside the launch needs a device-scope
+// fence and an atomic ticket per workgroup; on gfx950 that cost about 35 us
+// per 1024 workgroups, as much as streaming two 100 MB vectors.)
 #include <type_traits>
 
 #include "lqcd_internal.h"
@@ -69,14 +72,10 @@ template <typename S> __device__ __forceinline__ void st4(S *p, size_t i, const 
   }
 }
 
-__device__ __forceinline__ double atomic_load_relaxed(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
+// The workgroup's partial sums of NR values: partials[blockIdx.x * NR + k].
 template <int NR>
 __device__ void grid_reduce(double (&v)[NR], RedScratch r) {
   __shared__ double lds[kBT / 64][NR];
-  __shared__ int last;
 #pragma unroll
   for (int k = 0; k < NR; ++k)
 #pragma unroll
@@ -86,41 +85,44 @@ __device__ void grid_reduce(double (&v)[NR], RedScratch r) {
 #pragma unroll
     for (int k = 0; k < NR; ++k) lds[wave][k] = v[k];
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
     for (int k = 0; k < NR; ++k) {
       double t = 0;
       for (int w = 0; w < kBT / 64; ++w) t += lds[w][k];
-      __hip_atomic_store(r.partials + (size_t)blockIdx.x * NR + k, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      r.partials[(size_t)blockIdx.x * NR + k] = t;
     }
-    __threadfence();
-    const unsigned ticket = atomicAdd(r.counter, 1u);
-    last = (ticket == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double acc[NR];
+}
+
+// One workgroup: result[j * NR + k] = the sum over the nblocks workgroups of
+// partials[(w * nrows + j) * NR + k], thread t taking workgroups t, t + kBT,
+// ... in order, then the wave butterfly and the waves in order.
+template <int NR>
+__global__ void __launch_bounds__(kBT) reduce_finish_kernel(const double *partials, int nblocks, int nrows,
+                                                           double *result) {
+  __shared__ double lds[kBT / 64][NR];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = 0; j < nrows; ++j) {
+    double acc[NR];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) acc[k] = 0;
-  for (int w = threadIdx.x; w < (int)gridDim.x; w += kBT)
+    for (int k = 0; k < NR; ++k) acc[k] = 0;
+    for (int w = threadIdx.x; w < nblocks; w += kBT)
 #pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] += atomic_load_relaxed(r.partials + (size_t)w * NR + k);
+      for (int k = 0; k < NR; ++k) acc[k] += partials[((size_t)w * nrows + j) * NR + k];
 #pragma unroll
-  for (int k = 0; k < NR; ++k)
+    for (int k = 0; k < NR; ++k)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
-  __syncthreads();
-  if (lane == 0)
+      for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    __syncthreads();
+    if (lane == 0)
 #pragma unroll
-    for (int k = 0; k < NR; ++k) lds[wave][k] = acc[k];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < NR; ++k) {
-      double t = 0;
-      for (int w = 0; w < kBT / 64; ++w) t += lds[w][k];
-      r.result[k] = t;
-    }
-    atomicExch(r.counter, 0u);
+      for (int k = 0; k < NR; ++k) lds[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int k = 0; k < NR; ++k) {
+        double t = 0;
+        for (int w = 0; w < kBT / 64; ++w) t += lds[w][k];
+        result[j * NR + k] = t;
+      }
   }
 }
 
@@ -394,17 +396,27 @@ template <int LO, int HI, typename F> static hipError_t with_count(int k, F &&f)
   }
 }
 
+// The one-workgroup sum over the nblocks partials of a reducing launch (nr
+// values per row, nrows rows) into red.result, in stream order after it.
+static hipError_t finish_sums(int nr, int nblocks, int nrows, const RedScratch &red, hipStream_t st) {
+  return with_count<1, 16>(nr, [&](auto c) -> hipError_t {
+    hipLaunchKernelGGL((reduce_finish_kernel<decltype(c)::value>), dim3(1), dim3(kBT), 0, st,
+                       (const double *)red.partials, nblocks, nrows, red.result);
+    return hipGetLastError();
+  });
+}
+
 #define T1 std::remove_pointer_t<decltype(t1)>
 #define T2 std::remove_pointer_t<decltype(t2)>
 
-static const RedScratch kNoRed = {nullptr, nullptr, nullptr, 1024};
+static const RedScratch kNoRed = {nullptr, nullptr, 1024};
 
 hipError_t blas_axpby(int px, const void *x, int py, void *y, size_t n, double ar, double ai, double br, double bi,
                       const RedScratch *red, hipStream_t st) {
   const size_t nq = n / 2;
   const int g = grid_for(nq, red ? red->max_wg : 1024);
   const RedScratch r = red ? *red : kNoRed;
-  return dispatch2(px, py, [&](auto t1, auto t2) -> hipError_t {
+  const hipError_t e = dispatch2(px, py, [&](auto t1, auto t2) -> hipError_t {
     if (red)
       hipLaunchKernelGGL((axpby_kernel<T1, T2, true>), dim3(g), dim3(kBT), 0, st, (const T1 *)x, (T2 *)y, nq, ar, ai, br,
                          bi, r);
@@ -412,6 +424,8 @@ hipError_t blas_axpby(int px, const void *x, int py, void *y, size_t n, double a
       hipLaunchKernelGGL((axpby_kernel<T1, T2, false>), dim3(g), dim3(kBT), 0, st, (const T1 *)x, (T2 *)y, nq, ar, ai,
                          br, bi, r);
     return hipGetLastError();});
+  if (e != hipSuccess || !red) return e;
+  return finish_sums(1, g, 1, *red, st);
 }
 
 hipError_t blas_convert(int px, const void *x, int py, void *y, size_t n, double s, hipStream_t st) {
@@ -425,9 +439,10 @@ hipError_t blas_convert(int px, const void *x, int py, void *y, size_t n, double
 hipError_t blas_norm2(int px, const void *x, size_t n, const RedScratch &red, hipStream_t st) {
   const size_t nq = n / 2;
   const int g = grid_for(nq, red.max_wg);
-  return dispatch1(px, [&](auto t1) -> hipError_t {
+  const hipError_t e = dispatch1(px, [&](auto t1) -> hipError_t {
     hipLaunchKernelGGL((norm2_kernel<T1>), dim3(g), dim3(kBT), 0, st, (const T1 *)x, nq, red);
     return hipGetLastError();});
+  return e != hipSuccess ? e : finish_sums(1, g, 1, red, st);
 }
 
 hipError_t blas_cdot(int p, const void *x, const void *y, size_t n, const RedScratch &red, hipStream_t st) {
@@ -443,12 +458,13 @@ hipError_t blas_multi_cdot(int p, const void *const *z, int k, const void *w, si
   for (int j = 0; j < k; ++j) pk.p[j] = z[j];
   const size_t nq = n / 2;
   const int g = grid_for(nq, red.max_wg);
-  return dispatch1(p, [&](auto t1) -> hipError_t {
+  const hipError_t e = dispatch1(p, [&](auto t1) -> hipError_t {
     return with_count<1, 8>(k, [&](auto kc) {
       hipLaunchKernelGGL((multi_cdot_kernel<T1, decltype(kc)::value>), dim3(g), dim3(kBT), 0, st, pk, (const T1 *)w,
                          nq, red);
       return hipGetLastError();
     });});
+  return e != hipSuccess ? e : finish_sums(2 * k, g, 1, red, st);
 }
 
 hipError_t blas_multi_caxpy_dots(int p, const void *const *z, const double *beta, int k, void *w, const void *r,
@@ -463,7 +479,7 @@ hipError_t blas_multi_caxpy_dots(int p, const void *const *z, const double *beta
   }
   const size_t nq = n / 2;
   const int g = grid_for(nq, red.max_wg);
-  return dispatch1(p, [&](auto t1) -> hipError_t {
+  const hipError_t e = dispatch1(p, [&](auto t1) -> hipError_t {
     if (k > 16) {
       hipLaunchKernelGGL((multi_caxpy_dots_kernel<T1, -1>), dim3(g), dim3(kBT), 0, st, pk, (T1 *)w, (const T1 *)r, nq,
                          red);
@@ -474,16 +490,18 @@ hipError_t blas_multi_caxpy_dots(int p, const void *const *z, const double *beta
                          (const T1 *)r, nq, red);
       return hipGetLastError();
     });});
+  return e != hipSuccess ? e : finish_sums(3, g, 1, red, st);
 }
 
 hipError_t blas_gcr_update(int p, void *z, void *r, size_t n, double inv_gamma, double ar, double ai,
                            const RedScratch &red, hipStream_t st) {
   const size_t nq = n / 2;
   const int g = grid_for(nq, red.max_wg);
-  return dispatch1(p, [&](auto t1) -> hipError_t {
+  const hipError_t e = dispatch1(p, [&](auto t1) -> hipError_t {
     hipLaunchKernelGGL((gcr_update_kernel<T1>), dim3(g), dim3(kBT), 0, st, (T1 *)z, (T1 *)r, nq, inv_gamma, ar, ai,
                        red);
     return hipGetLastError();});
+  return e != hipSuccess ? e : finish_sums(1, g, 1, red, st);
 }
 
 hipError_t blas_multi_axpy_acc(int px, void *x, int pp, const void *const *p, const double *chi, int k, size_t n,
@@ -536,10 +554,11 @@ hipError_t blas_cg_update(int px, void *x, const void *p, int pr, void *r, const
                           const RedScratch &red, hipStream_t st) {
   const size_t nq = n / 2;
   const int g = grid_for(nq, red.max_wg);
-  return dispatch2(px, pr, [&](auto t1, auto t2) -> hipError_t {
+  const hipError_t e = dispatch2(px, pr, [&](auto t1, auto t2) -> hipError_t {
     hipLaunchKernelGGL((cg_update_kernel<T1, T2>), dim3(g), dim3(kBT), 0, st, (T1 *)x, (const T1 *)p, (T2 *)r,
                        (const T2 *)q, nq, a, red);
     return hipGetLastError();});
+  return e != hipSuccess ? e : finish_sums(1, g, 1, red, st);
 }
 
 
@@ -577,54 +596,11 @@ __device__ __forceinline__ void group_partials(double (&v)[NR], int R, int src0,
     for (int k = 0; k < NR; ++k) {
       double t = 0;
       for (int w = 0; w < kBT / 64; ++w) t += lds[w][threadIdx.x][k];
-      __hip_atomic_store(partials + ((size_t)blockIdx.x * nrhs + src0 + threadIdx.x) * NR + k, t, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      partials[((size_t)blockIdx.x * nrhs + src0 + threadIdx.x) * NR + k] = t;
     }
-  if ((int)threadIdx.x < R) __threadfence();
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NR; ++k) v[k] = 0;
-}
-
-// After every group: the last workgroup to finish sums each source's partials
-// over the workgroups in order into result[j * NR + k].
-template <int NR>
-__device__ void finish_rows(int nrhs, RedScratch r) {
-  __shared__ double lds[kBT / 64][NR];
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned ticket = atomicAdd(r.counter, 1u);
-    last = (ticket == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = 0; j < nrhs; ++j) {
-    double acc[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] = 0;
-    for (size_t w = threadIdx.x; w < gridDim.x; w += kBT)
-#pragma unroll
-      for (int k = 0; k < NR; ++k) acc[k] += atomic_load_relaxed(r.partials + (w * nrhs + j) * NR + k);
-#pragma unroll
-    for (int k = 0; k < NR; ++k)
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
-    __syncthreads();
-    if (lane == 0)
-#pragma unroll
-      for (int k = 0; k < NR; ++k) lds[wave][k] = acc[k];
-    __syncthreads();
-    if (threadIdx.x == 0)
-      for (int k = 0; k < NR; ++k) {
-        double t = 0;
-        for (int w = 0; w < kBT / 64; ++w) t += lds[w][k];
-        r.result[j * NR + k] = t;
-      }
-  }
-  if (threadIdx.x == 0) atomicExch(r.counter, 0u);
 }
 
 // y_j = a_j x_j + b_j y_j (y not read where b_j = 0); RED: ||y_j||^2 of the stored y.
@@ -657,7 +633,6 @@ __global__ void __launch_bounds__(kBT) mrhs_axpby_kernel(const SX *x, SY *y, int
     }
     if (RED) group_partials<1>(acc, R, g * R, nrhs, r.partials);
   }
-  if (RED) finish_rows<1>(nrhs, r);
 }
 
 // <x_j, y_j> (re, im) per source
@@ -679,7 +654,6 @@ __global__ void __launch_bounds__(kBT) mrhs_cdot_kernel(const S *x, const S *y, 
     }
     group_partials<2>(acc, R, g * R, nrhs, r.partials);
   }
-  finish_rows<2>(nrhs, r);
 }
 
 // x_j += a_j p_j ; r_j -= a_j q_j ; ||r_j||^2 of the stored r (sources with
@@ -712,7 +686,6 @@ __global__ void __launch_bounds__(kBT) mrhs_cg_update_kernel(SX *x, const SX *p,
     }
     group_partials<1>(acc, R, g * R, nrhs, r.partials);
   }
-  finish_rows<1>(nrhs, r);
 }
 
 static int mrhs_grid(int64_t vh, int nrhs, int nr, const RedScratch *red) {
@@ -750,7 +723,7 @@ hipError_t blas_mrhs_axpby(int px, const void *x, int py, void *y, int64_t vh, i
   }
   const dim3 grid(mrhs_grid(vh, nrhs, 1, red));
   const RedScratch r = red ? *red : kNoRed;
-  return dispatch2h(px, py, [&](auto t1, auto t2) -> hipError_t {
+  const hipError_t e = dispatch2h(px, py, [&](auto t1, auto t2) -> hipError_t {
     return dispatch_nsp(nsp, [&](auto ns) -> hipError_t {
       constexpr int NS = decltype(ns)::value;
       if (red)
@@ -762,13 +735,15 @@ hipError_t blas_mrhs_axpby(int px, const void *x, int py, void *y, int64_t vh, i
       return hipGetLastError();
     });
   });
+  if (e != hipSuccess || !red) return e;
+  return finish_sums(1, (int)grid.x, nrhs, *red, st);
 }
 
 hipError_t blas_mrhs_cdot(int p, const void *x, const void *y, int64_t vh, int nsp, int nrhs, const RedScratch &red,
                           hipStream_t st) {
   if (nrhs < 1 || 2 * nrhs > kMaxRed) return hipErrorInvalidValue;
   const dim3 grid(mrhs_grid(vh, nrhs, 2, &red));
-  return dispatch1h(p, [&](auto t1) -> hipError_t {
+  const hipError_t e = dispatch1h(p, [&](auto t1) -> hipError_t {
     return dispatch_nsp(nsp, [&](auto ns) -> hipError_t {
       constexpr int NS = decltype(ns)::value;
       hipLaunchKernelGGL((mrhs_cdot_kernel<T1, NS>), grid, dim3(kBT), 0, st, (const T1 *)x, (const T1 *)y, vh, nrhs,
@@ -776,6 +751,7 @@ hipError_t blas_mrhs_cdot(int p, const void *x, const void *y, int64_t vh, int n
       return hipGetLastError();
     });
   });
+  return e != hipSuccess ? e : finish_sums(2, (int)grid.x, nrhs, red, st);
 }
 
 hipError_t blas_mrhs_cg_update(int px, void *x, const void *p, int pr, void *r, const void *q, int64_t vh, int nsp,
@@ -787,7 +763,7 @@ hipError_t blas_mrhs_cg_update(int px, void *x, const void *p, int pr, void *r, 
     c.b[j] = 0;
   }
   const dim3 grid(mrhs_grid(vh, nrhs, 1, &red));
-  return dispatch2h(px, pr, [&](auto t1, auto t2) -> hipError_t {
+  const hipError_t e = dispatch2h(px, pr, [&](auto t1, auto t2) -> hipError_t {
     return dispatch_nsp(nsp, [&](auto ns) -> hipError_t {
       constexpr int NS = decltype(ns)::value;
       hipLaunchKernelGGL((mrhs_cg_update_kernel<T1, T2, NS>), grid, dim3(kBT), 0, st, (T1 *)x, (const T1 *)p, (T2 *)r,
@@ -795,6 +771,7 @@ hipError_t blas_mrhs_cg_update(int px, void *x, const void *p, int pr, void *r, 
       return hipGetLastError();
     });
   });
+  return e != hipSuccess ? e : finish_sums(1, (int)grid.x, nrhs, red, st);
 }
 
 // ---------------------------------------------------------------------------

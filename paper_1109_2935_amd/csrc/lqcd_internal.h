@@ -14,10 +14,9 @@
 struct lqcd_context {
   int device = 0;
   std::string last_error;
-  // reduction scratch: per-workgroup partials, a ticket counter and the result
+  // reduction scratch: per-workgroup partials and the result
   double *red_partials = nullptr;
   size_t red_partials_count = 0;
-  unsigned *red_counter = nullptr;
   double *red_result = nullptr;
   double *red_host = nullptr;  // pinned
   // general scratch vectors, grown on demand and reused between calls
@@ -174,9 +173,8 @@ hipError_t launch_staggered(const StagLaunch &s, hipStream_t st);
 // stored as 2n reals in precision `prec`.
 
 struct RedScratch {
-  double *partials;
-  unsigned *counter;
-  double *result;
+  double *partials;  // one set of values per workgroup of the reducing launch
+  double *result;    // their sum, written by a one-workgroup launch that follows it
   int max_wg;
 };
 
