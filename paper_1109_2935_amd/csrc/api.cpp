@@ -144,17 +144,15 @@ lqcd_status scratch(lqcd_context *ctx, int slot, size_t bytes, void **ptr) {
 RedScratch red_scratch(lqcd_context *ctx) {
   RedScratch r;
   r.partials = ctx->red_partials;
-  r.result = ctx->red_result;
+  r.result = ctx->red_host_dev;
   r.max_wg = 1024;
   return r;
 }
 
+// The finishing launch of a reduction writes its result straight into pinned
+// host memory, so reading it back is one stream synchronisation (no copy).
 lqcd_status read_result(lqcd_context *ctx, hipStream_t st, int n, double *out) {
-  lqcd_status s = hip_check(ctx, hipMemcpyAsync(ctx->red_host, ctx->red_result, n * sizeof(double),
-                                                hipMemcpyDeviceToHost, st),
-                            "reduction result copy");
-  if (s) return s;
-  s = hip_check(ctx, hipStreamSynchronize(st), "stream synchronize");
+  const lqcd_status s = hip_check(ctx, hipStreamSynchronize(st), "stream synchronize");
   if (s) return s;
   for (int i = 0; i < n; ++i) out[i] = ctx->red_host[i];
   return LQCD_OK;
@@ -434,9 +432,11 @@ lqcd_status lqcd_context_create(lqcd_context **out) {
   noalloc_init_device(ctx->device);
   lqcd_status s = LQCD_OK;
   if (hipMalloc(&ctx->red_partials, 1024 * kMaxRed * sizeof(double)) != hipSuccess ||
-      hipMalloc(&ctx->red_result, kMaxRed * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(&ctx->red_host, kMaxRed * sizeof(double), hipHostMallocDefault) != hipSuccess)
+      hipHostMalloc(&ctx->red_host, kMaxRed * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess)
     s = LQCD_ERR_OUT_OF_MEMORY;
+  if (!s && hipHostGetDevicePointer((void **)&ctx->red_host_dev, ctx->red_host, 0) != hipSuccess)
+    s = LQCD_ERR_DEVICE;
   if (s) {
     (void)hipGetLastError();
     lqcd_context_destroy(ctx);
@@ -454,7 +454,6 @@ lqcd_status lqcd_context_destroy(lqcd_context *ctx) {
     if (p) hipFree(p);
   for (void *p : ctx->retired) hipFree(p);
   if (ctx->red_partials) hipFree(ctx->red_partials);
-  if (ctx->red_result) hipFree(ctx->red_result);
   if (ctx->red_host) hipHostFree(ctx->red_host);
   delete ctx;
   return LQCD_OK;

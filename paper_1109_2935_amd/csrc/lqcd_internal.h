@@ -14,11 +14,12 @@
 struct lqcd_context {
   int device = 0;
   std::string last_error;
-  // reduction scratch: per-workgroup partials and the result
+  // reduction scratch: per-workgroup partials, and the result in pinned host
+  // memory (red_host; red_host_dev is its device address)
   double *red_partials = nullptr;
   size_t red_partials_count = 0;
-  double *red_result = nullptr;
-  double *red_host = nullptr;  // pinned
+  double *red_host = nullptr;
+  double *red_host_dev = nullptr;
   // general scratch vectors, grown on demand and reused between calls
   std::vector<void *> scratch;
   std::vector<size_t> scratch_bytes;
