@@ -91,15 +91,17 @@ def test_gcr_fp64_matches_oracle(ctx, precond, orth):
         assert abs(hist[k] - ref) <= 1e-10 * ref, (k, hist[k], ref)
 
 
-@pytest.mark.parametrize("kprec", [2, 3])
-def test_gcr_dd_mixed_precision(ctx, kprec):
-    """FP64 restarts, FP32 Krylov, FP16/BF16 Schwarz K: FP64 residual 1e-10."""
+@pytest.mark.parametrize("kprec,krecon", [(2, 12), (3, 12), (2, 18)])
+def test_gcr_dd_mixed_precision(ctx, kprec, krecon):
+    """FP64 restarts, FP32 Krylov, FP16/BF16 Schwarz K (12 or 18 link reals):
+    FP64 residual 1e-10."""
     dims, kappa, csw, block = (16, 8, 8, 16), 0.124, 1.0, (8, 8, 8, 8)
-    U, b, o = wilson_system(ctx, dims, kappa, csw, 0.25, 301, 302, [0, 1, kprec], tile=block)
+    U, b, o = wilson_system(ctx, dims, kappa, csw, 0.25, 301, 302, [0, 1], tile=block)
+    kop = ops.wilson_clover(ctx, U, dims, kappa, csw, kprec, krecon, tile=block)
     bp = o[0].import_spinor(b, -1)
     x = o[0].spinor(full=True)
     prm = ops.gcr_params(1e-10, k_max=16, delta=1e-3, precond=L.LQCD_PRECOND_SCHWARZ, block=block, mr_steps=8)
-    st, info = L.lqcd_gcr_solve(ctx, o[0].op, o[1].op, o[kprec].op, prm, x, bp)
+    st, info = L.lqcd_gcr_solve(ctx, o[0].op, o[1].op, kop.op, prm, x, bp)
     assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
     assert info.true_residual <= 1e-10
     res, _ = oracle_residual(dims, U, kappa, csw, np_of(o[0].export_spinor(x, -1)), b)
