@@ -296,7 +296,14 @@ template <typename R> __device__ __forceinline__ void third_row(Link<R> &u) {
 }
 
 __device__ __forceinline__ void sincos_r(double a, double *s, double *c) { sincos(a, s, c); }
-__device__ __forceinline__ void sincos_r(float a, float *s, float *c) { sincosf(a, s, c); }
+// FP32: the hardware sine and cosine, which take the angle in revolutions (the
+// stored angles lie in (-pi, pi], inside their domain); about 1e-6 absolute,
+// below the FP32 storage rounding of the other link reals' products.
+__device__ __forceinline__ void sincos_r(float a, float *s, float *c) {
+  const float t = a * 0.159154943091895336f;  // 1 / (2 pi)
+  *s = __builtin_amdgcn_sinf(t);
+  *c = __builtin_amdgcn_cosf(t);
+}
 
 template <int RECON, typename R> __device__ __forceinline__ Link<R> unpack_link(const R *v) {
   Link<R> u;

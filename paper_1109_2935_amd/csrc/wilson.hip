@@ -416,15 +416,16 @@ __device__ __forceinline__ void wilson_dir(const WArgs<S> &a, const Site &x, int
   }
 }
 
-// Where the pipelined hops pay (measured at 32^3x64): FP32 and 16-bit
-// storage with 12 or 18 link reals, and the FP64 hopping term with 12 (257 ->
-// 222 us). FP64 Schur kernels and the FP64 recon-18 hop spill with them, recon
-// 8's reconstruction makes the pipelined form slower, and the 16-bit xpay-only
-// kernel (W_XPAY) spills.
+// Where the pipelined hops pay (measured at 32^3x64): FP32 storage with 18,
+// 12 or 8 link reals (8: since the rebuild takes the hardware sine and cosine,
+// 110.5 -> 105.8 us), 16-bit storage with 12 or 18, and the FP64 hopping term
+// with 12 (257 -> 222 us). FP64 Schur kernels and the FP64 recon-18 hop spill
+// with them, and the 16-bit xpay-only kernel (W_XPAY) spills.
 template <typename S, int RECON, int MODE> constexpr bool pipelined_hops() {
   if constexpr (std::is_same<S, double>::value) return MODE == W_HOP && RECON == 12;
   if constexpr (is_fixed<S>()) return false;  // the neighbour's norm is read with its codes
-  return RECON != 8 && (sizeof(S) == 4 || MODE != W_XPAY);
+  if constexpr (sizeof(S) == 4) return true;
+  return RECON != 8 && MODE != W_XPAY;
 }
 
 // Apply the hop held in HA, then refill HA with the hop two ahead; the other
