@@ -261,7 +261,9 @@ lqcd_status schur_apply(lqcd_context *ctx, const OpInfo &info, const Geom &g, vo
 // launches and an update, with work vectors from scratch slots
 // [slot0, slot0+4); forms 1 and 2 run every MR step of a block in one
 // workgroup with the block in LDS (blocks equal to the tiles, 16-bit
-// storage), x in memory (1) or in registers (2).
+// storage), x in memory (1) or in registers (2); forms 3 and 4 are 1 and 2
+// with twice the threads and half the sites per thread (blocks with at least
+// two sites per thread of 512; elsewhere they run as 1 and 2).
 static lqcd_status schwarz_form(lqcd_context *ctx, const OpInfo &info, const Geom &g, const lqcd_schwarz_params *prm,
                                 void *out, const void *in, int slot0, hipStream_t st, int form) {
   const lqcd_operator *op = info.op;
@@ -278,7 +280,8 @@ static lqcd_status schwarz_form(lqcd_context *ctx, const OpInfo &info, const Geo
   bl.omega = omega;
   bl.steps = prm->mr_steps;
   bl.x = out;
-  bl.xreg = form == 2;
+  bl.xreg = form == 2 || form == 4;
+  bl.wide = form >= 3 && sap_block_wide_fits(g.Vt2);
   void *r = nullptr, *q = nullptr, *t = nullptr, *part = nullptr;
   if (form == 0 || prm->cycles > 0) {
     if ((s = scratch(ctx, slot0, sb, &r)) || (s = scratch(ctx, slot0 + 1, sb, &q)) ||
@@ -368,14 +371,16 @@ lqcd_status schwarz_apply(lqcd_context *ctx, const OpInfo &info, const lqcd_schw
   int form = 0;
   if (schwarz_block_form_fits(info, g)) {
     // the forms give the same result; the autotuner keeps the fastest, and
-    // LQCD_SCHWARZ_FORM=0, 1 or 2 fixes the choice
+    // LQCD_SCHWARZ_FORM=0 .. 4 fixes the choice
     const char *f = std::getenv("LQCD_SCHWARZ_FORM");
-    if (f && f[0] >= '0' && f[0] <= '2' && f[1] == 0) {
+    if (f && f[0] >= '0' && f[0] <= '4' && f[1] == 0) {
       form = f[0] - '0';
     } else {
       const std::string key = "schwarz p" + std::to_string(info.prec) + " r" + std::to_string(info.recon) + " " +
                               geom_key(g) + " m" + std::to_string(prm->mr_steps) + " c" + std::to_string(prm->cycles);
-      form = tune_pick(ctx, key, {2, 1, 0}, 2, out != in, st, [&](int c) {
+      std::vector<int> cands = {2, 1, 0};
+      if (sap_block_wide_fits(info.g.Vt2)) cands = {4, 3, 2, 1, 0};
+      form = tune_pick(ctx, key, cands, 2, out != in, st, [&](int c) {
         return schwarz_form(ctx, info, g, prm, out, in, slot0, st, c) == LQCD_OK ? hipSuccess : hipErrorUnknown;
       });
     }

@@ -128,9 +128,11 @@ struct SapLaunch {
   int steps;
   int first;
   int xreg;  // x kept in registers (else read and written in memory each step)
+  int wide;  // twice the threads, half the sites per thread (sap_block_wide_fits)
 };
 hipError_t launch_sap_block(const SapLaunch &l, hipStream_t st);
 int sap_block_spt(int vt2);  // sites per thread of that launch; 0: blocks of vt2 sites do not fit
+bool sap_block_wide_fits(int vt2);
 
 hipError_t launch_clover_apply(const Geom &g, int prec, void *out, const void *in, const void *clov, int nrhs,
                                hipStream_t st);

@@ -1076,8 +1076,9 @@ __device__ __forceinline__ void sap_clover(const S *__restrict__ clov, int64_t v
 // One workgroup per block (blockIdx.x: the block's tile, or the j-th tile of
 // one colour); SPT sites per thread and parity, site k = p * blockDim.x + tid.
 // XREG: x stays in registers (else it is read and written in memory each step).
-template <typename S, int RECON, int SPT, bool XREG>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) sap_block_kernel(SapArgs<S> a) {
+// NT: the most threads per workgroup (512, or 1024 for the wide launches).
+template <typename S, int RECON, int SPT, bool XREG, int NT>
+__global__ void __launch_bounds__(NT) sap_block_kernel(SapArgs<S> a) {
   extern __shared__ uint2 sap_lds[];  // the block's spinor (and norms), then the segment sums
   const int vt2 = a.vt2, nt = blockDim.x, tid = threadIdx.x;
   double *seg = reinterpret_cast<double *>(reinterpret_cast<char *>(sap_lds) + sap_lds_bytes(vt2, is_fixed<S>()) -
@@ -1237,7 +1238,11 @@ int sap_block_spt(int vt2) {
   return 0;
 }
 
-template <typename S, int RECON, int SPT, bool XREG>
+// The wide launch: twice the threads (up to 1024) with half the sites each,
+// where a block has at least two sites per thread of the 512-thread launch.
+bool sap_block_wide_fits(int vt2) { return sap_block_spt(vt2) >= 2; }
+
+template <typename S, int RECON, int SPT, bool XREG, int NT>
 static hipError_t launch_sap4(const SapLaunch &l, hipStream_t st) {
   SapArgs<S> a;
   a.x = (S *)l.x;
@@ -1261,28 +1266,36 @@ static hipError_t launch_sap4(const SapLaunch &l, hipStream_t st) {
   const size_t lds = sap_lds_bytes(l.g.Vt2, is_fixed<S>());
   static bool attr_set = false;  // per instantiation
   if (!attr_set) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sap_block_kernel<S, RECON, SPT, XREG>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sap_block_kernel<S, RECON, SPT, XREG, NT>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              (int)sap_lds_bytes(kSapMaxSites, is_fixed<S>()));
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   const int nblocks = launch_sites(l.g) / l.g.Vt2;
-  hipLaunchKernelGGL((sap_block_kernel<S, RECON, SPT, XREG>), dim3(nblocks), dim3(l.g.Vt2 / SPT), lds, st, a);
+  hipLaunchKernelGGL((sap_block_kernel<S, RECON, SPT, XREG, NT>), dim3(nblocks), dim3(l.g.Vt2 / SPT), lds, st, a);
   return hipGetLastError();
 }
 
-template <typename S, int RECON, int SPT>
+template <typename S, int RECON, int SPT, int NT>
 static hipError_t launch_sap3(const SapLaunch &l, hipStream_t st) {
-  return l.xreg ? launch_sap4<S, RECON, SPT, true>(l, st) : launch_sap4<S, RECON, SPT, false>(l, st);
+  return l.xreg ? launch_sap4<S, RECON, SPT, true, NT>(l, st) : launch_sap4<S, RECON, SPT, false, NT>(l, st);
 }
 
 template <typename S, int RECON>
 static hipError_t launch_sap2(const SapLaunch &l, hipStream_t st) {
-  switch (sap_block_spt(l.g.Vt2)) {
-    case 1: return launch_sap3<S, RECON, 1>(l, st);
-    case 2: return launch_sap3<S, RECON, 2>(l, st);
-    case 4: return launch_sap3<S, RECON, 4>(l, st);
+  const int spt = sap_block_spt(l.g.Vt2);
+  if (l.wide) {
+    switch (spt) {
+      case 2: return launch_sap3<S, RECON, 1, 1024>(l, st);
+      case 4: return launch_sap3<S, RECON, 2, 1024>(l, st);
+    }
+    return hipErrorInvalidValue;
+  }
+  switch (spt) {
+    case 1: return launch_sap3<S, RECON, 1, 512>(l, st);
+    case 2: return launch_sap3<S, RECON, 2, 512>(l, st);
+    case 4: return launch_sap3<S, RECON, 4, 512>(l, st);
   }
   return hipErrorInvalidValue;
 }

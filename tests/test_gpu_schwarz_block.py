@@ -1,6 +1,7 @@
-"""The Schwarz preconditioner's block-resident form (one workgroup per block,
-the block's spinor in LDS) against the form of separate launches, and both
-against the FP64 oracle.
+"""The Schwarz preconditioner's block-resident forms (one workgroup per block,
+the block's spinor in LDS; x in memory or in registers; 512 threads, or twice
+the threads with half the sites each) against the form of separate launches,
+and all against the FP64 oracle.
 
 The two forms take the same operations in the same order (the same roundings to
 the storage format and the same order of the FP64 block sums of <q,r> and
@@ -77,9 +78,9 @@ def test_block_form_matches_launches(ctx, monkeypatch, case, cycles, prec, recon
     keep = inp.clone()
     steps = 8 if cycles == 0 else 4
     prm = ops.schwarz_params(block, steps, cycles)
-    outs = [run_form(ctx, monkeypatch, o, prm, inp, f) for f in (0, 1, 2)]
+    outs = [run_form(ctx, monkeypatch, o, prm, inp, f) for f in (0, 1, 2, 3, 4)]
     assert torch.equal(inp, keep)  # the input is left as it was
-    for f in (1, 2):
+    for f in (1, 2, 3, 4):
         a, b = outs[0], outs[f]
         if prec != 4:  # (a fixed-point code of -1 is a value; an unwritten norm shows as NaN below)
             assert int((b.view(torch.int16) == -1).sum()) == 0, f
