@@ -665,7 +665,8 @@ def main():
     del reps, sets
     # the FP16 Schwarz preconditioner (8 MR steps on the 8^4 blocks) in each of
     # its forms: 0 separate launches per MR step, 1 and 2 one workgroup per
-    # block with the block in LDS (x in memory / in registers). Bytes: the
+    # block with the block in LDS (x in memory / in registers), 3 and 4 the
+    # same with 1024 threads of two sites each instead of 512 of four. Bytes: the
     # block form's algorithmic traffic per even site, r read once, then per MR
     # step the links of both half steps and both clover blocks, x written once
     # (x read and written each step in form 1 adds 96 bytes per step), for
@@ -677,7 +678,7 @@ def main():
         reps = [ko, ko.replica(), ko.replica()]
         ksets = [(r, r.import_spinor(b, 0), r.spinor()) for r in reps]
         k_bytes = vh * (48 + mr * (2 * 8 * 2 * krec + 2 * 144) + 48)
-        for form in (0, 1, 2):
+        for form in (0, 1, 2, 3, 4):
             os.environ["LQCD_SCHWARZ_FORM"] = str(form)
             dk = time_rotating(torch, [lambda r=r, i=i, q=q: L.lqcd_schwarz_precond(ctx, r.op, kprm, q, i)
                                        for r, i, q in ksets], 30)
