@@ -34,7 +34,7 @@ WILSON_REALS = {18: 192, 12: 144, 8: 112}  # in 24 + out 24 + 8 links per output
 # WRITE_SIZE scaled by the same counters on a 2 GiB device copy (summary under
 # profiles/). Valid only for the kernel sources it was measured on: their hash
 # is checked at run time and the traffic is reported as null when they differ.
-PROFILED_TRAFFIC = {"sources_sha1": "6d228b8627b0e335f759cc7e821722aff0f3307c", "bytes_per_launch": 662.8e6}
+PROFILED_TRAFFIC = {"sources_sha1": "d723e502af221fefc3ae477560ba39812b96399a", "bytes_per_launch": 662.6e6}
 
 
 def kernel_sources_sha1():
