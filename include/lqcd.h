@@ -456,8 +456,10 @@ lqcd_status lqcd_gcr_solve(lqcd_context *ctx, const lqcd_operator *op_hi,
  *   lattice through CG on the normal equations of Mhat (x, b packed FULL);
  * kind = LQCD_CG_STAG_NORMAL: solves N_e x_e = b_e on even sites (eq. (4)
  *   with one shift sigma = 0; x, b packed single-parity even).
- * op_sloppy may be NULL (pure op_hi). x holds the starting guess on entry
- * (zero for a cold start) and the solution on return.
+ * op_sloppy may be NULL (pure op_hi). With an FP16 or BF16 op_sloppy and
+ * kind STAG_NORMAL (one source), the iteration's vectors are kept in FP32 and
+ * only the operator's input and output are 16-bit. x holds the starting guess
+ * on entry (zero for a cold start) and the solution on return.
  */
 lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_hi,
                           const lqcd_operator *op_sloppy, const lqcd_cg_params *params, void *x,

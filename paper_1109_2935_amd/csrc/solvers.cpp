@@ -624,18 +624,27 @@ extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
     *prm->record_count = 0;
   }
   const bool half = lo.prec == LQCD_F16 || lo.prec == LQCD_BF16;
+  // 16-bit sloppy operator in the plain CG: the iteration's vectors (xs, rs,
+  // p, q) stay in FP32, and only the operator's input and output are 16-bit
+  const bool mid = half && !cgne;
+  const int vp = mid ? (int)LQCD_F32 : lo.prec;
+  const size_t vb = mid ? site_block_bytes(LQCD_F32, lo.nsp, lo.vh, true) : lo.spinor_bytes;
   const double delta = prm->delta_reliable;
-  void *bhat, *r, *y, *tmp_hi, *rs, *xs, *p, *q, *t, *tmp_lo;
+  void *bhat, *r, *y, *tmp_hi, *rs, *xs, *p, *q, *t, *tmp_lo, *p16 = nullptr, *q16 = nullptr;
   TRY(S.vec(hi.spinor_bytes, &bhat));
   TRY(S.vec(hi.spinor_bytes, &r));
   TRY(S.vec(hi.spinor_bytes, &y));
   TRY(S.vec(hi.spinor_bytes, &tmp_hi));
-  TRY(S.vec(lo.spinor_bytes, &rs));
-  TRY(S.vec(lo.spinor_bytes, &xs));
-  TRY(S.vec(lo.spinor_bytes, &p));
-  TRY(S.vec(lo.spinor_bytes, &q));
+  TRY(S.vec(vb, &rs));
+  TRY(S.vec(vb, &xs));
+  TRY(S.vec(vb, &p));
+  TRY(S.vec(vb, &q));
   TRY(S.vec(lo.spinor_bytes, &t));
   TRY(S.vec(lo.spinor_bytes, &tmp_lo));
+  if (mid) {
+    TRY(S.vec(lo.spinor_bytes, &p16));
+    TRY(S.vec(lo.spinor_bytes, &q16));
+  }
   RedScratch red = S.red();
   CgOps A{&S, &hi, &lo, kind, tmp_hi, tmp_lo};
   lqcd_solve_info inf{};
@@ -670,8 +679,8 @@ extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
   double rr_true;
   TRY(true_residual(&rr_true));
   double sc = half ? unit_rms_scale(std::sqrt(rr_true), 2 * n) : 1.0;
-  TRY(S.hip(blas_convert(hi.prec, r, lo.prec, rs, n, sc, S.st), "convert"));
-  TRY(S.hip(hipMemsetAsync(xs, 0, lo.spinor_bytes, S.st), "memset"));
+  TRY(S.hip(blas_convert(hi.prec, r, vp, rs, n, sc, S.st), "convert"));
+  TRY(S.hip(hipMemsetAsync(xs, 0, vb, S.st), "memset"));
   double rr = rr_true * sc * sc;  // in scaled units
   double pp = 0;
   if (cgne) {
@@ -680,7 +689,7 @@ extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
     TRY(S.result(1, &pp));
     inf.matvecs++;
   } else {
-    TRY(S.hip(hipMemcpyAsync(p, rs, lo.spinor_bytes, hipMemcpyDeviceToDevice, S.st), "copy"));
+    TRY(S.hip(hipMemcpyAsync(p, rs, vb, hipMemcpyDeviceToDevice, S.st), "copy"));
   }
   double maxrr = rr_true;
   const double stop = prm->tol * prm->tol * bn2;
@@ -689,20 +698,26 @@ extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
   int it = 0;
   while (!converged && it < prm->max_iter) {
     double a;
-    TRY(A.apply(lo, q, p, 0, tmp_lo));
+    if (mid) {
+      TRY(S.hip(blas_convert(vp, p, lo.prec, p16, n, 1.0, S.st), "convert"));
+      TRY(A.apply(lo, q16, p16, 0, tmp_lo));
+      TRY(S.hip(blas_convert(lo.prec, q16, vp, q, n, 1.0, S.st), "convert"));
+    } else {
+      TRY(A.apply(lo, q, p, 0, tmp_lo));
+    }
     inf.matvecs++;
     if (cgne) {
       if (!(pp > 0)) { status = set_error(ctx, LQCD_ERR_BREAKDOWN, "CGNE breakdown: |p| = 0"); break; }
       a = rr / pp;
     } else {
       double d[2];
-      TRY(S.hip(blas_cdot(lo.prec, p, q, n, red, S.st), "dot"));
+      TRY(S.hip(blas_cdot(vp, p, q, n, red, S.st), "dot"));
       TRY(S.result(2, d));
       if (!(d[0] > 0)) { status = set_error(ctx, LQCD_ERR_BREAKDOWN, "CG breakdown: <p, A p> <= 0"); break; }
       a = rr / d[0];
     }
     double rr_new;
-    TRY(S.hip(blas_cg_update(lo.prec, xs, p, lo.prec, rs, q, n, a, red, S.st), "cg update"));
+    TRY(S.hip(blas_cg_update(vp, xs, p, vp, rs, q, n, a, red, S.st), "cg update"));
     TRY(S.result(1, &rr_new));
     ++it;
     double rr_new_true = rr_new / (sc * sc);
@@ -724,14 +739,14 @@ extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
     const bool trigger = rr_new_true <= stop || (mixed && rr_new_true < delta * delta * maxrr);
     if (trigger) {
       // x += xs / sc ; r = bhat - A x ; restart the sloppy residual from it
-      TRY(S.hip(blas_axpby(lo.prec, xs, hi.prec, xe, n, 1.0 / sc, 0.0, 1.0, 0.0, nullptr, S.st), "x update"));
+      TRY(S.hip(blas_axpby(vp, xs, hi.prec, xe, n, 1.0 / sc, 0.0, 1.0, 0.0, nullptr, S.st), "x update"));
       TRY(true_residual(&rr_new_true));
       inf.restarts++;
       if (verbose()) fprintf(stderr, "cg reliable update %d true |r|/|b| %.3e\n", inf.restarts, std::sqrt(rr_new_true) / bn);
       const double sc_new = half ? unit_rms_scale(std::sqrt(rr_new_true), 2 * n) : 1.0;
-      TRY(S.hip(blas_convert(hi.prec, r, lo.prec, rs, n, sc_new, S.st), "convert"));
-      TRY(S.hip(hipMemsetAsync(xs, 0, lo.spinor_bytes, S.st), "memset"));
-      if (sc_new != sc) TRY(S.hip(blas_convert(lo.prec, p, lo.prec, p, n, sc_new / sc, S.st), "rescale"));
+      TRY(S.hip(blas_convert(hi.prec, r, vp, rs, n, sc_new, S.st), "convert"));
+      TRY(S.hip(hipMemsetAsync(xs, 0, vb, S.st), "memset"));
+      if (sc_new != sc) TRY(S.hip(blas_convert(vp, p, vp, p, n, sc_new / sc, S.st), "rescale"));
       rr *= (sc_new / sc) * (sc_new / sc);
       sc = sc_new;
       rr_new = rr_new_true * sc * sc;
@@ -748,14 +763,14 @@ extern "C" lqcd_status lqcd_cg_solve(lqcd_context *ctx, const lqcd_operator *op_
       TRY(S.hip(blas_axpby(lo.prec, t, lo.prec, p, n, 1.0, 0.0, bta, 0.0, &red, S.st), "xpay"));
       TRY(S.result(1, &pp));
     } else {
-      TRY(S.hip(blas_axpby(lo.prec, rs, lo.prec, p, n, 1.0, 0.0, bta, 0.0, nullptr, S.st), "xpay"));
+      TRY(S.hip(blas_axpby(vp, rs, vp, p, n, 1.0, 0.0, bta, 0.0, nullptr, S.st), "xpay"));
     }
     rr = rr_new;
     maxrr = std::max(maxrr, rr_new / (sc * sc));
   }
   if (!converged) {
     // fold in the last sloppy correction
-    TRY(S.hip(blas_axpby(lo.prec, xs, hi.prec, xe, n, 1.0 / sc, 0.0, 1.0, 0.0, nullptr, S.st), "x update"));
+    TRY(S.hip(blas_axpby(vp, xs, hi.prec, xe, n, 1.0 / sc, 0.0, 1.0, 0.0, nullptr, S.st), "x update"));
   }
   double tres;
   if (cgne) {
