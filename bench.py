@@ -317,8 +317,8 @@ def learned_solve(args, torch, L, ops, ctx, o64, o32, o32b, bp, block, mr, dims)
 
 def staggered_workload(args, torch, L, ops, ctx):
     """48^3x96 improved staggered (m = 0.01, eps = 0.2): dslash bandwidth per
-    precision and long-link format, reliable-update CG (FP32 / FP16 sloppy)
-    against plain FP64 CG."""
+    precision and long-link format, reliable-update CG (FP32 / FP16 sloppy
+    operator) against plain FP64 CG."""
     import numpy as np
     import synth
     dims, mass = (48, 48, 48, 96), 0.01
@@ -359,7 +359,8 @@ def staggered_workload(args, torch, L, ops, ctx):
         out["cg_" + name] = solve_record(med, allt, info)
         log("staggered CG %s: %d it, %.3f s, res %.2e" % (name, info.iters, med, info.true_residual))
     out["multishift"] = multishift_workload(L, ops, ctx, hi, inst[(1, 12)], b, mass)
-    out["speedup_fp32_sloppy_vs_fp64"] = round(out["cg_fp64"]["seconds"] / out["cg_fp32_sloppy"]["seconds"], 2)
+    for name in ("fp32_sloppy", "fp16_sloppy"):
+        out["speedup_%s_vs_fp64" % name] = round(out["cg_fp64"]["seconds"] / out["cg_" + name]["seconds"], 2)
     return out
 
 
