@@ -777,6 +777,17 @@ def main():
         if gold is not None:
             tts["fp64_cg"]["rel_error_vs_oracle"] = rel_error_sampled(o64, cg.x, gold)
         log("FP64 CGNE: %d iterations, %.3f s, true residual %.2e" % (info.iters, med, info.true_residual))
+        # CGNE with reliable updates: FP32 or FP16 sloppy iterations (recon 12), FP64 updates
+        for sp in (1, 2):
+            def cg_mixed(lo=inst[(sp, 12)]):
+                x = o64.spinor(full=True)
+                st, info = L.lqcd_cg_solve(ctx, o64.op, lo.op, ops.cg_params(1e-10, 20000, 0.1), x, bp)
+                assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+                return st, info
+            med, allt, info = timed_solves(args.solves, cg_mixed)
+            tts["cgne_%s_sloppy" % PREC_NAME[sp]] = solve_record(med, allt, info)
+            log("CGNE FP64/%s: %d iterations, %d reliable updates, %.3f s, true residual %.2e" % (
+                PREC_NAME[sp].upper(), info.iters, info.restarts, med, info.true_residual))
     # GCR-DD with the multiplicative Schwarz K (two block colours), FP16, same blocks
     sap_mr, sap_cycles = 4, 3
     sprm = ops.gcr_params(1e-10, k_max=16, delta=1e-3, max_iter=2000, precond=L.LQCD_PRECOND_SCHWARZ,
