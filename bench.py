@@ -499,7 +499,8 @@ def batched_solve(args, torch, L, ops, ctx, tile):
     24^3x48 (kappa 0.122) with FP32 sloppy iterations and FP64 reliable
     updates, all sources in one multi-source solve (each operator application
     one launch over the 12 sources) against 12 single-source solves in
-    sequence; a warm-up, then the median of 3 of each."""
+    sequence; a warm-up, then the median of 3 of each. The same with FP16
+    sloppy iterations under "fp16_sloppy"."""
     import numpy as np
     import synth
     dims = (24, 24, 24, 48)
@@ -507,38 +508,45 @@ def batched_solve(args, torch, L, ops, ctx, tile):
     Ud = torch.from_numpy(U).cuda()
     t = tile  # the layout tile tuned for the FP32 hop with 12 sources
     hi = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, 0, 18, tile=t, U_device=Ud)
-    lo = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, 1, 12, tile=t, U_device=Ud)
     srcs = np.stack([synth.point_source(dims, sc // 3, sc % 3) for sc in range(12)])
     bp = hi.import_spinor(srcs, -1, nrhs=12)
     singles = [hi.import_spinor(srcs[j], -1) for j in range(12)]
 
-    def batch():
-        x = hi.spinor(full=True, nrhs=12)
-        prm = ops.cg_params(1e-10, 20000, 0.1, nrhs=12)
-        st, info = L.lqcd_cg_solve(ctx, hi.op, lo.op, prm, x, bp)
-        assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
-        return st, info
+    def run(sp):
+        lo = ops.wilson_clover(ctx, U, dims, 0.122, 1.0, sp, 12, tile=t, U_device=Ud)
 
-    def sequential():
-        tot, its, worst = 0.0, [], 0.0
-        for bj in singles:
-            x = hi.spinor(full=True)
-            st, info = L.lqcd_cg_solve(ctx, hi.op, lo.op, ops.cg_params(1e-10, 20000, 0.1), x, bj)
+        def batch():
+            x = hi.spinor(full=True, nrhs=12)
+            prm = ops.cg_params(1e-10, 20000, 0.1, nrhs=12)
+            st, info = L.lqcd_cg_solve(ctx, hi.op, lo.op, prm, x, bp)
             assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
-            tot += info.seconds
-            its.append(info.iters)
-            worst = max(worst, info.true_residual)
-        return tot, its, worst
+            return st, info
 
-    med, allt, info = timed_solves(3, batch)
-    sequential()
-    seq = sorted(sequential() for _ in range(3))[1]
-    log("12 point sources on 24^3x48, CGNE FP32/FP64: one multi-source solve %.3f s (%d iterations, worst residual "
-        "%.2e); 12 single-source solves %.3f s" % (med, info.iters, info.true_residual, seq[0]))
-    return {"batched_seconds": round(med, 4), "batched_seconds_runs": allt, "batched_iters": info.iters,
-            "batched_updates": info.restarts, "batched_worst_true_residual": info.true_residual,
-            "sequential_seconds": round(seq[0], 4), "sequential_iters": seq[1],
-            "sequential_worst_true_residual": seq[2], "speedup_vs_sequential": round(seq[0] / med, 2)}
+        def sequential():
+            tot, its, worst = 0.0, [], 0.0
+            for bj in singles:
+                x = hi.spinor(full=True)
+                st, info = L.lqcd_cg_solve(ctx, hi.op, lo.op, ops.cg_params(1e-10, 20000, 0.1), x, bj)
+                assert st == L.LQCD_OK, L.lqcd_last_error(ctx)
+                tot += info.seconds
+                its.append(info.iters)
+                worst = max(worst, info.true_residual)
+            return tot, its, worst
+
+        med, allt, info = timed_solves(3, batch)
+        sequential()
+        seq = sorted(sequential() for _ in range(3))[1]
+        log("12 point sources on 24^3x48, CGNE %s/FP64: one multi-source solve %.3f s (%d iterations, worst "
+            "residual %.2e); 12 single-source solves %.3f s" % (PREC_NAME[sp].upper(), med, info.iters,
+                                                                info.true_residual, seq[0]))
+        return {"batched_seconds": round(med, 4), "batched_seconds_runs": allt, "batched_iters": info.iters,
+                "batched_updates": info.restarts, "batched_worst_true_residual": info.true_residual,
+                "sequential_seconds": round(seq[0], 4), "sequential_iters": seq[1],
+                "sequential_worst_true_residual": seq[2], "speedup_vs_sequential": round(seq[0] / med, 2)}
+
+    out = run(1)  # FP32 sloppy iterations
+    out["fp16_sloppy"] = run(2)
+    return out
 
 
 def main():
